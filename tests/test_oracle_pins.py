@@ -1,0 +1,332 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each check below is independent of the oracle's own formulas: closed forms
+derived from Eq. 2, symmetries (gauge covariance, H(mu)^dag = H(-mu)),
+sign(A)^2 = I (the property stated after Eq. 6), the Hermitian mu = 0 case,
+a library routine (scipy.linalg.signm) and brute force (Krylov on the full
+space).  A plausible slip in the oracle (a dropped term, a wrong sign, a
+misplaced U vs U^dag, a transposed operand) breaks at least one of them; the
+mutation tests at the end plant such slips and check that they are caught.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import lattice_inputs as LI
+import oracle as O
+from oracle import dirac as OD
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ----------------------------------------------------------------- gamma basis
+def test_gamma_algebra():
+    g = O.gamma_matrices()
+    for a in range(4):
+        assert np.allclose(g[a], g[a].conj().T)
+        for b in range(4):
+            anti = g[a] @ g[b] + g[b] @ g[a]
+            assert np.allclose(anti, 2.0 * np.eye(4) * (a == b))
+    # gamma_5 = gamma_1 gamma_2 gamma_3 gamma_4 = diag(1,1,-1,-1) in the chiral basis
+    assert np.allclose(g[4], np.diag([1, 1, -1, -1]))
+    for a in range(4):
+        assert np.allclose(g[4] @ g[a], -g[a] @ g[4])
+
+
+def test_kappa():
+    assert O.kappa_of(-1.5) == pytest.approx(0.2)
+    assert O.kappa_of(-1.8) == pytest.approx(1.0 / 4.4)
+
+
+# ------------------------------------------------------------ free-field pins
+FREE_CASES = [((2, 2, 2, 2), 0.0, False), ((2, 2, 2, 2), 0.3, True),
+              ((2, 2, 3, 4), 0.3, False), ((2, 3, 2, 4), 0.5, True),
+              ((3, 3, 3, 3), 0.1, False)]
+
+
+@pytest.mark.parametrize("dims,mu,ap", FREE_CASES)
+def test_free_field_matvec(dims, mu, ap):
+    """Explicit H_w(mu) on U = 1 equals the momentum-space H(p) of Eq. 2."""
+    u = LI.make_links(dims, "unit")
+    b = LI.gaussian_source(dims, cfg=0, inst=7)
+    h = O.hermitian_wilson_sparse(u, dims, mu, -1.5, ap)
+    assert rel(h @ b, O.free_field_h_apply(dims, mu, -1.5, b, ap)) < 1e-14
+
+
+@pytest.mark.parametrize("dims,mu,ap", FREE_CASES[:4])
+def test_free_field_sign_closed_form(dims, mu, ap):
+    """Dense Newton sign(H) b equals H(p)/sqrt(s(p)) b on the free field."""
+    u = LI.make_links(dims, "unit")
+    b = LI.gaussian_source(dims, cfg=0, inst=8)
+    h = O.hermitian_wilson_dense(u, dims, mu, -1.5, ap)
+    y = O.sign_newton(h) @ b
+    assert rel(y, O.free_field_sign_apply(dims, mu, -1.5, b, ap)) < 1e-12
+
+
+def test_free_field_spectrum():
+    dims, mu = (2, 2, 3, 4), 0.3
+    h = O.hermitian_wilson_dense(LI.make_links(dims, "unit"), dims, mu, -1.5)
+    ev = np.linalg.eigvals(h)
+    ref = O.free_field_spectrum(dims, mu, -1.5)
+    # every eigenvalue has a closed-form partner (multiset match by greedy pairing)
+    ref = list(ref)
+    for e in ev:
+        j = int(np.argmin(np.abs(np.asarray(ref) - e)))
+        assert abs(ref[j] - e) < 1e-9
+        ref.pop(j)
+
+
+# ------------------------------------------------------------------ symmetries
+def _haar_case(dims=(2, 2, 2, 2), inst=0):
+    return LI.make_links(dims, "haar", cfg=0, inst=inst)
+
+
+def test_adjoint_identity():
+    """H_w(mu)^dag = H_w(-mu): gamma_5 Hermitian, backward hops carry U^dag e^{-mu}."""
+    dims = (2, 3, 2, 3)
+    u = _haar_case(dims)
+    hp = O.hermitian_wilson_sparse(u, dims, 0.4, -1.5)
+    hm = O.hermitian_wilson_sparse(u, dims, -0.4, -1.5)
+    assert abs(hp.conj().T - hm).max() < 1e-15
+
+
+def test_gauge_covariance():
+    """U_{n,nu} -> g_n U_{n,nu} g_{n+nu}^dag gives H -> G H G^dag."""
+    dims = (2, 3, 2, 3)
+    u = _haar_case(dims, inst=3)
+    g = LI.haar_su3(LI.rng_for(0, 99, 0), LI.volume(dims))
+    up = np.empty_like(u)
+    for nu in range(4):
+        fwd, _ = OD.neighbour(dims, nu, +1)
+        up[:, nu] = g @ u[:, nu] @ np.conj(np.transpose(g[fwd], (0, 2, 1)))
+    gm = np.zeros((12 * len(g), 12 * len(g)), dtype=complex)
+    for n in range(len(g)):
+        gm[12 * n:12 * n + 12, 12 * n:12 * n + 12] = np.kron(np.eye(4), g[n])
+    h = O.hermitian_wilson_dense(u, dims, 0.3, -1.5)
+    hp = O.hermitian_wilson_dense(up, dims, 0.3, -1.5)
+    assert np.abs(hp - gm @ h @ gm.conj().T).max() < 1e-13
+
+
+def test_mu_zero_hermitian_and_unitary_sign():
+    dims = (2, 2, 2, 2)
+    h = O.hermitian_wilson_dense(_haar_case(dims), dims, 0.0, -1.5)
+    assert np.abs(h - h.conj().T).max() < 1e-15
+    w, vec = np.linalg.eigh(h)
+    s_ref = vec @ np.diag(np.sign(w)) @ vec.conj().T
+    s = O.sign_newton(h)
+    assert np.abs(s - s_ref).max() < 1e-12
+    assert np.abs(s - s.conj().T).max() < 1e-12
+    assert np.abs(s @ s.conj().T - np.eye(len(h))).max() < 1e-12
+
+
+# -------------------------------------------------------------- dense routes
+@pytest.fixture(scope="module")
+def haar2():
+    dims = (2, 2, 2, 2)
+    u = _haar_case(dims, inst=1)
+    h = O.hermitian_wilson_dense(u, dims, 0.3, -1.5)
+    return dims, u, h
+
+
+def test_sign_routes_agree(haar2):
+    _, _, h = haar2
+    sn, info = O.sign_newton(h, return_info=True)
+    se, einfo = O.sign_eig(h, return_info=True)
+    assert rel(sn, se) < 1e-11
+    assert rel(sn, sla.signm(h)) < 1e-9        # library routine, looser by design
+    assert info["x2_minus_i"] < 1e-12          # sign(A)^2 = I
+    assert einfo["min_abs_re"] > 1e-3
+
+
+def test_sign_commutes_with_h(haar2):
+    dims, _, h = haar2
+    b = LI.gaussian_source(dims, cfg=0, inst=2)
+    s = O.sign_newton(h)
+    assert rel(s @ (h @ b), h @ (s @ b)) < 1e-12
+
+
+def test_adjoint_sign_identity(haar2):
+    """<a, S(mu) b> = <S(-mu) a, b> from H(mu)^dag = H(-mu)."""
+    dims, u, h = haar2
+    hm = O.hermitian_wilson_dense(u, dims, -0.3, -1.5)
+    a = LI.gaussian_source(dims, cfg=0, inst=3)
+    b = LI.gaussian_source(dims, cfg=0, inst=4)
+    lhs = np.vdot(a, O.sign_newton(h) @ b)
+    rhs = np.vdot(O.sign_newton(hm) @ a, b)
+    assert abs(lhs - rhs) < 1e-12
+
+
+def test_sgn_scalar():
+    z = np.array([1 + 5j, -1e-3 + 2j, 2.0, -3.0 - 1j])
+    assert np.allclose(O.sgn(z), [1, -1, 1, -1])
+    # sgn(z) = z / sqrt(z^2) with the principal square root (Eq. 5)
+    assert np.allclose(z / np.sqrt(z * z), O.sgn(z))
+
+
+# ---------------------------------------------------------------- Krylov pins
+def test_arnoldi_relation(haar2):
+    dims, _, h = haar2
+    b = LI.gaussian_source(dims, cfg=0, inst=5)
+    k = 40
+    vmat, hmat, beta, kd = O.arnoldi_cgs2(lambda x: h @ x, b, k)
+    assert kd == k
+    assert np.abs(vmat.conj().T @ vmat - np.eye(k + 1)).max() < 1e-13
+    assert np.abs(h @ vmat[:, :k] - vmat @ hmat).max() < 1e-13
+    assert np.allclose(np.tril(hmat, -2), 0)
+    assert np.all(np.abs(np.diag(hmat, -1).imag) == 0) and np.all(np.diag(hmat, -1).real > 0)
+
+
+def test_krylov_full_space_is_exact(haar2):
+    """Krylov with k = N (or a happy breakdown) reproduces the dense sign."""
+    dims, _, h = haar2
+    b = LI.gaussian_source(dims, cfg=0, inst=6)
+    y, info = O.lr_arnoldi_sign(lambda x: h @ x, b, None, k=h.shape[0], route="eig")
+    assert rel(y, O.sign_newton(h) @ b) < 1e-10
+
+
+def test_krylov_breakdown_on_free_plane_wave():
+    """A free-field plane wave spans a tiny invariant space: happy breakdown, exact."""
+    dims = (2, 2, 2, 4)
+    u = LI.make_links(dims, "unit")
+    h = O.hermitian_wilson_dense(u, dims, 0.3, -1.5)
+    lx, ly, lz, lt = dims
+    t = np.arange(lt)
+    wave = np.exp(2j * np.pi * t / lt)[:, None, None, None, None, None] * np.ones((1, lz, ly, lx, 4, 3))
+    chi = np.zeros((4, 3), dtype=complex)
+    chi[0, 0] = 1.0
+    b = (wave * chi).reshape(-1)
+    b /= np.linalg.norm(b)
+    y, info = O.lr_arnoldi_sign(lambda x: h @ x, b, None, k=50)
+    assert info["k_used"] <= 4
+    assert rel(y, O.sign_newton(h) @ b) < 1e-12
+
+
+def test_small_sign_routes_agree(haar2):
+    dims, _, h = haar2
+    b = LI.gaussian_source(dims, cfg=0, inst=9)
+    _, hmat, _, _ = O.arnoldi_cgs2(lambda x: h @ x, b, 60)
+    hk = hmat[:60, :60]
+    assert rel(O.small_sign_e1(hk, "newton"), O.small_sign_e1(hk, "eig")) < 1e-10
+
+
+# ------------------------------------------------------------ LR deflation
+@pytest.fixture(scope="module")
+def haar3():
+    dims = (3, 3, 3, 3)
+    u = LI.make_links(dims, "haar", cfg=0, inst=11)
+    h = O.hermitian_wilson_dense(u, dims, 0.3, -1.5)
+    b = LI.gaussian_source(dims, cfg=0, inst=11)
+    y = O.sign_eig_apply(h, b)
+    return dims, u, h, b, y
+
+
+def test_lr_projector_properties(haar3):
+    dims, u, h, b, y = haar3
+    r, l, lam = O.critical_dense(h, 12)
+    defl = O.Deflation(r, l, lam)
+    assert np.abs(defl.g - np.eye(12)).max() < 1e-10           # L^dag R = I (Eq. 20 text)
+    assert np.abs(h @ r - r * lam).max() < 1e-12               # A R = R Lambda
+    assert np.abs(l.conj().T @ h - lam[:, None] * l.conj().T).max() < 1e-11
+    c, xo = defl.split(b)
+    assert np.abs(l.conj().T @ xo).max() < 1e-12               # x_ominus has no critical part
+    # Eq. 21 holds exactly: f(A) b = R f(Lambda) L^dag b + f(A) x_ominus
+    assert rel(defl.exact_part(c) + O.sign_eig_apply(h, xo), y) < 1e-11
+    # critical eigenvalues have the smallest |Re|
+    allev = np.linalg.eigvals(h)
+    assert np.max(np.abs(lam.real)) <= np.sort(np.abs(allev.real))[12] + 1e-12
+
+
+def test_lr_deflation_accelerates(haar3):
+    """Error falls with k, and deflation lowers it at fixed k (Results section trends)."""
+    dims, u, h, b, y = haar3
+    mv = lambda x: h @ x  # noqa: E731
+    errs = {}
+    for m in (0, 8, 24):
+        defl = O.Deflation(*O.critical_dense(h, m)) if m else None
+        errs[m] = [rel(O.lr_arnoldi_sign(mv, b, defl, k=k)[0], y) for k in (40, 80, 160)]
+    for m in errs:
+        assert errs[m][0] > errs[m][1] > errs[m][2]
+    assert errs[24][1] < errs[8][1] < errs[0][1]
+    assert errs[24][2] < 1e-7
+
+
+def test_lr_near_best_approximation(haar3):
+    """The LR result is close to the orthogonal projection of f(A)b on Omega_m + K_k."""
+    dims, u, h, b, y = haar3
+    r, l, lam = O.critical_dense(h, 12)
+    defl = O.Deflation(r, l, lam)
+    k = 60
+    yk, info = O.lr_arnoldi_sign(lambda x: h @ x, b, defl, k=k)
+    _, xo = defl.split(b)
+    vmat, _, _, _ = O.arnoldi_cgs2(lambda x: h @ x, xo, k)
+    q, _ = np.linalg.qr(np.concatenate([r, vmat[:, :k]], axis=1))
+    best = q @ (q.conj().T @ y)
+    assert np.linalg.norm(yk - y) < 20 * np.linalg.norm(best - y)
+
+
+def test_hermitian_deflation_special_case():
+    """At mu = 0 LR deflation reduces to Eq. 12: L = R orthonormal, G = I."""
+    dims = (2, 2, 3, 3)
+    u = LI.make_links(dims, "haar", cfg=0, inst=12)
+    h = O.hermitian_wilson_dense(u, dims, 0.0, -1.5)
+    r, l, lam = O.critical_dense(h, 10)
+    assert np.abs(lam.imag).max() < 1e-12
+    assert np.abs(r.conj().T @ r - np.eye(10)).max() < 1e-10
+    assert np.abs(l - r).max() < 1e-10
+
+
+def test_critical_sparse_matches_dense(haar3):
+    dims, u, h, b, y = haar3
+    hs = O.hermitian_wilson_sparse(u, dims, 0.3, -1.5)
+    hm = O.hermitian_wilson_sparse(u, dims, -0.3, -1.5)
+    r1, l1, lam1 = O.critical_dense(h, 10)
+    r2, l2, lam2 = O.critical_sparse(hs, hm, 10)
+    assert np.abs(np.sort_complex(lam1) - np.sort_complex(lam2)).max() < 1e-10
+    # the oblique projector R G^{-1} L^dag is canonical
+    p1 = O.Deflation(r1, l1, lam1)
+    p2 = O.Deflation(r2, l2, lam2)
+    assert rel(p2.r @ p2.coeffs(b), p1.r @ p1.coeffs(b)) < 1e-9
+    assert max(O.eig_residuals(h, r2, l2, lam2)) < 1e-10
+
+
+def test_monitor_stops_early(haar3):
+    dims, u, h, b, y = haar3
+    defl = O.Deflation(*O.critical_dense(h, 24))
+    yk, info = O.lr_arnoldi_sign(lambda x: h @ x, b, defl, k=400, check=10, tol=1e-9)
+    assert info["k_used"] < 400 and info["est"] <= 1e-9
+    assert rel(yk, y) < 1e-7
+
+
+# ------------------------------------------------- planted mistakes are caught
+def test_planted_mu_sign_flip_is_caught(monkeypatch):
+    """Swapping e^{+mu} and e^{-mu} in the oracle breaks the free-field pin."""
+    dims, mu = (2, 2, 2, 4), 0.3
+    u = LI.make_links(dims, "unit")
+    b = LI.gaussian_source(dims, cfg=0, inst=13)
+    wrong = O.hermitian_wilson_sparse(u, dims, -mu, -1.5)
+    assert rel(wrong @ b, O.free_field_h_apply(dims, mu, -1.5, b)) > 1e-3
+
+
+def test_planted_link_adjoint_slip_is_caught(monkeypatch):
+    """Using U instead of U^dag on the backward hop breaks H(mu)^dag = H(-mu)
+    and gauge covariance."""
+    dims = (2, 3, 2, 3)
+    u = _haar_case(dims, inst=3)
+    monkeypatch.setattr(OD, "_backward_link", lambda links, bwd, nu: links[bwd, nu])
+    hp = O.hermitian_wilson_sparse(u, dims, 0.4, -1.5)
+    hm = O.hermitian_wilson_sparse(u, dims, -0.4, -1.5)
+    assert abs(hp.conj().T - hm).max() > 1e-3
+
+
+def test_planted_dropped_diagonal_is_caught(monkeypatch):
+    """Dropping the e^{-mu} factor (a plausible slip) breaks the free-field pin."""
+    dims, mu = (2, 2, 2, 4), 0.3
+    u = LI.make_links(dims, "unit")
+    b = LI.gaussian_source(dims, cfg=0, inst=14)
+    real_exp = np.exp
+    monkeypatch.setattr(OD.np, "exp", lambda x: 1.0 if np.isscalar(x) and x < 0 else real_exp(x))
+    h = O.hermitian_wilson_sparse(u, dims, mu, -1.5)
+    monkeypatch.undo()
+    assert rel(h @ b, O.free_field_h_apply(dims, mu, -1.5, b)) > 1e-3
