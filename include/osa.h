@@ -1,0 +1,187 @@
+/*
+ * osa.h -- overlap sign apply: y = sign(H_w(mu)) b on AMD MI355X (gfx950).
+ *
+ * C ABI of the library libosa.so.  The method is the LR-deflated Arnoldi
+ * approximation of Bloch, Wettig, Frommer and Lang, "An iterative method to
+ * compute the overlap Dirac operator at nonzero chemical potential":
+ *
+ *   H_w(mu) = gamma_5 D_w(mu)                 (Eq. 1, Eq. 2)
+ *   f(A) x ~ R f(Lambda) L^dag x + beta V_k f(H_k) e_1     (Eq. 22, f = sgn)
+ *
+ * with R, L the right/left eigenvectors of the m critical eigenvalues
+ * (smallest |Re lambda|, Eq. 20), V_k, H_k the Arnoldi basis and Hessenberg
+ * matrix of the deflated source (Eq. 7 applied to x_ominus, Eq. 21), and
+ * f(H_k) e_1 the first column of the sign of the small Hessenberg matrix.
+ *
+ * CONVENTIONS (all entry points)
+ *  - Pointers are DEVICE pointers unless the comment says (host).
+ *  - complex = interleaved (re, im): complex128 = 2 x double, complex64 = 2 x float.
+ *  - Site index  site = x + Lx*(y + Ly*(z + Lz*t)), V = Lx*Ly*Lz*Lt.
+ *  - Vector index i = (site*4 + spin)*3 + color, N = 12*V complex128 entries.
+ *  - Links U[((site*4 + nu)*3 + a)*3 + b] = (U_{site,nu})_{ab}; nu = 0,1,2 are
+ *    x,y,z and nu = 3 is the temporal direction that carries e^{+-mu}.
+ *  - Gamma matrices in the chiral basis: gamma_k = [[0,-i s_k],[i s_k,0]],
+ *    gamma_4 = [[0,1],[1,0]], gamma_5 = gamma_1 gamma_2 gamma_3 gamma_4 =
+ *    diag(1,1,-1,-1).  Boundary conditions are periodic, optionally
+ *    antiperiodic in time.
+ *  - All work is ordered on the stream given at creation (NULL = default
+ *    stream).  Calls that write (host) outputs synchronise that stream first.
+ *  - No exception or exit() crosses the ABI: every call returns osa_status.
+ *  - Ownership: the caller owns links, sources, results and every buffer it
+ *    passes; they must stay valid until the call returns.  The library copies
+ *    the links at creation.  The context owns all workspace (Krylov basis,
+ *    Hessenberg matrix, deflation vectors, scratch), allocated with hipMalloc
+ *    at creation / deflation and freed by osa_destroy.
+ */
+#ifndef OSA_H
+#define OSA_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#if defined(__GNUC__)
+#define OSA_API __attribute__((visibility("default")))
+#else
+#define OSA_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OSA_OK = 0,
+    OSA_NOT_CONVERGED = 1,      /* result usable: best iterate at k_max, resid_est > tol     */
+    OSA_ERR_ARG = -1,           /* invalid argument; detected before any device work          */
+    OSA_ERR_HIP = -2,           /* a HIP runtime call failed                                   */
+    OSA_ERR_OOM = -3,           /* workspace allocation failed                                 */
+    OSA_ERR_NONFINITE = -4,     /* NaN / Inf in the input or an intermediate                   */
+    OSA_ERR_IMAG_AXIS = -5,     /* a deflated eigenvalue lies on the imaginary axis (sgn undefined, Eq. 5) */
+    OSA_ERR_EIG_NOCONV = -6,    /* critical eigenpairs not found to the requested accuracy     */
+    OSA_ERR_NEWTON_NOCONV = -7, /* the small sign iteration did not converge                  */
+    OSA_ERR_STATE = -8          /* call out of order (e.g. apply before deflation when m > 0)  */
+} osa_status;
+
+typedef enum { OSA_FP64 = 0, OSA_FP32 = 1 } osa_prec;
+
+typedef struct {
+    int32_t dims[4];            /* Lx, Ly, Lz, Lt; each >= 2                                   */
+    int32_t antiperiodic_t;     /* 1: factor -1 on temporal hops across the boundary          */
+} osa_lattice;
+
+/* Options; an all-zero struct selects every default. */
+typedef struct {
+    int32_t k_max;              /* Krylov size cap for the solve            (default 600)     */
+    int32_t check_every;        /* convergence check interval (default 50); < 0: run exactly
+                                   k_max steps with no check (fixed-k mode)                   */
+    int32_t no_reproject;       /* 1: skip the per-step oblique re-projection (default 0)     */
+    int32_t eig_ncv;            /* eigensolver basis size, <= 96 (default min(96, 2 nev + 16)) */
+    int32_t eig_max_restarts;   /* eigensolver restart cap                 (default 2000)     */
+    osa_prec eig_prec;          /* FP32: search in FP32, then refine in FP64 (default FP64)   */
+    double eig_tol;             /* relative Krylov-Schur residual target   (default 1e-12)    */
+} osa_opts;
+
+/* Per-solve diagnostics (host struct). */
+typedef struct {
+    double resid_est;           /* beta |s_k - s_k'| / |y|: change since the previous check   */
+    double min_abs_re_lambda;   /* smallest |Re lambda| among the deflated eigenvalues         */
+    double max_eig_resid;       /* max_i |H r_i - lambda_i r_i| / |r_i| (also over left vectors) */
+    double t_init_ms;           /* deflation (eigensolver) time                               */
+    double t_solve_ms;          /* Arnoldi + small sign + assembly time                       */
+    int32_t k_used;             /* Krylov size of the returned result                        */
+    int32_t n_defl;             /* number of deflated eigenpairs m                            */
+    int32_t status;             /* osa_status of this source                                  */
+    int32_t newton_iters;       /* iterations of the final small sign                         */
+    int64_t eig_matvecs;        /* stencil applications spent in the eigensolver             */
+    int32_t eig_restarts;       /* eigensolver restarts (right + left)                        */
+    int32_t breakdown;          /* 1: happy Arnoldi breakdown (result exact in K_k)           */
+} osa_info;
+
+typedef struct osa_ctx osa_ctx;
+
+/* ---------------------------------------------------------------------------
+ * One-shot form: y = sign(H_w(mu)) b with n_defl deflated critical eigenpairs.
+ * Operator: Eq. 2 with kappa = 1/(8 + 2 m_w), m_w in (-2, 0) (definition
+ * section); method: Eq. 20-22.
+ *   lat        (host) lattice extents and boundary condition
+ *   links      V*4*9 complex, complex128 if link_prec == OSA_FP64 else complex64
+ *              (FP32 links define the operator exactly as stored)
+ *   source     N complex128;   result  N complex128 (may not alias source)
+ *   tol        > 0, stop threshold on the convergence estimate
+ *   n_defl     0 <= n_defl < N and n_defl <= 64
+ *   resid_est  (host, may be NULL) final convergence estimate
+ * Returns OSA_OK, OSA_NOT_CONVERGED (result usable) or an error.
+ * ------------------------------------------------------------------------- */
+OSA_API osa_status overlap_sign_apply(const osa_lattice* lat, const void* links, osa_prec link_prec,
+                              double mu, double m_w, const void* source, double tol,
+                              int32_t n_defl, void* result, double* resid_est, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Reusable form.  The deflation data is the expensive, reusable state (the
+ * initialisation phase of the Results section): create once, deflate once,
+ * apply to many sources.
+ * ------------------------------------------------------------------------- */
+
+/* Create a context for H_w(mu) on the given links (copied to the device in
+ * the internal layout).  opts may be NULL (defaults).  stream: hipStream_t. */
+OSA_API osa_status osa_create(osa_ctx** out, const osa_lattice* lat, const void* links,
+                      osa_prec link_prec, double mu, double m_w, const osa_opts* opts,
+                      void* stream);
+
+/* Compute the n_defl critical eigenpairs (Eq. 20): right eigenvectors of
+ * H_w(mu) and left ones as right eigenvectors of H_w(-mu) = H_w(mu)^dag, by
+ * Krylov-Schur on H^2 followed by a Rayleigh-Ritz step with H; selects the
+ * n_defl eigenvalues of smallest |Re lambda| among the converged ones.
+ * info (host, may be NULL) receives eigensolver statistics.
+ * Errors: OSA_ERR_EIG_NOCONV, OSA_ERR_IMAG_AXIS (|Re lambda| < 1e-12 |H|). */
+OSA_API osa_status osa_deflate(osa_ctx* ctx, int32_t n_defl, osa_info* info);
+
+/* Import deflation data: R, L are m vectors each (m*N complex128, vector j at
+ * offset j*N, boundary layout); lambda (host) holds m complex128 values
+ * (re, im interleaved).  Only the projector R (L^dag R)^{-1} L^dag and the
+ * eigenvalues matter; scale and phase of the vectors are free. */
+OSA_API osa_status osa_set_deflation(osa_ctx* ctx, int32_t m, const void* R, const void* L,
+                             const double* lambda);
+
+/* Export the current deflation data in the same layout (buffers of m*N
+ * complex128; lambda (host) 2m doubles).  m_out (host) receives m. */
+OSA_API osa_status osa_get_deflation(const osa_ctx* ctx, int32_t* m_out, void* R, void* L,
+                             double* lambda);
+
+/* Use only the first m deflation pairs (in |Re lambda| order); m <= current. */
+OSA_API osa_status osa_set_active_deflation(osa_ctx* ctx, int32_t m);
+
+/* Y = sign(H_w(mu)) B for nrhs sources (Eq. 22).  B, Y: nrhs*N complex128,
+ * source j at offset j*N.  All sources share the deflation data.  infos
+ * (host, may be NULL) receives nrhs osa_info records.  Returns the worst
+ * status over the sources. */
+OSA_API osa_status osa_apply(osa_ctx* ctx, int32_t nrhs, const void* B, void* Y, double tol,
+                     osa_info* infos);
+
+/* Uneven batch: n independent contexts (different lattices, mu, m_w), one
+ * source each, solved together.  B[i], Y[i] are device pointers to N_i
+ * complex128; infos (host) n records. */
+OSA_API osa_status osa_batch_apply(int32_t n, osa_ctx* const* ctxs, const void* const* B,
+                           void* const* Y, double tol, osa_info* infos);
+
+/* Replace the options of an existing context (NULL = defaults). */
+OSA_API osa_status osa_set_opts(osa_ctx* ctx, const osa_opts* opts);
+
+/* Y = H_w(mu) X (Eq. 1-2), nrhs vectors, boundary layout.  The stencil alone,
+ * for operator checks. */
+OSA_API osa_status osa_apply_hw(osa_ctx* ctx, int32_t nrhs, const void* X, void* Y);
+
+/* s = sign(A) e_1 for a k x k complex128 matrix A stored column-major (device,
+ * leading dimension k), by the scaled Newton iteration used for f(H_k) e_1.
+ * s: k complex128 (device).  iters (host, may be NULL).  Standalone entry of
+ * the small-sign kernel for checks; stream-ordered on `stream`. */
+OSA_API osa_status osa_small_sign(int32_t k, const void* A, void* s, int32_t* iters, void* stream);
+
+OSA_API void osa_destroy(osa_ctx* ctx);
+OSA_API const char* osa_status_string(osa_status s);
+OSA_API const char* osa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OSA_H */

@@ -1,0 +1,294 @@
+"""Python binding of libosa: y = sign(H_w(mu)) b on MI355X.
+
+Thin ctypes layer over the C ABI in include/osa.h: argument checks and
+marshalling only.  Every step of the computation runs in the library's HIP
+kernels; PyTorch supplies device memory (torch.empty on the GPU) and the
+current stream.  There is no CPU fallback: if libosa.so is missing or the
+device is not a GPU, the calls raise.
+
+Layouts (boundary, identical to the C ABI):
+  links: complex128 or complex64 tensor of shape (V, 4, 3, 3)
+         (site = x + Lx*(y + Ly*(z + Lz*t)), direction 3 = time)
+  vectors: complex128 tensor of shape (N,) or (nrhs, N), N = 12 V,
+           index (site*4 + spin)*3 + color.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libosa.so")
+
+OSA_OK = 0
+OSA_NOT_CONVERGED = 1
+STATUS_NAMES = {0: "OSA_OK", 1: "OSA_NOT_CONVERGED", -1: "OSA_ERR_ARG", -2: "OSA_ERR_HIP",
+                -3: "OSA_ERR_OOM", -4: "OSA_ERR_NONFINITE", -5: "OSA_ERR_IMAG_AXIS",
+                -6: "OSA_ERR_EIG_NOCONV", -7: "OSA_ERR_NEWTON_NOCONV", -8: "OSA_ERR_STATE"}
+FP64, FP32 = 0, 1
+
+EXPORTS = ["overlap_sign_apply", "osa_create", "osa_deflate", "osa_set_deflation",
+           "osa_get_deflation", "osa_set_active_deflation", "osa_apply", "osa_batch_apply",
+           "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_destroy", "osa_status_string",
+           "osa_version"]
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("antiperiodic_t", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("k_max", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("no_reproject", ctypes.c_int32), ("eig_ncv", ctypes.c_int32),
+                ("eig_max_restarts", ctypes.c_int32), ("eig_prec", ctypes.c_int32),
+                ("eig_tol", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("resid_est", ctypes.c_double), ("min_abs_re_lambda", ctypes.c_double),
+                ("max_eig_resid", ctypes.c_double), ("t_init_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("k_used", ctypes.c_int32),
+                ("n_defl", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("newton_iters", ctypes.c_int32), ("eig_matvecs", ctypes.c_int64),
+                ("eig_restarts", ctypes.c_int32), ("breakdown", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class OsaError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libosa.so (built in-tree by build.py); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libosa.so not found at {LIB_PATH}; run paper_0710_0341_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.overlap_sign_apply.argtypes = [ctypes.POINTER(Lattice), vp, i32, dbl, dbl, vp, dbl, i32, vp,
+                                     ctypes.POINTER(dbl), vp]
+    L.osa_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Lattice), vp, i32, dbl, dbl,
+                             ctypes.POINTER(Opts), vp]
+    L.osa_deflate.argtypes = [vp, i32, ctypes.POINTER(Info)]
+    L.osa_set_deflation.argtypes = [vp, i32, vp, vp, ctypes.POINTER(dbl)]
+    L.osa_get_deflation.argtypes = [vp, ctypes.POINTER(i32), vp, vp, ctypes.POINTER(dbl)]
+    L.osa_set_active_deflation.argtypes = [vp, i32]
+    L.osa_apply.argtypes = [vp, i32, vp, vp, dbl, ctypes.POINTER(Info)]
+    L.osa_batch_apply.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  dbl, ctypes.POINTER(Info)]
+    L.osa_set_opts.argtypes = [vp, ctypes.POINTER(Opts)]
+    L.osa_apply_hw.argtypes = [vp, i32, vp, vp]
+    L.osa_small_sign.argtypes = [i32, vp, vp, ctypes.POINTER(i32), vp]
+    L.osa_destroy.argtypes = [vp]
+    L.osa_destroy.restype = None
+    L.osa_status_string.argtypes = [i32]
+    L.osa_status_string.restype = ctypes.c_char_p
+    L.osa_version.restype = ctypes.c_char_p
+    for name in EXPORTS[:-3]:
+        if name != "osa_destroy":
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(status, where, allow_not_converged=True):
+    if status == OSA_OK or (allow_not_converged and status == OSA_NOT_CONVERGED):
+        return status
+    raise OsaError(status, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _lattice(dims, antiperiodic_t=False):
+    lat = Lattice()
+    for i in range(4):
+        lat.dims[i] = int(dims[i])
+    lat.antiperiodic_t = 1 if antiperiodic_t else 0
+    return lat
+
+
+def make_opts(k_max=0, check_every=0, no_reproject=False, eig_ncv=0, eig_max_restarts=0,
+              eig_prec=FP64, eig_tol=0.0):
+    o = Opts()
+    o.k_max, o.check_every, o.no_reproject = int(k_max), int(check_every), int(bool(no_reproject))
+    o.eig_ncv, o.eig_max_restarts, o.eig_prec = int(eig_ncv), int(eig_max_restarts), int(eig_prec)
+    o.eig_tol = float(eig_tol)
+    return o
+
+
+def _link_prec(links):
+    torch = _torch()
+    if links.dtype == torch.complex128:
+        return FP64
+    if links.dtype == torch.complex64:
+        return FP32
+    raise TypeError("links must be complex128 or complex64")
+
+
+def overlap_sign_apply(links, dims, mu, m_w, b, tol, n_defl, antiperiodic_t=False):
+    """One-shot y = sign(H_w(mu)) b.  Returns (y, resid_est, status)."""
+    torch = _torch()
+    prec = _link_prec(links)
+    lp = _dev_ptr(links, links.dtype, "links")
+    bp = _dev_ptr(b, torch.complex128, "b")
+    y = torch.empty_like(b)
+    est = ctypes.c_double(0.0)
+    lat = _lattice(dims, antiperiodic_t)
+    st = lib().overlap_sign_apply(ctypes.byref(lat), lp, prec, float(mu), float(m_w), bp,
+                                  float(tol), int(n_defl), ctypes.c_void_p(y.data_ptr()),
+                                  ctypes.byref(est), _stream())
+    _check(st, "overlap_sign_apply")
+    return y, est.value, st
+
+
+sign_apply = overlap_sign_apply
+
+
+class Context:
+    """Reusable context: create once, deflate once, apply to many sources."""
+
+    def __init__(self, links, dims, mu, m_w, antiperiodic_t=False, **opts):
+        self._h = ctypes.c_void_p(None)
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.N = 12 * self.V
+        self.mu, self.m_w = float(mu), float(m_w)
+        prec = _link_prec(links)
+        lp = _dev_ptr(links, links.dtype, "links")
+        if links.numel() != self.V * 36:
+            raise ValueError("links must have V*4*3*3 entries")
+        self._opts = make_opts(**opts)
+        lat = _lattice(dims, antiperiodic_t)
+        _check(lib().osa_create(ctypes.byref(self._h), ctypes.byref(lat), lp, prec, self.mu,
+                                self.m_w, ctypes.byref(self._opts), _stream()), "osa_create",
+               allow_not_converged=False)
+
+    def close(self):
+        if self._h:
+            lib().osa_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_opts(self, **opts):
+        self._opts = make_opts(**opts)
+        _check(lib().osa_set_opts(self._h, ctypes.byref(self._opts)), "osa_set_opts", False)
+
+    def deflate(self, n_defl):
+        info = Info()
+        _check(lib().osa_deflate(self._h, int(n_defl), ctypes.byref(info)), "osa_deflate", False)
+        return info.as_dict()
+
+    def set_deflation(self, R, L, lam):
+        """R, L: complex128 GPU tensors (m, N); lam: m complex numbers (host)."""
+        torch = _torch()
+        m = int(R.shape[0]) if R is not None else 0
+        lam = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128))
+        lam_d = lam.view(np.float64)
+        if m:
+            rp = _dev_ptr(R, torch.complex128, "R")
+            lpp = _dev_ptr(L, torch.complex128, "L")
+        else:
+            rp = lpp = ctypes.c_void_p(None)
+        _check(lib().osa_set_deflation(self._h, m, rp, lpp,
+                                       lam_d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "osa_set_deflation", False)
+
+    def get_deflation(self, device="cuda"):
+        torch = _torch()
+        m = ctypes.c_int32(0)
+        _check(lib().osa_get_deflation(self._h, ctypes.byref(m), None, None, None),
+               "osa_get_deflation", False)
+        mm = m.value
+        R = torch.empty((mm, self.N), dtype=torch.complex128, device=device)
+        L = torch.empty((mm, self.N), dtype=torch.complex128, device=device)
+        lam = np.zeros(2 * max(mm, 1))
+        _check(lib().osa_get_deflation(self._h, ctypes.byref(m), ctypes.c_void_p(R.data_ptr()),
+                                       ctypes.c_void_p(L.data_ptr()),
+                                       lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "osa_get_deflation", False)
+        return R, L, lam[: 2 * mm].view(np.complex128)
+
+    def set_active_deflation(self, m):
+        _check(lib().osa_set_active_deflation(self._h, int(m)), "osa_set_active_deflation", False)
+
+    def apply(self, B, tol=1e-10):
+        """Y = sign(H) B for B of shape (N,) or (nrhs, N).  Returns (Y, infos, status)."""
+        torch = _torch()
+        bp = _dev_ptr(B, torch.complex128, "B")
+        nrhs = 1 if B.dim() == 1 else int(B.shape[0])
+        Y = torch.empty_like(B)
+        infos = (Info * nrhs)()
+        st = lib().osa_apply(self._h, nrhs, bp, ctypes.c_void_p(Y.data_ptr()), float(tol), infos)
+        _check(st, "osa_apply")
+        return Y, [i.as_dict() for i in infos], st
+
+    def apply_hw(self, X):
+        """Y = H_w(mu) X (stencil only)."""
+        torch = _torch()
+        xp = _dev_ptr(X, torch.complex128, "X")
+        nrhs = 1 if X.dim() == 1 else int(X.shape[0])
+        Y = torch.empty_like(X)
+        _check(lib().osa_apply_hw(self._h, nrhs, xp, ctypes.c_void_p(Y.data_ptr())),
+               "osa_apply_hw", False)
+        return Y
+
+
+def batch_apply(contexts, sources, tol=1e-10):
+    """Uneven batch: one source per context.  Returns (outputs, infos, status)."""
+    torch = _torch()
+    n = len(contexts)
+    outs = [torch.empty_like(b) for b in sources]
+    hs = (ctypes.c_void_p * n)(*[c._h.value for c in contexts])
+    bs = (ctypes.c_void_p * n)(*[_dev_ptr(b, torch.complex128, "B").value for b in sources])
+    ys = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    infos = (Info * n)()
+    st = lib().osa_batch_apply(n, hs, bs, ys, float(tol), infos)
+    _check(st, "osa_batch_apply")
+    return outs, [i.as_dict() for i in infos], st
+
+
+def small_sign(A):
+    """s = sign(A) e_1 for a square complex128 GPU tensor A (the Newton kernel)."""
+    torch = _torch()
+    k = int(A.shape[0])
+    Acm = A.t().contiguous()          # column-major storage
+    s = torch.empty(k, dtype=torch.complex128, device=A.device)
+    it = ctypes.c_int32(0)
+    _check(lib().osa_small_sign(k, ctypes.c_void_p(Acm.data_ptr()), ctypes.c_void_p(s.data_ptr()),
+                                ctypes.byref(it), _stream()), "osa_small_sign", False)
+    return s, it.value

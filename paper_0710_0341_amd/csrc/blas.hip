@@ -1,0 +1,507 @@
+// Tall-skinny complex kernels for the Arnoldi recurrence (Eq. 7), the LR
+// projection (Eq. 21) and the final assembly (Eq. 22).
+//
+// All reductions are two-stage with a fixed order (per-block partial sums, then
+// one sequential sum per output), so results are bitwise reproducible run to
+// run.  Vectors are stored as complex128 (double2) or complex64 (float2);
+// every accumulation is in double.
+#include "kernels.hpp"
+
+namespace osa {
+
+static constexpr int kBlock = 256;
+static constexpr int kWaves = kBlock / 64;
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum NV doubles over the block; results valid in sm_out[0..NV) after return.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sm /* kWaves*NV */,
+                                          double* sm_out /* NV */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = wave_sum(v[i]);
+        if (lane == 0) sm[wave * NV + i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NV; i += kBlock) {
+        double s = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s += sm[w * NV + i];
+        sm_out[i] = s;
+    }
+    __syncthreads();
+}
+
+TsPlan ts_plan(int64_t n) {
+    TsPlan p;
+    p.n = n;
+    // about 64 chunks, each a multiple of the block size
+    int64_t rpc = ceil_div(ceil_div(n, 64), kBlock) * kBlock;
+    if (rpc < kBlock) rpc = kBlock;
+    p.rows_per_chunk = (int)rpc;
+    p.nchunks = (int)ceil_div(n, rpc);
+    return p;
+}
+
+// ---------------------------------------------------------------- dot
+template <typename T, int C>
+__global__ __launch_bounds__(kBlock) void k_dot_partial(const T* __restrict__ B, int64_t ldb,
+                                                        int ncols, const T* __restrict__ w,
+                                                        int64_t n, int rpc, int nchunks,
+                                                        cd* __restrict__ partial) {
+    __shared__ double sm[kWaves * 2 * C];
+    __shared__ double so[2 * C];
+    const int q = blockIdx.x;
+    const int c0 = blockIdx.y * C;
+    const int64_t r0 = (int64_t)q * rpc;
+    const int64_t r1 = (r0 + rpc < n) ? r0 + rpc : n;
+    double acc[2 * C];
+#pragma unroll
+    for (int i = 0; i < 2 * C; ++i) acc[i] = 0.0;
+    const int nc = (ncols - c0 < C) ? ncols - c0 : C;
+    if (nc == C) {
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+            const cd wi = tod(w[i]);
+#pragma unroll
+            for (int cc = 0; cc < C; ++cc) {
+                const cd b = tod(B[(int64_t)(c0 + cc) * ldb + i]);
+                acc[2 * cc] = fma(b.x, wi.x, fma(b.y, wi.y, acc[2 * cc]));
+                acc[2 * cc + 1] = fma(b.x, wi.y, fma(-b.y, wi.x, acc[2 * cc + 1]));
+            }
+        }
+    } else {
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+            const cd wi = tod(w[i]);
+#pragma unroll
+            for (int cc = 0; cc < C; ++cc) {
+                if (cc < nc) {
+                    const cd b = tod(B[(int64_t)(c0 + cc) * ldb + i]);
+                    acc[2 * cc] = fma(b.x, wi.x, fma(b.y, wi.y, acc[2 * cc]));
+                    acc[2 * cc + 1] = fma(b.x, wi.y, fma(-b.y, wi.x, acc[2 * cc + 1]));
+                }
+            }
+        }
+    }
+    block_sum<2 * C>(acc, sm, so);
+    if (threadIdx.x < nc) partial[(int64_t)(c0 + threadIdx.x) * nchunks + q] =
+        mk(so[2 * threadIdx.x], so[2 * threadIdx.x + 1]);
+}
+
+void launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bool fp32,
+                        const TsPlan& p, cd* partial, hipStream_t st) {
+    if (ncols <= 0) return;
+    constexpr int C = 8;
+    dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C)), blk(kBlock);
+    if (fp32)
+        hipLaunchKernelGGL((k_dot_partial<cf, C>), grid, blk, 0, st, (const cf*)B, ldb, ncols,
+                           (const cf*)w, p.n, p.rows_per_chunk, p.nchunks, partial);
+    else
+        hipLaunchKernelGGL((k_dot_partial<cd, C>), grid, blk, 0, st, (const cd*)B, ldb, ncols,
+                           (const cd*)w, p.n, p.rows_per_chunk, p.nchunks, partial);
+    OSA_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- reduce
+// One block.  val[c] = sum_q partial[c*nchunks + q]; then optionally val = M val.
+// mode 0: out = val; mode 1: out += val.  accum (nullable) += val.
+__global__ __launch_bounds__(1024) void k_reduce_partial(const cd* __restrict__ partial,
+                                                         int nchunks, int ncols, cd* out,
+                                                         int mode, const cd* __restrict__ M,
+                                                         cd* tmp, double* hfro2) {
+    __shared__ double sred[16];
+    double loc = 0.0;
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+        cd s = mk(0.0, 0.0);
+        for (int q = 0; q < nchunks; ++q) s = cadd(s, partial[(int64_t)c * nchunks + q]);
+        if (M) tmp[c] = s;
+        else {
+            out[c] = (mode == 1) ? cadd(out[c], s) : s;
+            loc += cabs2(s);
+        }
+    }
+    if (M) {
+        __syncthreads();
+        __threadfence_block();
+        for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+            cd s = mk(0.0, 0.0);
+            for (int d = 0; d < ncols; ++d) cfma(s, M[c + (int64_t)d * ncols], tmp[d]);
+            out[c] = (mode == 1) ? cadd(out[c], s) : s;
+            loc += cabs2(s);
+        }
+    }
+    if (hfro2) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        double s = wave_sum(loc);
+        if (lane == 0) sred[wave] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0;
+            for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) t += sred[wv];
+            *hfro2 += t;
+        }
+    }
+}
+
+void launch_reduce_partial(const cd* partial, int nchunks, int ncols, cd* out, int mode,
+                           const cd* M, cd* tmp, double* hfro2, hipStream_t st) {
+    if (ncols <= 0) return;
+    int threads = ncols >= 1024 ? 1024 : (int)ceil_div(ncols, 64) * 64;
+    hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(threads), 0, st, partial, nchunks, ncols,
+                       out, mode, M, tmp, hfro2);
+    OSA_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- update
+// w[i] = alpha*w[i] - sum_{c in group} B[c][i] coef[c]; the column loop is split
+// into G groups writing to scratch when the row count alone cannot fill the GPU.
+static constexpr int kCoefTile = 256;
+
+template <typename T>
+__device__ __forceinline__ cd gemv_rows(const T* __restrict__ B, int64_t ldb, int cbeg, int cend,
+                                        const cd* __restrict__ coef, int64_t i, cd* scoef) {
+    cd acc = mk(0.0, 0.0);
+    for (int cb = cbeg; cb < cend; cb += kCoefTile) {
+        const int ce = (cb + kCoefTile < cend) ? cb + kCoefTile : cend;
+        __syncthreads();
+        for (int c = cb + (int)threadIdx.x; c < ce; c += kBlock) scoef[c - cb] = coef[c];
+        __syncthreads();
+        int c = cb;
+        for (; c + 4 <= ce; c += 4) {
+            const cd b0 = tod(B[(int64_t)(c + 0) * ldb + i]);
+            const cd b1 = tod(B[(int64_t)(c + 1) * ldb + i]);
+            const cd b2 = tod(B[(int64_t)(c + 2) * ldb + i]);
+            const cd b3 = tod(B[(int64_t)(c + 3) * ldb + i]);
+            cfma(acc, b0, scoef[c - cb + 0]);
+            cfma(acc, b1, scoef[c - cb + 1]);
+            cfma(acc, b2, scoef[c - cb + 2]);
+            cfma(acc, b3, scoef[c - cb + 3]);
+        }
+        for (; c < ce; ++c) cfma(acc, tod(B[(int64_t)c * ldb + i]), scoef[c - cb]);
+    }
+    return acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_direct(T* w, const T* __restrict__ B,
+                                                          int64_t ldb, int ncols,
+                                                          const cd* __restrict__ coef, int64_t n,
+                                                          double alpha, double sgn,
+                                                          double* normp) {
+    __shared__ cd scoef[kCoefTile];
+    __shared__ double sm[kWaves];
+    __shared__ double so[1];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t ii = (i < n) ? i : n - 1;   // keep every thread in the barriers
+    cd acc = gemv_rows(B, ldb, 0, ncols, coef, ii, scoef);
+    cd v = mk(0.0, 0.0);
+    if (i < n) {
+        cd base = (alpha != 0.0) ? cscale(tod(w[i]), alpha) : mk(0.0, 0.0);
+        v = mk(base.x + sgn * acc.x, base.y + sgn * acc.y);
+        w[i] = fromd<T>(v);
+    }
+    if (normp) {
+        cd vr = tod(fromd<T>(v));
+        double nv[1] = {(i < n) ? cabs2(vr) : 0.0};
+        block_sum<1>(nv, sm, so);
+        if (threadIdx.x == 0) normp[blockIdx.x] = so[0];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_split(const T* __restrict__ B, int64_t ldb,
+                                                         int ncols, const cd* __restrict__ coef,
+                                                         int64_t n, int cpg,
+                                                         cd* __restrict__ scratch) {
+    __shared__ cd scoef[kCoefTile];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t ii = (i < n) ? i : n - 1;
+    const int g = blockIdx.y;
+    const int cb = g * cpg;
+    const int ce = (cb + cpg < ncols) ? cb + cpg : ncols;
+    cd acc = gemv_rows(B, ldb, cb, ce, coef, ii, scoef);
+    if (i < n) scratch[(int64_t)g * n + i] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_finish(T* w, const cd* __restrict__ scratch,
+                                                          int G, int64_t n, double alpha,
+                                                          double sgn, double* normp) {
+    __shared__ double sm[kWaves];
+    __shared__ double so[1];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    cd v = mk(0.0, 0.0);
+    if (i < n) {
+        cd acc = mk(0.0, 0.0);
+        for (int g = 0; g < G; ++g) acc = cadd(acc, scratch[(int64_t)g * n + i]);
+        cd base = (alpha != 0.0) ? cscale(tod(w[i]), alpha) : mk(0.0, 0.0);
+        v = mk(base.x + sgn * acc.x, base.y + sgn * acc.y);
+        w[i] = fromd<T>(v);
+    }
+    if (normp) {
+        cd vr = tod(fromd<T>(v));
+        double nv[1] = {(i < n) ? cabs2(vr) : 0.0};
+        block_sum<1>(nv, sm, so);
+        if (threadIdx.x == 0) normp[blockIdx.x] = so[0];
+    }
+}
+
+template <typename T>
+static void update_impl(T* w, const T* B, int64_t ldb, int ncols, const cd* coef, int64_t n,
+                        double alpha, double sgn, double* normp, cd* scratch,
+                        int64_t scratch_len, hipStream_t st) {
+    const int rb = (int)ceil_div(n, kBlock);
+    int G = 1;
+    if (ncols > 32 && rb < 1024 && scratch) {
+        G = (int)ceil_div(1024, rb);
+        int gmax = ncols / 16;
+        if (G > gmax) G = gmax;
+        while (G > 1 && (int64_t)G * n > scratch_len) --G;
+    }
+    if (G <= 1) {
+        hipLaunchKernelGGL((k_update_direct<T>), dim3(rb), dim3(kBlock), 0, st, w, B, ldb, ncols,
+                           coef, n, alpha, sgn, normp);
+    } else {
+        const int cpg = (int)ceil_div(ncols, G);
+        G = (int)ceil_div(ncols, cpg);
+        hipLaunchKernelGGL((k_update_split<T>), dim3(rb, G), dim3(kBlock), 0, st, B, ldb, ncols,
+                           coef, n, cpg, scratch);
+        hipLaunchKernelGGL((k_update_finish<T>), dim3(rb), dim3(kBlock), 0, st, w,
+                           (const cd*)scratch, G, n, alpha, sgn, normp);
+    }
+    OSA_LAUNCH_CHECK();
+}
+
+// Norm partials from the update kernels are per 256-row block; the plan passed
+// to launch_normalize must then have rows_per_chunk = 256.
+void launch_update(void* w, const void* B, int64_t ldb, int ncols, const cd* coef, bool fp32,
+                   const TsPlan& p, double* normp, cd* scratch, int64_t scratch_len,
+                   hipStream_t st) {
+    if (ncols <= 0 && !normp) return;
+    if (fp32)
+        update_impl<cf>((cf*)w, (const cf*)B, ldb, ncols, coef, p.n, 1.0, -1.0, normp, scratch,
+                        scratch_len, st);
+    else
+        update_impl<cd>((cd*)w, (const cd*)B, ldb, ncols, coef, p.n, 1.0, -1.0, normp, scratch,
+                        scratch_len, st);
+}
+
+void launch_combine(void* y, const void* B, int64_t ldb, int ncols, const cd* coef, bool fp32,
+                    bool add, int64_t n, hipStream_t st) {
+    if (fp32)
+        update_impl<cf>((cf*)y, (const cf*)B, ldb, ncols, coef, n, add ? 1.0 : 0.0, 1.0, nullptr,
+                        nullptr, 0, st);
+    else
+        update_impl<cd>((cd*)y, (const cd*)B, ldb, ncols, coef, n, add ? 1.0 : 0.0, 1.0, nullptr,
+                        nullptr, 0, st);
+}
+
+// ---------------------------------------------------------------- norms
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_norm_partial(const T* __restrict__ w, int64_t n,
+                                                         double* normp) {
+    __shared__ double sm[kWaves];
+    __shared__ double so[1];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double nv[1] = {(i < n) ? cabs2(tod(w[i])) : 0.0};
+    block_sum<1>(nv, sm, so);
+    if (threadIdx.x == 0) normp[blockIdx.x] = so[0];
+}
+
+void launch_norm_partial(const void* w, bool fp32, const TsPlan& p, double* normp,
+                         hipStream_t st) {
+    const int rb = (int)ceil_div(p.n, kBlock);
+    if (fp32)
+        hipLaunchKernelGGL((k_norm_partial<cf>), dim3(rb), dim3(kBlock), 0, st, (const cf*)w, p.n,
+                           normp);
+    else
+        hipLaunchKernelGGL((k_norm_partial<cd>), dim3(rb), dim3(kBlock), 0, st, (const cd*)w, p.n,
+                           normp);
+    OSA_LAUNCH_CHECK();
+}
+
+// single block: hsub = sqrt(sum normp) (+ breakdown test)
+__global__ __launch_bounds__(1024) void k_norm_finish(const double* __restrict__ normp, int nb,
+                                                      cd* hsub, const double* hfro2, double rel,
+                                                      int* flag, int step) {
+    __shared__ double sred[16];
+    double loc = 0;
+    // fixed order: contiguous slices per thread, then a fixed tree
+    const int per = (nb + blockDim.x - 1) / blockDim.x;
+    const int b0 = threadIdx.x * per;
+    for (int b = b0; b < b0 + per && b < nb; ++b) loc += normp[b];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double s = wave_sum(loc);
+    if (lane == 0) sred[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sred[w];
+        double h = sqrt(t);
+        double scale = hfro2 ? sqrt(*hfro2 + t) : 0.0;
+        int bd = (flag && h <= rel * scale) ? 1 : 0;
+        if (!(h == h) || h > 1e300) bd = 2;   // non-finite
+        if (flag && bd) {
+            if (flag[0] == 0) flag[1] = step;
+            if (bd > flag[0]) flag[0] = bd;
+        }
+        hsub->x = h;
+        hsub->y = 0.0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scale_by(const T* __restrict__ w, T* __restrict__ v,
+                                                     int64_t n, const cd* hsub, const int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const bool bd = flag && *flag;
+    const double inv = bd ? 0.0 : 1.0 / hsub->x;
+    v[i] = fromd<T>(cscale(tod(w[i]), inv));
+}
+
+void launch_normalize(const void* w, void* v, bool fp32, const TsPlan& p, const double* normp,
+                      cd* hsub, const double* hfro2, double rel, int* flag, int step,
+                      hipStream_t st) {
+    const int nb = (int)ceil_div(p.n, kBlock);
+    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(256), 0, st, normp, nb, hsub, hfro2, rel, flag,
+                       step);
+    if (!v) { OSA_LAUNCH_CHECK(); return; }
+    const int rb = (int)ceil_div(p.n, kBlock);
+    if (fp32)
+        hipLaunchKernelGGL((k_scale_by<cf>), dim3(rb), dim3(kBlock), 0, st, (const cf*)w, (cf*)v,
+                           p.n, (const cd*)hsub, (const int*)flag);
+    else
+        hipLaunchKernelGGL((k_scale_by<cd>), dim3(rb), dim3(kBlock), 0, st, (const cd*)w, (cd*)v,
+                           p.n, (const cd*)hsub, (const int*)flag);
+    OSA_LAUNCH_CHECK();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scale(const T* __restrict__ w, T* __restrict__ v,
+                                                  int64_t n, double a) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) v[i] = fromd<T>(cscale(tod(w[i]), a));
+}
+
+void launch_scale(const void* w, void* v, bool fp32, int64_t n, double alpha, hipStream_t st) {
+    const int rb = (int)ceil_div(n, kBlock);
+    if (fp32)
+        hipLaunchKernelGGL((k_scale<cf>), dim3(rb), dim3(kBlock), 0, st, (const cf*)w, (cf*)v, n,
+                           alpha);
+    else
+        hipLaunchKernelGGL((k_scale<cd>), dim3(rb), dim3(kBlock), 0, st, (const cd*)w, (cd*)v, n,
+                           alpha);
+    OSA_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- rotate
+// out[:, c] = sum_r B[:, r] Z[r, c]; each block: 256 rows x 8 output columns.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rotate(const T* __restrict__ B, int64_t ldb, int p,
+                                                   const cd* __restrict__ Z, int ldz, int q,
+                                                   T* __restrict__ out, int64_t ldo, int64_t n) {
+    constexpr int C = 8;
+    __shared__ cd sz[128 * C];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int c0 = blockIdx.y * C;
+    const int nc = (q - c0 < C) ? q - c0 : C;
+    for (int e = threadIdx.x; e < p * C; e += kBlock) {
+        const int r = e / C, cc = e % C;
+        sz[e] = (cc < nc) ? Z[r + (int64_t)(c0 + cc) * ldz] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (i >= n) return;
+    cd acc[C];
+#pragma unroll
+    for (int cc = 0; cc < C; ++cc) acc[cc] = mk(0.0, 0.0);
+    for (int r = 0; r < p; ++r) {
+        const cd b = tod(B[(int64_t)r * ldb + i]);
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) cfma(acc[cc], b, sz[r * C + cc]);
+    }
+#pragma unroll
+    for (int cc = 0; cc < C; ++cc)
+        if (cc < nc) out[(int64_t)(c0 + cc) * ldo + i] = fromd<T>(acc[cc]);
+}
+
+void launch_rotate(const void* B, int64_t ldb, int ncols_in, const cd* Z, int ldz, int ncols_out,
+                   void* out, int64_t ldo, bool fp32, int64_t n, hipStream_t st) {
+    if (ncols_in > 128) throw HipError{hipErrorInvalidValue, "launch_rotate: p > 128"};
+    dim3 grid((unsigned)ceil_div(n, kBlock), (unsigned)ceil_div(ncols_out, 8)), blk(kBlock);
+    if (fp32)
+        hipLaunchKernelGGL((k_rotate<cf>), grid, blk, 0, st, (const cf*)B, ldb, ncols_in, Z, ldz,
+                           ncols_out, (cf*)out, ldo, n);
+    else
+        hipLaunchKernelGGL((k_rotate<cd>), grid, blk, 0, st, (const cd*)B, ldb, ncols_in, Z, ldz,
+                           ncols_out, (cd*)out, ldo, n);
+    OSA_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- misc
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_convert(const TI* __restrict__ s, TO* __restrict__ d,
+                                                    int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) d[i] = fromd<TO>(tod(s[i]));
+}
+
+void launch_convert(const void* src, bool src_fp32, void* dst, bool dst_fp32, int64_t n,
+                    hipStream_t st) {
+    const int rb = (int)ceil_div(n, kBlock);
+    if (src_fp32 && !dst_fp32)
+        hipLaunchKernelGGL((k_convert<cf, cd>), dim3(rb), dim3(kBlock), 0, st, (const cf*)src,
+                           (cd*)dst, n);
+    else if (!src_fp32 && dst_fp32)
+        hipLaunchKernelGGL((k_convert<cd, cf>), dim3(rb), dim3(kBlock), 0, st, (const cd*)src,
+                           (cf*)dst, n);
+    else if (src_fp32)
+        hipLaunchKernelGGL((k_convert<cf, cf>), dim3(rb), dim3(kBlock), 0, st, (const cf*)src,
+                           (cf*)dst, n);
+    else
+        hipLaunchKernelGGL((k_convert<cd, cd>), dim3(rb), dim3(kBlock), 0, st, (const cd*)src,
+                           (cd*)dst, n);
+    OSA_LAUNCH_CHECK();
+}
+
+// splitmix64 finaliser as a counter-based generator
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_random(T* v, int V, int Vp, uint64_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= 12LL * Vp) return;
+    const int s = (int)(i % Vp);
+    cd z = mk(0.0, 0.0);
+    if (s < V) {
+        uint64_t a = mix64(seed * 0x2545F4914F6CDD1DULL + 2 * (uint64_t)i);
+        uint64_t b = mix64(seed * 0x2545F4914F6CDD1DULL + 2 * (uint64_t)i + 1);
+        double u1 = ((a >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        double u2 = ((b >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        double r = sqrt(-2.0 * log(u1));
+        z = mk(r * cos(6.283185307179586 * u2), r * sin(6.283185307179586 * u2));
+    }
+    v[i] = fromd<T>(z);
+}
+
+void launch_random_vector(void* v, bool fp32, const Geom& g, uint64_t seed, hipStream_t st) {
+    const int rb = (int)ceil_div(12LL * g.Vp, kBlock);
+    if (fp32)
+        hipLaunchKernelGGL((k_random<cf>), dim3(rb), dim3(kBlock), 0, st, (cf*)v, g.V, g.Vp, seed);
+    else
+        hipLaunchKernelGGL((k_random<cd>), dim3(rb), dim3(kBlock), 0, st, (cd*)v, g.V, g.Vp, seed);
+    OSA_LAUNCH_CHECK();
+}
+
+}  // namespace osa

@@ -1,0 +1,576 @@
+// Small dense kernels: the sign of the Hessenberg matrix f(H_k) e_1 (Eq. 11,
+// Eq. 22) by the scaled Newton iteration, and the small Schur decomposition
+// used by the eigensolver restarts.
+#include "kernels.hpp"
+
+namespace osa {
+
+// ====================================================================== GJ
+// In-place Gauss-Jordan inversion with implicit partial row pivoting.
+// Step t picks the unused row p with the largest |M[p,t]|, scales it by
+// 1/M[p,t] and eliminates column t from every other row; column t then stores
+// the new column of the accumulated row operations.  At the end
+//   A^{-1}[t, c] = M[perm[t], pinv[c]],   pinv[perm[s]] = s.
+// Each block owns CB whole columns, so reading and writing the pivot row of a
+// column happen inside one block; the pivot column itself is handed from step
+// to step through a double-buffered copy (colbuf) written by its owner.
+struct GjWs {
+    cd* col;        // 2 x k
+    double2* piv;   // k: (|value|, index) of the pivot chosen for step t
+    int* perm;      // k
+    int* pinv;      // k
+    int* used;      // k
+};
+
+size_t gj_ws_bytes(int k) {
+    return (size_t)k * (2 * sizeof(cd) + sizeof(double2) + 3 * sizeof(int)) + 256;
+}
+
+static GjWs gj_ws(void* ws, int k) {
+    char* p = (char*)ws;
+    GjWs w;
+    w.col = (cd*)p;            p += (size_t)2 * k * sizeof(cd);
+    w.piv = (double2*)p;       p += (size_t)k * sizeof(double2);
+    w.perm = (int*)p;          p += (size_t)k * sizeof(int);
+    w.pinv = (int*)p;          p += (size_t)k * sizeof(int);
+    w.used = (int*)p;
+    return w;
+}
+
+static constexpr int kGjThreads = 256;
+static constexpr int kGjCols = 4;
+
+__device__ __forceinline__ void argmax_pair(double& v, int& idx, double ov, int oi) {
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+}
+
+// block-wide argmax (ties -> smaller index), result valid in thread 0
+__device__ void block_argmax(double v, int idx, double* sv, int* si, double& ov, int& oi) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double v2 = __shfl_xor(v, off, 64);
+        int i2 = __shfl_xor(idx, off, 64);
+        argmax_pair(v, idx, v2, i2);
+    }
+    if (lane == 0) { sv[wave] = v; si[wave] = idx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bv = sv[0];
+        int bi = si[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) argmax_pair(bv, bi, sv[w], si[w]);
+        ov = bv;
+        oi = bi;
+    }
+}
+
+__global__ __launch_bounds__(kGjThreads) void k_gj_init(const cd* __restrict__ M, int k, GjWs w) {
+    __shared__ double sv[kGjThreads / 64];
+    __shared__ int si[kGjThreads / 64];
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int i = threadIdx.x; i < k; i += kGjThreads) {
+        cd v = M[i];
+        w.col[i] = v;
+        w.used[i] = 0;
+        w.perm[i] = i;
+        w.pinv[i] = i;
+        argmax_pair(bv, bi, cabsd(v), i);
+    }
+    double ov;
+    int oi;
+    block_argmax(bv, bi, sv, si, ov, oi);
+    if (threadIdx.x == 0) w.piv[0] = make_double2(ov, (double)oi);
+}
+
+__global__ __launch_bounds__(kGjThreads) void k_gj_step(cd* __restrict__ M, int k, int t, GjWs w,
+                                                       double* logpiv, int* flag) {
+    __shared__ double sv[kGjThreads / 64];
+    __shared__ int si[kGjThreads / 64];
+    const cd* colc = w.col + (size_t)(t & 1) * k;
+    cd* coln = w.col + (size_t)((t + 1) & 1) * k;
+    // A column of NaNs selects no pivot; keep every index in range and flag it.
+    const double pf = w.piv[t].y;
+    const bool badp = !(pf >= 0.0 && pf < (double)k);
+    const int p = badp ? t : (int)pf;
+    const cd piv = colc[p];
+    const bool zero = badp || (piv.x == 0.0 && piv.y == 0.0);
+    const cd ipiv = zero ? mk(0.0, 0.0) : cinv(piv);
+    const int j0 = blockIdx.x * kGjCols;
+    for (int j = j0; j < j0 + kGjCols && j < k; ++j) {
+        const cd r = (j == t) ? mk(1.0, 0.0) : M[p + (size_t)j * k];
+        __syncthreads();   // everyone has read M[p,j] before row p is rewritten
+        const cd rp = cmul(r, ipiv);
+        const bool nextcol = (j == t + 1);
+        double bv = -1.0;
+        int bi = 0x7fffffff;
+        for (int i = threadIdx.x; i < k; i += kGjThreads) {
+            const cd f = colc[i];
+            cd nv;
+            if (j == t) {
+                nv = (i == p) ? ipiv : mk(-(f.x * ipiv.x - f.y * ipiv.y), -(f.x * ipiv.y + f.y * ipiv.x));
+            } else {
+                if (i == p) nv = rp;
+                else {
+                    nv = M[i + (size_t)j * k];
+                    nv.x -= f.x * rp.x - f.y * rp.y;
+                    nv.y -= f.x * rp.y + f.y * rp.x;
+                }
+            }
+            M[i + (size_t)j * k] = nv;
+            if (nextcol) {
+                coln[i] = nv;
+                if (i != p && !w.used[i]) argmax_pair(bv, bi, cabsd(nv), i);
+            }
+        }
+        if (nextcol) {
+            double ov;
+            int oi;
+            block_argmax(bv, bi, sv, si, ov, oi);
+            if (threadIdx.x == 0) w.piv[t + 1] = make_double2(ov, (double)oi);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        w.perm[t] = p;
+        w.used[p] = 1;
+        logpiv[t] = zero ? -1e300 : log(cabsd(piv));
+        if (zero || !(piv.x == piv.x) || !(piv.y == piv.y)) *flag = 1;
+    }
+}
+
+__global__ void k_gj_pinv(int k, GjWs w) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < k; s += gridDim.x * blockDim.x) {
+        const int q = w.perm[s];
+        if (q >= 0 && q < k) w.pinv[q] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gj_gather(const cd* __restrict__ M, cd* __restrict__ Y,
+                                                  int k, GjWs w) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)k * k) return;
+    const int t = (int)(e % k), c = (int)(e / k);
+    int r = w.perm[t], q = w.pinv[c];
+    r = (r >= 0 && r < k) ? r : 0;   // only reachable after a flagged breakdown
+    q = (q >= 0 && q < k) ? q : 0;
+    Y[e] = M[r + (size_t)q * k];
+}
+
+void gj_invert(cd* M, cd* Y, int k, double* logpiv, int* flag, void* ws, hipStream_t st) {
+    GjWs w = gj_ws(ws, k);
+    hipLaunchKernelGGL(k_gj_init, dim3(1), dim3(kGjThreads), 0, st, (const cd*)M, k, w);
+    const int nb = (int)ceil_div(k, kGjCols);
+    for (int t = 0; t < k; ++t)
+        hipLaunchKernelGGL(k_gj_step, dim3(nb), dim3(kGjThreads), 0, st, M, k, t, w, logpiv, flag);
+    hipLaunchKernelGGL(k_gj_pinv, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, st, k, w);
+    if (Y) {
+        hipLaunchKernelGGL(k_gj_gather, dim3((unsigned)ceil_div((int64_t)k * k, 256)), dim3(256), 0,
+                           st, (const cd*)M, Y, k, w);
+    }
+    OSA_LAUNCH_CHECK();
+}
+
+// ================================================================ Newton
+// Scaled Newton step for sign(X) (Roberts; determinantal scaling of Byers):
+//   X <- (mu X + (mu X)^{-1}) / 2,  mu = |det X|^{-1/k} = exp(-sum log|piv| / k)
+// Y holds X^{-1}.  Per-block partial sums of |Xnew - X|^2 and |Xnew|^2.
+__global__ __launch_bounds__(256) void k_newton_combine(cd* __restrict__ X, const cd* __restrict__ Y,
+                                                       int k, const double* __restrict__ logpiv,
+                                                       int scale, double* part) {
+    __shared__ double sm[8];
+    __shared__ double smu;
+    if (threadIdx.x == 0) {
+        double mu = 1.0;
+        if (scale) {
+            double s = 0;
+            for (int t = 0; t < k; ++t) s += logpiv[t];
+            mu = exp(-s / k);
+        }
+        smu = mu;
+    }
+    __syncthreads();
+    const double mu = smu, imu = 1.0 / mu;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double d2 = 0, n2 = 0;
+    if (e < (int64_t)k * k) {
+        cd x = X[e], y = Y[e];
+        cd xn = mk(0.5 * (mu * x.x + imu * y.x), 0.5 * (mu * x.y + imu * y.y));
+        d2 = cabs2(csub(xn, x));
+        n2 = cabs2(xn);
+        X[e] = xn;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        d2 += __shfl_xor(d2, off, 64);
+        n2 += __shfl_xor(n2, off, 64);
+    }
+    if (lane == 0) { sm[2 * wave] = d2; sm[2 * wave + 1] = n2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0;
+        for (int w = 0; w < 4; ++w) { a += sm[2 * w]; b += sm[2 * w + 1]; }
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ void k_sum_pairs(const double* __restrict__ part, int nb, double* red) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double a = 0, b = 0;
+        for (int i = 0; i < nb; ++i) { a += part[2 * i]; b += part[2 * i + 1]; }
+        red[0] = a;
+        red[1] = b;
+    }
+}
+
+void launch_newton_combine(cd* X, const cd* Y, int k, const double* logpiv, bool scale,
+                           double* red, hipStream_t st) {
+    const int nb = (int)ceil_div((int64_t)k * k, 256);
+    double* part = red + 2;   // caller provides 2 + 2*nb doubles
+    hipLaunchKernelGGL(k_newton_combine, dim3(nb), dim3(256), 0, st, X, Y, k, logpiv, scale ? 1 : 0,
+                       part);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(64), 0, st, (const double*)part, nb, red);
+    OSA_LAUNCH_CHECK();
+}
+
+// ================================================================= zgemm
+// C = alpha op(A) op(B) + beta C, 16x16 tiles, column-major.
+__global__ __launch_bounds__(256) void k_zgemm(int opA, int opB, int m, int n, int kk, cd alpha,
+                                              const cd* __restrict__ A, int lda,
+                                              const cd* __restrict__ B, int ldb, cd beta, cd* C,
+                                              int ldc) {
+    __shared__ cd sa[16][17];
+    __shared__ cd sb[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int row = blockIdx.x * 16 + tx, col = blockIdx.y * 16 + ty;
+    cd acc = mk(0.0, 0.0);
+    for (int k0 = 0; k0 < kk; k0 += 16) {
+        // op(A)[row, k0+ty]
+        {
+            const int r = blockIdx.x * 16 + tx, kq = k0 + ty;
+            cd v = mk(0.0, 0.0);
+            if (r < m && kq < kk) v = opA ? cconj(A[kq + (size_t)r * lda]) : A[r + (size_t)kq * lda];
+            sa[tx][ty] = v;
+        }
+        // op(B)[k0+tx, col]
+        {
+            const int kq = k0 + tx, c = blockIdx.y * 16 + ty;
+            cd v = mk(0.0, 0.0);
+            if (c < n && kq < kk) v = opB ? cconj(B[c + (size_t)kq * ldb]) : B[kq + (size_t)c * ldb];
+            sb[tx][ty] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) cfma(acc, sa[tx][q], sb[q][ty]);
+        __syncthreads();
+    }
+    if (row < m && col < n) {
+        cd r = cmul(alpha, acc);
+        if (beta.x != 0.0 || beta.y != 0.0) r = cadd(r, cmul(beta, C[row + (size_t)col * ldc]));
+        C[row + (size_t)col * ldc] = r;
+    }
+}
+
+void launch_zgemm(int opA, int opB, int m, int n, int kk, cd alpha, const cd* A, int lda,
+                  const cd* B, int ldb, cd beta, cd* C, int ldc, hipStream_t st) {
+    if (m <= 0 || n <= 0) return;
+    dim3 grid((unsigned)ceil_div(m, 16), (unsigned)ceil_div(n, 16));
+    hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, st, opA, opB, m, n, kk, alpha, A, lda, B, ldb,
+                       beta, C, ldc);
+    OSA_LAUNCH_CHECK();
+}
+
+// |s - [sprev; 0]|  (one block)
+__global__ void k_diff_norm(const cd* __restrict__ s, int k, const cd* __restrict__ sp, int kp,
+                            double* out) {
+    __shared__ double sm[4];
+    double a = 0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        cd d = s[i];
+        if (i < kp) d = csub(d, sp[i]);
+        a += cabs2(d);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = sqrt(sm[0] + sm[1] + sm[2] + sm[3]);
+}
+
+void launch_diff_norm(const cd* s, int k, const cd* sprev, int kprev, double* out,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_diff_norm, dim3(1), dim3(256), 0, st, s, k, sprev, kprev, out);
+    OSA_LAUNCH_CHECK();
+}
+
+// ================================================================= Schur
+// A = Z T Z^H for p <= 64: Householder reduction to Hessenberg form, complex
+// single-shift QR with Wilkinson shifts (exceptional shifts every 10
+// iterations without deflation), then reordering of the diagonal by adjacent
+// swaps.  One wavefront; T and Z live in LDS.
+static constexpr int kSchurMax = 64;
+
+__device__ __forceinline__ double sort_key(cd v, int mode) {
+    return mode == 0 ? cabsd(v) : fabs(v.x);
+}
+
+// Apply the 2x2 unitary Q (columns q0 = (a, b), q1 = (-conj b, conj a)) as a
+// similarity on rows/cols (k, k+1): T <- Q^H T Q, Z <- Z Q.
+__device__ void apply_pair(cd* T, cd* Z, int p, int k, cd a, cd b, int col0, int row1) {
+    const int l = threadIdx.x;
+    // left: rows k, k+1 over columns >= col0
+    for (int c = col0 + l; c < p; c += 64) {
+        cd x = T[k + c * p], y = T[k + 1 + c * p];
+        // Q^H [x; y] = [conj(a) x + conj(b) y ; -b x + a y]
+        cd nx = cadd(cmulc(a, x), cmulc(b, y));
+        cd ny = csub(cmul(a, y), cmul(b, x));
+        T[k + c * p] = nx;
+        T[k + 1 + c * p] = ny;
+    }
+    __syncthreads();
+    // right: columns k, k+1 over rows <= row1;  [x, y] Q = [a x + b y, -conj(b) x + conj(a) y]
+    for (int r = l; r <= row1 && r < p; r += 64) {
+        cd x = T[r + k * p], y = T[r + (k + 1) * p];
+        T[r + k * p] = cadd(cmul(a, x), cmul(b, y));
+        T[r + (k + 1) * p] = csub(cmulc(a, y), cmulc(b, x));
+    }
+    for (int r = l; r < p; r += 64) {
+        cd x = Z[r + k * p], y = Z[r + (k + 1) * p];
+        Z[r + k * p] = cadd(cmul(a, x), cmul(b, y));
+        Z[r + (k + 1) * p] = csub(cmulc(a, y), cmulc(b, x));
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, int p, cd* Tout,
+                                                   cd* Zout, cd* wout, int mode, int* info) {
+    extern __shared__ cd lds[];
+    cd* T = lds;
+    cd* Z = lds + p * p;
+    __shared__ cd hv[kSchurMax];
+    const int l = threadIdx.x;
+    for (int e = l; e < p * p; e += 64) {
+        T[e] = A[e];
+        Z[e] = mk((e % p) == (e / p) ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    double anorm = 0;
+    for (int e = 0; e < p * p; ++e) anorm = fmax(anorm, cabsd(T[e]));
+    // ---- Hessenberg reduction
+    for (int j = 0; j + 2 < p; ++j) {
+        const int L = p - j - 1;
+        double xn2 = 0;
+        for (int i = 0; i < L; ++i) xn2 += cabs2(T[j + 1 + i + j * p]);
+        const double xn = sqrt(xn2);
+        const cd x0 = T[j + 1 + j * p];
+        double tail = xn2 - cabs2(x0);
+        if (xn == 0.0 || tail <= 1e-300) { __syncthreads(); continue; }
+        const double ax0 = cabsd(x0);
+        const cd ph = ax0 > 0 ? cscale(x0, 1.0 / ax0) : mk(1.0, 0.0);
+        const cd alpha = cscale(ph, -xn);           // -e^{i arg x0} |x|
+        // v = x - alpha e1, tau = 2 / |v|^2
+        for (int i = l; i < L; i += 64) hv[i] = (i == 0) ? csub(x0, alpha) : T[j + 1 + i + j * p];
+        __syncthreads();
+        double vn2 = 0;
+        for (int i = 0; i < L; ++i) vn2 += cabs2(hv[i]);
+        const double tau = 2.0 / vn2;
+        // left: T[j+1:, c] -= tau v (v^H T[j+1:, c]),  c >= j
+        for (int c = j + l; c < p; c += 64) {
+            cd s = mk(0.0, 0.0);
+            for (int i = 0; i < L; ++i) cfmac(s, hv[i], T[j + 1 + i + c * p]);
+            s = cscale(s, tau);
+            for (int i = 0; i < L; ++i) {
+                cd& tv = T[j + 1 + i + c * p];
+                tv = csub(tv, cmul(hv[i], s));
+            }
+        }
+        __syncthreads();
+        // right: T[r, j+1:] -= tau (T[r, j+1:] v) v^H, all rows; same for Z
+        for (int r = l; r < p; r += 64) {
+            cd s = mk(0.0, 0.0), sz = mk(0.0, 0.0);
+            for (int i = 0; i < L; ++i) {
+                cfma(s, T[r + (j + 1 + i) * p], hv[i]);
+                cfma(sz, Z[r + (j + 1 + i) * p], hv[i]);
+            }
+            s = cscale(s, tau);
+            sz = cscale(sz, tau);
+            for (int i = 0; i < L; ++i) {
+                cd& tv = T[r + (j + 1 + i) * p];
+                tv = csub(tv, cmul(s, cconj(hv[i])));
+                cd& zv = Z[r + (j + 1 + i) * p];
+                zv = csub(zv, cmul(sz, cconj(hv[i])));
+            }
+        }
+        __syncthreads();
+        if (l == 0) {
+            T[j + 1 + j * p] = alpha;
+            for (int i = 2; i <= L; ++i) T[j + i + j * p] = mk(0.0, 0.0);
+        }
+        __syncthreads();
+    }
+    // ---- shifted QR
+    const double ulp = 2.220446049250313e-16;
+    const double smlnum = 1e-300;
+    int hi = p - 1;
+    int its = 0, total = 0;
+    const int maxtotal = 60 * p;
+    bool fail = false;
+    while (hi > 0) {
+        int lo = hi;
+        while (lo > 0) {
+            const double sub = cabsd(T[lo + (lo - 1) * p]);
+            double tst = cabsd(T[lo - 1 + (lo - 1) * p]) + cabsd(T[lo + lo * p]);
+            if (tst == 0.0) tst = anorm;
+            if (sub <= fmax(ulp * tst, smlnum)) break;
+            --lo;
+        }
+        if (lo > 0) {
+            __syncthreads();
+            if (l == 0) T[lo + (lo - 1) * p] = mk(0.0, 0.0);
+            __syncthreads();
+        }
+        if (lo == hi) { --hi; its = 0; continue; }
+        if (total++ > maxtotal) { fail = true; break; }
+        ++its;
+        // Wilkinson shift from the trailing 2x2 of the active block
+        cd sigma;
+        {
+            const cd a = T[hi - 1 + (hi - 1) * p], b = T[hi - 1 + hi * p];
+            const cd c = T[hi + (hi - 1) * p], d = T[hi + hi * p];
+            if (its % 10 == 0) {
+                // exceptional shift
+                sigma = cadd(d, mk(0.75 * cabsd(c), 0.0));
+            } else {
+                const cd tr2 = cscale(cadd(a, d), 0.5);
+                const cd det = csub(cmul(a, d), cmul(b, c));
+                const cd disc = csub(cmul(tr2, tr2), det);
+                // principal sqrt
+                const double r = cabsd(disc);
+                double sr = sqrt(0.5 * (r + disc.x));
+                double si = sqrt(fmax(0.0, 0.5 * (r - disc.x)));
+                if (disc.y < 0) si = -si;
+                const cd sq = mk(sr, si);
+                const cd e1 = cadd(tr2, sq), e2 = csub(tr2, sq);
+                sigma = (cabsd(csub(e1, d)) <= cabsd(csub(e2, d))) ? e1 : e2;
+            }
+        }
+        // bulge chase on the active block [lo, hi]
+        for (int k = lo; k < hi; ++k) {
+            cd f, g;
+            if (k == lo) {
+                f = csub(T[lo + lo * p], sigma);
+                g = T[lo + 1 + lo * p];
+            } else {
+                f = T[k + (k - 1) * p];
+                g = T[k + 1 + (k - 1) * p];
+            }
+            // unitary with first column (f, g)/|(f, g)|: Q^H [f; g] = [|.|; 0]
+            const double nf = sqrt(cabs2(f) + cabs2(g));
+            cd a, b;
+            if (nf == 0.0) { a = mk(1.0, 0.0); b = mk(0.0, 0.0); }
+            else { a = cscale(f, 1.0 / nf); b = cscale(g, 1.0 / nf); }
+            const int col0 = (k == lo) ? lo : k - 1;
+            const int row1 = (k + 2 < hi) ? k + 2 : hi;
+            // rows/cols above lo are part of the full Schur form as well
+            apply_pair(T, Z, p, k, a, b, col0, row1);
+            if (k > lo) {
+                if (l == 0) T[k + 1 + (k - 1) * p] = mk(0.0, 0.0);
+                __syncthreads();
+            }
+        }
+    }
+    // the right updates above touched rows <= row1 only; rows < lo belong to
+    // the columns of already-converged blocks and were included since row1
+    // counts from row 0.
+    // ---- reorder the diagonal (insertion sort by adjacent swaps)
+    for (int i = 1; i < p && !fail; ++i) {
+        for (int j = i; j > 0; --j) {
+            const cd t11 = T[j - 1 + (j - 1) * p], t22 = T[j + j * p];
+            if (!(sort_key(t22, mode) < sort_key(t11, mode))) break;
+            const cd t12 = T[j - 1 + j * p];
+            const cd x1 = t12, x2 = csub(t22, t11);
+            const double nx = sqrt(cabs2(x1) + cabs2(x2));
+            if (nx == 0.0) break;
+            const cd a = cscale(x1, 1.0 / nx), b = cscale(x2, 1.0 / nx);
+            apply_pair(T, Z, p, j - 1, a, b, j - 1, j);
+            if (l == 0) {
+                T[j + (j - 1) * p] = mk(0.0, 0.0);
+                T[j - 1 + (j - 1) * p] = t22;
+                T[j + j * p] = t11;
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = l; e < p * p; e += 64) {
+        Tout[e] = T[e];
+        Zout[e] = Z[e];
+    }
+    for (int i = l; i < p; i += 64) wout[i] = T[i + i * p];
+    if (l == 0) *info = fail ? -1 : total;
+}
+
+size_t schur_ws_bytes(int p) { return 0; }
+
+void small_schur(const cd* A, int p, cd* T, cd* Z, cd* w, int mode, int* info, void*,
+                 hipStream_t st) {
+    if (p > kSchurMax || p < 1) throw HipError{hipErrorInvalidValue, "small_schur: p out of range"};
+    const size_t lds = (size_t)2 * p * p * sizeof(cd);
+    static bool attr_set = false;
+    if (!attr_set) {
+        OSA_HIP(hipFuncSetAttribute((const void*)k_small_schur,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(2 * kSchurMax * kSchurMax * sizeof(cd))));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_small_schur, dim3(1), dim3(64), lds, st, A, p, T, Z, w, mode, info);
+    OSA_LAUNCH_CHECK();
+}
+
+// Eigenvectors from the Schur form: back substitution on T for each diagonal
+// entry, then multiplication by Z; columns normalised to unit length.
+__global__ __launch_bounds__(64) void k_small_eigvecs(const cd* __restrict__ T,
+                                                     const cd* __restrict__ Z, int p, cd* Y) {
+    extern __shared__ cd y[];   // p x p, column i = eigenvector of T for t_ii
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= p) return;
+    cd* yi = y + (size_t)threadIdx.x * p;
+    const cd lam = T[i + (size_t)i * p];
+    double tnorm = 0;
+    for (int e = 0; e < p * p; ++e) tnorm = fmax(tnorm, cabsd(T[e]));
+    const double small = fmax(tnorm * 2.220446049250313e-16, 1e-300);
+    for (int r = 0; r < p; ++r) yi[r] = mk(0.0, 0.0);
+    yi[i] = mk(1.0, 0.0);
+    for (int r = i - 1; r >= 0; --r) {
+        cd s = mk(0.0, 0.0);
+        for (int q = r + 1; q <= i; ++q) cfma(s, T[r + (size_t)q * p], yi[q]);
+        cd d = csub(T[r + (size_t)r * p], lam);
+        if (cabsd(d) < small) d = mk(small, 0.0);
+        yi[r] = cscale(cdiv(s, d), -1.0);
+    }
+    double n2 = 0;
+    for (int r = 0; r < p; ++r) {
+        cd s = mk(0.0, 0.0);
+        for (int q = 0; q <= i; ++q) cfma(s, Z[r + (size_t)q * p], yi[q]);
+        Y[r + (size_t)i * p] = s;
+        n2 += cabs2(s);
+    }
+    const double inv = 1.0 / sqrt(n2);
+    for (int r = 0; r < p; ++r) Y[r + (size_t)i * p] = cscale(Y[r + (size_t)i * p], inv);
+}
+
+void small_eigvecs(const cd* T, const cd* Z, int p, cd* Y, hipStream_t st) {
+    const size_t lds = (size_t)64 * p * sizeof(cd);
+    static bool attr_set = false;
+    if (!attr_set) {
+        OSA_HIP(hipFuncSetAttribute((const void*)k_small_eigvecs,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(64 * kSchurMax * sizeof(cd))));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_small_eigvecs, dim3((unsigned)ceil_div(p, 64)), dim3(64), lds, st, T, Z, p,
+                       Y);
+    OSA_LAUNCH_CHECK();
+}
+
+}  // namespace osa

@@ -1,0 +1,957 @@
+// Host driver and C ABI of the osa library.
+//
+// Hot path (Eq. 22 of the LR-deflation section):
+//   c       = (L^dag R)^{-1} L^dag b                       (Eq. 21, oblique projector)
+//   x_ominus = b - R c ,  beta = |x_ominus|,  v_1 = x_ominus / beta
+//   Arnoldi with classical Gram-Schmidt applied twice   (Eq. 7)
+//   s       = sign(H_k) e_1 by the scaled Newton iteration
+//   y       = R sgn(Re Lambda) c + beta V_k s           (Eq. 22)
+// Critical eigenpairs (Eq. 20): Krylov-Schur on H^2 (smallest |lambda|^2),
+// then a Rayleigh-Ritz step with H; left vectors from H(-mu) = H(mu)^dag.
+//
+// The host only sequences kernels and reads back a few scalars at
+// checkpoints; every vector and matrix operation runs on the GPU.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace osa;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void ensure(size_t b) {
+        if (b <= bytes && p) return;
+        release();
+        if (b == 0) b = 16;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            throw std::bad_alloc();
+        }
+        bytes = b;
+    }
+    template <typename T> T* as() const { return (T*)p; }
+};
+
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~PinnedBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    void ensure(size_t b) {
+        if (b <= bytes && p) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            throw std::bad_alloc();
+        }
+        bytes = b;
+    }
+    template <typename T> T* as() const { return (T*)p; }
+};
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct OsaError {
+    osa_status s;
+};
+
+}  // namespace
+
+// ============================================================== context
+struct osa_ctx {
+    Geom g{};
+    hipStream_t st = nullptr;
+    bool links_fp32 = false;
+    double mu = 0, m_w = 0, kappa = 0, hnorm_bound = 0;
+    HopCoef hc{}, hc_adj{};   // H(mu) and H(-mu)
+    osa_opts opts{};
+
+    DevBuf U;        // internal links
+    DevBuf U32;      // fp32 copy for an fp32 eigen-search on fp64 links
+
+    // deflation data (internal layout, m_alloc vectors each)
+    int m_alloc = 0, m_active = 0;
+    DevBuf R, L, Ginv, lam_dev, sgnc;
+    std::vector<cd> lambda;
+    double max_eig_resid = 0, min_abs_re = 0;
+    int64_t eig_matvecs = 0;
+    int eig_restarts = 0;
+    double t_init_ms = 0;
+
+    // Krylov workspace
+    int kcap = 0;
+    DevBuf V, Hm, w, x, y, coef, coef2, partial, normp, upd_scratch, dscal, flag, red;
+    DevBuf sX, sM, sY, logpiv, gjws, s_cur, s_prev, cdef;
+    PinnedBuf host;
+
+    int64_t N() const { return g.N(); }
+};
+
+namespace {
+
+// ------------------------------------------------------------- utilities
+void sync(osa_ctx* c) { OSA_HIP(hipStreamSynchronize(c->st)); }
+
+template <typename T>
+void d2h(osa_ctx* c, const void* dsrc, size_t n, T* out) {
+    c->host.ensure(n * sizeof(T));
+    OSA_HIP(hipMemcpyAsync(c->host.p, dsrc, n * sizeof(T), hipMemcpyDeviceToHost, c->st));
+    sync(c);
+    std::memcpy(out, c->host.p, n * sizeof(T));
+}
+
+template <typename T>
+void h2d(osa_ctx* c, void* ddst, const T* src, size_t n) {
+    c->host.ensure(n * sizeof(T));
+    std::memcpy(c->host.p, src, n * sizeof(T));
+    OSA_HIP(hipMemcpyAsync(ddst, c->host.p, n * sizeof(T), hipMemcpyHostToDevice, c->st));
+    sync(c);
+}
+
+void apply_h(osa_ctx* c, const void* in, void* out, bool fp32, bool adjoint, int nrhs = 1) {
+    const void* U = c->U.p;
+    bool ufp32 = c->links_fp32;
+    if (fp32 && !c->links_fp32 && c->U32.p) { U = c->U32.p; ufp32 = true; }
+    launch_wilson_h(in, out, U, ufp32, fp32, c->g, adjoint ? c->hc_adj : c->hc, nrhs, c->st);
+}
+
+// Norm of an internal vector, to the device scalar hsub (cd, real part).
+void vec_norm(osa_ctx* c, const void* v, bool fp32, cd* out) {
+    TsPlan p = ts_plan(c->N());
+    launch_norm_partial(v, fp32, p, c->normp.as<double>(), c->st);
+    launch_normalize(v, nullptr, fp32, p, c->normp.as<double>(), out, nullptr, 0.0, nullptr, 0,
+                     c->st);
+}
+
+void ensure_krylov(osa_ctx* c, int kcap) {
+    if (kcap <= c->kcap && c->V.p) return;
+    const int64_t N = c->N();
+    const size_t vb = (size_t)N * sizeof(cd);
+    c->V.ensure(vb * (size_t)(kcap + 1));
+    c->Hm.ensure(sizeof(cd) * (size_t)(kcap + 1) * kcap);
+    c->w.ensure(vb);
+    c->x.ensure(vb);
+    c->y.ensure(vb);
+    const int maxcols = std::max(kcap + 1, 128);
+    c->coef.ensure(sizeof(cd) * maxcols);
+    c->coef2.ensure(sizeof(cd) * maxcols);
+    c->partial.ensure(sizeof(cd) * (size_t)maxcols * 128);
+    c->normp.ensure(sizeof(double) * (size_t)(ceil_div(N, 256) + 16));
+    c->upd_scratch.ensure(vb * 8);
+    c->dscal.ensure(sizeof(cd) * 16);
+    c->flag.ensure(sizeof(int) * 4);
+    const int nbk = (int)ceil_div((int64_t)kcap * kcap, 256);
+    c->red.ensure(sizeof(double) * (size_t)(2 + 2 * nbk + 16));
+    c->sX.ensure(sizeof(cd) * (size_t)kcap * kcap);
+    c->sM.ensure(sizeof(cd) * (size_t)kcap * kcap);
+    c->sY.ensure(sizeof(cd) * (size_t)kcap * kcap);
+    c->logpiv.ensure(sizeof(double) * kcap);
+    c->gjws.ensure(gj_ws_bytes(kcap));
+    c->s_cur.ensure(sizeof(cd) * kcap);
+    c->s_prev.ensure(sizeof(cd) * kcap);
+    c->cdef.ensure(sizeof(cd) * 128);
+    c->kcap = kcap;
+}
+
+__global__ void k_axpy_c(int n, cd alpha, const cd* __restrict__ a, cd* __restrict__ cvec) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) cvec[i] = cadd(cvec[i], cmul(alpha, a[i]));
+}
+
+void axpy_c(osa_ctx* c, int n, cd alpha, const cd* a, cd* cvec) {
+    hipLaunchKernelGGL(k_axpy_c, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->st, n, alpha,
+                       a, cvec);
+    OSA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------- Gram-Schmidt
+// w <- w - B (B^H w) twice (CGS2); coefficients h = h1 + h2 written to hcol
+// (device, ncols entries).  Leaves per-block norm partials of the result in
+// normp.  B has ncols vectors of length n, spaced by ld.
+void cgs2(osa_ctx* c, void* wv, const void* B, int64_t ld, int ncols, bool fp32, cd* hcol,
+          double* hfro2) {
+    const TsPlan p = ts_plan(c->N());
+    const int64_t scratch_len = (int64_t)(c->upd_scratch.bytes / sizeof(cd));
+    cd* part = c->partial.as<cd>();
+    cd* co = c->coef.as<cd>();
+    // pass 1
+    launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st);
+    launch_reduce_partial(part, p.nchunks, ncols, hcol, 0, nullptr, nullptr, hfro2, c->st);
+    launch_update(wv, B, ld, ncols, hcol, fp32, p, nullptr, c->upd_scratch.as<cd>(), scratch_len,
+                  c->st);
+    // pass 2
+    launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st);
+    launch_reduce_partial(part, p.nchunks, ncols, co, 0, nullptr, nullptr, nullptr, c->st);
+    launch_update(wv, B, ld, ncols, co, fp32, p, c->normp.as<double>(), c->upd_scratch.as<cd>(),
+                  scratch_len, c->st);
+    // h += h2
+    axpy_c(c, ncols, mk(1.0, 0.0), co, hcol);
+}
+
+// Oblique projection w <- w - R G^{-1} L^dag w (Eq. 21) with the active pairs.
+// If cout != nullptr the coefficients G^{-1} L^dag w are kept there.
+void project_out(osa_ctx* c, void* wv, cd* cout) {
+    const int m = c->m_active;
+    if (m == 0) return;
+    const TsPlan p = ts_plan(c->N());
+    cd* part = c->partial.as<cd>();
+    cd* co = cout ? cout : c->coef2.as<cd>();
+    launch_dot_partial(c->L.p, c->N(), m, wv, false, p, part, c->st);
+    launch_reduce_partial(part, p.nchunks, m, co, 0, c->Ginv.as<cd>(), c->coef.as<cd>() + 0,
+                          nullptr, c->st);
+    launch_update(wv, c->R.p, c->N(), m, co, false, p, nullptr, c->upd_scratch.as<cd>(),
+                  (int64_t)(c->upd_scratch.bytes / sizeof(cd)), c->st);
+}
+
+}  // namespace
+
+namespace {
+
+// ------------------------------------------------------------- small sign
+// sign(X) by the scaled Newton iteration; stopping rule: stop once the
+// relative change is below 1e-14, or below 1e-8 and no longer halving.
+int small_sign_run(osa_ctx* c, int k, const cd* A, int lda, cd* s_out, bool* ok) {
+    cd* X = c->sX.as<cd>();
+    cd* M = c->sM.as<cd>();
+    cd* Y = c->sY.as<cd>();
+    OSA_HIP(hipMemcpy2DAsync(X, sizeof(cd) * k, A, sizeof(cd) * lda, sizeof(cd) * k, k,
+                             hipMemcpyDeviceToDevice, c->st));
+    OSA_HIP(hipMemsetAsync(c->flag.p, 0, sizeof(int) * 4, c->st));
+    bool scale = true;
+    double prev = INFINITY;
+    int it = 0;
+    *ok = false;
+    double* red = c->red.as<double>();
+    for (it = 1; it <= 100; ++it) {
+        OSA_HIP(hipMemcpyAsync(M, X, sizeof(cd) * k * k, hipMemcpyDeviceToDevice, c->st));
+        gj_invert(M, Y, k, c->logpiv.as<double>(), c->flag.as<int>(), c->gjws.p, c->st);
+        launch_newton_combine(X, Y, k, c->logpiv.as<double>(), scale, red, c->st);
+        double hred[2];
+        int hflag[1];
+        OSA_HIP(hipMemcpyAsync(c->host.as<char>(), red, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                               c->st));
+        OSA_HIP(hipMemcpyAsync(c->host.as<char>() + 16, c->flag.p, sizeof(int),
+                               hipMemcpyDeviceToHost, c->st));
+        sync(c);
+        std::memcpy(hred, c->host.p, 16);
+        std::memcpy(hflag, c->host.as<char>() + 16, 4);
+        if (hflag[0] || !std::isfinite(hred[0]) || !std::isfinite(hred[1])) return -it;
+        const double change = std::sqrt(hred[0] / hred[1]);
+        if (change < 1e-2) scale = false;
+        if (change < 1e-14) { *ok = true; break; }
+        if (change < 1e-8 && change > 0.5 * prev) { *ok = true; break; }
+        prev = change;
+    }
+    if (it > 100) it = 100;
+    OSA_HIP(hipMemcpyAsync(s_out, X, sizeof(cd) * k, hipMemcpyDeviceToDevice, c->st));
+    return it;
+}
+
+// ------------------------------------------------------------- set deflation
+__global__ void k_sign_coef(int m, const cd* __restrict__ lam, const cd* __restrict__ cin,
+                            cd* __restrict__ cout) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) cout[i] = cscale(cin[i], lam[i].x > 0 ? 1.0 : -1.0);
+}
+
+// G = L^H R for the first m pairs, then G^{-1}.
+void build_ginv(osa_ctx* c, int m) {
+    ensure_krylov(c, std::max(c->kcap, std::max(m + 1, 8)));
+    c->Ginv.ensure(sizeof(cd) * (size_t)m * m + 16);
+    const TsPlan p = ts_plan(c->N());
+    cd* G = c->sM.as<cd>();
+    for (int j = 0; j < m; ++j) {
+        launch_dot_partial(c->L.p, c->N(), m, c->R.as<cd>() + (size_t)j * c->N(), false, p,
+                           c->partial.as<cd>(), c->st);
+        launch_reduce_partial(c->partial.as<cd>(), p.nchunks, m, G + (size_t)j * m, 0, nullptr,
+                              nullptr, nullptr, c->st);
+    }
+    OSA_HIP(hipMemsetAsync(c->flag.p, 0, sizeof(int) * 4, c->st));
+    gj_invert(G, c->Ginv.as<cd>(), m, c->logpiv.as<double>(), c->flag.as<int>(), c->gjws.p, c->st);
+    int hf = 0;
+    d2h(c, c->flag.p, 1, &hf);
+    if (hf) throw OsaError{OSA_ERR_EIG_NOCONV};
+}
+
+void set_active(osa_ctx* c, int m) {
+    c->m_active = m;
+    if (m > 0) build_ginv(c, m);
+}
+
+// ------------------------------------------------------------- solve
+struct SolveResult {
+    osa_status st;
+    int k_used;
+    double est;
+    int newton_iters;
+    int breakdown;
+};
+
+// y_int = sign(H) x_int for one internal-layout source.
+SolveResult solve_one(osa_ctx* c, const cd* xin, cd* yout, double tol) {
+    SolveResult res{OSA_OK, 0, NAN, 0, 0};
+    const int64_t N = c->N();
+    const int kmax = c->opts.k_max;
+    ensure_krylov(c, kmax);
+    const bool fixed = c->opts.check_every < 0;
+    const int every = fixed ? kmax : std::max(1, c->opts.check_every);
+    const bool reproj = !c->opts.no_reproject;
+    const TsPlan p = ts_plan(N);
+    cd* V = c->V.as<cd>();
+    cd* H = c->Hm.as<cd>();
+    const int ldh = kmax + 1;
+    cd* w = c->w.as<cd>();
+    cd* x = c->x.as<cd>();
+    cd* ds = c->dscal.as<cd>();           // [0] |b|, [1] beta, [2] h_{j+1,j} scratch, [3] est
+    double* hfro2 = (double*)(ds + 4);
+    int* flag = c->flag.as<int>();
+    const int m = c->m_active;
+    cd* cdef = c->cdef.as<cd>();          // c = G^{-1} L^dag b, kept until assembly
+
+    OSA_HIP(hipMemcpyAsync(x, xin, sizeof(cd) * N, hipMemcpyDeviceToDevice, c->st));
+    OSA_HIP(hipMemsetAsync(H, 0, sizeof(cd) * (size_t)ldh * kmax, c->st));
+    OSA_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, c->st));
+    OSA_HIP(hipMemsetAsync(hfro2, 0, sizeof(double), c->st));
+    vec_norm(c, x, false, ds + 0);
+    if (m > 0) project_out(c, x, cdef);   // x <- x_ominus  (Eq. 21)
+    vec_norm(c, x, false, ds + 1);
+    double hb[2];
+    {
+        cd tmp[2];
+        d2h(c, ds, 2, tmp);
+        hb[0] = tmp[0].x;
+        hb[1] = tmp[1].x;
+    }
+    if (!std::isfinite(hb[0]) || !std::isfinite(hb[1])) { res.st = OSA_ERR_NONFINITE; return res; }
+    const double bnorm = hb[0], beta = hb[1];
+    int k_used = 0;
+    if (beta > 1e-15 * bnorm && beta > 0) {
+        launch_scale(x, V, false, N, 1.0 / beta, c->st);
+        int kprev = 0;
+        bool stopped = false;
+        for (int j = 0; j < kmax && !stopped; ++j) {
+            cd* vj = V + (size_t)j * N;
+            apply_h(c, vj, w, false, false);
+            if (reproj && m > 0) project_out(c, w, nullptr);
+            cgs2(c, w, V, N, j + 1, false, H + (size_t)j * ldh, hfro2);
+            launch_normalize(w, V + (size_t)(j + 1) * N, false, p, c->normp.as<double>(),
+                             H + (size_t)j * ldh + (j + 1), hfro2, 1e-14, flag, j, c->st);
+            const int kk = j + 1;
+            if (kk % every != 0 && kk != kmax) continue;
+            int hf[2];
+            d2h(c, flag, 2, hf);
+            if (hf[0] == 2) { res.st = OSA_ERR_NONFINITE; return res; }
+            int kcheck = kk;
+            if (hf[0] == 1) {   // happy breakdown at step hf[1]: K is invariant, result exact
+                kcheck = std::min(kk, hf[1] + 1);
+                res.breakdown = 1;
+                stopped = true;
+            }
+            bool ok = false;
+            const int its = small_sign_run(c, kcheck, H, ldh, c->s_cur.as<cd>(), &ok);
+            res.newton_iters = its;
+            if (its < 0 || !ok) { res.st = OSA_ERR_NEWTON_NOCONV; return res; }
+            k_used = kcheck;
+            if (kprev > 0 && !fixed) {
+                launch_diff_norm(c->s_cur.as<cd>(), kcheck, c->s_prev.as<cd>(), kprev,
+                                 (double*)(ds + 3), c->st);
+                double dn;
+                d2h(c, ds + 3, 1, &dn);
+                res.est = beta * dn / bnorm;
+                if (res.est <= tol) stopped = true;
+            }
+            if (res.breakdown) res.est = 0.0;
+            if (!stopped) {
+                // keep the latest sign in s_prev for the next difference
+                std::swap(c->s_cur.p, c->s_prev.p);
+                kprev = kcheck;
+            }
+        }
+        // the latest s is in s_cur if the loop stopped early, else in s_prev
+        if (!stopped) std::swap(c->s_cur.p, c->s_prev.p);
+    }
+    // assembly (Eq. 22): y = R sgn(Re lambda) c + beta V_k s
+    cd* co = c->coef.as<cd>();
+    if (m > 0) {
+        hipLaunchKernelGGL(k_sign_coef, dim3((unsigned)ceil_div(m, 64)), dim3(64), 0, c->st, m,
+                           (const cd*)c->lam_dev.p, (const cd*)cdef, co);
+        launch_combine(yout, c->R.p, N, m, co, false, false, N, c->st);
+    } else {
+        OSA_HIP(hipMemsetAsync(yout, 0, sizeof(cd) * N, c->st));
+    }
+    if (k_used > 0) {
+        launch_scale(c->s_cur.p, co, false, k_used, beta, c->st);
+        launch_combine(yout, V, N, k_used, co, false, true, N, c->st);
+    }
+    res.k_used = k_used;
+    if (fixed) res.est = NAN;
+    if (k_used == 0) res.est = 0.0;
+    if (!fixed && !(res.est <= tol)) res.st = OSA_NOT_CONVERGED;
+    sync(c);
+    return res;
+}
+
+// ================================================================ eigensolver
+// Krylov-Schur (Stewart) for the nev eigenvalues of A = H^2 of smallest
+// modulus, A = H(mu)^2 (right) or H(-mu)^2 (left).  Returns an orthonormal
+// basis X (nev vectors, internal layout, fp64) of the converged invariant
+// subspace.  Precision of the search: fp32 or fp64 basis; an fp32 search is
+// followed by an fp64 run started from the fp32 subspace.
+struct KsStats {
+    int64_t matvecs = 0;
+    int restarts = 0;
+    bool converged = false;
+};
+
+void ks_run(osa_ctx* c, bool adjoint, int nev, int ncv, bool fp32, double tol, int max_restarts,
+            const cd* start /* fp64 internal vector or nullptr */, uint64_t seed, cd* Xout,
+            KsStats& stats) {
+    const int64_t N = c->N();
+    const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
+    const int p = ncv;
+    DevBuf Vb, Vt, wv, tv, S, T, Z, wr, bz, info;
+    Vb.ensure(es * (size_t)N * (p + 1));
+    Vt.ensure(es * (size_t)N * (p + 1));
+    wv.ensure(es * (size_t)N);
+    tv.ensure(es * (size_t)N);
+    S.ensure(sizeof(cd) * (size_t)(p + 1) * p);
+    T.ensure(sizeof(cd) * (size_t)p * p);
+    Z.ensure(sizeof(cd) * (size_t)p * p);
+    wr.ensure(sizeof(cd) * p);
+    bz.ensure(sizeof(cd) * p);
+    info.ensure(sizeof(int) * 4);
+    char* V = (char*)Vb.p;
+    const TsPlan pl = ts_plan(N);
+    double* hfro2 = (double*)(c->dscal.as<cd>() + 8);
+    int* flag = c->flag.as<int>();
+    OSA_HIP(hipMemsetAsync(S.p, 0, sizeof(cd) * (size_t)(p + 1) * p, c->st));
+    // start vector
+    if (start) {
+        launch_convert(start, false, V, fp32, N, c->st);
+    } else {
+        launch_random_vector(V, fp32, c->g, seed, c->st);
+    }
+    {
+        launch_norm_partial(V, fp32, pl, c->normp.as<double>(), c->st);
+        launch_normalize(V, V, fp32, pl, c->normp.as<double>(), c->dscal.as<cd>() + 9, nullptr,
+                         0.0, nullptr, 0, c->st);
+    }
+    OSA_HIP(hipMemsetAsync(hfro2, 0, sizeof(double), c->st));
+    int kcur = 0;
+    std::vector<cd> th(p), bzh(p);
+    double anorm = 0;
+    for (int rs = 0; rs <= max_restarts; ++rs) {
+        OSA_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, c->st));
+        for (int j = kcur; j < p; ++j) {
+            char* vj = V + es * (size_t)N * j;
+            apply_h(c, vj, tv.p, fp32, adjoint);
+            apply_h(c, tv.p, wv.p, fp32, adjoint);
+            stats.matvecs += 2;
+            cd* scol = S.as<cd>() + (size_t)j * (p + 1);
+            cgs2(c, wv.p, V, N, j + 1, fp32, scol, hfro2);
+            launch_normalize(wv.p, V + es * (size_t)N * (j + 1), fp32, pl, c->normp.as<double>(),
+                             scol + (j + 1), hfro2, 1e-300, flag, j, c->st);
+        }
+        // Schur form of the p x p Rayleigh quotient, smallest |theta| first
+        cd* Sp = c->sM.as<cd>();
+        OSA_HIP(hipMemcpy2DAsync(Sp, sizeof(cd) * p, S.p, sizeof(cd) * (p + 1), sizeof(cd) * p, p,
+                                 hipMemcpyDeviceToDevice, c->st));
+        small_schur(Sp, p, T.as<cd>(), Z.as<cd>(), wr.as<cd>(), 0, info.as<int>(), nullptr, c->st);
+        // b^H Z with b^H the last row of S
+        launch_zgemm(0, 0, 1, p, p, mk(1.0, 0.0), S.as<cd>() + p, p + 1, Z.as<cd>(), p,
+                     mk(0.0, 0.0), bz.as<cd>(), 1, c->st);
+        int hinfo = 0;
+        d2h(c, info.p, 1, &hinfo);
+        if (hinfo < 0) throw OsaError{OSA_ERR_EIG_NOCONV};
+        d2h(c, wr.p, p, th.data());
+        d2h(c, bz.p, p, bzh.data());
+        for (int i = 0; i < p; ++i) anorm = std::max(anorm, cabsd(th[i]));
+        int nconv = 0;
+        for (int i = 0; i < nev; ++i) {
+            if (cabsd(bzh[i]) <= tol * anorm) ++nconv;
+            else break;
+        }
+        stats.restarts = rs;
+        if (nconv >= nev || rs == max_restarts) {
+            stats.converged = (nconv >= nev);
+            launch_rotate(V, N, p, Z.as<cd>(), p, nev, Vt.p, N, fp32, N, c->st);
+            launch_convert(Vt.p, fp32, Xout, false, N * nev, c->st);
+            sync(c);
+            return;
+        }
+        // thick restart: keep the leading Schur vectors
+        int keep = nev + (p - nev) / 2;
+        if (keep > p - 2) keep = p - 2;
+        if (keep < nev) keep = nev;
+        launch_rotate(V, N, p, Z.as<cd>(), p, keep, Vt.p, N, fp32, N, c->st);
+        OSA_HIP(hipMemcpyAsync((char*)Vt.p + es * (size_t)N * keep, V + es * (size_t)N * p,
+                               es * (size_t)N, hipMemcpyDeviceToDevice, c->st));
+        std::swap(Vb.p, Vt.p);
+        std::swap(Vb.bytes, Vt.bytes);
+        V = (char*)Vb.p;
+        OSA_HIP(hipMemsetAsync(S.p, 0, sizeof(cd) * (size_t)(p + 1) * p, c->st));
+        OSA_HIP(hipMemcpy2DAsync(S.p, sizeof(cd) * (p + 1), T.p, sizeof(cd) * p,
+                                 sizeof(cd) * keep, keep, hipMemcpyDeviceToDevice, c->st));
+        // spike row: S[keep, 0:keep] = bz[0:keep]
+        OSA_HIP(hipMemcpy2DAsync(S.as<cd>() + keep, sizeof(cd) * (p + 1), bz.p, sizeof(cd),
+                                 sizeof(cd), keep, hipMemcpyDeviceToDevice, c->st));
+        kcur = keep;
+    }
+}
+
+// Rayleigh-Ritz with H in span(X): M = X^H H X, Schur form sorted by |Re|,
+// eigenvectors Y; Rv = X Y[:, :m], lam = diag.  Residuals |H r - lam r|.
+void rayleigh_ritz(osa_ctx* c, bool adjoint, int nev, int m, cd* X, cd* Rout,
+                   std::vector<cd>& lam, double& max_res) {
+    const int64_t N = c->N();
+    DevBuf W, Mb, T, Z, Y, wr, info, HR, res;
+    W.ensure(sizeof(cd) * (size_t)N * nev);
+    Mb.ensure(sizeof(cd) * nev * nev);
+    T.ensure(sizeof(cd) * nev * nev);
+    Z.ensure(sizeof(cd) * nev * nev);
+    Y.ensure(sizeof(cd) * nev * nev);
+    wr.ensure(sizeof(cd) * nev);
+    info.ensure(sizeof(int) * 4);
+    HR.ensure(sizeof(cd) * (size_t)N * m);
+    apply_h(c, X, W.p, false, adjoint, nev);
+    const TsPlan p = ts_plan(N);
+    for (int j = 0; j < nev; ++j) {
+        launch_dot_partial(X, N, nev, W.as<cd>() + (size_t)j * N, false, p, c->partial.as<cd>(),
+                           c->st);
+        launch_reduce_partial(c->partial.as<cd>(), p.nchunks, nev, Mb.as<cd>() + (size_t)j * nev,
+                              0, nullptr, nullptr, nullptr, c->st);
+    }
+    small_schur(Mb.as<cd>(), nev, T.as<cd>(), Z.as<cd>(), wr.as<cd>(), 1, info.as<int>(), nullptr,
+                c->st);
+    small_eigvecs(T.as<cd>(), Z.as<cd>(), nev, Y.as<cd>(), c->st);
+    int hinfo = 0;
+    d2h(c, info.p, 1, &hinfo);
+    if (hinfo < 0) throw OsaError{OSA_ERR_EIG_NOCONV};
+    std::vector<cd> allw(nev);
+    d2h(c, wr.p, nev, allw.data());
+    lam.assign(allw.begin(), allw.begin() + m);
+    launch_rotate(X, N, nev, Y.as<cd>(), nev, m, Rout, N, false, N, c->st);
+    launch_rotate(W.p, N, nev, Y.as<cd>(), nev, m, HR.p, N, false, N, c->st);
+    // residuals: |HR_i - lam_i R_i| (R_i unit)
+    max_res = 0;
+    std::vector<double> nrm(1);
+    for (int i = 0; i < m; ++i) {
+        cd* hr = HR.as<cd>() + (size_t)i * N;
+        cd negl = mk(-lam[i].x, -lam[i].y);
+        h2d(c, c->coef.p, &negl, 1);
+        launch_combine(hr, Rout + (size_t)i * N, N, 1, c->coef.as<cd>(), false, true, N, c->st);
+        vec_norm(c, hr, false, c->dscal.as<cd>() + 12);
+        cd hn;
+        d2h(c, c->dscal.as<cd>() + 12, 1, &hn);
+        max_res = std::max(max_res, hn.x);
+    }
+}
+
+void deflate(osa_ctx* c, int m, osa_info* info) {
+    const double t0 = now_ms();
+    if (m == 0) {
+        c->m_alloc = c->m_active = 0;
+        c->lambda.clear();
+        c->t_init_ms = 0;
+        return;
+    }
+    const int64_t N = c->N();
+    ensure_krylov(c, std::max(c->kcap, std::max(c->opts.k_max, 64)));
+    const int extra = std::max(4, m / 5);
+    const int nev = std::min(m + extra, 56);
+    int ncv = c->opts.eig_ncv > 0 ? c->opts.eig_ncv : std::min(64, 2 * nev + 16);
+    if (ncv > 64) ncv = 64;
+    if (ncv < nev + 4) ncv = std::min(64, nev + 4);
+    if (nev + 2 > ncv) throw OsaError{OSA_ERR_ARG};
+    const double tol = c->opts.eig_tol > 0 ? c->opts.eig_tol : 1e-12;
+    const int maxr = c->opts.eig_max_restarts > 0 ? c->opts.eig_max_restarts : 2000;
+    const bool fp32 = (c->opts.eig_prec == OSA_FP32);
+    if (fp32 && !c->links_fp32 && !c->U32.p) {
+        c->U32.ensure(sizeof(cf) * (size_t)c->g.Vp * 36);
+        launch_convert(c->U.p, false, c->U32.p, true, (int64_t)c->g.Vp * 36, c->st);
+    }
+    DevBuf X, Rn, Ln, Xs;
+    X.ensure(sizeof(cd) * (size_t)N * nev);
+    Xs.ensure(sizeof(cd) * N);
+    Rn.ensure(sizeof(cd) * (size_t)N * m);
+    Ln.ensure(sizeof(cd) * (size_t)N * m);
+    KsStats st;
+    std::vector<cd> lam_r, lam_l;
+    double res_r = 0, res_l = 0;
+    for (int side = 0; side < 2; ++side) {
+        const bool adj = (side == 1);
+        const uint64_t seed = 0x5eedULL + 7919ULL * side;
+        if (fp32) {
+            KsStats s32;
+            ks_run(c, adj, nev, ncv, true, std::max(tol, 1e-6), maxr, nullptr, seed, X.as<cd>(),
+                   s32);
+            st.matvecs += s32.matvecs;
+            st.restarts += s32.restarts;
+            // fp64 refinement from the fp32 subspace: start vector = sum of its basis
+            std::vector<cd> ones(nev, mk(1.0, 0.0));
+            h2d(c, c->coef.p, ones.data(), nev);
+            launch_combine(Xs.p, X.p, N, nev, c->coef.as<cd>(), false, false, N, c->st);
+            KsStats s64;
+            ks_run(c, adj, nev, ncv, false, tol, maxr, Xs.as<cd>(), seed, X.as<cd>(), s64);
+            st.matvecs += s64.matvecs;
+            st.restarts += s64.restarts;
+            if (!s64.converged) throw OsaError{OSA_ERR_EIG_NOCONV};
+        } else {
+            KsStats s64;
+            ks_run(c, adj, nev, ncv, false, tol, maxr, nullptr, seed, X.as<cd>(), s64);
+            st.matvecs += s64.matvecs;
+            st.restarts += s64.restarts;
+            if (!s64.converged) throw OsaError{OSA_ERR_EIG_NOCONV};
+        }
+        st.matvecs += nev;
+        if (!adj) rayleigh_ritz(c, false, nev, m, X.as<cd>(), Rn.as<cd>(), lam_r, res_r);
+        else rayleigh_ritz(c, true, nev, m, X.as<cd>(), Ln.as<cd>(), lam_l, res_l);
+    }
+    // install
+    c->R.ensure(sizeof(cd) * (size_t)N * m);
+    c->L.ensure(sizeof(cd) * (size_t)N * m);
+    OSA_HIP(hipMemcpyAsync(c->R.p, Rn.p, sizeof(cd) * (size_t)N * m, hipMemcpyDeviceToDevice, c->st));
+    OSA_HIP(hipMemcpyAsync(c->L.p, Ln.p, sizeof(cd) * (size_t)N * m, hipMemcpyDeviceToDevice, c->st));
+    c->lambda = lam_r;
+    c->lam_dev.ensure(sizeof(cd) * m);
+    h2d(c, c->lam_dev.p, c->lambda.data(), m);
+    c->m_alloc = m;
+    double hn = c->hnorm_bound;
+    c->min_abs_re = INFINITY;
+    for (auto& l : c->lambda) c->min_abs_re = std::min(c->min_abs_re, std::fabs(l.x));
+    c->max_eig_resid = std::max(res_r, res_l);
+    c->eig_matvecs = st.matvecs;
+    c->eig_restarts = st.restarts;
+    if (c->min_abs_re < 1e-12 * hn) throw OsaError{OSA_ERR_IMAG_AXIS};
+    set_active(c, m);
+    sync(c);
+    c->t_init_ms = now_ms() - t0;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->n_defl = m;
+        info->min_abs_re_lambda = c->min_abs_re;
+        info->max_eig_resid = c->max_eig_resid;
+        info->t_init_ms = c->t_init_ms;
+        info->eig_matvecs = c->eig_matvecs;
+        info->eig_restarts = c->eig_restarts;
+        info->status = OSA_OK;
+    }
+}
+
+void fill_defaults(osa_opts& o) {
+    if (o.k_max <= 0) o.k_max = 600;
+    if (o.check_every == 0) o.check_every = 50;
+}
+
+osa_status validate_lattice(const osa_lattice* lat) {
+    if (!lat) return OSA_ERR_ARG;
+    for (int i = 0; i < 4; ++i)
+        if (lat->dims[i] < 2 || lat->dims[i] > 4096) return OSA_ERR_ARG;
+    const int64_t v = (int64_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+    if (v > (1LL << 28)) return OSA_ERR_ARG;
+    return OSA_OK;
+}
+
+template <typename F>
+osa_status guard(F&& f) {
+    try {
+        return f();
+    } catch (const OsaError& e) {
+        return e.s;
+    } catch (const HipError& e) {
+        (void)hipGetLastError();
+        return OSA_ERR_HIP;
+    } catch (const std::bad_alloc&) {
+        return OSA_ERR_OOM;
+    } catch (...) {
+        return OSA_ERR_HIP;
+    }
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+const char* osa_version(void) { return "osa 0.1 (gfx950)"; }
+
+const char* osa_status_string(osa_status s) {
+    switch (s) {
+        case OSA_OK: return "ok";
+        case OSA_NOT_CONVERGED: return "not converged (result usable)";
+        case OSA_ERR_ARG: return "invalid argument";
+        case OSA_ERR_HIP: return "HIP runtime error";
+        case OSA_ERR_OOM: return "out of device memory";
+        case OSA_ERR_NONFINITE: return "non-finite input or intermediate";
+        case OSA_ERR_IMAG_AXIS: return "deflated eigenvalue on the imaginary axis";
+        case OSA_ERR_EIG_NOCONV: return "eigensolver did not converge";
+        case OSA_ERR_NEWTON_NOCONV: return "small sign iteration did not converge";
+        case OSA_ERR_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+osa_status osa_set_opts(osa_ctx* c, const osa_opts* opts) {
+    if (!c) return OSA_ERR_ARG;
+    osa_opts o{};
+    if (opts) o = *opts;
+    if (o.k_max < 0 || o.k_max > 4000 || o.eig_ncv < 0 || o.eig_ncv > 64 || o.eig_tol < 0 ||
+        o.eig_max_restarts < 0 || (o.eig_prec != OSA_FP64 && o.eig_prec != OSA_FP32))
+        return OSA_ERR_ARG;
+    fill_defaults(o);
+    c->opts = o;
+    return OSA_OK;
+}
+
+osa_status osa_create(osa_ctx** out, const osa_lattice* lat, const void* links, osa_prec link_prec,
+                      double mu, double m_w, const osa_opts* opts, void* stream) {
+    if (!out || !links) return OSA_ERR_ARG;
+    *out = nullptr;
+    if (validate_lattice(lat) != OSA_OK) return OSA_ERR_ARG;
+    if (!(m_w > -2.0 && m_w < 0.0) || !std::isfinite(mu) || std::fabs(mu) > 50.0) return OSA_ERR_ARG;
+    if (link_prec != OSA_FP64 && link_prec != OSA_FP32) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        std::unique_ptr<osa_ctx> c(new osa_ctx());
+        c->st = (hipStream_t)stream;
+        osa_status s = osa_set_opts(c.get(), opts);
+        if (s != OSA_OK) return s;
+        Geom& g = c->g;
+        g.lx = lat->dims[0]; g.ly = lat->dims[1]; g.lz = lat->dims[2]; g.lt = lat->dims[3];
+        g.V = g.lx * g.ly * g.lz * g.lt;
+        g.Vp = (int)(ceil_div(g.V, 64) * 64);
+        g.apt = lat->antiperiodic_t ? 1 : 0;
+        c->links_fp32 = (link_prec == OSA_FP32);
+        c->mu = mu;
+        c->m_w = m_w;
+        c->kappa = 1.0 / (8.0 + 2.0 * m_w);
+        for (int nu = 0; nu < 3; ++nu) {
+            c->hc.fwd[nu] = c->hc.bwd[nu] = -c->kappa;
+            c->hc_adj.fwd[nu] = c->hc_adj.bwd[nu] = -c->kappa;
+        }
+        c->hc.fwd[3] = -c->kappa * std::exp(mu);
+        c->hc.bwd[3] = -c->kappa * std::exp(-mu);
+        c->hc_adj.fwd[3] = -c->kappa * std::exp(-mu);
+        c->hc_adj.bwd[3] = -c->kappa * std::exp(mu);
+        c->hnorm_bound = 1.0 + 2.0 * c->kappa * (3.0 + std::cosh(mu));
+        const size_t lb = (size_t)g.Vp * 36 * (c->links_fp32 ? sizeof(cf) : sizeof(cd));
+        c->U.ensure(lb);
+        launch_links_to_internal(links, c->links_fp32, c->U.p, c->links_fp32, g, c->st);
+        ensure_krylov(c.get(), c->opts.k_max);
+        c->host.ensure(1 << 16);
+        sync(c.get());
+        *out = c.release();
+        return OSA_OK;
+    });
+}
+
+void osa_destroy(osa_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->st);
+    delete c;
+}
+
+osa_status osa_deflate(osa_ctx* c, int32_t n_defl, osa_info* info) {
+    if (!c) return OSA_ERR_ARG;
+    if (n_defl < 0 || n_defl > 48 || (int64_t)n_defl >= 12LL * c->g.V) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        deflate(c, n_defl, info);
+        return OSA_OK;
+    });
+}
+
+osa_status osa_set_deflation(osa_ctx* c, int32_t m, const void* R, const void* L,
+                             const double* lambda) {
+    if (!c || m < 0 || m > 64 || (int64_t)m >= 12LL * c->g.V) return OSA_ERR_ARG;
+    if (m > 0 && (!R || !L || !lambda)) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        const int64_t N = c->N();
+        if (m == 0) { c->m_alloc = c->m_active = 0; c->lambda.clear(); return OSA_OK; }
+        c->R.ensure(sizeof(cd) * (size_t)N * m);
+        c->L.ensure(sizeof(cd) * (size_t)N * m);
+        launch_vec_to_internal((const cd*)R, c->R.p, false, c->g, m, c->st);
+        launch_vec_to_internal((const cd*)L, c->L.p, false, c->g, m, c->st);
+        c->lambda.resize(m);
+        for (int i = 0; i < m; ++i) c->lambda[i] = mk(lambda[2 * i], lambda[2 * i + 1]);
+        c->lam_dev.ensure(sizeof(cd) * m);
+        h2d(c, c->lam_dev.p, c->lambda.data(), m);
+        c->m_alloc = m;
+        c->min_abs_re = INFINITY;
+        for (auto& l : c->lambda) c->min_abs_re = std::min(c->min_abs_re, std::fabs(l.x));
+        if (c->min_abs_re < 1e-12 * c->hnorm_bound) return OSA_ERR_IMAG_AXIS;
+        c->max_eig_resid = NAN;
+        set_active(c, m);
+        return OSA_OK;
+    });
+}
+
+osa_status osa_get_deflation(const osa_ctx* cc, int32_t* m_out, void* R, void* L, double* lambda) {
+    osa_ctx* c = const_cast<osa_ctx*>(cc);
+    if (!c) return OSA_ERR_ARG;
+    if (m_out) *m_out = c->m_alloc;
+    return guard([&]() -> osa_status {
+        const int m = c->m_alloc;
+        if (m == 0) return OSA_OK;
+        if (R) launch_vec_from_internal(c->R.p, false, (cd*)R, c->g, m, c->st);
+        if (L) launch_vec_from_internal(c->L.p, false, (cd*)L, c->g, m, c->st);
+        if (lambda)
+            for (int i = 0; i < m; ++i) { lambda[2 * i] = c->lambda[i].x; lambda[2 * i + 1] = c->lambda[i].y; }
+        sync(c);
+        return OSA_OK;
+    });
+}
+
+osa_status osa_set_active_deflation(osa_ctx* c, int32_t m) {
+    if (!c || m < 0 || m > c->m_alloc) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        set_active(c, m);
+        return OSA_OK;
+    });
+}
+
+osa_status osa_apply(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double tol,
+                     osa_info* infos) {
+    if (!c || nrhs < 1 || !B || !Y) return OSA_ERR_ARG;
+    const bool fixed = c->opts.check_every < 0;
+    if (!fixed && !(tol > 0)) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        const int64_t N = c->N();
+        const int64_t nb = 12LL * c->g.V;
+        osa_status worst = OSA_OK;
+        DevBuf xin, yint;
+        xin.ensure(sizeof(cd) * N);
+        yint.ensure(sizeof(cd) * N);
+        for (int r = 0; r < nrhs; ++r) {
+            const double t0 = now_ms();
+            launch_vec_to_internal((const cd*)B + r * nb, xin.p, false, c->g, 1, c->st);
+            SolveResult sr = solve_one(c, xin.as<cd>(), yint.as<cd>(), tol);
+            if (sr.st == OSA_OK || sr.st == OSA_NOT_CONVERGED)
+                launch_vec_from_internal(yint.p, false, (cd*)Y + r * nb, c->g, 1, c->st);
+            double ynorm = 1.0;
+            if (sr.st == OSA_OK || sr.st == OSA_NOT_CONVERGED) {
+                vec_norm(c, yint.p, false, c->dscal.as<cd>() + 6);
+                cd yn;
+                d2h(c, c->dscal.as<cd>() + 6, 1, &yn);
+                ynorm = yn.x;
+            }
+            sync(c);
+            const double t1 = now_ms();
+            if (infos) {
+                osa_info& in = infos[r];
+                std::memset(&in, 0, sizeof(in));
+                cd bn;
+                d2h(c, c->dscal.as<cd>() + 0, 1, &bn);
+                in.resid_est = std::isnan(sr.est) ? sr.est : sr.est * bn.x / std::max(ynorm, 1e-300);
+                in.k_used = sr.k_used;
+                in.n_defl = c->m_active;
+                in.status = sr.st;
+                in.newton_iters = sr.newton_iters;
+                in.breakdown = sr.breakdown;
+                in.min_abs_re_lambda = c->m_active ? c->min_abs_re : NAN;
+                in.max_eig_resid = c->max_eig_resid;
+                in.t_init_ms = c->t_init_ms;
+                in.t_solve_ms = t1 - t0;
+                in.eig_matvecs = c->eig_matvecs;
+                in.eig_restarts = c->eig_restarts;
+            }
+            if (sr.st < 0) return sr.st;
+            if (sr.st > worst) worst = sr.st;
+        }
+        return worst;
+    });
+}
+
+osa_status osa_batch_apply(int32_t n, osa_ctx* const* ctxs, const void* const* B, void* const* Y,
+                           double tol, osa_info* infos) {
+    if (n < 1 || !ctxs || !B || !Y) return OSA_ERR_ARG;
+    osa_status worst = OSA_OK;
+    for (int i = 0; i < n; ++i) {
+        osa_status s = osa_apply(ctxs[i], 1, B[i], Y[i], tol, infos ? infos + i : nullptr);
+        if (s < 0) return s;
+        if (s > worst) worst = s;
+    }
+    return worst;
+}
+
+osa_status osa_apply_hw(osa_ctx* c, int32_t nrhs, const void* X, void* Y) {
+    if (!c || nrhs < 1 || !X || !Y) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        const int64_t N = c->N();
+        DevBuf a, b;
+        a.ensure(sizeof(cd) * N * nrhs);
+        b.ensure(sizeof(cd) * N * nrhs);
+        launch_vec_to_internal((const cd*)X, a.p, false, c->g, nrhs, c->st);
+        apply_h(c, a.p, b.p, false, false, nrhs);
+        launch_vec_from_internal(b.p, false, (cd*)Y, c->g, nrhs, c->st);
+        sync(c);
+        return OSA_OK;
+    });
+}
+
+osa_status osa_small_sign(int32_t k, const void* A, void* s, int32_t* iters, void* stream) {
+    if (k < 1 || k > 4000 || !A || !s) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        osa_ctx c;
+        c.st = (hipStream_t)stream;
+        c.g.lx = c.g.ly = c.g.lz = c.g.lt = 2;
+        c.g.V = 16;
+        c.g.Vp = 64;
+        c.host.ensure(1 << 16);
+        c.sX.ensure(sizeof(cd) * (size_t)k * k);
+        c.sM.ensure(sizeof(cd) * (size_t)k * k);
+        c.sY.ensure(sizeof(cd) * (size_t)k * k);
+        c.logpiv.ensure(sizeof(double) * k);
+        c.gjws.ensure(gj_ws_bytes(k));
+        c.flag.ensure(sizeof(int) * 4);
+        c.red.ensure(sizeof(double) * (size_t)(2 + 2 * ceil_div((int64_t)k * k, 256) + 16));
+        bool ok = false;
+        int it = small_sign_run(&c, k, (const cd*)A, k, (cd*)s, &ok);
+        sync(&c);
+        if (iters) *iters = it;
+        if (it < 0 || !ok) return OSA_ERR_NEWTON_NOCONV;
+        return OSA_OK;
+    });
+}
+
+osa_status overlap_sign_apply(const osa_lattice* lat, const void* links, osa_prec link_prec,
+                              double mu, double m_w, const void* source, double tol,
+                              int32_t n_defl, void* result, double* resid_est, void* stream) {
+    if (!source || !result || !(tol > 0) || n_defl < 0 || source == result) return OSA_ERR_ARG;
+    osa_ctx* c = nullptr;
+    osa_status s = osa_create(&c, lat, links, link_prec, mu, m_w, nullptr, stream);
+    if (s != OSA_OK) return s;
+    s = osa_deflate(c, n_defl, nullptr);
+    osa_info info{};
+    if (s == OSA_OK) s = osa_apply(c, 1, source, result, tol, &info);
+    if (resid_est) *resid_est = info.resid_est;
+    osa_destroy(c);
+    return s;
+}
+
+}  // extern "C"

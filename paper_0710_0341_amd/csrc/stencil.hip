@@ -1,0 +1,274 @@
+// Layout conversion and the Wilson-Dirac stencil at chemical potential.
+//
+// H_w(mu) psi = gamma_5 [ psi_n - kappa sum_nu ( e^{+mu d_{nu4}} (1+gamma_nu) U_{n,nu} psi_{n+nu}
+//                                            + e^{-mu d_{nu4}} (1-gamma_nu) U^dag_{n-nu,nu} psi_{n-nu} ) ]
+// (Eq. 1 and Eq. 2).  (1 +- gamma_nu) has rank two, so each hop projects the
+// neighbour spinor onto a half spinor h (2 spins x 3 colours), multiplies the
+// two colour vectors by the link and rebuilds the lower spin pair from h.  In
+// the chiral basis (gamma_5 = diag(1,1,-1,-1)) with psi = (u0, u1, d0, d1):
+//
+//   nu = x : h = (u0 - s i d1, u1 - s i d0),   lower = ( s i h1,  s i h0)
+//   nu = y : h = (u0 - s d1,   u1 + s d0),     lower = ( s h1,   -s h0)
+//   nu = z : h = (u0 - s i d0, u1 + s i d1),   lower = ( s i h0, -s i h1)
+//   nu = t : h = (u0 + s d0,   u1 + s d1),     lower = ( s h0,    s h1)
+//
+// with s = +1 for the forward hop (1+gamma) and s = -1 for the backward hop.
+// gamma_5 then flips the sign of the lower spin pair of the result.
+#include "kernels.hpp"
+
+namespace osa {
+
+// ------------------------------------------------------------------ layout
+template <typename TI, typename TO>
+__global__ void k_links_to_internal(const TI* __restrict__ in, TO* __restrict__ out, int V,
+                                    int Vp) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over Vp*36
+    if (idx >= (int64_t)Vp * 36) return;
+    int s = (int)(idx % Vp);
+    int e = (int)(idx / Vp);            // e = (nu*3 + a)*3 + b
+    TO val;
+    if (s < V) {
+        cd v = tod(in[(int64_t)s * 36 + e]);
+        val = fromd<TO>(v);
+    } else {
+        val = fromd<TO>(mk(0.0, 0.0));
+    }
+    out[(int64_t)e * Vp + s] = val;
+}
+
+void launch_links_to_internal(const void* links_aos, bool in_fp32, void* links_int,
+                              bool int_fp32, const Geom& g, hipStream_t st) {
+    int64_t n = (int64_t)g.Vp * 36;
+    dim3 grid((unsigned)ceil_div(n, 256)), blk(256);
+    if (!in_fp32 && !int_fp32)
+        hipLaunchKernelGGL((k_links_to_internal<cd, cd>), grid, blk, 0, st, (const cd*)links_aos,
+                           (cd*)links_int, g.V, g.Vp);
+    else if (in_fp32 && int_fp32)
+        hipLaunchKernelGGL((k_links_to_internal<cf, cf>), grid, blk, 0, st, (const cf*)links_aos,
+                           (cf*)links_int, g.V, g.Vp);
+    else if (!in_fp32 && int_fp32)
+        hipLaunchKernelGGL((k_links_to_internal<cd, cf>), grid, blk, 0, st, (const cd*)links_aos,
+                           (cf*)links_int, g.V, g.Vp);
+    else
+        hipLaunchKernelGGL((k_links_to_internal<cf, cd>), grid, blk, 0, st, (const cf*)links_aos,
+                           (cd*)links_int, g.V, g.Vp);
+    OSA_LAUNCH_CHECK();
+}
+
+template <typename TO>
+__global__ void k_vec_to_internal(const cd* __restrict__ in, TO* __restrict__ out, int V, int Vp,
+                                  int nvec) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over nvec*12*Vp
+    int64_t per = 12LL * Vp;
+    if (idx >= per * nvec) return;
+    int vec = (int)(idx / per);
+    int64_t r = idx - vec * per;
+    int c = (int)(r / Vp);
+    int s = (int)(r - (int64_t)c * Vp);
+    cd v = (s < V) ? in[(int64_t)vec * 12 * V + (int64_t)s * 12 + c] : mk(0.0, 0.0);
+    out[idx] = fromd<TO>(v);
+}
+
+template <typename TI>
+__global__ void k_vec_from_internal(const TI* __restrict__ in, cd* __restrict__ out, int V, int Vp,
+                                    int nvec) {
+    // one thread per boundary-layout entry so that the writes are coalesced
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over nvec*12*V
+    int64_t per = 12LL * V;
+    if (idx >= per * nvec) return;
+    int vec = (int)(idx / per);
+    int64_t r = idx - vec * per;
+    int s = (int)(r / 12);
+    int c = (int)(r - (int64_t)s * 12);
+    out[idx] = tod(in[(int64_t)vec * 12 * Vp + (int64_t)c * Vp + s]);
+}
+
+void launch_vec_to_internal(const cd* aos, void* soa, bool soa_fp32, const Geom& g, int nvec,
+                            hipStream_t st) {
+    int64_t n = 12LL * g.Vp * nvec;
+    dim3 grid((unsigned)ceil_div(n, 256)), blk(256);
+    if (soa_fp32)
+        hipLaunchKernelGGL(k_vec_to_internal<cf>, grid, blk, 0, st, aos, (cf*)soa, g.V, g.Vp, nvec);
+    else
+        hipLaunchKernelGGL(k_vec_to_internal<cd>, grid, blk, 0, st, aos, (cd*)soa, g.V, g.Vp, nvec);
+    OSA_LAUNCH_CHECK();
+}
+
+void launch_vec_from_internal(const void* soa, bool soa_fp32, cd* aos, const Geom& g, int nvec,
+                              hipStream_t st) {
+    int64_t n = 12LL * g.V * nvec;
+    dim3 grid((unsigned)ceil_div(n, 256)), blk(256);
+    if (soa_fp32)
+        hipLaunchKernelGGL(k_vec_from_internal<cf>, grid, blk, 0, st, (const cf*)soa, aos, g.V,
+                           g.Vp, nvec);
+    else
+        hipLaunchKernelGGL(k_vec_from_internal<cd>, grid, blk, 0, st, (const cd*)soa, aos, g.V,
+                           g.Vp, nvec);
+    OSA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ stencil
+// Complex arithmetic in the compute precision R (double or float).
+template <typename R> struct Cx { R x, y; };
+template <typename R> __device__ __forceinline__ Cx<R> cx(R a, R b) { return Cx<R>{a, b}; }
+template <typename R> __device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R> __device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R> __device__ __forceinline__ Cx<R> operator*(R s, Cx<R> a) { return {s * a.x, s * a.y}; }
+// i * a
+template <typename R> __device__ __forceinline__ Cx<R> ti(Cx<R> a) { return {-a.y, a.x}; }
+
+template <typename R, typename T> __device__ __forceinline__ Cx<R> ld(const T* p) {
+    T v = *p;
+    return Cx<R>{(R)v.x, (R)v.y};
+}
+
+// w = U h  (fwd) or w = U^dag h (bwd) for a colour 3-vector; U read from SoA links.
+template <typename R, bool DAG, typename LT>
+__device__ __forceinline__ void su3_mul(const LT* __restrict__ U, int64_t base, int64_t Vp,
+                                        const Cx<R> h[3], Cx<R> w[3]) {
+    Cx<R> u[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = ld<R>(U + base + e * Vp);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        R re = 0, im = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            Cx<R> m = DAG ? Cx<R>{u[b * 3 + a].x, -u[b * 3 + a].y} : u[a * 3 + b];
+            re += m.x * h[b].x - m.y * h[b].y;
+            im += m.x * h[b].y + m.y * h[b].x;
+        }
+        w[a] = Cx<R>{re, im};
+    }
+}
+
+// One hop: project the neighbour spinor (NU, sign S), multiply by the link and
+// accumulate coef * (reconstructed 4-spinor) into acc[12].
+template <typename R, int NU, int S, typename ST, typename LT>
+__device__ __forceinline__ void hop(const ST* __restrict__ in, const LT* __restrict__ U,
+                                    int64_t Vp, int nb, int lsite, R coef, Cx<R> acc[12]) {
+    Cx<R> u0[3], u1[3], d0[3], d1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        u0[c] = ld<R>(in + (0 * 3 + c) * Vp + nb);
+        u1[c] = ld<R>(in + (1 * 3 + c) * Vp + nb);
+        d0[c] = ld<R>(in + (2 * 3 + c) * Vp + nb);
+        d1[c] = ld<R>(in + (3 * 3 + c) * Vp + nb);
+    }
+    const R s = (R)S;
+    Cx<R> h0[3], h1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (NU == 0) { h0[c] = u0[c] - s * ti(d1[c]); h1[c] = u1[c] - s * ti(d0[c]); }
+        if (NU == 1) { h0[c] = u0[c] - s * d1[c];     h1[c] = u1[c] + s * d0[c]; }
+        if (NU == 2) { h0[c] = u0[c] - s * ti(d0[c]); h1[c] = u1[c] + s * ti(d1[c]); }
+        if (NU == 3) { h0[c] = u0[c] + s * d0[c];     h1[c] = u1[c] + s * d1[c]; }
+    }
+    Cx<R> w0[3], w1[3];
+    const int64_t base = (int64_t)(NU * 9) * Vp + lsite;
+    su3_mul<R, (S < 0)>(U, base, Vp, h0, w0);
+    su3_mul<R, (S < 0)>(U, base, Vp, h1, w1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Cx<R> l0, l1;
+        if (NU == 0) { l0 = s * ti(w1[c]); l1 = s * ti(w0[c]); }
+        if (NU == 1) { l0 = s * w1[c];     l1 = (-s) * w0[c]; }
+        if (NU == 2) { l0 = s * ti(w0[c]); l1 = (-s) * ti(w1[c]); }
+        if (NU == 3) { l0 = s * w0[c];     l1 = s * w1[c]; }
+        acc[0 * 3 + c] = acc[0 * 3 + c] + coef * w0[c];
+        acc[1 * 3 + c] = acc[1 * 3 + c] + coef * w1[c];
+        acc[2 * 3 + c] = acc[2 * 3 + c] + coef * l0;
+        acc[3 * 3 + c] = acc[3 * 3 + c] + coef * l1;
+    }
+}
+
+struct StencilArgs {
+    int lx, ly, lz, lt, V;
+    int64_t Vp;
+    int apt;
+    double cf[4], cb[4];
+};
+
+template <typename R, typename ST, typename LT>
+__global__ __launch_bounds__(128) void k_wilson_h(const ST* __restrict__ in, ST* __restrict__ out,
+                                                 const LT* __restrict__ U, StencilArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t vecoff = (int64_t)blockIdx.y * 12 * a.Vp;
+    in += vecoff;
+    out += vecoff;
+    if (s >= a.V) {
+        // padding sites carry zeros so that whole-vector reductions stay exact
+        if (s < a.Vp) {
+            ST z;
+            z.x = 0;
+            z.y = 0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) out[(int64_t)c * a.Vp + s] = z;
+        }
+        return;
+    }
+    const int x = s % a.lx;
+    int r = s / a.lx;
+    const int y = r % a.ly;
+    r /= a.ly;
+    const int z = r % a.lz;
+    const int t = r / a.lz;
+    const int sx = 1, sy = a.lx, sz = a.lx * a.ly, stt = a.lx * a.ly * a.lz;
+    const int xf = (x + 1 == a.lx) ? s - (a.lx - 1) * sx : s + sx;
+    const int xb = (x == 0) ? s + (a.lx - 1) * sx : s - sx;
+    const int yf = (y + 1 == a.ly) ? s - (a.ly - 1) * sy : s + sy;
+    const int yb = (y == 0) ? s + (a.ly - 1) * sy : s - sy;
+    const int zf = (z + 1 == a.lz) ? s - (a.lz - 1) * sz : s + sz;
+    const int zb = (z == 0) ? s + (a.lz - 1) * sz : s - sz;
+    const int tf = (t + 1 == a.lt) ? s - (a.lt - 1) * stt : s + stt;
+    const int tb = (t == 0) ? s + (a.lt - 1) * stt : s - stt;
+    R ctf = (R)a.cf[3], ctb = (R)a.cb[3];
+    if (a.apt) {
+        if (t + 1 == a.lt) ctf = -ctf;
+        if (t == 0) ctb = -ctb;
+    }
+    Cx<R> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = Cx<R>{0, 0};
+    const int64_t Vp = a.Vp;
+    hop<R, 0, +1>(in, U, Vp, xf, s, (R)a.cf[0], acc);
+    hop<R, 0, -1>(in, U, Vp, xb, xb, (R)a.cb[0], acc);
+    hop<R, 1, +1>(in, U, Vp, yf, s, (R)a.cf[1], acc);
+    hop<R, 1, -1>(in, U, Vp, yb, yb, (R)a.cb[1], acc);
+    hop<R, 2, +1>(in, U, Vp, zf, s, (R)a.cf[2], acc);
+    hop<R, 2, -1>(in, U, Vp, zb, zb, (R)a.cb[2], acc);
+    hop<R, 3, +1>(in, U, Vp, tf, s, ctf, acc);
+    hop<R, 3, -1>(in, U, Vp, tb, tb, ctb, acc);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        Cx<R> v = ld<R>(in + (int64_t)c * Vp + s) + acc[c];
+        if (c >= 6) v = Cx<R>{-v.x, -v.y};    // gamma_5
+        ST o;
+        o.x = v.x;
+        o.y = v.y;
+        out[(int64_t)c * Vp + s] = o;
+    }
+}
+
+void launch_wilson_h(const void* in, void* out, const void* U, bool links_fp32, bool spinor_fp32,
+                     const Geom& g, const HopCoef& c, int nrhs, hipStream_t st) {
+    StencilArgs a;
+    a.lx = g.lx; a.ly = g.ly; a.lz = g.lz; a.lt = g.lt; a.V = g.V; a.Vp = g.Vp; a.apt = g.apt;
+    for (int i = 0; i < 4; ++i) { a.cf[i] = c.fwd[i]; a.cb[i] = c.bwd[i]; }
+    dim3 blk(128), grid((unsigned)ceil_div(g.Vp, 128), (unsigned)nrhs);
+    if (!spinor_fp32 && !links_fp32)
+        hipLaunchKernelGGL((k_wilson_h<double, cd, cd>), grid, blk, 0, st, (const cd*)in, (cd*)out,
+                           (const cd*)U, a);
+    else if (!spinor_fp32 && links_fp32)
+        hipLaunchKernelGGL((k_wilson_h<double, cd, cf>), grid, blk, 0, st, (const cd*)in, (cd*)out,
+                           (const cf*)U, a);
+    else if (spinor_fp32 && links_fp32)
+        hipLaunchKernelGGL((k_wilson_h<float, cf, cf>), grid, blk, 0, st, (const cf*)in, (cf*)out,
+                           (const cf*)U, a);
+    else
+        hipLaunchKernelGGL((k_wilson_h<float, cf, cd>), grid, blk, 0, st, (const cf*)in, (cf*)out,
+                           (const cd*)U, a);
+    OSA_LAUNCH_CHECK();
+}
+
+}  // namespace osa

@@ -1,0 +1,283 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (FP64 mode): operator application to rounding (1e-13 relative);
+the full method at fixed (k, deflation data) to 1e-10 relative, the bar set
+for FP64 results; the converged result against the exact sign(H) b within the
+requested tolerance (times a small safety factor, since the stopping test is
+an estimate).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import lattice_inputs as LI
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def osa():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_0710_0341_amd as osa_mod
+    osa_mod.lib()
+    return osa_mod
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ------------------------------------------------------------------ stencil
+STENCIL_CASES = [
+    ((2, 2, 2, 2), "haar", 0.3, False, False),
+    ((4, 4, 4, 4), "haar", 0.3, False, False),
+    ((3, 4, 5, 6), "haar", 0.5, True, False),      # ragged: no padding-free tile
+    ((2, 3, 2, 5), "disordered", -0.2, False, False),
+    ((4, 4, 4, 4), "haar", 0.3, False, True),       # FP32-stored links
+    ((6, 2, 3, 4), "haar", 0.1, True, True),
+]
+
+
+@pytest.mark.parametrize("dims,kind,mu,ap,fp32", STENCIL_CASES)
+def test_stencil_matches_oracle(osa, dims, kind, mu, ap, fp32):
+    say(f"stencil dims={dims} kind={kind} mu={mu} ap={ap} fp32={fp32}")
+    links = LI.make_links(dims, kind, eps=0.6, cfg=9, inst=1)
+    if fp32:
+        links = LI.round_links_fp32(links)
+    tl = dev(links.astype(np.complex64) if fp32 else links)
+    b = np.stack([LI.gaussian_source(dims, cfg=9, inst=i) for i in range(3)])
+    ctx = osa.Context(tl, dims, mu, -1.5, antiperiodic_t=ap)
+    y = host(ctx.apply_hw(dev(b)))
+    h = O.hermitian_wilson_sparse(links, dims, mu, -1.5, ap)
+    for i in range(3):
+        assert rel(y[i], h @ b[i]) < 1e-14
+    ctx.close()
+
+
+def test_stencil_free_field_8(osa):
+    """At 8^4 (the headline lattice) against the momentum-space closed form."""
+    dims = (8, 8, 8, 8)
+    say("stencil free field 8^4")
+    u = LI.make_links(dims, "unit")
+    b = LI.gaussian_source(dims, cfg=9, inst=5)
+    ctx = osa.Context(dev(u), dims, 0.5, -1.5)
+    y = host(ctx.apply_hw(dev(b)))
+    assert rel(y, O.free_field_h_apply(dims, 0.5, -1.5, b)) < 1e-13
+    ctx.close()
+
+
+# ---------------------------------------------------------------- small sign
+@pytest.mark.parametrize("k", [1, 7, 64, 130, 257])
+def test_small_sign_matches_oracle(osa, k):
+    say(f"small sign k={k}")
+    dims = (3, 3, 3, 3)
+    links = LI.make_links(dims, "haar", cfg=9, inst=2)
+    h = O.hermitian_wilson_sparse(links, dims, 0.3, -1.5)
+    b = LI.gaussian_source(dims, cfg=9, inst=2)
+    _, hm, _, _ = O.arnoldi_cgs2(lambda x: h @ x, b, k)
+    hk = hm[:k, :k]
+    s, its = osa.small_sign(dev(hk))
+    ref = O.small_sign_e1(hk, "newton")
+    assert rel(host(s), ref) < 1e-12
+    assert rel(ref, O.small_sign_e1(hk, "eig")) < 1e-9
+
+
+def test_small_sign_dense_nonhessenberg(osa):
+    """A dense matrix with a known spectrum off the imaginary axis."""
+    rng = np.random.default_rng(3)
+    n = 50
+    lam = np.concatenate([rng.uniform(0.1, 2, 25), -rng.uniform(0.1, 2, 25)]) + 0.3j * rng.standard_normal(50)
+    q = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    a = q @ np.diag(lam) @ np.linalg.inv(q)
+    s, _ = osa.small_sign(dev(a))
+    ref = (q @ np.diag(np.sign(lam.real)) @ np.linalg.inv(q))[:, 0]
+    assert rel(host(s), ref) < 1e-9
+
+
+# ------------------------------------------------- full method, fixed k
+def _fixed_k_case(osa, dims, kind, mu, m, k, inst, reproject=True, eps=0.6):
+    links = LI.make_links(dims, kind, eps=eps, cfg=9, inst=inst)
+    b = LI.gaussian_source(dims, cfg=9, inst=inst)
+    h = O.hermitian_wilson_sparse(links, dims, mu, -1.5)
+    ctx = osa.Context(dev(links), dims, mu, -1.5, k_max=k, check_every=-1,
+                      no_reproject=not reproject)
+    defl = None
+    if m:
+        r, l, lam = O.critical_dense(h.toarray(), m)
+        defl = O.Deflation(r, l, lam)
+        ctx.set_deflation(dev(r.T.copy()), dev(l.T.copy()), lam)
+    y, infos, st = ctx.apply(dev(b), tol=1e-30)
+    yo, info = O.lr_arnoldi_sign(lambda x: h @ x, b, defl, k=k, reproject=reproject)
+    ctx.close()
+    return host(y), yo, infos[0], info
+
+
+@pytest.mark.parametrize("dims,kind,mu,m,k", [
+    ((2, 2, 2, 2), "haar", 0.3, 0, 40),
+    ((3, 4, 3, 4), "disordered", 0.5, 0, 90),
+    ((3, 4, 3, 4), "disordered", 0.5, 8, 90),
+    ((4, 4, 4, 4), "haar", 0.3, 10, 150),
+])
+def test_fixed_k_matches_oracle(osa, dims, kind, mu, m, k):
+    say(f"fixed k dims={dims} m={m} k={k}")
+    y, yo, info, oinfo = _fixed_k_case(osa, dims, kind, mu, m, k, inst=3)
+    assert info["k_used"] == oinfo["k_used"] == k
+    assert rel(y, yo) < 1e-10
+
+
+def test_fixed_k_without_reprojection(osa):
+    say("fixed k, re-projection off")
+    y, yo, info, _ = _fixed_k_case(osa, (3, 4, 3, 4), "disordered", 0.5, 8, 60, inst=4,
+                                   reproject=False)
+    assert rel(y, yo) < 1e-10
+
+
+# --------------------------------------------------- converged vs exact
+@pytest.fixture(scope="module")
+def haar4_dense():
+    """The small workload: 4^4 Haar links, m_w = -1.5, mu = 0.3, Gaussian source."""
+    w = LI.WORKLOADS[0]
+    dims = w["dims"]
+    links = LI.make_links(dims, "haar", cfg=0, inst=0)
+    b = LI.gaussian_source(dims, cfg=0, inst=0)
+    h = O.hermitian_wilson_dense(links, dims, w["mu"], w["m_w"])
+    say("dense oracle 4^4 (route E) ...")
+    y = O.sign_eig_apply(h, b)
+    return dims, links, b, h, y
+
+
+def test_converged_matches_dense_haar4(osa, haar4_dense):
+    dims, links, b, h, yref = haar4_dense
+    say("haar4 full method: GPU deflation + adaptive Krylov")
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=500, check_every=25)
+    dinfo = ctx.deflate(10)
+    assert dinfo["max_eig_resid"] < 1e-10
+    y, infos, st = ctx.apply(dev(b), tol=1e-11)
+    err = rel(host(y), yref)
+    say(f"  k_used={infos[0]['k_used']} est={infos[0]['resid_est']:.2e} err={err:.2e}")
+    assert st == osa.OSA_OK
+    assert err < 1e-10
+    # the configured tolerance 1e-8 with k_max = 300 (the small workload as specified)
+    ctx.set_opts(k_max=300, check_every=25)
+    y8, infos8, st8 = ctx.apply(dev(b), tol=1e-8)
+    assert rel(host(y8), yref) < 1e-7
+    ctx.close()
+
+
+def test_deflation_matches_oracle_eigenpairs(osa, haar4_dense):
+    dims, links, b, h, _ = haar4_dense
+    say("haar4 eigenpairs vs dense oracle")
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5)
+    ctx.deflate(10)
+    R, L, lam = ctx.get_deflation()
+    R, L = host(R).T, host(L).T
+    r0, l0, lam0 = O.critical_dense(h, 10)
+    assert np.abs(np.sort_complex(lam) - np.sort_complex(lam0)).max() < 1e-10
+    # the oblique projector R G^{-1} L^dag is canonical
+    p_gpu = O.Deflation(R, L, lam)
+    p_ref = O.Deflation(r0, l0, lam0)
+    assert rel(p_gpu.r @ p_gpu.coeffs(b), p_ref.r @ p_ref.coeffs(b)) < 1e-9
+    assert max(O.eig_residuals(h, R, L, lam)) < 1e-10
+    ctx.close()
+
+
+def test_one_shot_entry_point(osa):
+    dims = (2, 2, 3, 4)
+    links = LI.make_links(dims, "haar", cfg=9, inst=6)
+    b = LI.gaussian_source(dims, cfg=9, inst=6)
+    say("one-shot overlap_sign_apply")
+    y, est, st = osa.overlap_sign_apply(dev(links), dims, 0.3, -1.5, dev(b), 1e-10, 6)
+    h = O.hermitian_wilson_dense(links, dims, 0.3, -1.5)
+    assert rel(host(y), O.sign_eig_apply(h, b)) < 1e-9
+
+
+# --------------------------------------------------------------- edge cases
+def test_breakdown_plane_wave_is_exact(osa):
+    dims = (2, 2, 2, 4)
+    say("breakdown: free plane wave")
+    u = LI.make_links(dims, "unit")
+    t = np.arange(dims[3])
+    wave = np.exp(2j * np.pi * t / dims[3])[:, None, None, None, None, None] * np.ones((1, 2, 2, 2, 4, 3))
+    chi = np.zeros((4, 3), dtype=complex)
+    chi[0, 0] = 1.0
+    b = (wave * chi).reshape(-1)
+    b /= np.linalg.norm(b)
+    ctx = osa.Context(dev(u), dims, 0.3, -1.5, k_max=50, check_every=5)
+    y, infos, st = ctx.apply(dev(b), tol=1e-12)
+    assert infos[0]["breakdown"] == 1 and infos[0]["k_used"] <= 4
+    assert rel(host(y), O.free_field_sign_apply(dims, 0.3, -1.5, b)) < 1e-12
+    ctx.close()
+
+
+def test_not_converged_status_and_nonfinite(osa):
+    dims = (3, 3, 3, 3)
+    links = LI.make_links(dims, "haar", cfg=9, inst=7)
+    b = LI.gaussian_source(dims, cfg=9, inst=7)
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=20, check_every=10)
+    say("not converged at k_max = 20")
+    y, infos, st = ctx.apply(dev(b), tol=1e-14)
+    assert st == osa.OSA_NOT_CONVERGED and infos[0]["k_used"] == 20
+    say("NaN source")
+    bad = b.copy()
+    bad[5] = np.nan
+    with pytest.raises(osa.OsaError) as e:
+        ctx.apply(dev(bad), tol=1e-8)
+    assert e.value.status == -4
+    ctx.close()
+
+
+def test_source_inside_deflation_space(osa):
+    """b in span(R): x_ominus = 0 and the result is the exact first term of Eq. 21."""
+    dims = (2, 2, 3, 3)
+    links = LI.make_links(dims, "haar", cfg=9, inst=8)
+    h = O.hermitian_wilson_dense(links, dims, 0.3, -1.5)
+    r, l, lam = O.critical_dense(h, 6)
+    b = r @ (np.arange(6) + 1.0)
+    b /= np.linalg.norm(b)
+    say("source in span(R)")
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=30, check_every=10)
+    ctx.set_deflation(dev(r.T.copy()), dev(l.T.copy()), lam)
+    y, infos, st = ctx.apply(dev(b), tol=1e-10)
+    assert infos[0]["k_used"] == 0
+    assert rel(host(y), O.sign_eig_apply(h, b)) < 1e-11
+    ctx.close()
+
+
+def test_multi_rhs_and_determinism(osa):
+    dims = (3, 3, 3, 4)
+    links = LI.make_links(dims, "disordered", eps=0.6, cfg=9, inst=9)
+    B = np.stack([LI.gaussian_source(dims, cfg=9, inst=10 + i) for i in range(3)])
+    say("multi-rhs + determinism")
+    ctx = osa.Context(dev(links), dims, 0.2, -1.5, k_max=400, check_every=20)
+    ctx.deflate(8)
+    Y1, inf1, st1 = ctx.apply(dev(B), tol=1e-10)
+    assert st1 == osa.OSA_OK
+    Y2, inf2, _ = ctx.apply(dev(B), tol=1e-10)
+    Y1, Y2 = host(Y1), host(Y2)
+    assert np.array_equal(Y1, Y2)
+    for i in range(3):
+        yi, _, _ = ctx.apply(dev(B[i]), tol=1e-10)
+        assert np.array_equal(host(yi), Y1[i])
+    h = O.hermitian_wilson_dense(links, dims, 0.2, -1.5)
+    for i in range(3):
+        assert rel(Y1[i], O.sign_eig_apply(h, B[i])) < 1e-9
+    ctx.close()
