@@ -177,6 +177,28 @@ OSA_API osa_status osa_apply_hw(osa_ctx* ctx, int32_t nrhs, const void* X, void*
  * the small-sign kernel for checks; stream-ordered on `stream`. */
 OSA_API osa_status osa_small_sign(int32_t k, const void* A, void* s, int32_t* iters, void* stream);
 
+/* Replace the gauge links of an existing context (same lattice, same link
+ * precision, device pointer in the boundary layout).  Reuses all workspace;
+ * the deflation data is dropped (m becomes 0) because it belongs to the old
+ * operator. */
+OSA_API osa_status osa_set_links(osa_ctx* ctx, const void* links);
+
+/* Kernel timing with HIP events on the context's stream, for measurement.
+ * Classes: 0 Gram-Schmidt / projection dot products (V^H w), 1 Gram-Schmidt
+ * updates (w - V h), 2 stencil H_w(mu), 3 one small-matrix inversion of the
+ * Newton iteration, 4 small Schur decomposition of an eigensolver restart,
+ * 5 whole eigensolver restart (host wall clock, including synchronisation).
+ * bytes[] counts the algorithmic HBM bytes of each launch (vectors read and
+ * written once).  Enabling resets the counters; the events add a few
+ * microseconds of overhead per bracketed launch. */
+typedef struct {
+    double ms[6];
+    double bytes[6];
+    int64_t launches[6];
+} osa_profile;
+OSA_API osa_status osa_profile_enable(osa_ctx* ctx, int32_t enable);
+OSA_API osa_status osa_profile_read(osa_ctx* ctx, osa_profile* out);
+
 OSA_API void osa_destroy(osa_ctx* ctx);
 OSA_API const char* osa_status_string(osa_status s);
 OSA_API const char* osa_version(void);

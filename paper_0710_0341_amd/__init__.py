@@ -31,7 +31,8 @@ FP64, FP32 = 0, 1
 
 EXPORTS = ["overlap_sign_apply", "osa_create", "osa_deflate", "osa_set_deflation",
            "osa_get_deflation", "osa_set_active_deflation", "osa_apply", "osa_batch_apply",
-           "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_destroy", "osa_status_string",
+           "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_set_links",
+           "osa_profile_enable", "osa_profile_read", "osa_destroy", "osa_status_string",
            "osa_version"]
 
 
@@ -56,6 +57,18 @@ class Info(ctypes.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 6), ("bytes", ctypes.c_double * 6),
+                ("launches", ctypes.c_int64 * 6)]
+
+    CLASSES = ("cgs_dot", "cgs_update", "stencil", "small_inverse", "small_schur",
+               "eig_restart")
+
+    def as_dict(self):
+        return {name: dict(ms=self.ms[i], bytes=self.bytes[i], launches=self.launches[i])
+                for i, name in enumerate(self.CLASSES)}
 
 
 class OsaError(RuntimeError):
@@ -90,6 +103,9 @@ def lib() -> ctypes.CDLL:
     L.osa_set_opts.argtypes = [vp, ctypes.POINTER(Opts)]
     L.osa_apply_hw.argtypes = [vp, i32, vp, vp]
     L.osa_small_sign.argtypes = [i32, vp, vp, ctypes.POINTER(i32), vp]
+    L.osa_set_links.argtypes = [vp, vp]
+    L.osa_profile_enable.argtypes = [vp, i32]
+    L.osa_profile_read.argtypes = [vp, ctypes.POINTER(Profile)]
     L.osa_destroy.argtypes = [vp]
     L.osa_destroy.restype = None
     L.osa_status_string.argtypes = [i32]
@@ -256,6 +272,19 @@ class Context:
         st = lib().osa_apply(self._h, nrhs, bp, ctypes.c_void_p(Y.data_ptr()), float(tol), infos)
         _check(st, "osa_apply")
         return Y, [i.as_dict() for i in infos], st
+
+    def set_links(self, links):
+        """Re-ingest new links (same lattice and precision); drops the deflation data."""
+        lp = _dev_ptr(links, links.dtype, "links")
+        _check(lib().osa_set_links(self._h, lp), "osa_set_links", False)
+
+    def profile(self, enable=True):
+        _check(lib().osa_profile_enable(self._h, int(bool(enable))), "osa_profile_enable", False)
+
+    def profile_read(self):
+        out = Profile()
+        _check(lib().osa_profile_read(self._h, ctypes.byref(out)), "osa_profile_read", False)
+        return out.as_dict()
 
     def apply_hw(self, X):
         """Y = H_w(mu) X (stencil only)."""

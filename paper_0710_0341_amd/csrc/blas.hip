@@ -109,52 +109,58 @@ void launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bo
 }
 
 // ---------------------------------------------------------------- reduce
-// One block.  val[c] = sum_q partial[c*nchunks + q]; then optionally val = M val.
-// mode 0: out = val; mode 1: out += val.  accum (nullable) += val.
-__global__ __launch_bounds__(1024) void k_reduce_partial(const cd* __restrict__ partial,
-                                                         int nchunks, int ncols, cd* out,
-                                                         int mode, const cd* __restrict__ M,
-                                                         cd* tmp, double* hfro2) {
-    __shared__ double sred[16];
-    double loc = 0.0;
-    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
-        cd s = mk(0.0, 0.0);
-        for (int q = 0; q < nchunks; ++q) s = cadd(s, partial[(int64_t)c * nchunks + q]);
-        if (M) tmp[c] = s;
-        else {
-            out[c] = (mode == 1) ? cadd(out[c], s) : s;
-            loc += cabs2(s);
-        }
+// val[c] = sum_q partial[c*nchunks + q], one wavefront per column (lane q holds
+// chunk q, q + 64, ...; fixed shuffle tree, so the order never changes).
+// out[c] = val (set); accum[c] += val when accum != nullptr.
+__global__ __launch_bounds__(256) void k_reduce_cols(const cd* __restrict__ partial, int nchunks,
+                                                     int ncols, cd* __restrict__ out,
+                                                     cd* __restrict__ accum) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= ncols) return;
+    double re = 0, im = 0;
+    for (int q = lane; q < nchunks; q += 64) {
+        const cd v = partial[(int64_t)c * nchunks + q];
+        re += v.x;
+        im += v.y;
     }
-    if (M) {
-        __syncthreads();
-        __threadfence_block();
-        for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
-            cd s = mk(0.0, 0.0);
-            for (int d = 0; d < ncols; ++d) cfma(s, M[c + (int64_t)d * ncols], tmp[d]);
-            out[c] = (mode == 1) ? cadd(out[c], s) : s;
-            loc += cabs2(s);
-        }
-    }
-    if (hfro2) {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        double s = wave_sum(loc);
-        if (lane == 0) sred[wave] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0;
-            for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) t += sred[wv];
-            *hfro2 += t;
-        }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) {
+        out[c] = mk(re, im);
+        if (accum) accum[c] = mk(accum[c].x + re, accum[c].y + im);
     }
 }
 
-void launch_reduce_partial(const cd* partial, int nchunks, int ncols, cd* out, int mode,
-                           const cd* M, cd* tmp, double* hfro2, hipStream_t st) {
+// One block: val = sum over chunks, then out = M val (M: ncols x ncols, used for
+// G^{-1} L^dag w with the small m x m matrix G^{-1}).
+__global__ __launch_bounds__(1024) void k_reduce_apply(const cd* __restrict__ partial, int nchunks,
+                                                       int ncols, cd* out,
+                                                       const cd* __restrict__ M, cd* tmp) {
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+        cd s = mk(0.0, 0.0);
+        for (int q = 0; q < nchunks; ++q) s = cadd(s, partial[(int64_t)c * nchunks + q]);
+        tmp[c] = s;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+        cd s = mk(0.0, 0.0);
+        for (int d = 0; d < ncols; ++d) cfma(s, M[c + (int64_t)d * ncols], tmp[d]);
+        out[c] = s;
+    }
+}
+
+void launch_reduce_partial(const cd* partial, int nchunks, int ncols, cd* out, cd* accum,
+                           const cd* M, cd* tmp, hipStream_t st) {
     if (ncols <= 0) return;
-    int threads = ncols >= 1024 ? 1024 : (int)ceil_div(ncols, 64) * 64;
-    hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(threads), 0, st, partial, nchunks, ncols,
-                       out, mode, M, tmp, hfro2);
+    if (M) {
+        int threads = ncols >= 1024 ? 1024 : (int)ceil_div(ncols, 64) * 64;
+        hipLaunchKernelGGL(k_reduce_apply, dim3(1), dim3(threads), 0, st, partial, nchunks, ncols,
+                           out, M, tmp);
+    } else {
+        hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)ceil_div(ncols, 4)), dim3(256), 0, st,
+                           partial, nchunks, ncols, out, accum);
+    }
     OSA_LAUNCH_CHECK();
 }
 
@@ -328,9 +334,25 @@ void launch_norm_partial(const void* w, bool fp32, const TsPlan& p, double* norm
 
 // single block: hsub = sqrt(sum normp) (+ breakdown test)
 __global__ __launch_bounds__(1024) void k_norm_finish(const double* __restrict__ normp, int nb,
-                                                      cd* hsub, const double* hfro2, double rel,
-                                                      int* flag, int step) {
+                                                      cd* hsub, double* hfro2, double rel,
+                                                      int* flag, int step,
+                                                      const cd* __restrict__ hcol, int hlen) {
     __shared__ double sred[16];
+    __shared__ double shcol;
+    if (hcol && hfro2) {
+        double a = 0;
+        for (int i = threadIdx.x; i < hlen; i += blockDim.x) a += cabs2(hcol[i]);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        a = wave_sum(a);
+        if (lane == 0) sred[wave] = a;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sred[w];
+            shcol = t;
+        }
+        __syncthreads();
+    }
     double loc = 0;
     // fixed order: contiguous slices per thread, then a fixed tree
     const int per = (nb + blockDim.x - 1) / blockDim.x;
@@ -344,6 +366,7 @@ __global__ __launch_bounds__(1024) void k_norm_finish(const double* __restrict__
         double t = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sred[w];
         double h = sqrt(t);
+        if (hcol && hfro2) *hfro2 += shcol;
         double scale = hfro2 ? sqrt(*hfro2 + t) : 0.0;
         int bd = (flag && h <= rel * scale) ? 1 : 0;
         if (!(h == h) || h > 1e300) bd = 2;   // non-finite
@@ -367,11 +390,11 @@ __global__ __launch_bounds__(kBlock) void k_scale_by(const T* __restrict__ w, T*
 }
 
 void launch_normalize(const void* w, void* v, bool fp32, const TsPlan& p, const double* normp,
-                      cd* hsub, const double* hfro2, double rel, int* flag, int step,
-                      hipStream_t st) {
+                      cd* hsub, double* hfro2, double rel, int* flag, int step,
+                      const cd* hcol, int hlen, hipStream_t st) {
     const int nb = (int)ceil_div(p.n, kBlock);
     hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(256), 0, st, normp, nb, hsub, hfro2, rel, flag,
-                       step);
+                       step, hcol, hlen);
     if (!v) { OSA_LAUNCH_CHECK(); return; }
     const int rb = (int)ceil_div(p.n, kBlock);
     if (fp32)

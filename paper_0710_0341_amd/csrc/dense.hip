@@ -317,96 +317,105 @@ __device__ __forceinline__ double sort_key(cd v, int mode) {
 
 // Apply the 2x2 unitary Q (columns q0 = (a, b), q1 = (-conj b, conj a)) as a
 // similarity on rows/cols (k, k+1): T <- Q^H T Q, Z <- Z Q.
-__device__ void apply_pair(cd* T, cd* Z, int p, int k, cd a, cd b, int col0, int row1) {
+// zero_col >= 0: the left update annihilates T[k+1, zero_col]; store an exact 0.
+__device__ void apply_pair(cd* T, cd* Z, int p, int ld, int k, cd a, cd b, int col0, int row1,
+                           int zero_col = -1) {
     const int l = threadIdx.x;
     // left: rows k, k+1 over columns >= col0
     for (int c = col0 + l; c < p; c += 64) {
-        cd x = T[k + c * p], y = T[k + 1 + c * p];
+        cd x = T[k + c * ld], y = T[k + 1 + c * ld];
         // Q^H [x; y] = [conj(a) x + conj(b) y ; -b x + a y]
         cd nx = cadd(cmulc(a, x), cmulc(b, y));
-        cd ny = csub(cmul(a, y), cmul(b, x));
-        T[k + c * p] = nx;
-        T[k + 1 + c * p] = ny;
+        cd ny = (c == zero_col) ? mk(0.0, 0.0) : csub(cmul(a, y), cmul(b, x));
+        T[k + c * ld] = nx;
+        T[k + 1 + c * ld] = ny;
     }
     __syncthreads();
     // right: columns k, k+1 over rows <= row1;  [x, y] Q = [a x + b y, -conj(b) x + conj(a) y]
     for (int r = l; r <= row1 && r < p; r += 64) {
-        cd x = T[r + k * p], y = T[r + (k + 1) * p];
-        T[r + k * p] = cadd(cmul(a, x), cmul(b, y));
-        T[r + (k + 1) * p] = csub(cmulc(a, y), cmulc(b, x));
+        cd x = T[r + k * ld], y = T[r + (k + 1) * ld];
+        T[r + k * ld] = cadd(cmul(a, x), cmul(b, y));
+        T[r + (k + 1) * ld] = csub(cmulc(a, y), cmulc(b, x));
     }
     for (int r = l; r < p; r += 64) {
-        cd x = Z[r + k * p], y = Z[r + (k + 1) * p];
-        Z[r + k * p] = cadd(cmul(a, x), cmul(b, y));
-        Z[r + (k + 1) * p] = csub(cmulc(a, y), cmulc(b, x));
+        cd x = Z[r + k * ld], y = Z[r + (k + 1) * ld];
+        Z[r + k * ld] = cadd(cmul(a, x), cmul(b, y));
+        Z[r + (k + 1) * ld] = csub(cmulc(a, y), cmulc(b, x));
     }
     __syncthreads();
 }
 
 __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, int p, cd* Tout,
                                                    cd* Zout, cd* wout, int mode, int* info) {
+    // T and Z in LDS, column-major with the odd leading dimension ld = p + 1 so
+    // that row sweeps (stride ld) and column sweeps (stride 1) are both free of
+    // bank conflicts.
     extern __shared__ cd lds[];
+    const int ld = p + 1;
     cd* T = lds;
-    cd* Z = lds + p * p;
+    cd* Z = lds + (size_t)p * ld;
     __shared__ cd hv[kSchurMax];
+    __shared__ double sanorm;
     const int l = threadIdx.x;
+#define TT(i, j) T[(i) + (j) * ld]
+#define ZZ(i, j) Z[(i) + (j) * ld]
+    double amax = 0;
     for (int e = l; e < p * p; e += 64) {
-        T[e] = A[e];
-        Z[e] = mk((e % p) == (e / p) ? 1.0 : 0.0, 0.0);
+        const int i = e % p, j = e / p;
+        const cd v = A[e];
+        TT(i, j) = v;
+        ZZ(i, j) = mk(i == j ? 1.0 : 0.0, 0.0);
+        amax = fmax(amax, cabsd(v));
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    if (l == 0) sanorm = amax;
     __syncthreads();
-    double anorm = 0;
-    for (int e = 0; e < p * p; ++e) anorm = fmax(anorm, cabsd(T[e]));
-    // ---- Hessenberg reduction
+    const double anorm = sanorm;
+    // ---- Hessenberg reduction (Householder)
     for (int j = 0; j + 2 < p; ++j) {
         const int L = p - j - 1;
-        double xn2 = 0;
-        for (int i = 0; i < L; ++i) xn2 += cabs2(T[j + 1 + i + j * p]);
+        double xp = 0;
+        for (int i = l; i < L; i += 64) xp += cabs2(TT(j + 1 + i, j));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) xp += __shfl_xor(xp, off, 64);
+        const double xn2 = xp;
         const double xn = sqrt(xn2);
-        const cd x0 = T[j + 1 + j * p];
-        double tail = xn2 - cabs2(x0);
+        const cd x0 = TT(j + 1, j);
+        const double tail = xn2 - cabs2(x0);
         if (xn == 0.0 || tail <= 1e-300) { __syncthreads(); continue; }
         const double ax0 = cabsd(x0);
         const cd ph = ax0 > 0 ? cscale(x0, 1.0 / ax0) : mk(1.0, 0.0);
         const cd alpha = cscale(ph, -xn);           // -e^{i arg x0} |x|
-        // v = x - alpha e1, tau = 2 / |v|^2
-        for (int i = l; i < L; i += 64) hv[i] = (i == 0) ? csub(x0, alpha) : T[j + 1 + i + j * p];
-        __syncthreads();
-        double vn2 = 0;
-        for (int i = 0; i < L; ++i) vn2 += cabs2(hv[i]);
+        // v = x - alpha e1, |v|^2 = |x|^2 - 2 Re(conj(alpha) x0) + |alpha|^2, tau = 2 / |v|^2
+        for (int i = l; i < L; i += 64) hv[i] = (i == 0) ? csub(x0, alpha) : TT(j + 1 + i, j);
+        const double vn2 = 2.0 * xn2 + 2.0 * xn * ax0;
         const double tau = 2.0 / vn2;
-        // left: T[j+1:, c] -= tau v (v^H T[j+1:, c]),  c >= j
+        __syncthreads();
+        // left: T[j+1:, c] -= tau v (v^H T[j+1:, c]),  c >= j   (one column per lane)
         for (int c = j + l; c < p; c += 64) {
-            cd s = mk(0.0, 0.0);
-            for (int i = 0; i < L; ++i) cfmac(s, hv[i], T[j + 1 + i + c * p]);
-            s = cscale(s, tau);
-            for (int i = 0; i < L; ++i) {
-                cd& tv = T[j + 1 + i + c * p];
-                tv = csub(tv, cmul(hv[i], s));
-            }
+            cd sacc = mk(0.0, 0.0);
+            for (int i = 0; i < L; ++i) cfmac(sacc, hv[i], TT(j + 1 + i, c));
+            sacc = cscale(sacc, tau);
+            for (int i = 0; i < L; ++i) TT(j + 1 + i, c) = csub(TT(j + 1 + i, c), cmul(hv[i], sacc));
         }
         __syncthreads();
         // right: T[r, j+1:] -= tau (T[r, j+1:] v) v^H, all rows; same for Z
         for (int r = l; r < p; r += 64) {
-            cd s = mk(0.0, 0.0), sz = mk(0.0, 0.0);
+            cd sacc = mk(0.0, 0.0), sz = mk(0.0, 0.0);
             for (int i = 0; i < L; ++i) {
-                cfma(s, T[r + (j + 1 + i) * p], hv[i]);
-                cfma(sz, Z[r + (j + 1 + i) * p], hv[i]);
+                cfma(sacc, TT(r, j + 1 + i), hv[i]);
+                cfma(sz, ZZ(r, j + 1 + i), hv[i]);
             }
-            s = cscale(s, tau);
+            sacc = cscale(sacc, tau);
             sz = cscale(sz, tau);
             for (int i = 0; i < L; ++i) {
-                cd& tv = T[r + (j + 1 + i) * p];
-                tv = csub(tv, cmul(s, cconj(hv[i])));
-                cd& zv = Z[r + (j + 1 + i) * p];
-                zv = csub(zv, cmul(sz, cconj(hv[i])));
+                TT(r, j + 1 + i) = csub(TT(r, j + 1 + i), cmul(sacc, cconj(hv[i])));
+                ZZ(r, j + 1 + i) = csub(ZZ(r, j + 1 + i), cmul(sz, cconj(hv[i])));
             }
         }
         __syncthreads();
-        if (l == 0) {
-            T[j + 1 + j * p] = alpha;
-            for (int i = 2; i <= L; ++i) T[j + i + j * p] = mk(0.0, 0.0);
-        }
+        for (int i = l; i < L; i += 64) TT(j + 1 + i, j) = (i == 0) ? alpha : mk(0.0, 0.0);
         __syncthreads();
     }
     // ---- shifted QR
@@ -417,17 +426,20 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
     const int maxtotal = 60 * p;
     bool fail = false;
     while (hi > 0) {
-        int lo = hi;
-        while (lo > 0) {
-            const double sub = cabsd(T[lo + (lo - 1) * p]);
-            double tst = cabsd(T[lo - 1 + (lo - 1) * p]) + cabsd(T[lo + lo * p]);
+        // lo = largest l in [1, hi] with a negligible subdiagonal T[l, l-1], else 0;
+        // lane l tests entry l, a ballot picks the highest one.
+        bool neg = false;
+        if (l >= 1 && l <= hi) {
+            const double sub = cabsd(TT(l, l - 1));
+            double tst = cabsd(TT(l - 1, l - 1)) + cabsd(TT(l, l));
             if (tst == 0.0) tst = anorm;
-            if (sub <= fmax(ulp * tst, smlnum)) break;
-            --lo;
+            neg = sub <= fmax(ulp * tst, smlnum);
         }
+        const unsigned long long mask = __ballot(neg);
+        const int lo = mask ? 63 - __clzll(mask) : 0;
         if (lo > 0) {
             __syncthreads();
-            if (l == 0) T[lo + (lo - 1) * p] = mk(0.0, 0.0);
+            if (l == 0) TT(lo, lo - 1) = mk(0.0, 0.0);
             __syncthreads();
         }
         if (lo == hi) { --hi; its = 0; continue; }
@@ -436,16 +448,14 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
         // Wilkinson shift from the trailing 2x2 of the active block
         cd sigma;
         {
-            const cd a = T[hi - 1 + (hi - 1) * p], b = T[hi - 1 + hi * p];
-            const cd c = T[hi + (hi - 1) * p], d = T[hi + hi * p];
+            const cd a = TT(hi - 1, hi - 1), b = TT(hi - 1, hi);
+            const cd c = TT(hi, hi - 1), d = TT(hi, hi);
             if (its % 10 == 0) {
-                // exceptional shift
-                sigma = cadd(d, mk(0.75 * cabsd(c), 0.0));
+                sigma = cadd(d, mk(0.75 * cabsd(c), 0.0));   // exceptional shift
             } else {
                 const cd tr2 = cscale(cadd(a, d), 0.5);
                 const cd det = csub(cmul(a, d), cmul(b, c));
                 const cd disc = csub(cmul(tr2, tr2), det);
-                // principal sqrt
                 const double r = cabsd(disc);
                 double sr = sqrt(0.5 * (r + disc.x));
                 double si = sqrt(fmax(0.0, 0.5 * (r - disc.x)));
@@ -459,55 +469,50 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
         for (int k = lo; k < hi; ++k) {
             cd f, g;
             if (k == lo) {
-                f = csub(T[lo + lo * p], sigma);
-                g = T[lo + 1 + lo * p];
+                f = csub(TT(lo, lo), sigma);
+                g = TT(lo + 1, lo);
             } else {
-                f = T[k + (k - 1) * p];
-                g = T[k + 1 + (k - 1) * p];
+                f = TT(k, k - 1);
+                g = TT(k + 1, k - 1);
             }
             // unitary with first column (f, g)/|(f, g)|: Q^H [f; g] = [|.|; 0]
             const double nf = sqrt(cabs2(f) + cabs2(g));
             cd a, b;
             if (nf == 0.0) { a = mk(1.0, 0.0); b = mk(0.0, 0.0); }
-            else { a = cscale(f, 1.0 / nf); b = cscale(g, 1.0 / nf); }
+            else { const double inf = 1.0 / nf; a = cscale(f, inf); b = cscale(g, inf); }
             const int col0 = (k == lo) ? lo : k - 1;
             const int row1 = (k + 2 < hi) ? k + 2 : hi;
-            // rows/cols above lo are part of the full Schur form as well
-            apply_pair(T, Z, p, k, a, b, col0, row1);
-            if (k > lo) {
-                if (l == 0) T[k + 1 + (k - 1) * p] = mk(0.0, 0.0);
-                __syncthreads();
-            }
+            apply_pair(T, Z, p, ld, k, a, b, col0, row1, (k > lo) ? k - 1 : -1);
         }
     }
-    // the right updates above touched rows <= row1 only; rows < lo belong to
-    // the columns of already-converged blocks and were included since row1
-    // counts from row 0.
     // ---- reorder the diagonal (insertion sort by adjacent swaps)
     for (int i = 1; i < p && !fail; ++i) {
         for (int j = i; j > 0; --j) {
-            const cd t11 = T[j - 1 + (j - 1) * p], t22 = T[j + j * p];
+            const cd t11 = TT(j - 1, j - 1), t22 = TT(j, j);
             if (!(sort_key(t22, mode) < sort_key(t11, mode))) break;
-            const cd t12 = T[j - 1 + j * p];
+            const cd t12 = TT(j - 1, j);
             const cd x1 = t12, x2 = csub(t22, t11);
             const double nx = sqrt(cabs2(x1) + cabs2(x2));
             if (nx == 0.0) break;
             const cd a = cscale(x1, 1.0 / nx), b = cscale(x2, 1.0 / nx);
-            apply_pair(T, Z, p, j - 1, a, b, j - 1, j);
+            apply_pair(T, Z, p, ld, j - 1, a, b, j - 1, j);
             if (l == 0) {
-                T[j + (j - 1) * p] = mk(0.0, 0.0);
-                T[j - 1 + (j - 1) * p] = t22;
-                T[j + j * p] = t11;
+                TT(j, j - 1) = mk(0.0, 0.0);   // touched by both sides: set after them
+                TT(j - 1, j - 1) = t22;
+                TT(j, j) = t11;
             }
             __syncthreads();
         }
     }
     for (int e = l; e < p * p; e += 64) {
-        Tout[e] = T[e];
-        Zout[e] = Z[e];
+        const int i = e % p, j = e / p;
+        Tout[e] = TT(i, j);
+        Zout[e] = ZZ(i, j);
     }
-    for (int i = l; i < p; i += 64) wout[i] = T[i + i * p];
+    for (int i = l; i < p; i += 64) wout[i] = TT(i, i);
     if (l == 0) *info = fail ? -1 : total;
+#undef TT
+#undef ZZ
 }
 
 size_t schur_ws_bytes(int p) { return 0; }
@@ -515,12 +520,12 @@ size_t schur_ws_bytes(int p) { return 0; }
 void small_schur(const cd* A, int p, cd* T, cd* Z, cd* w, int mode, int* info, void*,
                  hipStream_t st) {
     if (p > kSchurMax || p < 1) throw HipError{hipErrorInvalidValue, "small_schur: p out of range"};
-    const size_t lds = (size_t)2 * p * p * sizeof(cd);
+    const size_t lds = (size_t)2 * p * (p + 1) * sizeof(cd);
     static bool attr_set = false;
     if (!attr_set) {
         OSA_HIP(hipFuncSetAttribute((const void*)k_small_schur,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(2 * kSchurMax * kSchurMax * sizeof(cd))));
+                                    (int)(2 * kSchurMax * (kSchurMax + 1) * sizeof(cd))));
         attr_set = true;
     }
     hipLaunchKernelGGL(k_small_schur, dim3(1), dim3(64), lds, st, A, p, T, Z, w, mode, info);
@@ -534,29 +539,33 @@ __global__ __launch_bounds__(64) void k_small_eigvecs(const cd* __restrict__ T,
     extern __shared__ cd y[];   // p x p, column i = eigenvector of T for t_ii
     const int i = blockIdx.x * 64 + threadIdx.x;
     if (i >= p) return;
-    cd* yi = y + (size_t)threadIdx.x * p;
+    // thread-private columns interleaved (stride 64) so that equal indices of
+    // different threads fall in different banks
+    cd* yi = y + threadIdx.x;
+#define YI(r) yi[(size_t)(r) * 64]
     const cd lam = T[i + (size_t)i * p];
     double tnorm = 0;
     for (int e = 0; e < p * p; ++e) tnorm = fmax(tnorm, cabsd(T[e]));
     const double small = fmax(tnorm * 2.220446049250313e-16, 1e-300);
-    for (int r = 0; r < p; ++r) yi[r] = mk(0.0, 0.0);
-    yi[i] = mk(1.0, 0.0);
+    for (int r = 0; r < p; ++r) YI(r) = mk(0.0, 0.0);
+    YI(i) = mk(1.0, 0.0);
     for (int r = i - 1; r >= 0; --r) {
         cd s = mk(0.0, 0.0);
-        for (int q = r + 1; q <= i; ++q) cfma(s, T[r + (size_t)q * p], yi[q]);
+        for (int q = r + 1; q <= i; ++q) cfma(s, T[r + (size_t)q * p], YI(q));
         cd d = csub(T[r + (size_t)r * p], lam);
         if (cabsd(d) < small) d = mk(small, 0.0);
-        yi[r] = cscale(cdiv(s, d), -1.0);
+        YI(r) = cscale(cdiv(s, d), -1.0);
     }
     double n2 = 0;
     for (int r = 0; r < p; ++r) {
         cd s = mk(0.0, 0.0);
-        for (int q = 0; q <= i; ++q) cfma(s, Z[r + (size_t)q * p], yi[q]);
+        for (int q = 0; q <= i; ++q) cfma(s, Z[r + (size_t)q * p], YI(q));
         Y[r + (size_t)i * p] = s;
         n2 += cabs2(s);
     }
     const double inv = 1.0 / sqrt(n2);
     for (int r = 0; r < p; ++r) Y[r + (size_t)i * p] = cscale(Y[r + (size_t)i * p], inv);
+#undef YI
 }
 
 void small_eigvecs(const cd* T, const cd* Z, int p, cd* Y, hipStream_t st) {

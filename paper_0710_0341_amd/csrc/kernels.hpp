@@ -42,12 +42,11 @@ TsPlan ts_plan(int64_t n);
 // B: ncols vectors of length n spaced by ldb; storage fp64 or fp32.
 void launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bool fp32,
                         const TsPlan& p, cd* partial, hipStream_t st);
-// out[c] (= | += | -=) sum_q partial[c*nchunks+q].  mode 0 set, 1 add.
-// Optionally applies a small dense matrix afterwards: out = M * out (m x m,
-// column-major) when M != nullptr (used for G^{-1} L^dag w).  hfro2 (nullable)
-// accumulates sum |out|^2.
-void launch_reduce_partial(const cd* partial, int nchunks, int ncols, cd* out, int mode,
-                           const cd* M, cd* tmp, double* hfro2, hipStream_t st);
+// out[c] = sum_q partial[c*nchunks+q] and accum[c] += out[c] (accum nullable).
+// With M != nullptr (m x m, column-major) out = M * sums instead (used for
+// G^{-1} L^dag w); tmp then holds ncols scratch entries.
+void launch_reduce_partial(const cd* partial, int nchunks, int ncols, cd* out, cd* accum,
+                           const cd* M, cd* tmp, hipStream_t st);
 // w[i] = alpha*w[i] - sum_c B[c][i] coef[c]  (coef on device).  If normp != nullptr
 // the kernel also writes per-chunk partial sums of |w|^2 (plan p) into normp.
 void launch_update(void* w, const void* B, int64_t ldb, int ncols, const cd* coef, bool fp32,
@@ -62,9 +61,11 @@ void launch_norm_partial(const void* w, bool fp32, const TsPlan& p, double* norm
 // hsub = sqrt(sum normp); v = w / hsub unless hsub <= rel*sqrt(hfro2 + hsub^2)
 // (breakdown: flag[0] = 1 and flag[1] = step of the first one, v = 0; a
 // non-finite norm sets flag[0] = 2).  v == nullptr computes the norm only.
+// hcol (nullable, hlen entries) is added to hfro2 first: the running squared
+// Frobenius norm of the Hessenberg matrix.
 void launch_normalize(const void* w, void* v, bool fp32, const TsPlan& p, const double* normp,
-                      cd* hsub, const double* hfro2, double rel, int* flag, int step,
-                      hipStream_t st);
+                      cd* hsub, double* hfro2, double rel, int* flag, int step,
+                      const cd* hcol, int hlen, hipStream_t st);
 // v = alpha * w (alpha on host)
 void launch_scale(const void* w, void* v, bool fp32, int64_t n, double alpha, hipStream_t st);
 // out[c] = sum_r B[r][i] Z[r + c*ldz], c < ncols_out, r < ncols_in  (basis rotation)

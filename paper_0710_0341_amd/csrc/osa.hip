@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -111,13 +112,66 @@ struct osa_ctx {
     DevBuf sX, sM, sY, logpiv, gjws, s_cur, s_prev, cdef;
     PinnedBuf host;
 
+    // optional kernel timing (events on st, resolved at synchronisation points)
+    struct Pending { hipEvent_t a, b; int cls; double bytes; };
+    bool prof_on = false;
+    std::vector<Pending> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    osa_profile prof{};
+    ~osa_ctx() {
+        for (auto& p : prof_pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+        for (auto e : prof_pool) (void)hipEventDestroy(e);
+    }
+
     int64_t N() const { return g.N(); }
 };
 
 namespace {
 
 // ------------------------------------------------------------- utilities
-void sync(osa_ctx* c) { OSA_HIP(hipStreamSynchronize(c->st)); }
+void prof_resolve(osa_ctx* c) {
+    for (auto& p : c->prof_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->prof.ms[p.cls] += ms;
+            c->prof.bytes[p.cls] += p.bytes;
+            c->prof.launches[p.cls] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        c->prof_pool.push_back(p.a);
+        c->prof_pool.push_back(p.b);
+    }
+    c->prof_pending.clear();
+}
+
+void sync(osa_ctx* c) {
+    OSA_HIP(hipStreamSynchronize(c->st));
+    if (!c->prof_pending.empty()) prof_resolve(c);
+}
+
+hipEvent_t prof_event(osa_ctx* c) {
+    if (c->prof_pool.empty()) {
+        hipEvent_t e;
+        OSA_HIP(hipEventCreate(&e));
+        return e;
+    }
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+}
+
+// Brackets the launches issued by f() with events when profiling is on.
+template <typename F>
+void timed(osa_ctx* c, int cls, double bytes, F&& f) {
+    if (!c->prof_on) { f(); return; }
+    hipEvent_t a = prof_event(c), b = prof_event(c);
+    OSA_HIP(hipEventRecord(a, c->st));
+    f();
+    OSA_HIP(hipEventRecord(b, c->st));
+    c->prof_pending.push_back({a, b, cls, bytes});
+    if (c->prof_pending.size() > 4096) sync(c);
+}
 
 template <typename T>
 void d2h(osa_ctx* c, const void* dsrc, size_t n, T* out) {
@@ -139,7 +193,12 @@ void apply_h(osa_ctx* c, const void* in, void* out, bool fp32, bool adjoint, int
     const void* U = c->U.p;
     bool ufp32 = c->links_fp32;
     if (fp32 && !c->links_fp32 && c->U32.p) { U = c->U32.p; ufp32 = true; }
-    launch_wilson_h(in, out, U, ufp32, fp32, c->g, adjoint ? c->hc_adj : c->hc, nrhs, c->st);
+    // algorithmic bytes per site: spinor in + out, 8 links (4 own, 4 backward neighbours')
+    const double sb = fp32 ? 8.0 : 16.0, lb = ufp32 ? 8.0 : 16.0;
+    const double bytes = (double)c->g.V * (nrhs * 24.0 * sb + 36.0 * lb);
+    timed(c, 2, bytes, [&] {
+        launch_wilson_h(in, out, U, ufp32, fp32, c->g, adjoint ? c->hc_adj : c->hc, nrhs, c->st);
+    });
 }
 
 // Norm of an internal vector, to the device scalar hsub (cd, real part).
@@ -147,7 +206,7 @@ void vec_norm(osa_ctx* c, const void* v, bool fp32, cd* out) {
     TsPlan p = ts_plan(c->N());
     launch_norm_partial(v, fp32, p, c->normp.as<double>(), c->st);
     launch_normalize(v, nullptr, fp32, p, c->normp.as<double>(), out, nullptr, 0.0, nullptr, 0,
-                     c->st);
+                     nullptr, 0, c->st);
 }
 
 void ensure_krylov(osa_ctx* c, int kcap) {
@@ -201,18 +260,24 @@ void cgs2(osa_ctx* c, void* wv, const void* B, int64_t ld, int ncols, bool fp32,
     const int64_t scratch_len = (int64_t)(c->upd_scratch.bytes / sizeof(cd));
     cd* part = c->partial.as<cd>();
     cd* co = c->coef.as<cd>();
+    const double eb = fp32 ? 8.0 : 16.0;
+    const double n = (double)c->N();
+    const double dot_bytes = (ncols + 1.0) * n * eb;     // read V_j and w
+    const double upd_bytes = (ncols + 2.0) * n * eb;     // read V_j and w, write w
     // pass 1
-    launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st);
-    launch_reduce_partial(part, p.nchunks, ncols, hcol, 0, nullptr, nullptr, hfro2, c->st);
-    launch_update(wv, B, ld, ncols, hcol, fp32, p, nullptr, c->upd_scratch.as<cd>(), scratch_len,
-                  c->st);
+    timed(c, 0, dot_bytes, [&] { launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st); });
+    launch_reduce_partial(part, p.nchunks, ncols, hcol, nullptr, nullptr, nullptr, c->st);
+    timed(c, 1, upd_bytes, [&] {
+        launch_update(wv, B, ld, ncols, hcol, fp32, p, nullptr, c->upd_scratch.as<cd>(),
+                      scratch_len, c->st);
+    });
     // pass 2
-    launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st);
-    launch_reduce_partial(part, p.nchunks, ncols, co, 0, nullptr, nullptr, nullptr, c->st);
-    launch_update(wv, B, ld, ncols, co, fp32, p, c->normp.as<double>(), c->upd_scratch.as<cd>(),
-                  scratch_len, c->st);
-    // h += h2
-    axpy_c(c, ncols, mk(1.0, 0.0), co, hcol);
+    timed(c, 0, dot_bytes, [&] { launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st); });
+    launch_reduce_partial(part, p.nchunks, ncols, co, hcol, nullptr, nullptr, c->st);   // h += h2
+    timed(c, 1, upd_bytes, [&] {
+        launch_update(wv, B, ld, ncols, co, fp32, p, c->normp.as<double>(),
+                      c->upd_scratch.as<cd>(), scratch_len, c->st);
+    });
 }
 
 // Oblique projection w <- w - R G^{-1} L^dag w (Eq. 21) with the active pairs.
@@ -224,8 +289,8 @@ void project_out(osa_ctx* c, void* wv, cd* cout) {
     cd* part = c->partial.as<cd>();
     cd* co = cout ? cout : c->coef2.as<cd>();
     launch_dot_partial(c->L.p, c->N(), m, wv, false, p, part, c->st);
-    launch_reduce_partial(part, p.nchunks, m, co, 0, c->Ginv.as<cd>(), c->coef.as<cd>() + 0,
-                          nullptr, c->st);
+    launch_reduce_partial(part, p.nchunks, m, co, nullptr, c->Ginv.as<cd>(), c->coef.as<cd>(),
+                          c->st);
     launch_update(wv, c->R.p, c->N(), m, co, false, p, nullptr, c->upd_scratch.as<cd>(),
                   (int64_t)(c->upd_scratch.bytes / sizeof(cd)), c->st);
 }
@@ -251,7 +316,9 @@ int small_sign_run(osa_ctx* c, int k, const cd* A, int lda, cd* s_out, bool* ok)
     double* red = c->red.as<double>();
     for (it = 1; it <= 100; ++it) {
         OSA_HIP(hipMemcpyAsync(M, X, sizeof(cd) * k * k, hipMemcpyDeviceToDevice, c->st));
-        gj_invert(M, Y, k, c->logpiv.as<double>(), c->flag.as<int>(), c->gjws.p, c->st);
+        timed(c, 3, 2.0 * 16.0 * k * (double)k, [&] {
+            gj_invert(M, Y, k, c->logpiv.as<double>(), c->flag.as<int>(), c->gjws.p, c->st);
+        });
         launch_newton_combine(X, Y, k, c->logpiv.as<double>(), scale, red, c->st);
         double hred[2];
         int hflag[1];
@@ -290,7 +357,7 @@ void build_ginv(osa_ctx* c, int m) {
     for (int j = 0; j < m; ++j) {
         launch_dot_partial(c->L.p, c->N(), m, c->R.as<cd>() + (size_t)j * c->N(), false, p,
                            c->partial.as<cd>(), c->st);
-        launch_reduce_partial(c->partial.as<cd>(), p.nchunks, m, G + (size_t)j * m, 0, nullptr,
+        launch_reduce_partial(c->partial.as<cd>(), p.nchunks, m, G + (size_t)j * m, nullptr,
                               nullptr, nullptr, c->st);
     }
     OSA_HIP(hipMemsetAsync(c->flag.p, 0, sizeof(int) * 4, c->st));
@@ -356,15 +423,31 @@ SolveResult solve_one(osa_ctx* c, const cd* xin, cd* yout, double tol) {
         launch_scale(x, V, false, N, 1.0 / beta, c->st);
         int kprev = 0;
         bool stopped = false;
+        // Check schedule.  The estimate at a check is the change since the previous
+        // check, i.e. about the error of the previous check.  After two estimates
+        // the geometric rate predicts where the error crosses tol; checks far
+        // before that point are skipped (at most 3 in a row).
+        std::vector<int> cj;       // performed checks
+        std::vector<double> ce;    // ce[i]: estimate at check i (error of check i-1)
         for (int j = 0; j < kmax && !stopped; ++j) {
             cd* vj = V + (size_t)j * N;
             apply_h(c, vj, w, false, false);
             if (reproj && m > 0) project_out(c, w, nullptr);
             cgs2(c, w, V, N, j + 1, false, H + (size_t)j * ldh, hfro2);
             launch_normalize(w, V + (size_t)(j + 1) * N, false, p, c->normp.as<double>(),
-                             H + (size_t)j * ldh + (j + 1), hfro2, 1e-14, flag, j, c->st);
+                             H + (size_t)j * ldh + (j + 1), hfro2, 1e-14, flag, j,
+                             H + (size_t)j * ldh, j + 1, c->st);
             const int kk = j + 1;
             if (kk % every != 0 && kk != kmax) continue;
+            if (!fixed && kk != kmax && ce.size() >= 3) {
+                const size_t q = ce.size() - 1;
+                const double e1 = ce[q - 1], e2 = ce[q];
+                const int j1 = cj[q - 2], j2 = cj[q - 1];
+                const double r = (e1 > 0 && e2 > 0) ? std::log(e2 / e1) / (double)(j2 - j1) : 0.0;
+                const double pred = e2 * std::exp(r * (double)(kk - j2));
+                const bool near = !(r < 0) || pred <= 3.0 * tol;
+                if (!near && kk - cj.back() < 4 * every) continue;
+            }
             int hf[2];
             d2h(c, flag, 2, hf);
             if (hf[0] == 2) { res.st = OSA_ERR_NONFINITE; return res; }
@@ -387,6 +470,8 @@ SolveResult solve_one(osa_ctx* c, const cd* xin, cd* yout, double tol) {
                 res.est = beta * dn / bnorm;
                 if (res.est <= tol) stopped = true;
             }
+            cj.push_back(kcheck);
+            ce.push_back(kprev > 0 ? res.est : NAN);
             if (res.breakdown) res.est = 0.0;
             if (!stopped) {
                 // keep the latest sign in s_prev for the next difference
@@ -419,110 +504,127 @@ SolveResult solve_one(osa_ctx* c, const cd* xin, cd* yout, double tol) {
 }
 
 // ================================================================ eigensolver
-// Krylov-Schur (Stewart) for the nev eigenvalues of A = H^2 of smallest
-// modulus, A = H(mu)^2 (right) or H(-mu)^2 (left).  Returns an orthonormal
-// basis X (nev vectors, internal layout, fp64) of the converged invariant
-// subspace.  Precision of the search: fp32 or fp64 basis; an fp32 search is
-// followed by an fp64 run started from the fp32 subspace.
+// Krylov-Schur (Stewart) with locking for the nev eigenvalues of A = H^2 of
+// smallest modulus, A = H(mu)^2 (right) or H(-mu)^2 (left).  The basis is
+// [V_L | V_A | v]: V_L holds locked Schur vectors of converged eigenvalues,
+// V_A the active block (at most pa <= 64 vectors), v the next Arnoldi vector,
+// with A V_A = V_L C + V_A S_A + v b^H.  Each restart takes the Schur form of
+// the active Rayleigh quotient S_A (smallest |theta| first), locks the leading
+// converged Schur vectors and keeps a few more.  Because span(V_L) is
+// invariant, S_A projects the remaining (block-triangular) part of A, so the
+// locked coupling C never enters the small problem.  Output: an orthonormal
+// basis X (nev vectors, fp64 internal layout) of the wanted invariant subspace.
+// An fp32 search is followed by an fp64 run started from the fp32 subspace.
 struct KsStats {
     int64_t matvecs = 0;
     int restarts = 0;
     bool converged = false;
 };
 
-void ks_run(osa_ctx* c, bool adjoint, int nev, int ncv, bool fp32, double tol, int max_restarts,
+void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, int max_restarts,
             const cd* start /* fp64 internal vector or nullptr */, uint64_t seed, cd* Xout,
             KsStats& stats) {
+    const int win = pa;   // converge all wanted eigenvalues together (a cluster needs it)
     const int64_t N = c->N();
     const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
-    const int p = ncv;
+    const int P = nev + pa;              // basis capacity (plus the next vector)
+    const int ldS = P + 1;
     DevBuf Vb, Vt, wv, tv, S, T, Z, wr, bz, info;
-    Vb.ensure(es * (size_t)N * (p + 1));
-    Vt.ensure(es * (size_t)N * (p + 1));
+    Vb.ensure(es * (size_t)N * (P + 1));
+    Vt.ensure(es * (size_t)N * pa);
     wv.ensure(es * (size_t)N);
     tv.ensure(es * (size_t)N);
-    S.ensure(sizeof(cd) * (size_t)(p + 1) * p);
-    T.ensure(sizeof(cd) * (size_t)p * p);
-    Z.ensure(sizeof(cd) * (size_t)p * p);
-    wr.ensure(sizeof(cd) * p);
-    bz.ensure(sizeof(cd) * p);
+    S.ensure(sizeof(cd) * (size_t)ldS * P);
+    T.ensure(sizeof(cd) * (size_t)pa * pa);
+    Z.ensure(sizeof(cd) * (size_t)pa * pa);
+    wr.ensure(sizeof(cd) * pa);
+    bz.ensure(sizeof(cd) * pa);
     info.ensure(sizeof(int) * 4);
     char* V = (char*)Vb.p;
+    auto vec = [&](int j) { return V + es * (size_t)N * j; };
     const TsPlan pl = ts_plan(N);
     double* hfro2 = (double*)(c->dscal.as<cd>() + 8);
     int* flag = c->flag.as<int>();
-    OSA_HIP(hipMemsetAsync(S.p, 0, sizeof(cd) * (size_t)(p + 1) * p, c->st));
-    // start vector
-    if (start) {
-        launch_convert(start, false, V, fp32, N, c->st);
-    } else {
-        launch_random_vector(V, fp32, c->g, seed, c->st);
-    }
-    {
-        launch_norm_partial(V, fp32, pl, c->normp.as<double>(), c->st);
-        launch_normalize(V, V, fp32, pl, c->normp.as<double>(), c->dscal.as<cd>() + 9, nullptr,
-                         0.0, nullptr, 0, c->st);
-    }
+    OSA_HIP(hipMemsetAsync(S.p, 0, sizeof(cd) * (size_t)ldS * P, c->st));
+    if (start) launch_convert(start, false, vec(0), fp32, N, c->st);
+    else launch_random_vector(vec(0), fp32, c->g, seed, c->st);
+    launch_norm_partial(vec(0), fp32, pl, c->normp.as<double>(), c->st);
+    launch_normalize(vec(0), vec(0), fp32, pl, c->normp.as<double>(), c->dscal.as<cd>() + 9,
+                     nullptr, 0.0, nullptr, 0, nullptr, 0, c->st);
     OSA_HIP(hipMemsetAsync(hfro2, 0, sizeof(double), c->st));
-    int kcur = 0;
-    std::vector<cd> th(p), bzh(p);
+    int nlock = 0, kcur = 0;
+    std::vector<cd> th(pa), bzh(pa);
     double anorm = 0;
     for (int rs = 0; rs <= max_restarts; ++rs) {
         OSA_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, c->st));
-        for (int j = kcur; j < p; ++j) {
-            char* vj = V + es * (size_t)N * j;
-            apply_h(c, vj, tv.p, fp32, adjoint);
+        const int ptot = nlock + pa;
+        for (int j = kcur; j < ptot; ++j) {
+            apply_h(c, vec(j), tv.p, fp32, adjoint);
             apply_h(c, tv.p, wv.p, fp32, adjoint);
             stats.matvecs += 2;
-            cd* scol = S.as<cd>() + (size_t)j * (p + 1);
+            cd* scol = S.as<cd>() + (size_t)j * ldS;
             cgs2(c, wv.p, V, N, j + 1, fp32, scol, hfro2);
-            launch_normalize(wv.p, V + es * (size_t)N * (j + 1), fp32, pl, c->normp.as<double>(),
-                             scol + (j + 1), hfro2, 1e-300, flag, j, c->st);
+            launch_normalize(wv.p, vec(j + 1), fp32, pl, c->normp.as<double>(), scol + (j + 1),
+                             hfro2, 1e-300, flag, j, scol, j + 1, c->st);
         }
-        // Schur form of the p x p Rayleigh quotient, smallest |theta| first
+        // Schur form of the active Rayleigh quotient, smallest |theta| first
+        const double tr0 = now_ms();
+        const int na = pa;
         cd* Sp = c->sM.as<cd>();
-        OSA_HIP(hipMemcpy2DAsync(Sp, sizeof(cd) * p, S.p, sizeof(cd) * (p + 1), sizeof(cd) * p, p,
-                                 hipMemcpyDeviceToDevice, c->st));
-        small_schur(Sp, p, T.as<cd>(), Z.as<cd>(), wr.as<cd>(), 0, info.as<int>(), nullptr, c->st);
-        // b^H Z with b^H the last row of S
-        launch_zgemm(0, 0, 1, p, p, mk(1.0, 0.0), S.as<cd>() + p, p + 1, Z.as<cd>(), p,
-                     mk(0.0, 0.0), bz.as<cd>(), 1, c->st);
+        OSA_HIP(hipMemcpy2DAsync(Sp, sizeof(cd) * na, S.as<cd>() + nlock + (size_t)nlock * ldS,
+                                 sizeof(cd) * ldS, sizeof(cd) * na, na, hipMemcpyDeviceToDevice,
+                                 c->st));
+        timed(c, 4, 0.0, [&] {
+            small_schur(Sp, na, T.as<cd>(), Z.as<cd>(), wr.as<cd>(), 0, info.as<int>(), nullptr,
+                        c->st);
+        });
+        // spike in the Schur basis: b^H Z with b^H = S[ptot, nlock:ptot]
+        launch_zgemm(0, 0, 1, na, na, mk(1.0, 0.0), S.as<cd>() + ptot + (size_t)nlock * ldS, ldS,
+                     Z.as<cd>(), na, mk(0.0, 0.0), bz.as<cd>(), 1, c->st);
         int hinfo = 0;
         d2h(c, info.p, 1, &hinfo);
         if (hinfo < 0) throw OsaError{OSA_ERR_EIG_NOCONV};
-        d2h(c, wr.p, p, th.data());
-        d2h(c, bz.p, p, bzh.data());
-        for (int i = 0; i < p; ++i) anorm = std::max(anorm, cabsd(th[i]));
-        int nconv = 0;
-        for (int i = 0; i < nev; ++i) {
-            if (cabsd(bzh[i]) <= tol * anorm) ++nconv;
-            else break;
-        }
+        d2h(c, wr.p, na, th.data());
+        d2h(c, bz.p, na, bzh.data());
+        for (int i = 0; i < na; ++i) anorm = std::max(anorm, cabsd(th[i]));
+        const int want = nev - nlock;
+        int nc = 0;
+        while (nc < want && cabsd(bzh[nc]) <= tol * anorm) ++nc;
         stats.restarts = rs;
-        if (nconv >= nev || rs == max_restarts) {
-            stats.converged = (nconv >= nev);
-            launch_rotate(V, N, p, Z.as<cd>(), p, nev, Vt.p, N, fp32, N, c->st);
-            launch_convert(Vt.p, fp32, Xout, false, N * nev, c->st);
+        if (nc >= want || rs == max_restarts) {
+            stats.converged = (nc >= want);
+            if (nlock > 0) launch_convert(V, fp32, Xout, false, N * nlock, c->st);
+            launch_rotate(vec(nlock), N, na, Z.as<cd>(), na, want, Vt.p, N, fp32, N, c->st);
+            launch_convert(Vt.p, fp32, Xout + (size_t)nlock * N, false, N * want, c->st);
             sync(c);
             return;
         }
-        // thick restart: keep the leading Schur vectors
-        int keep = nev + (p - nev) / 2;
-        if (keep > p - 2) keep = p - 2;
-        if (keep < nev) keep = nev;
-        launch_rotate(V, N, p, Z.as<cd>(), p, keep, Vt.p, N, fp32, N, c->st);
-        OSA_HIP(hipMemcpyAsync((char*)Vt.p + es * (size_t)N * keep, V + es * (size_t)N * p,
-                               es * (size_t)N, hipMemcpyDeviceToDevice, c->st));
-        std::swap(Vb.p, Vt.p);
-        std::swap(Vb.bytes, Vt.bytes);
-        V = (char*)Vb.p;
-        OSA_HIP(hipMemsetAsync(S.p, 0, sizeof(cd) * (size_t)(p + 1) * p, c->st));
-        OSA_HIP(hipMemcpy2DAsync(S.p, sizeof(cd) * (p + 1), T.p, sizeof(cd) * p,
-                                 sizeof(cd) * keep, keep, hipMemcpyDeviceToDevice, c->st));
-        // spike row: S[keep, 0:keep] = bz[0:keep]
-        OSA_HIP(hipMemcpy2DAsync(S.as<cd>() + keep, sizeof(cd) * (p + 1), bz.p, sizeof(cd),
-                                 sizeof(cd), keep, hipMemcpyDeviceToDevice, c->st));
-        kcur = keep;
+        // restart: lock nc vectors, keep the wanted ones plus up to half the surplus
+        const int wa = std::min(want, win);
+        int keep = wa + std::min(nc, (na - wa) / 2);
+        if (keep > na - 2) keep = na - 2;
+        if (keep < wa) keep = wa;
+        launch_rotate(vec(nlock), N, na, Z.as<cd>(), na, keep, Vt.p, N, fp32, N, c->st);
+        OSA_HIP(hipMemcpyAsync(vec(nlock), Vt.p, es * (size_t)N * keep, hipMemcpyDeviceToDevice,
+                               c->st));
+        OSA_HIP(hipMemcpyAsync(vec(nlock + keep), vec(ptot), es * (size_t)N,
+                               hipMemcpyDeviceToDevice, c->st));
+        OSA_HIP(hipMemsetAsync(S.p, 0, sizeof(cd) * (size_t)ldS * P, c->st));
+        const int nl2 = nlock + nc, na2 = keep - nc;
+        // active block: T[nc:keep, nc:keep]; spike row at index nlock + keep
+        OSA_HIP(hipMemcpy2DAsync(S.as<cd>() + nl2 + (size_t)nl2 * ldS, sizeof(cd) * ldS,
+                                 T.as<cd>() + nc + (size_t)nc * na, sizeof(cd) * na,
+                                 sizeof(cd) * na2, na2, hipMemcpyDeviceToDevice, c->st));
+        OSA_HIP(hipMemcpy2DAsync(S.as<cd>() + (nlock + keep) + (size_t)nl2 * ldS, sizeof(cd) * ldS,
+                                 bz.as<cd>() + nc, sizeof(cd), sizeof(cd), na2,
+                                 hipMemcpyDeviceToDevice, c->st));
+        kcur = nlock + keep;
+        nlock = nl2;
+        if (c->prof_on) {
+            sync(c);
+            c->prof.ms[5] += now_ms() - tr0;
+            c->prof.launches[5] += 1;
+        }
     }
 }
 
@@ -546,7 +648,7 @@ void rayleigh_ritz(osa_ctx* c, bool adjoint, int nev, int m, cd* X, cd* Rout,
         launch_dot_partial(X, N, nev, W.as<cd>() + (size_t)j * N, false, p, c->partial.as<cd>(),
                            c->st);
         launch_reduce_partial(c->partial.as<cd>(), p.nchunks, nev, Mb.as<cd>() + (size_t)j * nev,
-                              0, nullptr, nullptr, nullptr, c->st);
+                              nullptr, nullptr, nullptr, c->st);
     }
     small_schur(Mb.as<cd>(), nev, T.as<cd>(), Z.as<cd>(), wr.as<cd>(), 1, info.as<int>(), nullptr,
                 c->st);
@@ -585,11 +687,14 @@ void deflate(osa_ctx* c, int m, osa_info* info) {
     const int64_t N = c->N();
     ensure_krylov(c, std::max(c->kcap, std::max(c->opts.k_max, 64)));
     const int extra = std::max(4, m / 5);
-    const int nev = std::min(m + extra, 56);
-    int ncv = c->opts.eig_ncv > 0 ? c->opts.eig_ncv : std::min(64, 2 * nev + 16);
+    const int nev = m + extra;
+    // active block of the Krylov-Schur basis (the small Schur kernel holds 64)
+    // (the whole basis must fit in the 12 V dimensional space)
+    const int64_t dim = 12LL * c->g.V;
+    int ncv = c->opts.eig_ncv > 0 ? c->opts.eig_ncv : 64;
     if (ncv > 64) ncv = 64;
-    if (ncv < nev + 4) ncv = std::min(64, nev + 4);
-    if (nev + 2 > ncv) throw OsaError{OSA_ERR_ARG};
+    if ((int64_t)nev + ncv + 1 > dim) ncv = (int)std::max<int64_t>(8, dim - nev - 1);
+    if (ncv < nev + 4 || (int64_t)nev + ncv + 1 > dim) throw OsaError{OSA_ERR_ARG};
     const double tol = c->opts.eig_tol > 0 ? c->opts.eig_tol : 1e-12;
     const int maxr = c->opts.eig_max_restarts > 0 ? c->opts.eig_max_restarts : 2000;
     const bool fp32 = (c->opts.eig_prec == OSA_FP32);
@@ -897,6 +1002,37 @@ osa_status osa_batch_apply(int32_t n, osa_ctx* const* ctxs, const void* const* B
         if (s > worst) worst = s;
     }
     return worst;
+}
+
+osa_status osa_set_links(osa_ctx* c, const void* links) {
+    if (!c || !links) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        launch_links_to_internal(links, c->links_fp32, c->U.p, c->links_fp32, c->g, c->st);
+        if (c->U32.p) launch_convert(c->U.p, false, c->U32.p, true, (int64_t)c->g.Vp * 36, c->st);
+        c->m_alloc = c->m_active = 0;
+        c->lambda.clear();
+        sync(c);
+        return OSA_OK;
+    });
+}
+
+osa_status osa_profile_enable(osa_ctx* c, int32_t enable) {
+    if (!c) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        sync(c);
+        c->prof = osa_profile{};
+        c->prof_on = enable != 0;
+        return OSA_OK;
+    });
+}
+
+osa_status osa_profile_read(osa_ctx* c, osa_profile* out) {
+    if (!c || !out) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        sync(c);
+        *out = c->prof;
+        return OSA_OK;
+    });
 }
 
 osa_status osa_apply_hw(osa_ctx* c, int32_t nrhs, const void* X, void* Y) {
