@@ -75,7 +75,7 @@ typedef struct {
     int32_t check_every;        /* convergence check interval (default 50); < 0: run exactly
                                    k_max steps with no check (fixed-k mode)                   */
     int32_t no_reproject;       /* 1: skip the per-step oblique re-projection (default 0)     */
-    int32_t eig_ncv;            /* eigensolver basis size, <= 96 (default min(96, 2 nev + 16)) */
+    int32_t eig_ncv;            /* eigensolver active block, 8..96 (default 96)                */
     int32_t eig_max_restarts;   /* eigensolver restart cap                 (default 2000)     */
     osa_prec eig_prec;          /* FP32: search in FP32, then refine in FP64 (default FP64)   */
     double eig_tol;             /* relative Krylov-Schur residual target   (default 1e-12)    */
@@ -177,6 +177,14 @@ OSA_API osa_status osa_apply_hw(osa_ctx* ctx, int32_t nrhs, const void* X, void*
  * the small-sign kernel for checks; stream-ordered on `stream`. */
 OSA_API osa_status osa_small_sign(int32_t k, const void* A, void* s, int32_t* iters, void* stream);
 
+/* Schur decomposition A = Z T Z^H of a p x p complex128 matrix (column-major,
+ * device, 1 <= p <= 96), with the diagonal of T ordered by |t_ii| ascending
+ * (mode 0) or |Re t_ii| ascending (mode 1): the small dense step of the
+ * eigensolver restarts.  T, Z: p x p column-major (device); w: p eigenvalues.
+ * Standalone entry of the kernel for checks; stream-ordered on `stream`. */
+OSA_API osa_status osa_small_schur(int32_t p, const void* A, void* T, void* Z, void* w,
+                                   int32_t mode, void* stream);
+
 /* Replace the gauge links of an existing context (same lattice, same link
  * precision, device pointer in the boundary layout).  Reuses all workspace;
  * the deflation data is dropped (m becomes 0) because it belongs to the old
@@ -198,6 +206,10 @@ typedef struct {
 } osa_profile;
 OSA_API osa_status osa_profile_enable(osa_ctx* ctx, int32_t enable);
 OSA_API osa_status osa_profile_read(osa_ctx* ctx, osa_profile* out);
+
+/* Human-readable detail of the last error on this context ("" if none);
+ * valid until the next call on the context. */
+OSA_API const char* osa_last_message(const osa_ctx* ctx);
 
 OSA_API void osa_destroy(osa_ctx* ctx);
 OSA_API const char* osa_status_string(osa_status s);

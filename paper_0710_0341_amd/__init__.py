@@ -31,8 +31,9 @@ FP64, FP32 = 0, 1
 
 EXPORTS = ["overlap_sign_apply", "osa_create", "osa_deflate", "osa_set_deflation",
            "osa_get_deflation", "osa_set_active_deflation", "osa_apply", "osa_batch_apply",
-           "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_set_links",
-           "osa_profile_enable", "osa_profile_read", "osa_destroy", "osa_status_string",
+           "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_small_schur", "osa_set_links",
+           "osa_profile_enable", "osa_profile_read", "osa_last_message", "osa_destroy",
+           "osa_status_string",
            "osa_version"]
 
 
@@ -103,16 +104,19 @@ def lib() -> ctypes.CDLL:
     L.osa_set_opts.argtypes = [vp, ctypes.POINTER(Opts)]
     L.osa_apply_hw.argtypes = [vp, i32, vp, vp]
     L.osa_small_sign.argtypes = [i32, vp, vp, ctypes.POINTER(i32), vp]
+    L.osa_small_schur.argtypes = [i32, vp, vp, vp, vp, i32, vp]
     L.osa_set_links.argtypes = [vp, vp]
     L.osa_profile_enable.argtypes = [vp, i32]
     L.osa_profile_read.argtypes = [vp, ctypes.POINTER(Profile)]
+    L.osa_last_message.argtypes = [vp]
+    L.osa_last_message.restype = ctypes.c_char_p
     L.osa_destroy.argtypes = [vp]
     L.osa_destroy.restype = None
     L.osa_status_string.argtypes = [i32]
     L.osa_status_string.restype = ctypes.c_char_p
     L.osa_version.restype = ctypes.c_char_p
-    for name in EXPORTS[:-3]:
-        if name != "osa_destroy":
+    for name in EXPORTS:
+        if name not in ("osa_destroy", "osa_status_string", "osa_version", "osa_last_message"):
             getattr(L, name).restype = i32
     _lib = L
     return L
@@ -226,7 +230,9 @@ class Context:
 
     def deflate(self, n_defl):
         info = Info()
-        _check(lib().osa_deflate(self._h, int(n_defl), ctypes.byref(info)), "osa_deflate", False)
+        st = lib().osa_deflate(self._h, int(n_defl), ctypes.byref(info))
+        if st != OSA_OK:
+            raise OsaError(st, "osa_deflate (" + lib().osa_last_message(self._h).decode() + ")")
         return info.as_dict()
 
     def set_deflation(self, R, L, lam):
@@ -309,6 +315,20 @@ def batch_apply(contexts, sources, tol=1e-10):
     st = lib().osa_batch_apply(n, hs, bs, ys, float(tol), infos)
     _check(st, "osa_batch_apply")
     return outs, [i.as_dict() for i in infos], st
+
+
+def small_schur(A, mode=0):
+    """(T, Z, w) with A = Z T Z^H for a square complex128 GPU tensor A (p <= 96)."""
+    torch = _torch()
+    p = int(A.shape[0])
+    Acm = A.t().contiguous()
+    T = torch.empty((p, p), dtype=torch.complex128, device=A.device)
+    Z = torch.empty((p, p), dtype=torch.complex128, device=A.device)
+    w = torch.empty(p, dtype=torch.complex128, device=A.device)
+    _check(lib().osa_small_schur(p, ctypes.c_void_p(Acm.data_ptr()), ctypes.c_void_p(T.data_ptr()),
+                                 ctypes.c_void_p(Z.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                 int(mode), _stream()), "osa_small_schur", False)
+    return T.t(), Z.t(), w          # column-major storage -> row-major views
 
 
 def small_sign(A):

@@ -515,19 +515,297 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
 #undef ZZ
 }
 
-size_t schur_ws_bytes(int p) { return 0; }
+// ---------------------------------------------------------------------------
+// Larger Schur problems (64 < p <= 96).  Only T fits in LDS, so kernel A keeps T
+// there and writes every transformation applied from the right to a log: the
+// Householder vectors of the Hessenberg reduction and the 2x2 unitaries of the
+// QR sweeps and of the reordering.  Kernel B rebuilds Z = product of the logged
+// transformations, one thread per row of Z (rows staged in LDS), applying the
+// log in order.  A runs as a single wavefront (two elements per lane for
+// p > 64): a two-wavefront version gave run-to-run different Schur forms for
+// identical input, while this one is bitwise reproducible.
+static constexpr int kSchurBig = 96;
+static constexpr int kBigThreads = 64;
 
-void small_schur(const cd* A, int p, cd* T, cd* Z, cd* w, int mode, int* info, void*,
+struct RotEntry {   // columns (k, k+1) <- [a x + b y, -conj(b) x + conj(a) y]
+    cd a, b;
+    int k, pad;
+};
+
+__global__ __launch_bounds__(kBigThreads) void k_schur_log(const cd* __restrict__ A, int p,
+                                                           cd* Tout, cd* wout, int mode, int* info,
+                                                           cd* hlog, double* tlog,
+                                                           RotEntry* rlog, int rcap) {
+    extern __shared__ cd lds[];
+    const int ld = p + 1;
+    cd* T = lds;
+    __shared__ cd hv[kSchurBig];
+    __shared__ double sred[kBigThreads / 64];
+    __shared__ unsigned long long sball[kBigThreads / 64];
+    const int l = threadIdx.x;
+    const int lane = l & 63, wave = l >> 6;
+#define TT(i, j) T[(i) + (j) * ld]
+    double amax = 0;
+    for (int e = l; e < p * p; e += kBigThreads) {
+        const cd v = A[e];
+        TT(e % p, e / p) = v;
+        amax = fmax(amax, cabsd(v));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    if (lane == 0) sred[wave] = amax;
+    __syncthreads();
+    const double anorm = sred[0];
+    __syncthreads();
+    // ---- Hessenberg reduction; reflectors logged for Z
+    for (int j = 0; j + 2 < p; ++j) {
+        const int L = p - j - 1;
+        double xp = 0;
+        for (int i = l; i < L; i += kBigThreads) xp += cabs2(TT(j + 1 + i, j));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) xp += __shfl_xor(xp, off, 64);
+        if (lane == 0) sred[wave] = xp;
+        __syncthreads();
+        const double xn2 = sred[0];
+        const double xn = sqrt(xn2);
+        const cd x0 = TT(j + 1, j);
+        const double tail = xn2 - cabs2(x0);
+        __syncthreads();
+        if (xn == 0.0 || tail <= 1e-300) {
+            if (l == 0) tlog[j] = 0.0;
+            continue;
+        }
+        const double ax0 = cabsd(x0);
+        const cd ph = ax0 > 0 ? cscale(x0, 1.0 / ax0) : mk(1.0, 0.0);
+        const cd alpha = cscale(ph, -xn);
+        for (int i = l; i < L; i += kBigThreads) {
+            const cd v = (i == 0) ? csub(x0, alpha) : TT(j + 1 + i, j);
+            hv[i] = v;
+            hlog[(size_t)j * p + i] = v;
+        }
+        const double tau = 2.0 / (2.0 * xn2 + 2.0 * xn * ax0);
+        if (l == 0) tlog[j] = tau;
+        __syncthreads();
+        for (int c = j + l; c < p; c += kBigThreads) {
+            cd sacc = mk(0.0, 0.0);
+            for (int i = 0; i < L; ++i) cfmac(sacc, hv[i], TT(j + 1 + i, c));
+            sacc = cscale(sacc, tau);
+            for (int i = 0; i < L; ++i) TT(j + 1 + i, c) = csub(TT(j + 1 + i, c), cmul(hv[i], sacc));
+        }
+        __syncthreads();
+        for (int r = l; r < p; r += kBigThreads) {
+            cd sacc = mk(0.0, 0.0);
+            for (int i = 0; i < L; ++i) cfma(sacc, TT(r, j + 1 + i), hv[i]);
+            sacc = cscale(sacc, tau);
+            for (int i = 0; i < L; ++i) TT(r, j + 1 + i) = csub(TT(r, j + 1 + i), cmul(sacc, cconj(hv[i])));
+        }
+        __syncthreads();
+        for (int i = l; i < L; i += kBigThreads) TT(j + 1 + i, j) = (i == 0) ? alpha : mk(0.0, 0.0);
+        __syncthreads();
+    }
+    int nrot = 0;
+    bool overflow = false;
+    auto pair = [&](int k, cd a, cd b, int col0, int row1, int zero_col) {
+        for (int c = col0 + l; c < p; c += kBigThreads) {
+            const cd x = TT(k, c), y = TT(k + 1, c);
+            TT(k, c) = cadd(cmulc(a, x), cmulc(b, y));
+            TT(k + 1, c) = (c == zero_col) ? mk(0.0, 0.0) : csub(cmul(a, y), cmul(b, x));
+        }
+        __syncthreads();
+        for (int r = l; r <= row1 && r < p; r += kBigThreads) {
+            const cd x = TT(r, k), y = TT(r, k + 1);
+            TT(r, k) = cadd(cmul(a, x), cmul(b, y));
+            TT(r, k + 1) = csub(cmulc(a, y), cmulc(b, x));
+        }
+        if (l == 0) {
+            if (nrot < rcap) rlog[nrot] = RotEntry{a, b, k, 0};
+        }
+        if (nrot >= rcap) overflow = true;
+        ++nrot;
+        __syncthreads();
+    };
+    // ---- shifted QR
+    const double ulp = 2.220446049250313e-16;
+    const double smlnum = 1e-300;
+    int hi = p - 1;
+    int its = 0, total = 0;
+    const int maxtotal = 60 * p;
+    bool fail = false;
+    while (hi > 0) {
+        auto negl = [&](int q) -> bool {
+            if (q < 1 || q > hi) return false;
+            const double sub = cabsd(TT(q, q - 1));
+            double tst = cabsd(TT(q - 1, q - 1)) + cabsd(TT(q, q));
+            if (tst == 0.0) tst = anorm;
+            return sub <= fmax(ulp * tst, smlnum);
+        };
+        const unsigned long long m0 = __ballot(negl(l));
+        const unsigned long long m1 = __ballot(negl(l + 64));
+        int lo = 0;
+        if (m1) lo = 64 + 63 - __clzll(m1);
+        else if (m0) lo = 63 - __clzll(m0);
+        __syncthreads();
+        if (lo > 0) {
+            if (l == 0) TT(lo, lo - 1) = mk(0.0, 0.0);
+            __syncthreads();
+        }
+        if (lo == hi) { --hi; its = 0; continue; }
+        if (total++ > maxtotal) { fail = true; break; }
+        ++its;
+        cd sigma;
+        {
+            const cd a = TT(hi - 1, hi - 1), b = TT(hi - 1, hi);
+            const cd c = TT(hi, hi - 1), d = TT(hi, hi);
+            if (its % 10 == 0) {
+                sigma = cadd(d, mk(0.75 * cabsd(c), 0.0));
+            } else {
+                const cd tr2 = cscale(cadd(a, d), 0.5);
+                const cd det = csub(cmul(a, d), cmul(b, c));
+                const cd disc = csub(cmul(tr2, tr2), det);
+                const double r = cabsd(disc);
+                double sr = sqrt(0.5 * (r + disc.x));
+                double si = sqrt(fmax(0.0, 0.5 * (r - disc.x)));
+                if (disc.y < 0) si = -si;
+                const cd sq = mk(sr, si);
+                const cd e1 = cadd(tr2, sq), e2 = csub(tr2, sq);
+                sigma = (cabsd(csub(e1, d)) <= cabsd(csub(e2, d))) ? e1 : e2;
+            }
+        }
+        for (int k = lo; k < hi; ++k) {
+            cd f, g;
+            if (k == lo) { f = csub(TT(lo, lo), sigma); g = TT(lo + 1, lo); }
+            else { f = TT(k, k - 1); g = TT(k + 1, k - 1); }
+            const double nf = sqrt(cabs2(f) + cabs2(g));
+            cd a, b;
+            if (nf == 0.0) { a = mk(1.0, 0.0); b = mk(0.0, 0.0); }
+            else { const double inf = 1.0 / nf; a = cscale(f, inf); b = cscale(g, inf); }
+            const int col0 = (k == lo) ? lo : k - 1;
+            const int row1 = (k + 2 < hi) ? k + 2 : hi;
+            pair(k, a, b, col0, row1, (k > lo) ? k - 1 : -1);
+        }
+    }
+    // ---- reorder the diagonal
+    for (int i = 1; i < p && !fail; ++i) {
+        for (int j = i; j > 0; --j) {
+            const cd t11 = TT(j - 1, j - 1), t22 = TT(j, j);
+            if (!(sort_key(t22, mode) < sort_key(t11, mode))) break;
+            const cd t12 = TT(j - 1, j);
+            const cd x1 = t12, x2 = csub(t22, t11);
+            const double nx = sqrt(cabs2(x1) + cabs2(x2));
+            if (nx == 0.0) break;
+            const cd a = cscale(x1, 1.0 / nx), b = cscale(x2, 1.0 / nx);
+            pair(j - 1, a, b, j - 1, j, -1);
+            if (l == 0) {
+                TT(j, j - 1) = mk(0.0, 0.0);
+                TT(j - 1, j - 1) = t22;
+                TT(j, j) = t11;
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = l; e < p * p; e += kBigThreads) Tout[e] = TT(e % p, e / p);
+    for (int i = l; i < p; i += kBigThreads) wout[i] = TT(i, i);
+    if (l == 0) {
+        info[0] = (fail || overflow) ? -1 : total;
+        info[1] = nrot < rcap ? nrot : rcap;
+    }
+#undef TT
+}
+
+// Z = (I - tau_0 v_0 v_0^H)(I - tau_1 v_1 v_1^H) ... G_1 G_2 ..., row by row.
+__global__ __launch_bounds__(64) void k_schur_build_z(int p, const cd* __restrict__ hlog,
+                                                      const double* __restrict__ tlog,
+                                                      const RotEntry* __restrict__ rlog,
+                                                      const int* __restrict__ info, cd* Zout) {
+    extern __shared__ cd zs[];                   // zs[c*64 + lane]: row (blockIdx*64 + lane)
+    __shared__ RotEntry chunk[128];
+    __shared__ cd vsh[kSchurBig];
+    const int lane = threadIdx.x;
+    const int r = blockIdx.x * 64 + lane;
+    const bool live = r < p;
+    for (int c = 0; c < p; ++c) zs[c * 64 + lane] = mk((live && c == r) ? 1.0 : 0.0, 0.0);
+    for (int j = 0; j + 2 < p; ++j) {
+        const double tau = tlog[j];
+        if (tau == 0.0) continue;
+        const int L = p - j - 1;
+        __syncthreads();
+        for (int i = lane; i < L; i += 64) vsh[i] = hlog[(size_t)j * p + i];   // stage v_j
+        __syncthreads();
+        cd s = mk(0.0, 0.0);
+        for (int i = 0; i < L; ++i) cfma(s, zs[(j + 1 + i) * 64 + lane], vsh[i]);
+        s = cscale(s, tau);
+        for (int i = 0; i < L; ++i) {
+            cd& z = zs[(j + 1 + i) * 64 + lane];
+            z = csub(z, cmul(s, cconj(vsh[i])));
+        }
+    }
+    const int nrot = info[1];
+    for (int base = 0; base < nrot; base += 128) {
+        const int cnt = (nrot - base < 128) ? nrot - base : 128;
+        __syncthreads();
+        for (int e = lane; e < cnt; e += 64) chunk[e] = rlog[base + e];
+        __syncthreads();
+        for (int e = 0; e < cnt; ++e) {
+            const RotEntry q = chunk[e];
+            cd& zx = zs[q.k * 64 + lane];
+            cd& zy = zs[(q.k + 1) * 64 + lane];
+            const cd x = zx, y = zy;
+            zx = cadd(cmul(q.a, x), cmul(q.b, y));
+            zy = csub(cmulc(q.a, y), cmulc(q.b, x));
+        }
+    }
+    if (live)
+        for (int c = 0; c < p; ++c) Zout[r + (size_t)c * p] = zs[c * 64 + lane];
+}
+
+size_t schur_ws_bytes(int p) {
+    const size_t rcap = (size_t)60 * p * p + (size_t)p * p;
+    return (size_t)p * p * sizeof(cd) + (size_t)p * sizeof(double) + rcap * sizeof(RotEntry) + 512;
+}
+
+static void small_schur_big(const cd* A, int p, cd* T, cd* Z, cd* w, int mode, int* info, void* ws,
+                            hipStream_t st) {
+    char* q = (char*)ws;
+    cd* hlog = (cd*)q;               q += (size_t)p * p * sizeof(cd);
+    double* tlog = (double*)q;       q += (size_t)p * sizeof(double);
+    q = (char*)(((uintptr_t)q + 63) & ~(uintptr_t)63);
+    RotEntry* rlog = (RotEntry*)q;
+    const int rcap = 60 * p * p + p * p;
+    static const bool attr = [] {
+        OSA_HIP(hipFuncSetAttribute((const void*)k_schur_log,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(kSchurBig * (kSchurBig + 1) * sizeof(cd))));
+        OSA_HIP(hipFuncSetAttribute((const void*)k_schur_build_z,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(kSchurBig * 64 * sizeof(cd))));
+        return true;
+    }();
+    (void)attr;
+    hipLaunchKernelGGL(k_schur_log, dim3(1), dim3(kBigThreads), (size_t)p * (p + 1) * sizeof(cd), st,
+                       A, p, T, w, mode, info, hlog, tlog, rlog, rcap);
+    hipLaunchKernelGGL(k_schur_build_z, dim3((unsigned)ceil_div(p, 64)), dim3(64),
+                       (size_t)p * 64 * sizeof(cd), st, p, (const cd*)hlog, (const double*)tlog,
+                       (const RotEntry*)rlog, (const int*)info, Z);
+    OSA_LAUNCH_CHECK();
+}
+
+
+void small_schur(const cd* A, int p, cd* T, cd* Z, cd* w, int mode, int* info, void* ws,
                  hipStream_t st) {
-    if (p > kSchurMax || p < 1) throw HipError{hipErrorInvalidValue, "small_schur: p out of range"};
+    if (p > kSchurMax) {
+        if (p > kSchurBig || !ws) throw HipError{hipErrorInvalidValue, "small_schur: p out of range"};
+        small_schur_big(A, p, T, Z, w, mode, info, ws, st);
+        return;
+    }
+    if (p < 1) throw HipError{hipErrorInvalidValue, "small_schur: p out of range"};
     const size_t lds = (size_t)2 * p * (p + 1) * sizeof(cd);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static const bool attr_set = [] {   // thread-safe one-time initialisation
         OSA_HIP(hipFuncSetAttribute((const void*)k_small_schur,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(2 * kSchurMax * (kSchurMax + 1) * sizeof(cd))));
-        attr_set = true;
-    }
+        return true;
+    }();
+    (void)attr_set;
     hipLaunchKernelGGL(k_small_schur, dim3(1), dim3(64), lds, st, A, p, T, Z, w, mode, info);
     OSA_LAUNCH_CHECK();
 }
@@ -570,13 +848,13 @@ __global__ __launch_bounds__(64) void k_small_eigvecs(const cd* __restrict__ T,
 
 void small_eigvecs(const cd* T, const cd* Z, int p, cd* Y, hipStream_t st) {
     const size_t lds = (size_t)64 * p * sizeof(cd);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static const bool attr_set = [] {
         OSA_HIP(hipFuncSetAttribute((const void*)k_small_eigvecs,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(64 * kSchurMax * sizeof(cd))));
-        attr_set = true;
-    }
+        return true;
+    }();
+    (void)attr_set;
     hipLaunchKernelGGL(k_small_eigvecs, dim3((unsigned)ceil_div(p, 64)), dim3(64), lds, st, T, Z, p,
                        Y);
     OSA_LAUNCH_CHECK();

@@ -97,7 +97,8 @@ void launch_diff_norm(const cd* s, int k, const cd* sprev, int kprev, double* ou
                       hipStream_t st);
 // Small Schur decomposition A = Z T Z^H (p <= 96) with the diagonal of T sorted
 // by |t_ii| ascending (mode 0) or |Re t_ii| ascending (mode 1).  A, T, Z:
-// column-major p x p (ld = p).  w: eigenvalues (p).  info: iterations or -1.
+// column-major p x p (ld = p).  w: eigenvalues (p).  info[0]: QR iterations or
+// -1, info[1]: scratch (2 ints).  p > 64 needs ws of schur_ws_bytes(p) bytes.
 size_t schur_ws_bytes(int p);
 void small_schur(const cd* A, int p, cd* T, cd* Z, cd* w, int mode, int* info, void* ws,
                  hipStream_t st);

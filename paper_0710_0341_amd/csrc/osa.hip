@@ -18,7 +18,9 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <exception>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.hpp"
@@ -81,6 +83,7 @@ double now_ms() {
 
 struct OsaError {
     osa_status s;
+    std::string why = "";
 };
 
 }  // namespace
@@ -96,6 +99,11 @@ struct osa_ctx {
 
     DevBuf U;        // internal links
     DevBuf U32;      // fp32 copy for an fp32 eigen-search on fp64 links
+    const void* u_ext = nullptr;     // a worker clone reads its parent's links
+    const void* u32_ext = nullptr;
+    bool own_stream = false;
+    const void* links() const { return u_ext ? u_ext : U.p; }
+    const void* links32() const { return u_ext ? u32_ext : U32.p; }
 
     // deflation data (internal layout, m_alloc vectors each)
     int m_alloc = 0, m_active = 0;
@@ -118,9 +126,11 @@ struct osa_ctx {
     std::vector<Pending> prof_pending;
     std::vector<hipEvent_t> prof_pool;
     osa_profile prof{};
+    std::string msg;
     ~osa_ctx() {
         for (auto& p : prof_pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
         for (auto e : prof_pool) (void)hipEventDestroy(e);
+        if (own_stream && st) (void)hipStreamDestroy(st);
     }
 
     int64_t N() const { return g.N(); }
@@ -190,9 +200,9 @@ void h2d(osa_ctx* c, void* ddst, const T* src, size_t n) {
 }
 
 void apply_h(osa_ctx* c, const void* in, void* out, bool fp32, bool adjoint, int nrhs = 1) {
-    const void* U = c->U.p;
+    const void* U = c->links();
     bool ufp32 = c->links_fp32;
-    if (fp32 && !c->links_fp32 && c->U32.p) { U = c->U32.p; ufp32 = true; }
+    if (fp32 && !c->links_fp32 && c->links32()) { U = c->links32(); ufp32 = true; }
     // algorithmic bytes per site: spinor in + out, 8 links (4 own, 4 backward neighbours')
     const double sb = fp32 ? 8.0 : 16.0, lb = ufp32 ? 8.0 : 16.0;
     const double bytes = (double)c->g.V * (nrhs * 24.0 * sb + 36.0 * lb);
@@ -209,6 +219,22 @@ void vec_norm(osa_ctx* c, const void* v, bool fp32, cd* out) {
                      nullptr, 0, c->st);
 }
 
+// Work buffers of the tall-skinny kernels (Gram-Schmidt against up to maxcols
+// vectors), shared by the solve and the eigensolver.
+void ensure_exec(osa_ctx* c, int maxcols) {
+    const int64_t N = c->N();
+    const size_t vb = (size_t)N * sizeof(cd);
+    maxcols = std::max(maxcols, 160);
+    c->coef.ensure(sizeof(cd) * maxcols);
+    c->coef2.ensure(sizeof(cd) * maxcols);
+    c->partial.ensure(sizeof(cd) * (size_t)maxcols * 128);
+    c->normp.ensure(sizeof(double) * (size_t)(ceil_div(N, 256) + 16));
+    c->upd_scratch.ensure(vb * 8);
+    c->dscal.ensure(sizeof(cd) * 16);
+    c->flag.ensure(sizeof(int) * 4);
+    c->host.ensure(1 << 16);
+}
+
 void ensure_krylov(osa_ctx* c, int kcap) {
     if (kcap <= c->kcap && c->V.p) return;
     const int64_t N = c->N();
@@ -218,14 +244,7 @@ void ensure_krylov(osa_ctx* c, int kcap) {
     c->w.ensure(vb);
     c->x.ensure(vb);
     c->y.ensure(vb);
-    const int maxcols = std::max(kcap + 1, 128);
-    c->coef.ensure(sizeof(cd) * maxcols);
-    c->coef2.ensure(sizeof(cd) * maxcols);
-    c->partial.ensure(sizeof(cd) * (size_t)maxcols * 128);
-    c->normp.ensure(sizeof(double) * (size_t)(ceil_div(N, 256) + 16));
-    c->upd_scratch.ensure(vb * 8);
-    c->dscal.ensure(sizeof(cd) * 16);
-    c->flag.ensure(sizeof(int) * 4);
+    ensure_exec(c, kcap + 1);
     const int nbk = (int)ceil_div((int64_t)kcap * kcap, 256);
     c->red.ensure(sizeof(double) * (size_t)(2 + 2 * nbk + 16));
     c->sX.ensure(sizeof(cd) * (size_t)kcap * kcap);
@@ -529,7 +548,9 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
     const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
     const int P = nev + pa;              // basis capacity (plus the next vector)
     const int ldS = P + 1;
-    DevBuf Vb, Vt, wv, tv, S, T, Z, wr, bz, info;
+    DevBuf Vb, Vt, wv, tv, S, T, Z, wr, bz, info, Spb, sws;
+    Spb.ensure(sizeof(cd) * (size_t)pa * pa);
+    if (pa > 64) sws.ensure(schur_ws_bytes(pa));
     Vb.ensure(es * (size_t)N * (P + 1));
     Vt.ensure(es * (size_t)N * pa);
     wv.ensure(es * (size_t)N);
@@ -570,12 +591,12 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
         // Schur form of the active Rayleigh quotient, smallest |theta| first
         const double tr0 = now_ms();
         const int na = pa;
-        cd* Sp = c->sM.as<cd>();
+        cd* Sp = Spb.as<cd>();
         OSA_HIP(hipMemcpy2DAsync(Sp, sizeof(cd) * na, S.as<cd>() + nlock + (size_t)nlock * ldS,
                                  sizeof(cd) * ldS, sizeof(cd) * na, na, hipMemcpyDeviceToDevice,
                                  c->st));
         timed(c, 4, 0.0, [&] {
-            small_schur(Sp, na, T.as<cd>(), Z.as<cd>(), wr.as<cd>(), 0, info.as<int>(), nullptr,
+            small_schur(Sp, na, T.as<cd>(), Z.as<cd>(), wr.as<cd>(), 0, info.as<int>(), sws.p,
                         c->st);
         });
         // spike in the Schur basis: b^H Z with b^H = S[ptot, nlock:ptot]
@@ -583,7 +604,10 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
                      Z.as<cd>(), na, mk(0.0, 0.0), bz.as<cd>(), 1, c->st);
         int hinfo = 0;
         d2h(c, info.p, 1, &hinfo);
-        if (hinfo < 0) throw OsaError{OSA_ERR_EIG_NOCONV};
+        if (hinfo < 0)
+            throw OsaError{OSA_ERR_EIG_NOCONV, "small Schur QR did not converge (active block " +
+                                                   std::to_string(na) + ", restart " +
+                                                   std::to_string(rs) + ")"};
         d2h(c, wr.p, na, th.data());
         d2h(c, bz.p, na, bzh.data());
         for (int i = 0; i < na; ++i) anorm = std::max(anorm, cabsd(th[i]));
@@ -599,10 +623,12 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
             sync(c);
             return;
         }
-        // restart: lock nc vectors, keep the wanted ones plus up to half the surplus
+        // restart: lock nc vectors; keep the wanted Schur vectors plus up to half the
+        // surplus, and never less than half of the active block (with few wanted
+        // left, a thin restart would discard the cluster around them)
         const int wa = std::min(want, win);
-        int keep = wa + std::min(nc, (na - wa) / 2);
-        if (keep > na - 2) keep = na - 2;
+        int keep = std::max(wa + std::min(nc, (na - wa) / 2), na / 2);
+        if (keep > na - 4) keep = na - 4;
         if (keep < wa) keep = wa;
         launch_rotate(vec(nlock), N, na, Z.as<cd>(), na, keep, Vt.p, N, fp32, N, c->st);
         OSA_HIP(hipMemcpyAsync(vec(nlock), Vt.p, es * (size_t)N * keep, hipMemcpyDeviceToDevice,
@@ -650,7 +676,9 @@ void rayleigh_ritz(osa_ctx* c, bool adjoint, int nev, int m, cd* X, cd* Rout,
         launch_reduce_partial(c->partial.as<cd>(), p.nchunks, nev, Mb.as<cd>() + (size_t)j * nev,
                               nullptr, nullptr, nullptr, c->st);
     }
-    small_schur(Mb.as<cd>(), nev, T.as<cd>(), Z.as<cd>(), wr.as<cd>(), 1, info.as<int>(), nullptr,
+    DevBuf sws;
+    if (nev > 64) sws.ensure(schur_ws_bytes(nev));
+    small_schur(Mb.as<cd>(), nev, T.as<cd>(), Z.as<cd>(), wr.as<cd>(), 1, info.as<int>(), sws.p,
                 c->st);
     small_eigvecs(T.as<cd>(), Z.as<cd>(), nev, Y.as<cd>(), c->st);
     int hinfo = 0;
@@ -688,11 +716,11 @@ void deflate(osa_ctx* c, int m, osa_info* info) {
     ensure_krylov(c, std::max(c->kcap, std::max(c->opts.k_max, 64)));
     const int extra = std::max(4, m / 5);
     const int nev = m + extra;
-    // active block of the Krylov-Schur basis (the small Schur kernel holds 64)
-    // (the whole basis must fit in the 12 V dimensional space)
+    // active block of the Krylov-Schur basis (the small Schur kernels take up
+    // to 96); the whole basis must fit in the 12 V dimensional space
     const int64_t dim = 12LL * c->g.V;
-    int ncv = c->opts.eig_ncv > 0 ? c->opts.eig_ncv : 64;
-    if (ncv > 64) ncv = 64;
+    int ncv = c->opts.eig_ncv > 0 ? c->opts.eig_ncv : 96;
+    if (ncv > 96) ncv = 96;
     if ((int64_t)nev + ncv + 1 > dim) ncv = (int)std::max<int64_t>(8, dim - nev - 1);
     if (ncv < nev + 4 || (int64_t)nev + ncv + 1 > dim) throw OsaError{OSA_ERR_ARG};
     const double tol = c->opts.eig_tol > 0 ? c->opts.eig_tol : 1e-12;
@@ -710,35 +738,89 @@ void deflate(osa_ctx* c, int m, osa_info* info) {
     KsStats st;
     std::vector<cd> lam_r, lam_l;
     double res_r = 0, res_l = 0;
-    for (int side = 0; side < 2; ++side) {
-        const bool adj = (side == 1);
-        const uint64_t seed = 0x5eedULL + 7919ULL * side;
+    // One side of the eigenproblem: right vectors of H(mu) (adj = false) or of
+    // H(-mu) = H(mu)^dag, i.e. left vectors of H(mu) (adj = true).
+    auto side = [&](osa_ctx* e, bool adj, cd* Xb, cd* Xs, cd* out, std::vector<cd>& lam,
+                    double& res, KsStats& sst) {
+        const uint64_t seed = 0x5eedULL + 7919ULL * (adj ? 1 : 0);
         if (fp32) {
             KsStats s32;
-            ks_run(c, adj, nev, ncv, true, std::max(tol, 1e-6), maxr, nullptr, seed, X.as<cd>(),
-                   s32);
-            st.matvecs += s32.matvecs;
-            st.restarts += s32.restarts;
+            ks_run(e, adj, nev, ncv, true, std::max(tol, 1e-6), maxr, nullptr, seed, Xb, s32);
+            sst.matvecs += s32.matvecs;
+            sst.restarts += s32.restarts;
             // fp64 refinement from the fp32 subspace: start vector = sum of its basis
             std::vector<cd> ones(nev, mk(1.0, 0.0));
-            h2d(c, c->coef.p, ones.data(), nev);
-            launch_combine(Xs.p, X.p, N, nev, c->coef.as<cd>(), false, false, N, c->st);
+            h2d(e, e->coef.p, ones.data(), nev);
+            launch_combine(Xs, Xb, N, nev, e->coef.as<cd>(), false, false, N, e->st);
             KsStats s64;
-            ks_run(c, adj, nev, ncv, false, tol, maxr, Xs.as<cd>(), seed, X.as<cd>(), s64);
-            st.matvecs += s64.matvecs;
-            st.restarts += s64.restarts;
-            if (!s64.converged) throw OsaError{OSA_ERR_EIG_NOCONV};
+            ks_run(e, adj, nev, ncv, false, tol, maxr, Xs, seed, Xb, s64);
+            sst.matvecs += s64.matvecs;
+            sst.restarts += s64.restarts;
+            if (!s64.converged)
+                throw OsaError{OSA_ERR_EIG_NOCONV, "fp64 refinement hit the restart cap"};
         } else {
             KsStats s64;
-            ks_run(c, adj, nev, ncv, false, tol, maxr, nullptr, seed, X.as<cd>(), s64);
-            st.matvecs += s64.matvecs;
-            st.restarts += s64.restarts;
-            if (!s64.converged) throw OsaError{OSA_ERR_EIG_NOCONV};
+            ks_run(e, adj, nev, ncv, false, tol, maxr, nullptr, seed, Xb, s64);
+            sst.matvecs += s64.matvecs;
+            sst.restarts += s64.restarts;
+            if (!s64.converged)
+                throw OsaError{OSA_ERR_EIG_NOCONV, "Krylov-Schur hit the restart cap (" +
+                                                       std::to_string(maxr) + ")"};
         }
-        st.matvecs += nev;
-        if (!adj) rayleigh_ritz(c, false, nev, m, X.as<cd>(), Rn.as<cd>(), lam_r, res_r);
-        else rayleigh_ritz(c, true, nev, m, X.as<cd>(), Ln.as<cd>(), lam_l, res_l);
+        sst.matvecs += nev;
+        rayleigh_ritz(e, adj, nev, m, Xb, out, lam, res);
+    };
+    // the left side runs on a worker clone: own non-blocking stream and work
+    // buffers, the parent's links; ordered after everything queued so far
+    std::unique_ptr<osa_ctx> w(new osa_ctx());
+    w->g = c->g;
+    w->links_fp32 = c->links_fp32;
+    w->mu = c->mu; w->m_w = c->m_w; w->kappa = c->kappa; w->hnorm_bound = c->hnorm_bound;
+    w->hc = c->hc; w->hc_adj = c->hc_adj; w->opts = c->opts;
+    w->u_ext = c->U.p;
+    w->u32_ext = c->U32.p;
+    w->prof_on = c->prof_on;
+    OSA_HIP(hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking));
+    w->own_stream = true;
+    ensure_exec(w.get(), nev + ncv + 1);
+    {
+        hipEvent_t ready;
+        OSA_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        OSA_HIP(hipEventRecord(ready, c->st));
+        OSA_HIP(hipStreamWaitEvent(w->st, ready, 0));
+        OSA_HIP(hipEventSynchronize(ready));
+        (void)hipEventDestroy(ready);
     }
+    DevBuf X2, Xs2;
+    X2.ensure(sizeof(cd) * (size_t)N * nev);
+    Xs2.ensure(sizeof(cd) * N);
+    KsStats st_l;
+    std::exception_ptr werr;
+    std::thread worker([&] {
+        try {
+            side(w.get(), true, X2.as<cd>(), Xs2.as<cd>(), Ln.as<cd>(), lam_l, res_l, st_l);
+        } catch (...) {
+            werr = std::current_exception();
+        }
+    });
+    std::exception_ptr merr;
+    try {
+        side(c, false, X.as<cd>(), Xs.as<cd>(), Rn.as<cd>(), lam_r, res_r, st);
+    } catch (...) {
+        merr = std::current_exception();
+    }
+    worker.join();
+    if (c->prof_on) {
+        for (int i = 0; i < 6; ++i) {
+            c->prof.ms[i] += w->prof.ms[i];
+            c->prof.bytes[i] += w->prof.bytes[i];
+            c->prof.launches[i] += w->prof.launches[i];
+        }
+    }
+    if (merr) std::rethrow_exception(merr);
+    if (werr) std::rethrow_exception(werr);
+    st.matvecs += st_l.matvecs;
+    st.restarts += st_l.restarts;
     // install
     c->R.ensure(sizeof(cd) * (size_t)N * m);
     c->L.ensure(sizeof(cd) * (size_t)N * m);
@@ -755,6 +837,14 @@ void deflate(osa_ctx* c, int m, osa_info* info) {
     c->eig_matvecs = st.matvecs;
     c->eig_restarts = st.restarts;
     if (c->min_abs_re < 1e-12 * hn) throw OsaError{OSA_ERR_IMAG_AXIS};
+    // the Krylov-Schur test is on H^2; the pairs used are checked on H itself
+    if (!(c->max_eig_resid <= 1e-8 * hn)) {
+        c->m_alloc = c->m_active = 0;
+        char b[160];
+        snprintf(b, sizeof b, "eigenpair residual %.3e (right %.3e, left %.3e) above 1e-8 |H|",
+                 c->max_eig_resid, res_r, res_l);
+        throw OsaError{OSA_ERR_EIG_NOCONV, b};
+    }
     set_active(c, m);
     sync(c);
     c->t_init_ms = now_ms() - t0;
@@ -785,15 +875,19 @@ osa_status validate_lattice(const osa_lattice* lat) {
 }
 
 template <typename F>
-osa_status guard(F&& f) {
+osa_status guard(F&& f, std::string* msg = nullptr) {
+    if (msg) msg->clear();
     try {
         return f();
     } catch (const OsaError& e) {
+        if (msg) *msg = e.why;
         return e.s;
     } catch (const HipError& e) {
+        if (msg) *msg = std::string(e.where) + ": " + hipGetErrorString(e.e);
         (void)hipGetLastError();
         return OSA_ERR_HIP;
     } catch (const std::bad_alloc&) {
+        if (msg) *msg = "device allocation failed";
         return OSA_ERR_OOM;
     } catch (...) {
         return OSA_ERR_HIP;
@@ -806,6 +900,8 @@ osa_status guard(F&& f) {
 extern "C" {
 
 const char* osa_version(void) { return "osa 0.1 (gfx950)"; }
+
+const char* osa_last_message(const osa_ctx* c) { return c ? c->msg.c_str() : ""; }
 
 const char* osa_status_string(osa_status s) {
     switch (s) {
@@ -827,7 +923,7 @@ osa_status osa_set_opts(osa_ctx* c, const osa_opts* opts) {
     if (!c) return OSA_ERR_ARG;
     osa_opts o{};
     if (opts) o = *opts;
-    if (o.k_max < 0 || o.k_max > 4000 || o.eig_ncv < 0 || o.eig_ncv > 64 || o.eig_tol < 0 ||
+    if (o.k_max < 0 || o.k_max > 4000 || o.eig_ncv < 0 || o.eig_ncv > 96 || o.eig_tol < 0 ||
         o.eig_max_restarts < 0 || (o.eig_prec != OSA_FP64 && o.eig_prec != OSA_FP32))
         return OSA_ERR_ARG;
     fill_defaults(o);
@@ -888,7 +984,7 @@ osa_status osa_deflate(osa_ctx* c, int32_t n_defl, osa_info* info) {
     return guard([&]() -> osa_status {
         deflate(c, n_defl, info);
         return OSA_OK;
-    });
+    }, &c->msg);
 }
 
 osa_status osa_set_deflation(osa_ctx* c, int32_t m, const void* R, const void* L,
@@ -1072,6 +1168,22 @@ osa_status osa_small_sign(int32_t k, const void* A, void* s, int32_t* iters, voi
         if (iters) *iters = it;
         if (it < 0 || !ok) return OSA_ERR_NEWTON_NOCONV;
         return OSA_OK;
+    });
+}
+
+osa_status osa_small_schur(int32_t p, const void* A, void* T, void* Z, void* w, int32_t mode,
+                           void* stream) {
+    if (p < 1 || p > 96 || !A || !T || !Z || !w || (mode != 0 && mode != 1)) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        hipStream_t st = (hipStream_t)stream;
+        DevBuf info, ws;
+        info.ensure(sizeof(int) * 4);
+        if (p > 64) ws.ensure(schur_ws_bytes(p));
+        small_schur((const cd*)A, p, (cd*)T, (cd*)Z, (cd*)w, mode, info.as<int>(), ws.p, st);
+        int h = 0;
+        OSA_HIP(hipMemcpyAsync(&h, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        OSA_HIP(hipStreamSynchronize(st));
+        return h < 0 ? OSA_ERR_EIG_NOCONV : OSA_OK;
     });
 }
 

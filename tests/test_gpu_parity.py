@@ -113,6 +113,36 @@ def test_small_sign_dense_nonhessenberg(osa):
     assert rel(host(s), ref) < 1e-9
 
 
+# ---------------------------------------------------------- small Schur
+def _ks_like(p, rng, keep):
+    """Triangular leading block + spike row + Hessenberg tail, as after a restart."""
+    a = np.triu(rng.standard_normal((p, p)) + 1j * rng.standard_normal((p, p)), -1)
+    a[:keep, :keep] = np.triu(a[:keep, :keep])
+    a[keep, :keep] = rng.standard_normal(keep) + 1j * rng.standard_normal(keep)
+    return a
+
+
+@pytest.mark.parametrize("p,kind,mode", [(5, "dense", 0), (33, "dense", 1), (64, "ks", 0),
+                                         (65, "dense", 0), (80, "ks", 1), (96, "ks", 0),
+                                         (96, "dense", 1)])
+def test_small_schur_properties(osa, p, kind, mode):
+    say(f"small schur p={p} kind={kind} mode={mode}")
+    rng = np.random.default_rng(p + 7 * mode)
+    a = (rng.standard_normal((p, p)) + 1j * rng.standard_normal((p, p))) if kind == "dense" \
+        else _ks_like(p, rng, p // 2)
+    T, Z, w = osa.small_schur(dev(a), mode)
+    T, Z, w = host(T), host(Z), host(w)
+    nrm = np.linalg.norm(a)
+    assert np.linalg.norm(Z @ T @ Z.conj().T - a) < 1e-12 * nrm
+    assert np.abs(Z.conj().T @ Z - np.eye(p)).max() < 1e-12
+    assert np.abs(np.tril(T, -1)).max() < 1e-13 * nrm
+    key = np.abs(w) if mode == 0 else np.abs(w.real)
+    assert np.all(np.diff(key) >= -1e-12 * nrm)
+    ev = np.linalg.eigvals(a)
+    for x in w:
+        assert np.min(np.abs(ev - x)) < 1e-9 * nrm
+
+
 # ------------------------------------------------- full method, fixed k
 def _fixed_k_case(osa, dims, kind, mu, m, k, inst, reproject=True, eps=0.6):
     links = LI.make_links(dims, kind, eps=eps, cfg=9, inst=inst)
@@ -183,10 +213,12 @@ def test_converged_matches_dense_haar4(osa, haar4_dense):
     ctx.close()
 
 
-def test_deflation_matches_oracle_eigenpairs(osa, haar4_dense):
+@pytest.mark.parametrize("ncv", [96, 32])
+def test_deflation_matches_oracle_eigenpairs(osa, haar4_dense, ncv):
+    """Both Schur kernels: the LDS one (active block <= 64) and the logged one (<= 96)."""
     dims, links, b, h, _ = haar4_dense
-    say("haar4 eigenpairs vs dense oracle")
-    ctx = osa.Context(dev(links), dims, 0.3, -1.5)
+    say(f"haar4 eigenpairs vs dense oracle, active block {ncv}")
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, eig_ncv=ncv)
     ctx.deflate(10)
     R, L, lam = ctx.get_deflation()
     R, L = host(R).T, host(L).T
