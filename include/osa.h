@@ -79,6 +79,9 @@ typedef struct {
     int32_t eig_max_restarts;   /* eigensolver restart cap                 (default 2000)     */
     osa_prec eig_prec;          /* FP32: search in FP32, then refine in FP64 (default FP64)   */
     double eig_tol;             /* relative Krylov-Schur residual target   (default 1e-12)    */
+    int32_t max_batch;          /* sources solved together in lockstep by osa_apply, 1..64
+                                   (default 16); workspace grows with it: max_batch Krylov
+                                   bases of k_max + 1 vectors of N complex128                */
 } osa_opts;
 
 /* Per-solve diagnostics (host struct). */
@@ -95,6 +98,8 @@ typedef struct {
     int64_t eig_matvecs;        /* stencil applications spent in the eigensolver             */
     int32_t eig_restarts;       /* eigensolver restarts (right + left)                        */
     int32_t breakdown;          /* 1: happy Arnoldi breakdown (result exact in K_k)           */
+    int32_t batch;              /* number of sources in the lockstep batch this one ran in;
+                                   t_solve_ms is that batch's wall time                      */
 } osa_info;
 
 typedef struct osa_ctx osa_ctx;
@@ -152,9 +157,15 @@ OSA_API osa_status osa_get_deflation(const osa_ctx* ctx, int32_t* m_out, void* R
 OSA_API osa_status osa_set_active_deflation(osa_ctx* ctx, int32_t m);
 
 /* Y = sign(H_w(mu)) B for nrhs sources (Eq. 22).  B, Y: nrhs*N complex128,
- * source j at offset j*N.  All sources share the deflation data.  infos
- * (host, may be NULL) receives nrhs osa_info records.  Returns the worst
- * status over the sources. */
+ * source j at offset j*N.  All sources share the operator and the deflation
+ * data.  Up to opts.max_batch sources run in lockstep: each Arnoldi step
+ * applies the stencil (links read once for the batch), the re-projection, the
+ * Gram-Schmidt passes and the small sign to all of them with shared launches,
+ * while every source keeps its own Krylov basis, convergence check and
+ * stopping point (the method itself is per source, Eq. 22).  infos (host,
+ * may be NULL) receives nrhs osa_info records.  Returns the first error in
+ * source order, else the worst status; Y of a source with an error status is
+ * left unwritten. */
 OSA_API osa_status osa_apply(osa_ctx* ctx, int32_t nrhs, const void* B, void* Y, double tol,
                      osa_info* infos);
 

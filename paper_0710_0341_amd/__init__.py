@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("no_reproject", ctypes.c_int32), ("eig_ncv", ctypes.c_int32),
                 ("eig_max_restarts", ctypes.c_int32), ("eig_prec", ctypes.c_int32),
-                ("eig_tol", ctypes.c_double)]
+                ("eig_tol", ctypes.c_double), ("max_batch", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -54,7 +54,8 @@ class Info(ctypes.Structure):
                 ("t_solve_ms", ctypes.c_double), ("k_used", ctypes.c_int32),
                 ("n_defl", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("newton_iters", ctypes.c_int32), ("eig_matvecs", ctypes.c_int64),
-                ("eig_restarts", ctypes.c_int32), ("breakdown", ctypes.c_int32)]
+                ("eig_restarts", ctypes.c_int32), ("breakdown", ctypes.c_int32),
+                ("batch", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -158,11 +159,12 @@ def _lattice(dims, antiperiodic_t=False):
 
 
 def make_opts(k_max=0, check_every=0, no_reproject=False, eig_ncv=0, eig_max_restarts=0,
-              eig_prec=FP64, eig_tol=0.0):
+              eig_prec=FP64, eig_tol=0.0, max_batch=0):
     o = Opts()
     o.k_max, o.check_every, o.no_reproject = int(k_max), int(check_every), int(bool(no_reproject))
     o.eig_ncv, o.eig_max_restarts, o.eig_prec = int(eig_ncv), int(eig_max_restarts), int(eig_prec)
     o.eig_tol = float(eig_tol)
+    o.max_batch = int(max_batch)
     return o
 
 
@@ -268,15 +270,18 @@ class Context:
     def set_active_deflation(self, m):
         _check(lib().osa_set_active_deflation(self._h, int(m)), "osa_set_active_deflation", False)
 
-    def apply(self, B, tol=1e-10):
-        """Y = sign(H) B for B of shape (N,) or (nrhs, N).  Returns (Y, infos, status)."""
+    def apply(self, B, tol=1e-10, check=True):
+        """Y = sign(H) B for B of shape (N,) or (nrhs, N).  Returns (Y, infos, status).
+        Up to max_batch sources run in lockstep.  check=False returns error
+        statuses instead of raising (per-source statuses are in infos)."""
         torch = _torch()
         bp = _dev_ptr(B, torch.complex128, "B")
         nrhs = 1 if B.dim() == 1 else int(B.shape[0])
-        Y = torch.empty_like(B)
+        Y = torch.zeros_like(B)
         infos = (Info * nrhs)()
         st = lib().osa_apply(self._h, nrhs, bp, ctypes.c_void_p(Y.data_ptr()), float(tol), infos)
-        _check(st, "osa_apply")
+        if check:
+            _check(st, "osa_apply")
         return Y, [i.as_dict() for i in infos], st
 
     def set_links(self, links):

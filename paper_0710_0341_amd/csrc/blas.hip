@@ -5,6 +5,10 @@
 // one sequential sum per output), so results are bitwise reproducible run to
 // run.  Vectors are stored as complex128 (double2) or complex64 (float2);
 // every accumulation is in double.
+//
+// Every kernel takes a Batch: one grid axis runs over the problems of the
+// batch, and each array argument is offset by the problem's stride.  The
+// arithmetic of one problem does not depend on the batch it runs in.
 #include "kernels.hpp"
 
 namespace osa {
@@ -55,9 +59,13 @@ template <typename T, int C>
 __global__ __launch_bounds__(kBlock) void k_dot_partial(const T* __restrict__ B, int64_t ldb,
                                                         int ncols, const T* __restrict__ w,
                                                         int64_t n, int rpc, int nchunks,
-                                                        cd* __restrict__ partial) {
+                                                        cd* __restrict__ partial, Batch bt) {
     __shared__ double sm[kWaves * 2 * C];
     __shared__ double so[2 * C];
+    const int pb = bt.idx[blockIdx.z];
+    B += pb * bt.basis;
+    w += pb * bt.vec;
+    partial += pb * bt.part;
     const int q = blockIdx.x;
     const int c0 = blockIdx.y * C;
     const int64_t r0 = (int64_t)q * rpc;
@@ -95,16 +103,16 @@ __global__ __launch_bounds__(kBlock) void k_dot_partial(const T* __restrict__ B,
 }
 
 void launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bool fp32,
-                        const TsPlan& p, cd* partial, hipStream_t st) {
-    if (ncols <= 0) return;
+                        const TsPlan& p, cd* partial, hipStream_t st, const Batch& bt) {
+    if (ncols <= 0 || bt.n <= 0) return;
     constexpr int C = 8;
-    dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C)), blk(kBlock);
+    dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)bt.n), blk(kBlock);
     if (fp32)
         hipLaunchKernelGGL((k_dot_partial<cf, C>), grid, blk, 0, st, (const cf*)B, ldb, ncols,
-                           (const cf*)w, p.n, p.rows_per_chunk, p.nchunks, partial);
+                           (const cf*)w, p.n, p.rows_per_chunk, p.nchunks, partial, bt);
     else
         hipLaunchKernelGGL((k_dot_partial<cd, C>), grid, blk, 0, st, (const cd*)B, ldb, ncols,
-                           (const cd*)w, p.n, p.rows_per_chunk, p.nchunks, partial);
+                           (const cd*)w, p.n, p.rows_per_chunk, p.nchunks, partial, bt);
     OSA_LAUNCH_CHECK();
 }
 
@@ -114,7 +122,11 @@ void launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bo
 // out[c] = val (set); accum[c] += val when accum != nullptr.
 __global__ __launch_bounds__(256) void k_reduce_cols(const cd* __restrict__ partial, int nchunks,
                                                      int ncols, cd* __restrict__ out,
-                                                     cd* __restrict__ accum) {
+                                                     cd* __restrict__ accum, Batch bt) {
+    const int pb = bt.idx[blockIdx.y];
+    partial += pb * bt.part;
+    out += pb * bt.small;
+    if (accum) accum += pb * bt.small;
     const int lane = threadIdx.x & 63;
     const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (c >= ncols) return;
@@ -132,11 +144,16 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const cd* __restrict__ part
     }
 }
 
-// One block: val = sum over chunks, then out = M val (M: ncols x ncols, used for
-// G^{-1} L^dag w with the small m x m matrix G^{-1}).
+// One block per problem: val = sum over chunks, then out = M val (M: ncols x
+// ncols, used for G^{-1} L^dag w with the small m x m matrix G^{-1}).
 __global__ __launch_bounds__(1024) void k_reduce_apply(const cd* __restrict__ partial, int nchunks,
                                                        int ncols, cd* out,
-                                                       const cd* __restrict__ M, cd* tmp) {
+                                                       const cd* __restrict__ M, cd* tmp,
+                                                       Batch bt) {
+    const int pb = bt.idx[blockIdx.x];
+    partial += pb * bt.part;
+    out += pb * bt.small;
+    tmp += pb * bt.small;
     for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
         cd s = mk(0.0, 0.0);
         for (int q = 0; q < nchunks; ++q) s = cadd(s, partial[(int64_t)c * nchunks + q]);
@@ -151,15 +168,15 @@ __global__ __launch_bounds__(1024) void k_reduce_apply(const cd* __restrict__ pa
 }
 
 void launch_reduce_partial(const cd* partial, int nchunks, int ncols, cd* out, cd* accum,
-                           const cd* M, cd* tmp, hipStream_t st) {
-    if (ncols <= 0) return;
+                           const cd* M, cd* tmp, hipStream_t st, const Batch& bt) {
+    if (ncols <= 0 || bt.n <= 0) return;
     if (M) {
         int threads = ncols >= 1024 ? 1024 : (int)ceil_div(ncols, 64) * 64;
-        hipLaunchKernelGGL(k_reduce_apply, dim3(1), dim3(threads), 0, st, partial, nchunks, ncols,
-                           out, M, tmp);
+        hipLaunchKernelGGL(k_reduce_apply, dim3((unsigned)bt.n), dim3(threads), 0, st, partial,
+                           nchunks, ncols, out, M, tmp, bt);
     } else {
-        hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)ceil_div(ncols, 4)), dim3(256), 0, st,
-                           partial, nchunks, ncols, out, accum);
+        hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)ceil_div(ncols, 4), (unsigned)bt.n),
+                           dim3(256), 0, st, partial, nchunks, ncols, out, accum, bt);
     }
     OSA_LAUNCH_CHECK();
 }
@@ -199,10 +216,15 @@ __global__ __launch_bounds__(kBlock) void k_update_direct(T* w, const T* __restr
                                                           int64_t ldb, int ncols,
                                                           const cd* __restrict__ coef, int64_t n,
                                                           double alpha, double sgn,
-                                                          double* normp) {
+                                                          double* normp, Batch bt) {
     __shared__ cd scoef[kCoefTile];
     __shared__ double sm[kWaves];
     __shared__ double so[1];
+    const int pb = bt.idx[blockIdx.y];
+    w += pb * bt.vec;
+    B += pb * bt.basis;
+    coef += pb * bt.small;
+    if (normp) normp += pb * bt.part;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t ii = (i < n) ? i : n - 1;   // keep every thread in the barriers
     cd acc = gemv_rows(B, ldb, 0, ncols, coef, ii, scoef);
@@ -224,8 +246,13 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_split(const T* __restrict__ B, int64_t ldb,
                                                          int ncols, const cd* __restrict__ coef,
                                                          int64_t n, int cpg,
-                                                         cd* __restrict__ scratch) {
+                                                         cd* __restrict__ scratch, int G,
+                                                         Batch bt) {
     __shared__ cd scoef[kCoefTile];
+    const int pb = bt.idx[blockIdx.z];
+    B += pb * bt.basis;
+    coef += pb * bt.small;
+    scratch += (int64_t)blockIdx.z * G * n;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t ii = (i < n) ? i : n - 1;
     const int g = blockIdx.y;
@@ -238,9 +265,13 @@ __global__ __launch_bounds__(kBlock) void k_update_split(const T* __restrict__ B
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_finish(T* w, const cd* __restrict__ scratch,
                                                           int G, int64_t n, double alpha,
-                                                          double sgn, double* normp) {
+                                                          double sgn, double* normp, Batch bt) {
     __shared__ double sm[kWaves];
     __shared__ double so[1];
+    const int pb = bt.idx[blockIdx.y];
+    w += pb * bt.vec;
+    if (normp) normp += pb * bt.part;
+    scratch += (int64_t)blockIdx.y * G * n;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     cd v = mk(0.0, 0.0);
     if (i < n) {
@@ -261,59 +292,67 @@ __global__ __launch_bounds__(kBlock) void k_update_finish(T* w, const cd* __rest
 template <typename T>
 static void update_impl(T* w, const T* B, int64_t ldb, int ncols, const cd* coef, int64_t n,
                         double alpha, double sgn, double* normp, cd* scratch,
-                        int64_t scratch_len, hipStream_t st) {
+                        int64_t scratch_len, hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0) return;
     const int rb = (int)ceil_div(n, kBlock);
+    // The split depends on the row count and the column count only, not on the
+    // batch, so a problem gets the same summation order in any batch (the
+    // caller sizes scratch to 8 n per problem).
     int G = 1;
     if (ncols > 32 && rb < 1024 && scratch) {
         G = (int)ceil_div(1024, rb);
         int gmax = ncols / 16;
         if (G > gmax) G = gmax;
-        while (G > 1 && (int64_t)G * n > scratch_len) --G;
+        if (G > 8) G = 8;
+        while (G > 1 && (int64_t)G * n * bt.n > scratch_len) --G;
     }
     if (G <= 1) {
-        hipLaunchKernelGGL((k_update_direct<T>), dim3(rb), dim3(kBlock), 0, st, w, B, ldb, ncols,
-                           coef, n, alpha, sgn, normp);
+        hipLaunchKernelGGL((k_update_direct<T>), dim3(rb, bt.n), dim3(kBlock), 0, st, w, B, ldb,
+                           ncols, coef, n, alpha, sgn, normp, bt);
     } else {
         const int cpg = (int)ceil_div(ncols, G);
         G = (int)ceil_div(ncols, cpg);
-        hipLaunchKernelGGL((k_update_split<T>), dim3(rb, G), dim3(kBlock), 0, st, B, ldb, ncols,
-                           coef, n, cpg, scratch);
-        hipLaunchKernelGGL((k_update_finish<T>), dim3(rb), dim3(kBlock), 0, st, w,
-                           (const cd*)scratch, G, n, alpha, sgn, normp);
+        hipLaunchKernelGGL((k_update_split<T>), dim3(rb, G, bt.n), dim3(kBlock), 0, st, B, ldb,
+                           ncols, coef, n, cpg, scratch, G, bt);
+        hipLaunchKernelGGL((k_update_finish<T>), dim3(rb, bt.n), dim3(kBlock), 0, st, w,
+                           (const cd*)scratch, G, n, alpha, sgn, normp, bt);
     }
     OSA_LAUNCH_CHECK();
 }
 
-// Norm partials from the update kernels are per 256-row block; the plan passed
-// to launch_normalize must then have rows_per_chunk = 256.
+// Norm partials from the update kernels are per 256-row block, the layout
+// launch_normalize reads.
 void launch_update(void* w, const void* B, int64_t ldb, int ncols, const cd* coef, bool fp32,
                    const TsPlan& p, double* normp, cd* scratch, int64_t scratch_len,
-                   hipStream_t st) {
+                   hipStream_t st, const Batch& bt) {
     if (ncols <= 0 && !normp) return;
     if (fp32)
         update_impl<cf>((cf*)w, (const cf*)B, ldb, ncols, coef, p.n, 1.0, -1.0, normp, scratch,
-                        scratch_len, st);
+                        scratch_len, st, bt);
     else
         update_impl<cd>((cd*)w, (const cd*)B, ldb, ncols, coef, p.n, 1.0, -1.0, normp, scratch,
-                        scratch_len, st);
+                        scratch_len, st, bt);
 }
 
 void launch_combine(void* y, const void* B, int64_t ldb, int ncols, const cd* coef, bool fp32,
-                    bool add, int64_t n, hipStream_t st) {
+                    bool add, int64_t n, hipStream_t st, const Batch& bt) {
     if (fp32)
         update_impl<cf>((cf*)y, (const cf*)B, ldb, ncols, coef, n, add ? 1.0 : 0.0, 1.0, nullptr,
-                        nullptr, 0, st);
+                        nullptr, 0, st, bt);
     else
         update_impl<cd>((cd*)y, (const cd*)B, ldb, ncols, coef, n, add ? 1.0 : 0.0, 1.0, nullptr,
-                        nullptr, 0, st);
+                        nullptr, 0, st, bt);
 }
 
 // ---------------------------------------------------------------- norms
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_norm_partial(const T* __restrict__ w, int64_t n,
-                                                         double* normp) {
+                                                         double* normp, Batch bt) {
     __shared__ double sm[kWaves];
     __shared__ double so[1];
+    const int pb = bt.idx[blockIdx.y];
+    w += pb * bt.vec;
+    normp += pb * bt.part;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double nv[1] = {(i < n) ? cabs2(tod(w[i])) : 0.0};
     block_sum<1>(nv, sm, so);
@@ -321,24 +360,32 @@ __global__ __launch_bounds__(kBlock) void k_norm_partial(const T* __restrict__ w
 }
 
 void launch_norm_partial(const void* w, bool fp32, const TsPlan& p, double* normp,
-                         hipStream_t st) {
+                         hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0) return;
     const int rb = (int)ceil_div(p.n, kBlock);
     if (fp32)
-        hipLaunchKernelGGL((k_norm_partial<cf>), dim3(rb), dim3(kBlock), 0, st, (const cf*)w, p.n,
-                           normp);
+        hipLaunchKernelGGL((k_norm_partial<cf>), dim3(rb, bt.n), dim3(kBlock), 0, st,
+                           (const cf*)w, p.n, normp, bt);
     else
-        hipLaunchKernelGGL((k_norm_partial<cd>), dim3(rb), dim3(kBlock), 0, st, (const cd*)w, p.n,
-                           normp);
+        hipLaunchKernelGGL((k_norm_partial<cd>), dim3(rb, bt.n), dim3(kBlock), 0, st,
+                           (const cd*)w, p.n, normp, bt);
     OSA_LAUNCH_CHECK();
 }
 
-// single block: hsub = sqrt(sum normp) (+ breakdown test)
+// one block per problem: hsub = sqrt(sum normp) (+ breakdown test)
 __global__ __launch_bounds__(1024) void k_norm_finish(const double* __restrict__ normp, int nb,
                                                       cd* hsub, double* hfro2, double rel,
                                                       int* flag, int step,
-                                                      const cd* __restrict__ hcol, int hlen) {
+                                                      const cd* __restrict__ hcol, int hlen,
+                                                      Batch bt) {
     __shared__ double sred[16];
     __shared__ double shcol;
+    const int pb = bt.idx[blockIdx.x];
+    normp += pb * bt.part;
+    hsub += pb * bt.scal;
+    if (hfro2) hfro2 += 2 * pb * bt.scal;
+    if (flag) flag += pb * bt.flag;
+    if (hcol) hcol += pb * bt.small;
     if (hcol && hfro2) {
         double a = 0;
         for (int i = threadIdx.x; i < hlen; i += blockDim.x) a += cabs2(hcol[i]);
@@ -379,30 +426,51 @@ __global__ __launch_bounds__(1024) void k_norm_finish(const double* __restrict__
     }
 }
 
+// v = w / f (divide) or w * f with f = factor->x; v = 0 when flag is set.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scale_by(const T* __restrict__ w, T* __restrict__ v,
-                                                     int64_t n, const cd* hsub, const int* flag) {
+                                                     int64_t n, const cd* factor, const int* flag,
+                                                     int divide, Batch bt) {
+    const int pb = bt.idx[blockIdx.y];
+    w += pb * bt.vec;
+    v += pb * bt.basis;
+    factor += pb * bt.scal;
+    if (flag) flag += pb * bt.flag;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const bool bd = flag && *flag;
-    const double inv = bd ? 0.0 : 1.0 / hsub->x;
-    v[i] = fromd<T>(cscale(tod(w[i]), inv));
+    const double f = bd ? 0.0 : (divide ? 1.0 / factor->x : factor->x);
+    v[i] = fromd<T>(cscale(tod(w[i]), f));
 }
 
 void launch_normalize(const void* w, void* v, bool fp32, const TsPlan& p, const double* normp,
                       cd* hsub, double* hfro2, double rel, int* flag, int step,
-                      const cd* hcol, int hlen, hipStream_t st) {
+                      const cd* hcol, int hlen, hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0) return;
     const int nb = (int)ceil_div(p.n, kBlock);
-    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(256), 0, st, normp, nb, hsub, hfro2, rel, flag,
-                       step, hcol, hlen);
+    hipLaunchKernelGGL(k_norm_finish, dim3((unsigned)bt.n), dim3(256), 0, st, normp, nb, hsub,
+                       hfro2, rel, flag, step, hcol, hlen, bt);
     if (!v) { OSA_LAUNCH_CHECK(); return; }
     const int rb = (int)ceil_div(p.n, kBlock);
     if (fp32)
-        hipLaunchKernelGGL((k_scale_by<cf>), dim3(rb), dim3(kBlock), 0, st, (const cf*)w, (cf*)v,
-                           p.n, (const cd*)hsub, (const int*)flag);
+        hipLaunchKernelGGL((k_scale_by<cf>), dim3(rb, bt.n), dim3(kBlock), 0, st, (const cf*)w,
+                           (cf*)v, p.n, (const cd*)hsub, (const int*)flag, 1, bt);
     else
-        hipLaunchKernelGGL((k_scale_by<cd>), dim3(rb), dim3(kBlock), 0, st, (const cd*)w, (cd*)v,
-                           p.n, (const cd*)hsub, (const int*)flag);
+        hipLaunchKernelGGL((k_scale_by<cd>), dim3(rb, bt.n), dim3(kBlock), 0, st, (const cd*)w,
+                           (cd*)v, p.n, (const cd*)hsub, (const int*)flag, 1, bt);
+    OSA_LAUNCH_CHECK();
+}
+
+void launch_scale_dev(const void* w, void* v, bool fp32, int64_t n, const cd* factor, bool divide,
+                      hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0) return;
+    const int rb = (int)ceil_div(n, kBlock);
+    if (fp32)
+        hipLaunchKernelGGL((k_scale_by<cf>), dim3(rb, bt.n), dim3(kBlock), 0, st, (const cf*)w,
+                           (cf*)v, n, factor, (const int*)nullptr, divide ? 1 : 0, bt);
+    else
+        hipLaunchKernelGGL((k_scale_by<cd>), dim3(rb, bt.n), dim3(kBlock), 0, st, (const cd*)w,
+                           (cd*)v, n, factor, (const int*)nullptr, divide ? 1 : 0, bt);
     OSA_LAUNCH_CHECK();
 }
 

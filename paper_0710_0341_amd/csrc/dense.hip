@@ -26,6 +26,17 @@ size_t gj_ws_bytes(int k) {
     return (size_t)k * (2 * sizeof(cd) + sizeof(double2) + 3 * sizeof(int)) + 256;
 }
 
+// the workspace of problem pb of a batch (byte stride bt.ws)
+__device__ __forceinline__ GjWs gj_at(GjWs w, const Batch& bt, int pb) {
+    const int64_t off = pb * bt.ws;
+    w.col = (cd*)((char*)w.col + off);
+    w.piv = (double2*)((char*)w.piv + off);
+    w.perm = (int*)((char*)w.perm + off);
+    w.pinv = (int*)((char*)w.pinv + off);
+    w.used = (int*)((char*)w.used + off);
+    return w;
+}
+
 static GjWs gj_ws(void* ws, int k) {
     char* p = (char*)ws;
     GjWs w;
@@ -64,9 +75,13 @@ __device__ void block_argmax(double v, int idx, double* sv, int* si, double& ov,
     }
 }
 
-__global__ __launch_bounds__(kGjThreads) void k_gj_init(const cd* __restrict__ M, int k, GjWs w) {
+__global__ __launch_bounds__(kGjThreads) void k_gj_init(const cd* __restrict__ M, int k, GjWs w,
+                                                       Batch bt) {
     __shared__ double sv[kGjThreads / 64];
     __shared__ int si[kGjThreads / 64];
+    const int pb = bt.idx[blockIdx.x];
+    M += pb * bt.mat;
+    w = gj_at(w, bt, pb);
     double bv = -1.0;
     int bi = 0x7fffffff;
     for (int i = threadIdx.x; i < k; i += kGjThreads) {
@@ -84,9 +99,14 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_init(const cd* __restrict__ M
 }
 
 __global__ __launch_bounds__(kGjThreads) void k_gj_step(cd* __restrict__ M, int k, int t, GjWs w,
-                                                       double* logpiv, int* flag) {
+                                                       double* logpiv, int* flag, Batch bt) {
     __shared__ double sv[kGjThreads / 64];
     __shared__ int si[kGjThreads / 64];
+    const int pb = bt.idx[blockIdx.y];
+    M += pb * bt.mat;
+    w = gj_at(w, bt, pb);
+    logpiv += pb * bt.small;
+    flag += pb * bt.flag;
     const cd* colc = w.col + (size_t)(t & 1) * k;
     cd* coln = w.col + (size_t)((t + 1) & 1) * k;
     // A column of NaNs selects no pivot; keep every index in range and flag it.
@@ -138,7 +158,8 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_step(cd* __restrict__ M, int 
     }
 }
 
-__global__ void k_gj_pinv(int k, GjWs w) {
+__global__ void k_gj_pinv(int k, GjWs w, Batch bt) {
+    w = gj_at(w, bt, bt.idx[blockIdx.y]);
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < k; s += gridDim.x * blockDim.x) {
         const int q = w.perm[s];
         if (q >= 0 && q < k) w.pinv[q] = s;
@@ -146,7 +167,11 @@ __global__ void k_gj_pinv(int k, GjWs w) {
 }
 
 __global__ __launch_bounds__(256) void k_gj_gather(const cd* __restrict__ M, cd* __restrict__ Y,
-                                                  int k, GjWs w) {
+                                                  int k, GjWs w, Batch bt) {
+    const int pb = bt.idx[blockIdx.y];
+    M += pb * bt.mat;
+    Y += pb * bt.mat;
+    w = gj_at(w, bt, pb);
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)k * k) return;
     const int t = (int)(e % k), c = (int)(e / k);
@@ -156,16 +181,21 @@ __global__ __launch_bounds__(256) void k_gj_gather(const cd* __restrict__ M, cd*
     Y[e] = M[r + (size_t)q * k];
 }
 
-void gj_invert(cd* M, cd* Y, int k, double* logpiv, int* flag, void* ws, hipStream_t st) {
+void gj_invert(cd* M, cd* Y, int k, double* logpiv, int* flag, void* ws, hipStream_t st,
+               const Batch& bt) {
+    if (bt.n <= 0) return;
     GjWs w = gj_ws(ws, k);
-    hipLaunchKernelGGL(k_gj_init, dim3(1), dim3(kGjThreads), 0, st, (const cd*)M, k, w);
+    const unsigned nbt = (unsigned)bt.n;
+    hipLaunchKernelGGL(k_gj_init, dim3(nbt), dim3(kGjThreads), 0, st, (const cd*)M, k, w, bt);
     const int nb = (int)ceil_div(k, kGjCols);
     for (int t = 0; t < k; ++t)
-        hipLaunchKernelGGL(k_gj_step, dim3(nb), dim3(kGjThreads), 0, st, M, k, t, w, logpiv, flag);
-    hipLaunchKernelGGL(k_gj_pinv, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, st, k, w);
+        hipLaunchKernelGGL(k_gj_step, dim3(nb, nbt), dim3(kGjThreads), 0, st, M, k, t, w, logpiv,
+                           flag, bt);
+    hipLaunchKernelGGL(k_gj_pinv, dim3((unsigned)ceil_div(k, 256), nbt), dim3(256), 0, st, k, w,
+                       bt);
     if (Y) {
-        hipLaunchKernelGGL(k_gj_gather, dim3((unsigned)ceil_div((int64_t)k * k, 256)), dim3(256), 0,
-                           st, (const cd*)M, Y, k, w);
+        hipLaunchKernelGGL(k_gj_gather, dim3((unsigned)ceil_div((int64_t)k * k, 256), nbt),
+                           dim3(256), 0, st, (const cd*)M, Y, k, w, bt);
     }
     OSA_LAUNCH_CHECK();
 }
@@ -176,9 +206,16 @@ void gj_invert(cd* M, cd* Y, int k, double* logpiv, int* flag, void* ws, hipStre
 // Y holds X^{-1}.  Per-block partial sums of |Xnew - X|^2 and |Xnew|^2.
 __global__ __launch_bounds__(256) void k_newton_combine(cd* __restrict__ X, const cd* __restrict__ Y,
                                                        int k, const double* __restrict__ logpiv,
-                                                       int scale, double* part) {
+                                                       uint64_t scale_mask, double* part,
+                                                       Batch bt) {
     __shared__ double sm[8];
     __shared__ double smu;
+    const int pb = bt.idx[blockIdx.y];
+    X += pb * bt.mat;
+    Y += pb * bt.mat;
+    logpiv += pb * bt.small;
+    part += pb * bt.part + 2;
+    const bool scale = (scale_mask >> pb) & 1ULL;
     if (threadIdx.x == 0) {
         double mu = 1.0;
         if (scale) {
@@ -215,8 +252,11 @@ __global__ __launch_bounds__(256) void k_newton_combine(cd* __restrict__ X, cons
     }
 }
 
-__global__ void k_sum_pairs(const double* __restrict__ part, int nb, double* red) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ void k_sum_pairs(const double* __restrict__ part, int nb, double* red, Batch bt) {
+    const int pb = bt.idx[blockIdx.x];
+    red += pb * bt.part;
+    part = red + 2;
+    if (threadIdx.x == 0) {
         double a = 0, b = 0;
         for (int i = 0; i < nb; ++i) { a += part[2 * i]; b += part[2 * i + 1]; }
         red[0] = a;
@@ -224,13 +264,51 @@ __global__ void k_sum_pairs(const double* __restrict__ part, int nb, double* red
     }
 }
 
-void launch_newton_combine(cd* X, const cd* Y, int k, const double* logpiv, bool scale,
-                           double* red, hipStream_t st) {
+int64_t newton_red_len(int k) { return 2 + 2 * ceil_div((int64_t)k * k, 256); }
+
+void launch_newton_combine(cd* X, const cd* Y, int k, const double* logpiv, uint64_t scale_mask,
+                           double* red, hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0) return;
     const int nb = (int)ceil_div((int64_t)k * k, 256);
-    double* part = red + 2;   // caller provides 2 + 2*nb doubles
-    hipLaunchKernelGGL(k_newton_combine, dim3(nb), dim3(256), 0, st, X, Y, k, logpiv, scale ? 1 : 0,
-                       part);
-    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(64), 0, st, (const double*)part, nb, red);
+    // per problem: red[0..1] the sums, red[2..] the per-block partials
+    hipLaunchKernelGGL(k_newton_combine, dim3(nb, bt.n), dim3(256), 0, st, X, Y, k, logpiv,
+                       scale_mask, red, bt);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(bt.n), dim3(64), 0, st, (const double*)nullptr, nb, red,
+                       bt);
+    OSA_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(256) void k_copy_square(const cd* __restrict__ A, int lda,
+                                                    cd* __restrict__ X, int k, Batch bt) {
+    const int pb = bt.idx[blockIdx.y];
+    A += pb * bt.basis;
+    X += pb * bt.mat;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)k * k) return;
+    const int i = (int)(e % k), j = (int)(e / k);
+    X[e] = A[i + (int64_t)j * lda];
+}
+
+void launch_copy_square(const cd* A, int lda, cd* X, int k, hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0 || k <= 0) return;
+    hipLaunchKernelGGL(k_copy_square, dim3((unsigned)ceil_div((int64_t)k * k, 256), bt.n),
+                       dim3(256), 0, st, A, lda, X, k, bt);
+    OSA_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(256) void k_copy_col(const cd* __restrict__ X, int k,
+                                                 cd* __restrict__ s, Batch bt) {
+    const int pb = bt.idx[blockIdx.y];
+    X += pb * bt.mat;
+    s += pb * bt.small;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) s[i] = X[i];
+}
+
+void launch_copy_col0(const cd* X, int k, cd* s, hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0 || k <= 0) return;
+    hipLaunchKernelGGL(k_copy_col, dim3((unsigned)ceil_div(k, 256), bt.n), dim3(256), 0, st, X, k,
+                       s, bt);
     OSA_LAUNCH_CHECK();
 }
 
@@ -283,8 +361,12 @@ void launch_zgemm(int opA, int opB, int m, int n, int kk, cd alpha, const cd* A,
 
 // |s - [sprev; 0]|  (one block)
 __global__ void k_diff_norm(const cd* __restrict__ s, int k, const cd* __restrict__ sp, int kp,
-                            double* out) {
+                            double* out, Batch bt) {
     __shared__ double sm[4];
+    const int pb = bt.idx[blockIdx.x];
+    s += pb * bt.small;
+    sp += pb * bt.small;
+    out += pb * bt.scal;
     double a = 0;
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
         cd d = s[i];
@@ -299,8 +381,9 @@ __global__ void k_diff_norm(const cd* __restrict__ s, int k, const cd* __restric
 }
 
 void launch_diff_norm(const cd* s, int k, const cd* sprev, int kprev, double* out,
-                      hipStream_t st) {
-    hipLaunchKernelGGL(k_diff_norm, dim3(1), dim3(256), 0, st, s, k, sprev, kprev, out);
+                      hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0) return;
+    hipLaunchKernelGGL(k_diff_norm, dim3(bt.n), dim3(256), 0, st, s, k, sprev, kprev, out, bt);
     OSA_LAUNCH_CHECK();
 }
 

@@ -15,6 +15,27 @@ struct HopCoef {
     double bwd[4];
 };
 
+// ------------------------------------------------------------- batching
+// One launch can work on several independent problems (sources) at once.
+// Launch entry z works on problem idx[z]; an array argument of problem b starts
+// at its base pointer plus b times the stride named below (in elements of that
+// array; 0 = shared by all problems).  A default Batch is the single-problem
+// case.  Each launcher states which strides it reads.
+constexpr int kMaxBatch = 64;
+struct Batch {
+    int n = 1;
+    int64_t basis = 0;   // a basis / the columns read by a dot or an update
+    int64_t vec = 0;     // an N-length work vector
+    int64_t small = 0;   // coefficient vectors (h columns, G^{-1} L^dag w, s)
+    int64_t part = 0;    // partial-sum workspace
+    int64_t scal = 0;    // per-problem scalar slots (cd)
+    int64_t flag = 0;    // per-problem int flags
+    int64_t mat = 0;     // small dense matrices
+    int64_t ws = 0;      // small dense workspace (bytes)
+    int16_t idx[kMaxBatch];
+    Batch() { for (int i = 0; i < kMaxBatch; ++i) idx[i] = (int16_t)i; }
+};
+
 // ------------------------------------------------------------- layout (S0)
 void launch_links_to_internal(const void* links_aos, bool in_fp32, void* links_int,
                               bool int_fp32, const Geom& g, hipStream_t st);
@@ -24,10 +45,16 @@ void launch_vec_from_internal(const void* soa, bool soa_fp32, cd* aos, const Geo
                               int nvec, hipStream_t st);
 
 // ------------------------------------------------------------- stencil (S1)
-// out = gamma_5 D_w(mu) in, for nrhs vectors spaced by the internal length.
+// out = gamma_5 D_w(mu) in.  Batch strides: basis (in), vec (out).  The
+// problems of a batch share the links; the launch visits each block of sites
+// for all problems back to back so that the links are read from HBM once.
 void launch_wilson_h(const void* in, void* out, const void* U, bool links_fp32,
-                     bool spinor_fp32, const Geom& g, const HopCoef& c, int nrhs,
-                     hipStream_t st);
+                     bool spinor_fp32, const Geom& g, const HopCoef& c, hipStream_t st,
+                     const Batch& bt = Batch());
+// Contiguous vectors: nrhs inputs and outputs spaced by the internal length.
+void launch_wilson_h_contig(const void* in, void* out, const void* U, bool links_fp32,
+                            bool spinor_fp32, const Geom& g, const HopCoef& c, int nrhs,
+                            hipStream_t st);
 
 // ------------------------------------------------- tall-skinny BLAS (S3,S4,S7)
 // Workspace sizes for the two-stage reductions.
@@ -40,34 +67,44 @@ TsPlan ts_plan(int64_t n);
 
 // partial[c*nchunks + q] = sum over chunk q of conj(B[c][i]) w[i], c < ncols.
 // B: ncols vectors of length n spaced by ldb; storage fp64 or fp32.
+// Batch strides: basis (B), vec (w), part (partial).
 void launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bool fp32,
-                        const TsPlan& p, cd* partial, hipStream_t st);
+                        const TsPlan& p, cd* partial, hipStream_t st, const Batch& bt = Batch());
 // out[c] = sum_q partial[c*nchunks+q] and accum[c] += out[c] (accum nullable).
 // With M != nullptr (m x m, column-major) out = M * sums instead (used for
-// G^{-1} L^dag w); tmp then holds ncols scratch entries.
+// G^{-1} L^dag w, M shared by the batch); tmp then holds ncols scratch entries.
+// Batch strides: part (partial), small (out, accum, tmp).
 void launch_reduce_partial(const cd* partial, int nchunks, int ncols, cd* out, cd* accum,
-                           const cd* M, cd* tmp, hipStream_t st);
+                           const cd* M, cd* tmp, hipStream_t st, const Batch& bt = Batch());
 // w[i] = alpha*w[i] - sum_c B[c][i] coef[c]  (coef on device).  If normp != nullptr
-// the kernel also writes per-chunk partial sums of |w|^2 (plan p) into normp.
+// the kernel also writes per-256-row partial sums of |w|^2 into normp.
+// scratch (scratch_len cd entries in total) is shared out among the batch.
+// Batch strides: vec (w), basis (B), small (coef), part (normp).
 void launch_update(void* w, const void* B, int64_t ldb, int ncols, const cd* coef, bool fp32,
                    const TsPlan& p, double* normp, cd* scratch, int64_t scratch_len,
-                   hipStream_t st);
-// y[i] = sum_c B[c][i] coef[c] + (add ? y[i] : 0)
+                   hipStream_t st, const Batch& bt = Batch());
+// y[i] = sum_c B[c][i] coef[c] + (add ? y[i] : 0).  Batch strides as launch_update.
 void launch_combine(void* y, const void* B, int64_t ldb, int ncols, const cd* coef, bool fp32,
-                    bool add, int64_t n, hipStream_t st);
-// Partial sums of |w|^2 per chunk.
+                    bool add, int64_t n, hipStream_t st, const Batch& bt = Batch());
+// Partial sums of |w|^2 per 256 rows.  Batch strides: vec (w), part (normp).
 void launch_norm_partial(const void* w, bool fp32, const TsPlan& p, double* normp,
-                         hipStream_t st);
+                         hipStream_t st, const Batch& bt = Batch());
 // hsub = sqrt(sum normp); v = w / hsub unless hsub <= rel*sqrt(hfro2 + hsub^2)
 // (breakdown: flag[0] = 1 and flag[1] = step of the first one, v = 0; a
 // non-finite norm sets flag[0] = 2).  v == nullptr computes the norm only.
 // hcol (nullable, hlen entries) is added to hfro2 first: the running squared
-// Frobenius norm of the Hessenberg matrix.
+// Frobenius norm of the Hessenberg matrix.  Batch strides: part (normp),
+// scal (hsub and hfro2, counted in cd slots), flag (flag), small (hcol),
+// vec (w), basis (v).
 void launch_normalize(const void* w, void* v, bool fp32, const TsPlan& p, const double* normp,
                       cd* hsub, double* hfro2, double rel, int* flag, int step,
-                      const cd* hcol, int hlen, hipStream_t st);
+                      const cd* hcol, int hlen, hipStream_t st, const Batch& bt = Batch());
 // v = alpha * w (alpha on host)
 void launch_scale(const void* w, void* v, bool fp32, int64_t n, double alpha, hipStream_t st);
+// v = w / f (divide) or v = w * f, with the real scalar f = factor->x on the
+// device.  Batch strides: vec (w), basis (v), scal (factor).
+void launch_scale_dev(const void* w, void* v, bool fp32, int64_t n, const cd* factor, bool divide,
+                      hipStream_t st, const Batch& bt = Batch());
 // out[c] = sum_r B[r][i] Z[r + c*ldz], c < ncols_out, r < ncols_in  (basis rotation)
 void launch_rotate(const void* B, int64_t ldb, int ncols_in, const cd* Z, int ldz,
                    int ncols_out, void* out, int64_t ldo, bool fp32, int64_t n, hipStream_t st);
@@ -82,19 +119,31 @@ void launch_random_vector(void* v, bool fp32, const Geom& g, uint64_t seed, hipS
 // Gauss-Jordan inverse of a k x k column-major complex matrix (in place in M),
 // written to Y (may equal nothing else).  logpiv[t] = log|pivot_t|; flag != 0 on
 // a zero pivot.  Work arrays: ws of at least gj_ws_bytes(k) bytes.
+// Batch strides: mat (M, Y), small (logpiv, in doubles), flag (flag), ws (bytes).
 size_t gj_ws_bytes(int k);
-void gj_invert(cd* M, cd* Y, int k, double* logpiv, int* flag, void* ws, hipStream_t st);
-// X <- (mu X + Y / mu) / 2 with mu = exp(-sum(logpiv)/k) if scale else 1;
-// red[0] += |Xnew - X|^2, red[1] += |Xnew|^2 (red zeroed by the launcher).
-void launch_newton_combine(cd* X, const cd* Y, int k, const double* logpiv, bool scale,
-                           double* red, hipStream_t st);
+void gj_invert(cd* M, cd* Y, int k, double* logpiv, int* flag, void* ws, hipStream_t st,
+               const Batch& bt = Batch());
+// X <- (mu X + Y / mu) / 2 with mu = exp(-sum(logpiv)/k) if bit b of scale_mask
+// is set for problem b, else mu = 1; red[0] = |Xnew - X|^2, red[1] = |Xnew|^2.
+// red needs newton_red_len(k) doubles per problem.
+// Batch strides: mat (X, Y), small (logpiv, doubles), part (red, doubles).
+int64_t newton_red_len(int k);
+void launch_newton_combine(cd* X, const cd* Y, int k, const double* logpiv, uint64_t scale_mask,
+                           double* red, hipStream_t st, const Batch& bt = Batch());
+// Copy the leading k x k block of A (leading dimension lda) to X (ld k).
+// Batch strides: basis (A), mat (X).
+void launch_copy_square(const cd* A, int lda, cd* X, int k, hipStream_t st,
+                        const Batch& bt = Batch());
+// s = first column of X (k x k).  Batch strides: mat (X), small (s).
+void launch_copy_col0(const cd* X, int k, cd* s, hipStream_t st, const Batch& bt = Batch());
 // small complex GEMM: C = alpha * op(A) op(B) + beta * C, column-major.
 // opA/opB: 0 = N, 1 = conjugate transpose.
 void launch_zgemm(int opA, int opB, int m, int n, int kk, cd alpha, const cd* A, int lda,
                   const cd* B, int ldb, cd beta, cd* C, int ldc, hipStream_t st);
-// est = beta_ * |s - [sprev; 0]| / bnorm  written into *out (device)
+// *out = |s - [sprev; 0]|  (device).  Batch strides: small (s, sprev),
+// scal (out, counted in doubles).
 void launch_diff_norm(const cd* s, int k, const cd* sprev, int kprev, double* out,
-                      hipStream_t st);
+                      hipStream_t st, const Batch& bt = Batch());
 // Small Schur decomposition A = Z T Z^H (p <= 96) with the diagonal of T sorted
 // by |t_ii| ascending (mode 0) or |Re t_ii| ascending (mode 1).  A, T, Z:
 // column-major p x p (ld = p).  w: eigenvalues (p).  info[0]: QR iterations or

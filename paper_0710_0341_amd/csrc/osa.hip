@@ -86,6 +86,32 @@ struct OsaError {
     std::string why = "";
 };
 
+// Per-problem block of the small data of a solve (in cd entries): the
+// Hessenberg matrix (ldh = kcap + 1 rows, kcap columns), the coefficient
+// vectors and a few scalar slots.  One stride covers all of them, so a batched
+// launch reaches any of them with the same per-problem offset.
+struct ArenaLayout {
+    int ldh = 0;
+    int64_t vec_len = 0;   // entries of each vector slot
+    int64_t H = 0, coef = 0, coef2 = 0, cdef = 0, tmp = 0, s_cur = 0, s_prev = 0, ds = 0;
+    int64_t stride = 0;
+    static ArenaLayout make(int kcap, int m) {
+        ArenaLayout a;
+        a.ldh = kcap + 1;
+        a.vec_len = std::max<int64_t>(std::max(kcap + 1, m + 1), 160);
+        int64_t o = (int64_t)a.ldh * kcap;
+        a.coef = o;   o += a.vec_len;
+        a.coef2 = o;  o += a.vec_len;
+        a.cdef = o;   o += a.vec_len;
+        a.tmp = o;    o += a.vec_len;
+        a.s_cur = o;  o += a.vec_len;
+        a.s_prev = o; o += a.vec_len;
+        a.ds = o;     o += 8;
+        a.stride = ceil_div(o, 16) * 16;
+        return a;
+    }
+};
+
 }  // namespace
 
 // ============================================================== context
@@ -114,10 +140,12 @@ struct osa_ctx {
     int eig_restarts = 0;
     double t_init_ms = 0;
 
-    // Krylov workspace
-    int kcap = 0;
-    DevBuf V, Hm, w, x, y, coef, coef2, partial, normp, upd_scratch, dscal, flag, red;
-    DevBuf sX, sM, sY, logpiv, gjws, s_cur, s_prev, cdef;
+    // Krylov workspace, for up to kbatch sources solved in lockstep
+    int kcap = 0, kbatch = 0;
+    DevBuf V, arena, w, x, y, coef, coef2, partial, normp, upd_scratch, dscal, flag, nflag, red;
+    DevBuf sX, sM, sY, logpiv, gjws;
+    ArenaLayout lay;
+    int64_t part_stride = 0, normp_stride = 0, red_stride = 0, gj_stride = 0;
     PinnedBuf host;
 
     // optional kernel timing (events on st, resolved at synchronisation points)
@@ -199,16 +227,31 @@ void h2d(osa_ctx* c, void* ddst, const T* src, size_t n) {
     sync(c);
 }
 
-void apply_h(osa_ctx* c, const void* in, void* out, bool fp32, bool adjoint, int nrhs = 1) {
+// out = H in (adjoint: H(-mu) = H(mu)^dag).  Batch strides: basis (in), vec (out).
+void apply_h(osa_ctx* c, const void* in, void* out, bool fp32, bool adjoint,
+             const Batch& bt = Batch()) {
     const void* U = c->links();
     bool ufp32 = c->links_fp32;
     if (fp32 && !c->links_fp32 && c->links32()) { U = c->links32(); ufp32 = true; }
-    // algorithmic bytes per site: spinor in + out, 8 links (4 own, 4 backward neighbours')
+    // algorithmic bytes per site: spinor in + out per source, 8 links (4 own,
+    // 4 backward neighbours') once for the whole batch
     const double sb = fp32 ? 8.0 : 16.0, lb = ufp32 ? 8.0 : 16.0;
-    const double bytes = (double)c->g.V * (nrhs * 24.0 * sb + 36.0 * lb);
+    const double bytes = (double)c->g.V * (bt.n * 24.0 * sb + 36.0 * lb);
     timed(c, 2, bytes, [&] {
-        launch_wilson_h(in, out, U, ufp32, fp32, c->g, adjoint ? c->hc_adj : c->hc, nrhs, c->st);
+        launch_wilson_h(in, out, U, ufp32, fp32, c->g, adjoint ? c->hc_adj : c->hc, c->st, bt);
     });
+}
+
+// nrhs contiguous vectors
+void apply_h_contig(osa_ctx* c, const void* in, void* out, bool fp32, bool adjoint, int nrhs) {
+    const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxBatch) {
+        Batch bt;
+        bt.n = std::min(kMaxBatch, nrhs - r0);
+        bt.basis = bt.vec = c->N();
+        const size_t off = (size_t)r0 * c->N() * es;
+        apply_h(c, (const char*)in + off, (char*)out + off, fp32, adjoint, bt);
+    }
 }
 
 // Norm of an internal vector, to the device scalar hsub (cd, real part).
@@ -220,42 +263,55 @@ void vec_norm(osa_ctx* c, const void* v, bool fp32, cd* out) {
 }
 
 // Work buffers of the tall-skinny kernels (Gram-Schmidt against up to maxcols
-// vectors), shared by the solve and the eigensolver.
-void ensure_exec(osa_ctx* c, int maxcols) {
+// vectors, for up to nb problems at once), shared by the solve and the
+// eigensolver.  Per-problem strides: partial maxcols*64 (at most 64 chunks),
+// normp ceil(N/256) + 16.
+void ensure_exec(osa_ctx* c, int maxcols, int nb = 1) {
     const int64_t N = c->N();
     const size_t vb = (size_t)N * sizeof(cd);
     maxcols = std::max(maxcols, 160);
     c->coef.ensure(sizeof(cd) * maxcols);
     c->coef2.ensure(sizeof(cd) * maxcols);
-    c->partial.ensure(sizeof(cd) * (size_t)maxcols * 128);
-    c->normp.ensure(sizeof(double) * (size_t)(ceil_div(N, 256) + 16));
-    c->upd_scratch.ensure(vb * 8);
+    c->part_stride = std::max<int64_t>(c->part_stride, (int64_t)maxcols * 64);
+    c->normp_stride = ceil_div(N, 256) + 16;
+    c->partial.ensure(sizeof(cd) * (size_t)c->part_stride * nb);
+    c->normp.ensure(sizeof(double) * (size_t)c->normp_stride * nb);
+    c->upd_scratch.ensure(vb * 8 * nb);
     c->dscal.ensure(sizeof(cd) * 16);
-    c->flag.ensure(sizeof(int) * 4);
+    c->flag.ensure(sizeof(int) * 4 * nb);
+    c->nflag.ensure(sizeof(int) * 4 * nb);
     c->host.ensure(1 << 16);
 }
 
-void ensure_krylov(osa_ctx* c, int kcap) {
-    if (kcap <= c->kcap && c->V.p) return;
+// Workspace of a lockstep solve of nb sources with Krylov size up to kcap:
+//   V      nb bases of kcap+1 vectors (problem b at b*(kcap+1)*N)
+//   arena  nb per-problem blocks of small data, see ArenaLayout
+//   w, x   nb vectors each
+//   sX, sM, sY, logpiv, gjws, red: nb copies of the small-sign workspace
+void ensure_krylov(osa_ctx* c, int kcap, int nb = 1) {
+    if (kcap <= c->kcap && nb <= c->kbatch && c->V.p) return;
+    kcap = std::max(kcap, c->kcap);
+    nb = std::max(nb, c->kbatch);
     const int64_t N = c->N();
     const size_t vb = (size_t)N * sizeof(cd);
-    c->V.ensure(vb * (size_t)(kcap + 1));
-    c->Hm.ensure(sizeof(cd) * (size_t)(kcap + 1) * kcap);
-    c->w.ensure(vb);
-    c->x.ensure(vb);
+    c->V.release();   // the largest buffer: free before growing
+    c->V.ensure(vb * (size_t)(kcap + 1) * nb);
+    c->lay = ArenaLayout::make(kcap, std::max(c->m_alloc, 1));
+    c->arena.ensure(sizeof(cd) * (size_t)c->lay.stride * nb);
+    c->w.ensure(vb * nb);
+    c->x.ensure(vb * nb);
     c->y.ensure(vb);
-    ensure_exec(c, kcap + 1);
-    const int nbk = (int)ceil_div((int64_t)kcap * kcap, 256);
-    c->red.ensure(sizeof(double) * (size_t)(2 + 2 * nbk + 16));
-    c->sX.ensure(sizeof(cd) * (size_t)kcap * kcap);
-    c->sM.ensure(sizeof(cd) * (size_t)kcap * kcap);
-    c->sY.ensure(sizeof(cd) * (size_t)kcap * kcap);
-    c->logpiv.ensure(sizeof(double) * kcap);
-    c->gjws.ensure(gj_ws_bytes(kcap));
-    c->s_cur.ensure(sizeof(cd) * kcap);
-    c->s_prev.ensure(sizeof(cd) * kcap);
-    c->cdef.ensure(sizeof(cd) * 128);
+    ensure_exec(c, kcap + 1, nb);
+    c->red_stride = newton_red_len(kcap) + 16;
+    c->red.ensure(sizeof(double) * (size_t)c->red_stride * nb);
+    c->sX.ensure(sizeof(cd) * (size_t)kcap * kcap * nb);
+    c->sM.ensure(sizeof(cd) * (size_t)kcap * kcap * nb);
+    c->sY.ensure(sizeof(cd) * (size_t)kcap * kcap * nb);
+    c->logpiv.ensure(sizeof(double) * (size_t)kcap * nb);
+    c->gj_stride = (int64_t)ceil_div((int64_t)gj_ws_bytes(kcap), 256) * 256;
+    c->gjws.ensure((size_t)c->gj_stride * nb);
     c->kcap = kcap;
+    c->kbatch = nb;
 }
 
 __global__ void k_axpy_c(int n, cd alpha, const cd* __restrict__ a, cd* __restrict__ cvec) {
@@ -269,49 +325,80 @@ void axpy_c(osa_ctx* c, int n, cd alpha, const cd* a, cd* cvec) {
     OSA_LAUNCH_CHECK();
 }
 
+Batch batch_of(const std::vector<int>& probs) {
+    Batch bt;
+    bt.n = (int)probs.size();
+    for (int i = 0; i < bt.n; ++i) bt.idx[i] = (int16_t)probs[i];
+    return bt;
+}
+
 // ------------------------------------------------------- Gram-Schmidt
 // w <- w - B (B^H w) twice (CGS2); coefficients h = h1 + h2 written to hcol
-// (device, ncols entries).  Leaves per-block norm partials of the result in
-// normp.  B has ncols vectors of length n, spaced by ld.
+// (device, ncols entries); co holds the pass-2 coefficients.  Leaves per-block
+// norm partials of the result in normp.  B has ncols vectors of length n,
+// spaced by ld.  Batch strides: vec (w), basis (B), small (hcol, co).
 void cgs2(osa_ctx* c, void* wv, const void* B, int64_t ld, int ncols, bool fp32, cd* hcol,
-          double* hfro2) {
+          cd* co, const Batch& bt = Batch()) {
     const TsPlan p = ts_plan(c->N());
     const int64_t scratch_len = (int64_t)(c->upd_scratch.bytes / sizeof(cd));
     cd* part = c->partial.as<cd>();
-    cd* co = c->coef.as<cd>();
+    Batch bd = bt, bu = bt;
+    bd.part = c->part_stride;
+    bu.part = c->normp_stride;
     const double eb = fp32 ? 8.0 : 16.0;
-    const double n = (double)c->N();
+    const double n = (double)c->N() * bt.n;
     const double dot_bytes = (ncols + 1.0) * n * eb;     // read V_j and w
     const double upd_bytes = (ncols + 2.0) * n * eb;     // read V_j and w, write w
     // pass 1
-    timed(c, 0, dot_bytes, [&] { launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st); });
-    launch_reduce_partial(part, p.nchunks, ncols, hcol, nullptr, nullptr, nullptr, c->st);
+    timed(c, 0, dot_bytes, [&] { launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st, bd); });
+    launch_reduce_partial(part, p.nchunks, ncols, hcol, nullptr, nullptr, nullptr, c->st, bd);
     timed(c, 1, upd_bytes, [&] {
         launch_update(wv, B, ld, ncols, hcol, fp32, p, nullptr, c->upd_scratch.as<cd>(),
-                      scratch_len, c->st);
+                      scratch_len, c->st, bu);
     });
     // pass 2
-    timed(c, 0, dot_bytes, [&] { launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st); });
-    launch_reduce_partial(part, p.nchunks, ncols, co, hcol, nullptr, nullptr, c->st);   // h += h2
+    timed(c, 0, dot_bytes, [&] { launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st, bd); });
+    launch_reduce_partial(part, p.nchunks, ncols, co, hcol, nullptr, nullptr, c->st, bd);  // h += h2
     timed(c, 1, upd_bytes, [&] {
         launch_update(wv, B, ld, ncols, co, fp32, p, c->normp.as<double>(),
-                      c->upd_scratch.as<cd>(), scratch_len, c->st);
+                      c->upd_scratch.as<cd>(), scratch_len, c->st, bu);
     });
 }
 
-// Oblique projection w <- w - R G^{-1} L^dag w (Eq. 21) with the active pairs.
-// If cout != nullptr the coefficients G^{-1} L^dag w are kept there.
-void project_out(osa_ctx* c, void* wv, cd* cout) {
+// Oblique projection w <- w - R G^{-1} L^dag w (Eq. 21) with the active pairs,
+// shared by every problem of the batch.  The coefficients G^{-1} L^dag w are
+// left in cout; tmp is m scratch entries.  Batch strides: vec (w), small (cout,
+// tmp).
+void project_out(osa_ctx* c, void* wv, cd* cout, cd* tmp, const Batch& bt) {
     const int m = c->m_active;
     if (m == 0) return;
     const TsPlan p = ts_plan(c->N());
     cd* part = c->partial.as<cd>();
-    cd* co = cout ? cout : c->coef2.as<cd>();
-    launch_dot_partial(c->L.p, c->N(), m, wv, false, p, part, c->st);
-    launch_reduce_partial(part, p.nchunks, m, co, nullptr, c->Ginv.as<cd>(), c->coef.as<cd>(),
-                          c->st);
-    launch_update(wv, c->R.p, c->N(), m, co, false, p, nullptr, c->upd_scratch.as<cd>(),
-                  (int64_t)(c->upd_scratch.bytes / sizeof(cd)), c->st);
+    Batch bd = bt, bu = bt;
+    bd.basis = bu.basis = 0;   // L and R are shared
+    bd.part = c->part_stride;
+    bu.part = 0;
+    launch_dot_partial(c->L.p, c->N(), m, wv, false, p, part, c->st, bd);
+    launch_reduce_partial(part, p.nchunks, m, cout, nullptr, c->Ginv.as<cd>(), tmp, c->st, bd);
+    launch_update(wv, c->R.p, c->N(), m, cout, false, p, nullptr, c->upd_scratch.as<cd>(),
+                  (int64_t)(c->upd_scratch.bytes / sizeof(cd)), c->st, bu);
+}
+
+// Strided device-to-host copy of `width` bytes from each of the problems in
+// probs (byte stride `stride` from src); out[i] receives problem probs[i].
+template <typename T>
+void d2h_strided(osa_ctx* c, const void* src, int64_t stride, int count,
+                 const std::vector<int>& probs, std::vector<T>& out) {
+    int nb = 0;
+    for (int b : probs) nb = std::max(nb, b + 1);
+    const size_t w = sizeof(T) * count;
+    c->host.ensure(w * nb + 16);
+    OSA_HIP(hipMemcpy2DAsync(c->host.p, w, src, (size_t)stride, w, nb, hipMemcpyDeviceToHost,
+                             c->st));
+    sync(c);
+    out.resize((size_t)count * probs.size());
+    for (size_t i = 0; i < probs.size(); ++i)
+        std::memcpy(&out[i * count], c->host.as<char>() + w * probs[i], w);
 }
 
 }  // namespace
@@ -319,50 +406,88 @@ void project_out(osa_ctx* c, void* wv, cd* cout) {
 namespace {
 
 // ------------------------------------------------------------- small sign
-// sign(X) by the scaled Newton iteration; stopping rule: stop once the
-// relative change is below 1e-14, or below 1e-8 and no longer halving.
-int small_sign_run(osa_ctx* c, int k, const cd* A, int lda, cd* s_out, bool* ok) {
+// s = sign(A) e_1 for the problems in probs (k x k each, A of problem b at
+// A + b*a_stride with leading dimension lda; s written at s_out + b*s_stride)
+// by the scaled Newton iteration (Eq. 11): determinantal scaling until the
+// relative change drops below 1e-2; stop once the change is below 1e-14, or
+// below 1e-8 and no longer halving; at most 100 iterations.  All problems of
+// the group share every launch; each stops on its own.
+// iters[b] > 0: iterations used, ok[b] = 1 on convergence; iters[b] < 0: a
+// singular or non-finite iterate at iteration -iters[b].
+void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd* A, int lda,
+                      int64_t a_stride, cd* s_out, int64_t s_stride, std::vector<int>& iters,
+                      std::vector<char>& ok) {
+    const int64_t ms = (int64_t)c->kcap * c->kcap;
     cd* X = c->sX.as<cd>();
     cd* M = c->sM.as<cd>();
     cd* Y = c->sY.as<cd>();
-    OSA_HIP(hipMemcpy2DAsync(X, sizeof(cd) * k, A, sizeof(cd) * lda, sizeof(cd) * k, k,
-                             hipMemcpyDeviceToDevice, c->st));
-    OSA_HIP(hipMemsetAsync(c->flag.p, 0, sizeof(int) * 4, c->st));
-    bool scale = true;
-    double prev = INFINITY;
-    int it = 0;
-    *ok = false;
-    double* red = c->red.as<double>();
-    for (it = 1; it <= 100; ++it) {
-        OSA_HIP(hipMemcpyAsync(M, X, sizeof(cd) * k * k, hipMemcpyDeviceToDevice, c->st));
-        timed(c, 3, 2.0 * 16.0 * k * (double)k, [&] {
-            gj_invert(M, Y, k, c->logpiv.as<double>(), c->flag.as<int>(), c->gjws.p, c->st);
-        });
-        launch_newton_combine(X, Y, k, c->logpiv.as<double>(), scale, red, c->st);
-        double hred[2];
-        int hflag[1];
-        OSA_HIP(hipMemcpyAsync(c->host.as<char>(), red, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                               c->st));
-        OSA_HIP(hipMemcpyAsync(c->host.as<char>() + 16, c->flag.p, sizeof(int),
-                               hipMemcpyDeviceToHost, c->st));
-        sync(c);
-        std::memcpy(hred, c->host.p, 16);
-        std::memcpy(hflag, c->host.as<char>() + 16, 4);
-        if (hflag[0] || !std::isfinite(hred[0]) || !std::isfinite(hred[1])) return -it;
-        const double change = std::sqrt(hred[0] / hred[1]);
-        if (change < 1e-2) scale = false;
-        if (change < 1e-14) { *ok = true; break; }
-        if (change < 1e-8 && change > 0.5 * prev) { *ok = true; break; }
-        prev = change;
+    Batch bt;   // strides of the Newton workspace
+    bt.basis = a_stride;
+    bt.mat = ms;
+    bt.small = c->kcap;   // logpiv (doubles)
+    bt.flag = 4;
+    bt.ws = c->gj_stride;
+    bt.part = c->red_stride;
+    for (int b : probs) { iters[b] = 0; ok[b] = 0; }
+    std::vector<int> act = probs;
+    {
+        Batch b0 = bt;
+        b0.n = (int)act.size();
+        for (int i = 0; i < b0.n; ++i) b0.idx[i] = (int16_t)act[i];
+        launch_copy_square(A, lda, X, k, c->st, b0);
     }
-    if (it > 100) it = 100;
-    OSA_HIP(hipMemcpyAsync(s_out, X, sizeof(cd) * k, hipMemcpyDeviceToDevice, c->st));
-    return it;
+    OSA_HIP(hipMemsetAsync(c->nflag.p, 0, c->nflag.bytes, c->st));
+    uint64_t scale = ~0ULL;
+    std::vector<double> prev(c->kbatch, INFINITY);
+    double* red = c->red.as<double>();
+    std::vector<double> hred;
+    std::vector<int> hflag;
+    for (int it = 1; it <= 100 && !act.empty(); ++it) {
+        Batch ba = bt;
+        ba.n = (int)act.size();
+        for (int i = 0; i < ba.n; ++i) ba.idx[i] = (int16_t)act[i];
+        Batch bc = ba;   // M <- X: X has leading dimension k
+        bc.basis = ms;
+        launch_copy_square(X, k, M, k, c->st, bc);
+        timed(c, 3, 2.0 * 16.0 * k * (double)k * ba.n, [&] {
+            gj_invert(M, Y, k, c->logpiv.as<double>(), c->nflag.as<int>(), c->gjws.p, c->st, ba);
+        });
+        launch_newton_combine(X, Y, k, c->logpiv.as<double>(), scale, red, c->st, ba);
+        d2h_strided(c, red, c->red_stride * (int64_t)sizeof(double), 2, act, hred);
+        d2h_strided(c, c->nflag.p, 4 * (int64_t)sizeof(int), 1, act, hflag);
+        std::vector<int> next;
+        for (size_t i = 0; i < act.size(); ++i) {
+            const int b = act[i];
+            const double d2 = hred[2 * i], n2 = hred[2 * i + 1];
+            iters[b] = it;
+            if (hflag[i] || !std::isfinite(d2) || !std::isfinite(n2)) { iters[b] = -it; continue; }
+            const double change = std::sqrt(d2 / n2);
+            if (change < 1e-2) scale &= ~(1ULL << b);
+            if (change < 1e-14 || (change < 1e-8 && change > 0.5 * prev[b])) {
+                ok[b] = 1;
+                continue;
+            }
+            prev[b] = change;
+            next.push_back(b);
+        }
+        act.swap(next);
+    }
+    std::vector<int> good;
+    for (int b : probs)
+        if (iters[b] > 0) good.push_back(b);
+    Batch bs = bt;
+    bs.n = (int)good.size();
+    for (int i = 0; i < bs.n; ++i) bs.idx[i] = (int16_t)good[i];
+    bs.small = s_stride;
+    launch_copy_col0(X, k, s_out, c->st, bs);
 }
 
 // ------------------------------------------------------------- set deflation
 __global__ void k_sign_coef(int m, const cd* __restrict__ lam, const cd* __restrict__ cin,
-                            cd* __restrict__ cout) {
+                            cd* __restrict__ cout, Batch bt) {
+    const int pb = bt.idx[blockIdx.y];
+    cin += pb * bt.small;
+    cout += pb * bt.small;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m) cout[i] = cscale(cin[i], lam[i].x > 0 ? 1.0 : -1.0);
 }
@@ -393,133 +518,239 @@ void set_active(osa_ctx* c, int m) {
 
 // ------------------------------------------------------------- solve
 struct SolveResult {
-    osa_status st;
-    int k_used;
-    double est;
-    int newton_iters;
-    int breakdown;
+    osa_status st = OSA_OK;
+    int k_used = 0;
+    double est = NAN;
+    int newton_iters = 0;
+    int breakdown = 0;
+    double bnorm = 0;
 };
 
-// y_int = sign(H) x_int for one internal-layout source.
-SolveResult solve_one(osa_ctx* c, const cd* xin, cd* yout, double tol) {
-    SolveResult res{OSA_OK, 0, NAN, 0, 0};
+// y_b = sign(H) x_b for nb internal-layout sources (contiguous, N apart) in
+// lockstep: every Arnoldi step applies the stencil, the re-projection, both
+// Gram-Schmidt passes and the normalisation to all unfinished sources in one
+// launch each; each source keeps its own basis, Hessenberg matrix, check
+// history and stopping point, so its result is that of a single-source solve.
+void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
+                 std::vector<SolveResult>& res) {
+    res.assign(nb, SolveResult{});
     const int64_t N = c->N();
     const int kmax = c->opts.k_max;
-    ensure_krylov(c, kmax);
+    ensure_krylov(c, kmax, nb);
+    if (c->lay.vec_len < std::max(kmax + 1, c->m_active + 1)) {
+        c->lay = ArenaLayout::make(c->kcap, std::max(c->m_alloc, 1));
+        c->arena.ensure(sizeof(cd) * (size_t)c->lay.stride * c->kbatch);
+    }
+    const ArenaLayout& L = c->lay;
     const bool fixed = c->opts.check_every < 0;
     const int every = fixed ? kmax : std::max(1, c->opts.check_every);
     const bool reproj = !c->opts.no_reproject;
     const TsPlan p = ts_plan(N);
+    const int64_t VS = (int64_t)(c->kcap + 1) * N;   // basis stride
+    const int ldh = L.ldh;
     cd* V = c->V.as<cd>();
-    cd* H = c->Hm.as<cd>();
-    const int ldh = kmax + 1;
+    cd* ar = c->arena.as<cd>();
+    cd* H = ar + L.H;
+    cd* ds = ar + L.ds;   // [0] |b|, [1] beta, [3] |s - s'| (double), [4] hfro2 (double)
+    double* hfro2 = (double*)(ds + 4);
     cd* w = c->w.as<cd>();
     cd* x = c->x.as<cd>();
-    cd* ds = c->dscal.as<cd>();           // [0] |b|, [1] beta, [2] h_{j+1,j} scratch, [3] est
-    double* hfro2 = (double*)(ds + 4);
     int* flag = c->flag.as<int>();
     const int m = c->m_active;
-    cd* cdef = c->cdef.as<cd>();          // c = G^{-1} L^dag b, kept until assembly
+    Batch base;   // strides of the solve workspace
+    base.basis = VS;
+    base.vec = N;
+    base.small = L.stride;
+    base.scal = L.stride;
+    base.flag = 4;
+    base.part = c->normp_stride;
+    auto bat = [&](const std::vector<int>& probs) {
+        Batch bt = base;
+        bt.n = (int)probs.size();
+        for (int i = 0; i < bt.n; ++i) bt.idx[i] = (int16_t)probs[i];
+        return bt;
+    };
+    std::vector<int> all(nb);
+    for (int b = 0; b < nb; ++b) all[b] = b;
+    const Batch ball = bat(all);
 
-    OSA_HIP(hipMemcpyAsync(x, xin, sizeof(cd) * N, hipMemcpyDeviceToDevice, c->st));
-    OSA_HIP(hipMemsetAsync(H, 0, sizeof(cd) * (size_t)ldh * kmax, c->st));
-    OSA_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, c->st));
-    OSA_HIP(hipMemsetAsync(hfro2, 0, sizeof(double), c->st));
-    vec_norm(c, x, false, ds + 0);
-    if (m > 0) project_out(c, x, cdef);   // x <- x_ominus  (Eq. 21)
-    vec_norm(c, x, false, ds + 1);
-    double hb[2];
-    {
-        cd tmp[2];
-        d2h(c, ds, 2, tmp);
-        hb[0] = tmp[0].x;
-        hb[1] = tmp[1].x;
+    OSA_HIP(hipMemcpyAsync(x, xin, sizeof(cd) * N * nb, hipMemcpyDeviceToDevice, c->st));
+    OSA_HIP(hipMemsetAsync(ar, 0, sizeof(cd) * (size_t)L.stride * nb, c->st));
+    OSA_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4 * nb, c->st));
+    launch_norm_partial(x, false, p, c->normp.as<double>(), c->st, ball);
+    launch_normalize(x, nullptr, false, p, c->normp.as<double>(), ds + 0, nullptr, 0.0, nullptr, 0,
+                     nullptr, 0, c->st, ball);
+    if (m > 0) project_out(c, x, ar + L.cdef, ar + L.tmp, ball);   // x <- x_ominus  (Eq. 21)
+    launch_norm_partial(x, false, p, c->normp.as<double>(), c->st, ball);
+    launch_normalize(x, nullptr, false, p, c->normp.as<double>(), ds + 1, nullptr, 0.0, nullptr, 0,
+                     nullptr, 0, c->st, ball);
+    std::vector<cd> hb;
+    d2h_strided(c, ds, L.stride * (int64_t)sizeof(cd), 2, all, hb);
+    std::vector<double> beta(nb), bnorm(nb);
+    std::vector<int> act;
+    std::vector<char> done(nb, 0);
+    for (int b = 0; b < nb; ++b) {
+        bnorm[b] = hb[2 * b].x;
+        beta[b] = hb[2 * b + 1].x;
+        res[b].bnorm = bnorm[b];
+        if (!std::isfinite(bnorm[b]) || !std::isfinite(beta[b])) {
+            res[b].st = OSA_ERR_NONFINITE;
+            done[b] = 1;
+        } else if (beta[b] > 1e-15 * bnorm[b] && beta[b] > 0) {
+            act.push_back(b);
+        }
     }
-    if (!std::isfinite(hb[0]) || !std::isfinite(hb[1])) { res.st = OSA_ERR_NONFINITE; return res; }
-    const double bnorm = hb[0], beta = hb[1];
-    int k_used = 0;
-    if (beta > 1e-15 * bnorm && beta > 0) {
-        launch_scale(x, V, false, N, 1.0 / beta, c->st);
-        int kprev = 0;
-        bool stopped = false;
-        // Check schedule.  The estimate at a check is the change since the previous
-        // check, i.e. about the error of the previous check.  After two estimates
-        // the geometric rate predicts where the error crosses tol; checks far
-        // before that point are skipped (at most 3 in a row).
-        std::vector<int> cj;       // performed checks
-        std::vector<double> ce;    // ce[i]: estimate at check i (error of check i-1)
-        for (int j = 0; j < kmax && !stopped; ++j) {
-            cd* vj = V + (size_t)j * N;
-            apply_h(c, vj, w, false, false);
-            if (reproj && m > 0) project_out(c, w, nullptr);
-            cgs2(c, w, V, N, j + 1, false, H + (size_t)j * ldh, hfro2);
-            launch_normalize(w, V + (size_t)(j + 1) * N, false, p, c->normp.as<double>(),
-                             H + (size_t)j * ldh + (j + 1), hfro2, 1e-14, flag, j,
-                             H + (size_t)j * ldh, j + 1, c->st);
-            const int kk = j + 1;
-            if (kk % every != 0 && kk != kmax) continue;
-            if (!fixed && kk != kmax && ce.size() >= 3) {
-                const size_t q = ce.size() - 1;
-                const double e1 = ce[q - 1], e2 = ce[q];
-                const int j1 = cj[q - 2], j2 = cj[q - 1];
+    if (!act.empty()) {
+        Batch b0 = bat(act);
+        launch_scale_dev(x, V, false, N, ds + 1, true, c->st, b0);   // v_1 = x_ominus / beta
+    }
+    std::vector<int> kprev(nb, 0);
+    // Check schedule.  The estimate at a check is the change since the previous
+    // check, i.e. about the error of the previous check.  After two estimates
+    // the geometric rate predicts where the error crosses tol; checks far
+    // before that point are skipped (at most 3 in a row).
+    std::vector<std::vector<int>> cj(nb);       // performed checks
+    std::vector<std::vector<double>> ce(nb);    // ce[i]: estimate at check i (error of check i-1)
+    std::vector<int> hf;
+    std::vector<double> hd;
+    for (int j = 0; j < kmax && !act.empty(); ++j) {
+        const Batch bt = bat(act);
+        apply_h(c, V + (size_t)j * N, w, false, false, bt);
+        if (reproj && m > 0) project_out(c, w, ar + L.coef2, ar + L.tmp, bt);
+        cgs2(c, w, V, N, j + 1, false, H + (size_t)j * ldh, ar + L.coef, bt);
+        launch_normalize(w, V + (size_t)(j + 1) * N, false, p, c->normp.as<double>(),
+                         H + (size_t)j * ldh + (j + 1), hfro2, 1e-14, flag, j,
+                         H + (size_t)j * ldh, j + 1, c->st, bt);
+        const int kk = j + 1;
+        if (kk % every != 0 && kk != kmax) continue;
+        // each source follows its own schedule, as it would alone
+        std::vector<int> chk, wait;
+        for (int b : act) {
+            bool want = true;
+            if (!fixed && kk != kmax && ce[b].size() >= 3) {
+                const size_t q = ce[b].size() - 1;
+                const double e1 = ce[b][q - 1], e2 = ce[b][q];
+                const int j1 = cj[b][q - 2], j2 = cj[b][q - 1];
                 const double r = (e1 > 0 && e2 > 0) ? std::log(e2 / e1) / (double)(j2 - j1) : 0.0;
                 const double pred = e2 * std::exp(r * (double)(kk - j2));
                 const bool near = !(r < 0) || pred <= 3.0 * tol;
-                if (!near && kk - cj.back() < 4 * every) continue;
+                if (!near && kk - cj[b].back() < 4 * every) want = false;
             }
-            int hf[2];
-            d2h(c, flag, 2, hf);
-            if (hf[0] == 2) { res.st = OSA_ERR_NONFINITE; return res; }
-            int kcheck = kk;
-            if (hf[0] == 1) {   // happy breakdown at step hf[1]: K is invariant, result exact
-                kcheck = std::min(kk, hf[1] + 1);
-                res.breakdown = 1;
-                stopped = true;
-            }
-            bool ok = false;
-            const int its = small_sign_run(c, kcheck, H, ldh, c->s_cur.as<cd>(), &ok);
-            res.newton_iters = its;
-            if (its < 0 || !ok) { res.st = OSA_ERR_NEWTON_NOCONV; return res; }
-            k_used = kcheck;
-            if (kprev > 0 && !fixed) {
-                launch_diff_norm(c->s_cur.as<cd>(), kcheck, c->s_prev.as<cd>(), kprev,
-                                 (double*)(ds + 3), c->st);
-                double dn;
-                d2h(c, ds + 3, 1, &dn);
-                res.est = beta * dn / bnorm;
-                if (res.est <= tol) stopped = true;
-            }
-            cj.push_back(kcheck);
-            ce.push_back(kprev > 0 ? res.est : NAN);
-            if (res.breakdown) res.est = 0.0;
-            if (!stopped) {
-                // keep the latest sign in s_prev for the next difference
-                std::swap(c->s_cur.p, c->s_prev.p);
-                kprev = kcheck;
-            }
+            (want ? chk : wait).push_back(b);
         }
-        // the latest s is in s_cur if the loop stopped early, else in s_prev
-        if (!stopped) std::swap(c->s_cur.p, c->s_prev.p);
+        if (chk.empty()) continue;
+        d2h_strided(c, flag, 4 * (int64_t)sizeof(int), 2, chk, hf);
+        // group the sources by the Krylov size of this check
+        std::vector<int> kcheck(nb, kk), live;
+        for (size_t i = 0; i < chk.size(); ++i) {
+            const int b = chk[i];
+            if (hf[2 * i] == 2) { res[b].st = OSA_ERR_NONFINITE; done[b] = 1; continue; }
+            if (hf[2 * i] == 1) {   // happy breakdown at step hf[1]: K is invariant, result exact
+                kcheck[b] = std::min(kk, hf[2 * i + 1] + 1);
+                res[b].breakdown = 1;
+            }
+            live.push_back(b);
+        }
+        std::vector<int> iters(nb, 0);
+        std::vector<char> okv(nb, 0);
+        std::vector<int> ks;
+        for (int b : live)
+            if (std::find(ks.begin(), ks.end(), kcheck[b]) == ks.end()) ks.push_back(kcheck[b]);
+        std::vector<int> next;
+        for (int kc : ks) {
+            std::vector<int> grp;
+            for (int b : live)
+                if (kcheck[b] == kc) grp.push_back(b);
+            small_sign_batch(c, grp, kc, H, ldh, L.stride, ar + L.s_cur, L.stride, iters, okv);
+            std::vector<int> good, withprev;
+            for (int b : grp) {
+                res[b].newton_iters = iters[b];
+                if (iters[b] < 0 || !okv[b]) {
+                    res[b].st = OSA_ERR_NEWTON_NOCONV;
+                    done[b] = 1;
+                    continue;
+                }
+                res[b].k_used = kc;
+                good.push_back(b);
+                if (kprev[b] > 0 && !fixed) withprev.push_back(b);
+            }
+            // est = beta |s - [s_prev; 0]| / |b|, per previous check size
+            while (!withprev.empty()) {
+                const int kp = kprev[withprev[0]];
+                std::vector<int> sub, rest;
+                for (int b : withprev) (kprev[b] == kp ? sub : rest).push_back(b);
+                Batch bd = bat(sub);
+                bd.scal = 2 * L.stride;   // counted in doubles
+                launch_diff_norm(ar + L.s_cur, kc, ar + L.s_prev, kp, (double*)(ds + 3), c->st, bd);
+                d2h_strided(c, (double*)(ds + 3), L.stride * (int64_t)sizeof(cd), 1, sub, hd);
+                for (size_t i = 0; i < sub.size(); ++i) {
+                    const int b = sub[i];
+                    res[b].est = beta[b] * hd[i] / bnorm[b];
+                }
+                withprev.swap(rest);
+            }
+            std::vector<int> cont;
+            for (int b : good) {
+                bool stop = res[b].breakdown != 0;
+                if (kprev[b] > 0 && !fixed && res[b].est <= tol) stop = true;
+                cj[b].push_back(kc);
+                ce[b].push_back(kprev[b] > 0 ? res[b].est : NAN);
+                if (res[b].breakdown) res[b].est = 0.0;
+                if (stop) { done[b] = 1; continue; }
+                kprev[b] = kc;
+                cont.push_back(b);
+            }
+            if (!cont.empty()) {   // keep the latest sign in s_prev for the next difference
+                Batch bcp = bat(cont);
+                bcp.mat = L.stride;
+                launch_copy_col0(ar + L.s_cur, kc, ar + L.s_prev, c->st, bcp);
+            }
+            next.insert(next.end(), cont.begin(), cont.end());
+        }
+        next.insert(next.end(), wait.begin(), wait.end());
+        std::sort(next.begin(), next.end());
+        act.swap(next);
     }
     // assembly (Eq. 22): y = R sgn(Re lambda) c + beta V_k s
-    cd* co = c->coef.as<cd>();
-    if (m > 0) {
-        hipLaunchKernelGGL(k_sign_coef, dim3((unsigned)ceil_div(m, 64)), dim3(64), 0, c->st, m,
-                           (const cd*)c->lam_dev.p, (const cd*)cdef, co);
-        launch_combine(yout, c->R.p, N, m, co, false, false, N, c->st);
-    } else {
-        OSA_HIP(hipMemsetAsync(yout, 0, sizeof(cd) * N, c->st));
+    std::vector<int> okp;
+    for (int b = 0; b < nb; ++b)
+        if (res[b].st >= 0) okp.push_back(b);
+    if (!okp.empty()) {
+        const Batch bo = bat(okp);
+        if (m > 0) {
+            hipLaunchKernelGGL(k_sign_coef, dim3((unsigned)ceil_div(m, 64), bo.n), dim3(64), 0,
+                               c->st, m, (const cd*)c->lam_dev.p, (const cd*)(ar + L.cdef),
+                               ar + L.coef, bo);
+            Batch br = bo;
+            br.basis = 0;   // R is shared
+            launch_combine(yout, c->R.p, N, m, ar + L.coef, false, false, N, c->st, br);
+        } else {
+            OSA_HIP(hipMemsetAsync(yout, 0, sizeof(cd) * N * nb, c->st));
+        }
+        std::vector<int> ks;
+        for (int b : okp)
+            if (res[b].k_used > 0 && std::find(ks.begin(), ks.end(), res[b].k_used) == ks.end())
+                ks.push_back(res[b].k_used);
+        for (int ku : ks) {
+            std::vector<int> grp;
+            for (int b : okp)
+                if (res[b].k_used == ku) grp.push_back(b);
+            Batch bg = bat(grp);
+            Batch bsc = bg;   // coef = beta * s  (s read as the "vector", coef as the "basis")
+            bsc.vec = L.stride;
+            bsc.basis = L.stride;
+            launch_scale_dev(ar + L.s_cur, ar + L.coef, false, ku, ds + 1, false, c->st, bsc);
+            launch_combine(yout, V, N, ku, ar + L.coef, false, true, N, c->st, bg);
+        }
     }
-    if (k_used > 0) {
-        launch_scale(c->s_cur.p, co, false, k_used, beta, c->st);
-        launch_combine(yout, V, N, k_used, co, false, true, N, c->st);
+    for (int b = 0; b < nb; ++b) {
+        SolveResult& r = res[b];
+        if (r.st < 0) continue;
+        if (fixed) r.est = NAN;
+        if (r.k_used == 0) r.est = 0.0;
+        if (!fixed && !(r.est <= tol)) r.st = OSA_NOT_CONVERGED;
     }
-    res.k_used = k_used;
-    if (fixed) res.est = NAN;
-    if (k_used == 0) res.est = 0.0;
-    if (!fixed && !(res.est <= tol)) res.st = OSA_NOT_CONVERGED;
     sync(c);
-    return res;
 }
 
 // ================================================================ eigensolver
@@ -584,7 +815,7 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
             apply_h(c, tv.p, wv.p, fp32, adjoint);
             stats.matvecs += 2;
             cd* scol = S.as<cd>() + (size_t)j * ldS;
-            cgs2(c, wv.p, V, N, j + 1, fp32, scol, hfro2);
+            cgs2(c, wv.p, V, N, j + 1, fp32, scol, c->coef.as<cd>());
             launch_normalize(wv.p, vec(j + 1), fp32, pl, c->normp.as<double>(), scol + (j + 1),
                              hfro2, 1e-300, flag, j, scol, j + 1, c->st);
         }
@@ -668,7 +899,7 @@ void rayleigh_ritz(osa_ctx* c, bool adjoint, int nev, int m, cd* X, cd* Rout,
     wr.ensure(sizeof(cd) * nev);
     info.ensure(sizeof(int) * 4);
     HR.ensure(sizeof(cd) * (size_t)N * m);
-    apply_h(c, X, W.p, false, adjoint, nev);
+    apply_h_contig(c, X, W.p, false, adjoint, nev);
     const TsPlan p = ts_plan(N);
     for (int j = 0; j < nev; ++j) {
         launch_dot_partial(X, N, nev, W.as<cd>() + (size_t)j * N, false, p, c->partial.as<cd>(),
@@ -861,6 +1092,7 @@ void deflate(osa_ctx* c, int m, osa_info* info) {
 }
 
 void fill_defaults(osa_opts& o) {
+    if (o.max_batch <= 0) o.max_batch = 16;
     if (o.k_max <= 0) o.k_max = 600;
     if (o.check_every == 0) o.check_every = 50;
 }
@@ -924,7 +1156,8 @@ osa_status osa_set_opts(osa_ctx* c, const osa_opts* opts) {
     osa_opts o{};
     if (opts) o = *opts;
     if (o.k_max < 0 || o.k_max > 4000 || o.eig_ncv < 0 || o.eig_ncv > 96 || o.eig_tol < 0 ||
-        o.eig_max_restarts < 0 || (o.eig_prec != OSA_FP64 && o.eig_prec != OSA_FP32))
+        o.eig_max_restarts < 0 || (o.eig_prec != OSA_FP64 && o.eig_prec != OSA_FP32) ||
+        o.max_batch < 0 || o.max_batch > 64)
         return OSA_ERR_ARG;
     fill_defaults(o);
     c->opts = o;
@@ -1043,48 +1276,69 @@ osa_status osa_apply(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double to
     if (!fixed && !(tol > 0)) return OSA_ERR_ARG;
     return guard([&]() -> osa_status {
         const int64_t N = c->N();
-        const int64_t nb = 12LL * c->g.V;
-        osa_status worst = OSA_OK;
+        const int64_t nbnd = 12LL * c->g.V;
+        const int maxb = std::max(1, std::min(c->opts.max_batch, kMaxBatch));
+        const int gmax = std::min<int>(nrhs, maxb);
+        osa_status first_err = OSA_OK, worst = OSA_OK;
         DevBuf xin, yint;
-        xin.ensure(sizeof(cd) * N);
-        yint.ensure(sizeof(cd) * N);
-        for (int r = 0; r < nrhs; ++r) {
+        xin.ensure(sizeof(cd) * N * gmax);
+        yint.ensure(sizeof(cd) * N * gmax);
+        std::vector<SolveResult> res;
+        for (int r0 = 0; r0 < nrhs; r0 += maxb) {
+            const int nb = std::min(maxb, nrhs - r0);
             const double t0 = now_ms();
-            launch_vec_to_internal((const cd*)B + r * nb, xin.p, false, c->g, 1, c->st);
-            SolveResult sr = solve_one(c, xin.as<cd>(), yint.as<cd>(), tol);
-            if (sr.st == OSA_OK || sr.st == OSA_NOT_CONVERGED)
-                launch_vec_from_internal(yint.p, false, (cd*)Y + r * nb, c->g, 1, c->st);
-            double ynorm = 1.0;
-            if (sr.st == OSA_OK || sr.st == OSA_NOT_CONVERGED) {
-                vec_norm(c, yint.p, false, c->dscal.as<cd>() + 6);
-                cd yn;
-                d2h(c, c->dscal.as<cd>() + 6, 1, &yn);
-                ynorm = yn.x;
+            launch_vec_to_internal((const cd*)B + r0 * nbnd, xin.p, false, c->g, nb, c->st);
+            solve_batch(c, nb, xin.as<cd>(), yint.as<cd>(), tol, res);
+            // |y| of each result, for the relative estimate
+            std::vector<int> okp;
+            for (int b = 0; b < nb; ++b)
+                if (res[b].st == OSA_OK || res[b].st == OSA_NOT_CONVERGED) okp.push_back(b);
+            std::vector<cd> yn;
+            if (!okp.empty()) {
+                Batch bt = batch_of(okp);
+                bt.vec = N;
+                bt.part = c->normp_stride;
+                bt.scal = c->lay.stride;
+                const TsPlan p = ts_plan(N);
+                cd* slot = c->arena.as<cd>() + c->lay.ds + 2;
+                launch_norm_partial(yint.p, false, p, c->normp.as<double>(), c->st, bt);
+                launch_normalize(yint.p, nullptr, false, p, c->normp.as<double>(), slot, nullptr,
+                                 0.0, nullptr, 0, nullptr, 0, c->st, bt);
+                for (int b : okp)
+                    launch_vec_from_internal(yint.as<cd>() + (size_t)b * N, false,
+                                             (cd*)Y + (r0 + b) * nbnd, c->g, 1, c->st);
+                d2h_strided(c, slot, c->lay.stride * (int64_t)sizeof(cd), 1, okp, yn);
             }
             sync(c);
             const double t1 = now_ms();
-            if (infos) {
-                osa_info& in = infos[r];
-                std::memset(&in, 0, sizeof(in));
-                cd bn;
-                d2h(c, c->dscal.as<cd>() + 0, 1, &bn);
-                in.resid_est = std::isnan(sr.est) ? sr.est : sr.est * bn.x / std::max(ynorm, 1e-300);
-                in.k_used = sr.k_used;
-                in.n_defl = c->m_active;
-                in.status = sr.st;
-                in.newton_iters = sr.newton_iters;
-                in.breakdown = sr.breakdown;
-                in.min_abs_re_lambda = c->m_active ? c->min_abs_re : NAN;
-                in.max_eig_resid = c->max_eig_resid;
-                in.t_init_ms = c->t_init_ms;
-                in.t_solve_ms = t1 - t0;
-                in.eig_matvecs = c->eig_matvecs;
-                in.eig_restarts = c->eig_restarts;
+            for (int b = 0; b < nb; ++b) {
+                const SolveResult& sr = res[b];
+                double ynorm = 1.0;
+                for (size_t i = 0; i < okp.size(); ++i)
+                    if (okp[i] == b) ynorm = yn[i].x;
+                if (infos) {
+                    osa_info& in = infos[r0 + b];
+                    std::memset(&in, 0, sizeof(in));
+                    in.resid_est = std::isnan(sr.est) ? sr.est
+                                                      : sr.est * sr.bnorm / std::max(ynorm, 1e-300);
+                    in.k_used = sr.k_used;
+                    in.n_defl = c->m_active;
+                    in.status = sr.st;
+                    in.newton_iters = sr.newton_iters;
+                    in.breakdown = sr.breakdown;
+                    in.min_abs_re_lambda = c->m_active ? c->min_abs_re : NAN;
+                    in.max_eig_resid = c->max_eig_resid;
+                    in.t_init_ms = c->t_init_ms;
+                    in.t_solve_ms = t1 - t0;
+                    in.eig_matvecs = c->eig_matvecs;
+                    in.eig_restarts = c->eig_restarts;
+                    in.batch = nb;
+                }
+                if (sr.st < 0 && first_err == OSA_OK) first_err = sr.st;
+                if (sr.st > worst) worst = sr.st;
             }
-            if (sr.st < 0) return sr.st;
-            if (sr.st > worst) worst = sr.st;
         }
-        return worst;
+        return first_err != OSA_OK ? first_err : worst;
     });
 }
 
@@ -1139,7 +1393,7 @@ osa_status osa_apply_hw(osa_ctx* c, int32_t nrhs, const void* X, void* Y) {
         a.ensure(sizeof(cd) * N * nrhs);
         b.ensure(sizeof(cd) * N * nrhs);
         launch_vec_to_internal((const cd*)X, a.p, false, c->g, nrhs, c->st);
-        apply_h(c, a.p, b.p, false, false, nrhs);
+        apply_h_contig(c, a.p, b.p, false, false, nrhs);
         launch_vec_from_internal(b.p, false, (cd*)Y, c->g, nrhs, c->st);
         sync(c);
         return OSA_OK;
@@ -1155,18 +1409,23 @@ osa_status osa_small_sign(int32_t k, const void* A, void* s, int32_t* iters, voi
         c.g.V = 16;
         c.g.Vp = 64;
         c.host.ensure(1 << 16);
+        c.kcap = k;
+        c.kbatch = 1;
         c.sX.ensure(sizeof(cd) * (size_t)k * k);
         c.sM.ensure(sizeof(cd) * (size_t)k * k);
         c.sY.ensure(sizeof(cd) * (size_t)k * k);
         c.logpiv.ensure(sizeof(double) * k);
-        c.gjws.ensure(gj_ws_bytes(k));
-        c.flag.ensure(sizeof(int) * 4);
-        c.red.ensure(sizeof(double) * (size_t)(2 + 2 * ceil_div((int64_t)k * k, 256) + 16));
-        bool ok = false;
-        int it = small_sign_run(&c, k, (const cd*)A, k, (cd*)s, &ok);
+        c.gj_stride = (int64_t)ceil_div((int64_t)gj_ws_bytes(k), 256) * 256;
+        c.gjws.ensure((size_t)c.gj_stride);
+        c.nflag.ensure(sizeof(int) * 4);
+        c.red_stride = newton_red_len(k) + 16;
+        c.red.ensure(sizeof(double) * (size_t)c.red_stride);
+        std::vector<int> its(1, 0);
+        std::vector<char> ok(1, 0);
+        small_sign_batch(&c, std::vector<int>{0}, k, (const cd*)A, k, 0, (cd*)s, 0, its, ok);
         sync(&c);
-        if (iters) *iters = it;
-        if (it < 0 || !ok) return OSA_ERR_NEWTON_NOCONV;
+        if (iters) *iters = its[0];
+        if (its[0] < 0 || !ok[0]) return OSA_ERR_NEWTON_NOCONV;
         return OSA_OK;
     });
 }

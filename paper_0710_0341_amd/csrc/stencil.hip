@@ -191,11 +191,15 @@ struct StencilArgs {
 
 template <typename R, typename ST, typename LT>
 __global__ __launch_bounds__(128) void k_wilson_h(const ST* __restrict__ in, ST* __restrict__ out,
-                                                 const LT* __restrict__ U, StencilArgs a) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t vecoff = (int64_t)blockIdx.y * 12 * a.Vp;
-    in += vecoff;
-    out += vecoff;
+                                                 const LT* __restrict__ U, StencilArgs a,
+                                                 Batch bt) {
+    // consecutive blocks take the same sites for the problems of the batch, so
+    // a block of links is fetched from HBM once and then served from L2
+    const int entry = (int)(blockIdx.x % (unsigned)bt.n);
+    const int s = (int)(blockIdx.x / (unsigned)bt.n) * blockDim.x + threadIdx.x;
+    const int pb = bt.idx[entry];
+    in += pb * bt.basis;
+    out += pb * bt.vec;
     if (s >= a.V) {
         // padding sites carry zeros so that whole-vector reductions stay exact
         if (s < a.Vp) {
@@ -251,24 +255,40 @@ __global__ __launch_bounds__(128) void k_wilson_h(const ST* __restrict__ in, ST*
 }
 
 void launch_wilson_h(const void* in, void* out, const void* U, bool links_fp32, bool spinor_fp32,
-                     const Geom& g, const HopCoef& c, int nrhs, hipStream_t st) {
+                     const Geom& g, const HopCoef& c, hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0) return;
     StencilArgs a;
     a.lx = g.lx; a.ly = g.ly; a.lz = g.lz; a.lt = g.lt; a.V = g.V; a.Vp = g.Vp; a.apt = g.apt;
     for (int i = 0; i < 4; ++i) { a.cf[i] = c.fwd[i]; a.cb[i] = c.bwd[i]; }
-    dim3 blk(128), grid((unsigned)ceil_div(g.Vp, 128), (unsigned)nrhs);
+    // the grid covers Vp sites (padding included) for each problem
+    dim3 blk(128), grid((unsigned)(ceil_div(g.Vp, 128) * bt.n));
     if (!spinor_fp32 && !links_fp32)
         hipLaunchKernelGGL((k_wilson_h<double, cd, cd>), grid, blk, 0, st, (const cd*)in, (cd*)out,
-                           (const cd*)U, a);
+                           (const cd*)U, a, bt);
     else if (!spinor_fp32 && links_fp32)
         hipLaunchKernelGGL((k_wilson_h<double, cd, cf>), grid, blk, 0, st, (const cd*)in, (cd*)out,
-                           (const cf*)U, a);
+                           (const cf*)U, a, bt);
     else if (spinor_fp32 && links_fp32)
         hipLaunchKernelGGL((k_wilson_h<float, cf, cf>), grid, blk, 0, st, (const cf*)in, (cf*)out,
-                           (const cf*)U, a);
+                           (const cf*)U, a, bt);
     else
         hipLaunchKernelGGL((k_wilson_h<float, cf, cd>), grid, blk, 0, st, (const cf*)in, (cf*)out,
-                           (const cd*)U, a);
+                           (const cd*)U, a, bt);
     OSA_LAUNCH_CHECK();
+}
+
+void launch_wilson_h_contig(const void* in, void* out, const void* U, bool links_fp32,
+                            bool spinor_fp32, const Geom& g, const HopCoef& c, int nrhs,
+                            hipStream_t st) {
+    const size_t es = spinor_fp32 ? sizeof(cf) : sizeof(cd);
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxBatch) {
+        Batch bt;
+        bt.n = (nrhs - r0 < kMaxBatch) ? nrhs - r0 : kMaxBatch;
+        bt.basis = bt.vec = g.N();
+        const size_t off = (size_t)r0 * g.N() * es;
+        launch_wilson_h((const char*)in + off, (char*)out + off, U, links_fp32, spinor_fp32, g, c,
+                        st, bt);
+    }
 }
 
 }  // namespace osa

@@ -313,3 +313,93 @@ def test_multi_rhs_and_determinism(osa):
     for i in range(3):
         assert rel(Y1[i], O.sign_eig_apply(h, B[i])) < 1e-9
     ctx.close()
+
+
+# ------------------------------------------------------------ batched solve
+@pytest.fixture(scope="module")
+def haar4_sign(haar4_dense):
+    _, _, _, h, _ = haar4_dense
+    say("dense sign matrix 4^4 ...")
+    return O.sign_eig(h)
+
+
+def test_batched_point_sources_match_single_and_dense(osa, haar4_dense, haar4_sign):
+    """12 spin-colour point sources at one site in one lockstep batch: every
+    result matches the dense sign and is bitwise the single-source result."""
+    dims, links, _, _, _ = haar4_dense
+    V = int(np.prod(dims))
+    site = 37
+    B = np.zeros((12, 12 * V), dtype=complex)
+    for sc in range(12):
+        B[sc, site * 12 + sc] = 1.0
+    say("batch of 12 point sources, haar 4^4, m = 10")
+    # the oracle's error at k = 400 is 1.7e-11, so the estimate crosses 1e-10 just after
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=500, check_every=25, max_batch=12)
+    ctx.deflate(10)
+    Yb, infb, st = ctx.apply(dev(B), tol=1e-10)
+    assert st == osa.OSA_OK and all(i["batch"] == 12 for i in infb)
+    Yb = host(Yb)
+    ref = (haar4_sign @ B.T).T
+    for sc in range(12):
+        assert rel(Yb[sc], ref[sc]) < 1e-9, sc
+    ctx.set_opts(k_max=500, check_every=25, max_batch=1)
+    for sc in (0, 5, 11):
+        y1, inf1, _ = ctx.apply(dev(B[sc]), tol=1e-10)
+        assert inf1[0]["batch"] == 1 and inf1[0]["k_used"] == infb[sc]["k_used"]
+        assert np.array_equal(host(y1), Yb[sc])
+    ctx.close()
+
+
+def test_batch_mixed_sources_and_split(osa, haar4_dense, haar4_sign):
+    """One batch with sources that stop at different Krylov sizes (one inside
+    span(R), k = 0; one almost inside it; Gaussian and point sources) and one
+    NaN source, whose error stays its own.  Splitting the batch (max_batch 2)
+    gives bitwise the same results."""
+    dims, links, b, h, _ = haar4_dense
+    N = 12 * int(np.prod(dims))
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=400, check_every=20, max_batch=8)
+    ctx.deflate(10)
+    R, _, _ = ctx.get_deflation()
+    r = host(R)
+    in_span = (np.arange(10) + 1.0) @ r
+    in_span /= np.linalg.norm(in_span)
+    near = in_span + 1e-7 * LI.gaussian_source(dims, cfg=9, inst=22)
+    point = np.zeros(N, dtype=complex)
+    point[12 * 200 + 7] = 1.0
+    nan = LI.gaussian_source(dims, cfg=9, inst=23)
+    nan[3] = np.nan
+    B = np.stack([b, in_span, nan, near, point, LI.gaussian_source(dims, cfg=9, inst=21)])
+    say("mixed batch of 6 (k = 0, near span(R), NaN, point, 2 Gaussian)")
+    Y, inf, st = ctx.apply(dev(B), tol=1e-10, check=False)
+    assert st == -4
+    stat = [i["status"] for i in inf]
+    assert stat == [0, 0, -4, 0, 0, 0], stat
+    assert inf[1]["k_used"] == 0
+    ks = [inf[i]["k_used"] for i in (0, 3, 4, 5)]
+    assert len(set(ks)) > 1, ks
+    Y = host(Y)
+    for i in (0, 1, 3, 4, 5):
+        assert rel(Y[i], haar4_sign @ B[i]) < 1e-9, i
+    ctx.set_opts(k_max=400, check_every=20, max_batch=2)
+    Y2, inf2, st2 = ctx.apply(dev(B), tol=1e-10, check=False)
+    assert st2 == -4 and [i["batch"] for i in inf2] == [2, 2, 2, 2, 2, 2]
+    Y2 = host(Y2)
+    for i in (0, 1, 3, 4, 5):
+        assert np.array_equal(Y2[i], Y[i]), i
+        assert inf2[i]["k_used"] == inf[i]["k_used"]
+    ctx.close()
+
+
+def test_stencil_many_rhs(osa):
+    """70 right-hand sides: more than one launch group of the batched stencil."""
+    dims = (2, 2, 3, 2)
+    links = LI.make_links(dims, "haar", cfg=9, inst=24)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((70, 12 * 24)) + 1j * rng.standard_normal((70, 12 * 24))
+    say("stencil with 70 rhs")
+    ctx = osa.Context(dev(links), dims, 0.4, -1.5)
+    Y = host(ctx.apply_hw(dev(X)))
+    h = O.hermitian_wilson_sparse(links, dims, 0.4, -1.5)
+    for i in (0, 33, 63, 64, 69):
+        assert rel(Y[i], h @ X[i]) < 1e-14, i
+    ctx.close()
