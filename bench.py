@@ -220,7 +220,10 @@ def main():
     value = n_solves * args.steps / (t1 - t0)
     # dominant kernel class by accumulated time
     agg = {}
+    counters = {}
     for p in prof:
+        for k, v in p.pop("counters").items():
+            counters[k] = counters.get(k, 0) + v // args.steps
         for k, v in p.items():
             a = agg.setdefault(k, dict(ms=0.0, bytes=0.0, launches=0))
             for f in ("ms", "bytes", "launches"):
@@ -257,6 +260,7 @@ def main():
         "kernels": {k: {"ms": v["ms"] / args.steps, "launches": v["launches"] // args.steps,
                         "GB/s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else 0.0}
                     for k, v in agg.items()},
+        "counters_per_step": counters,
         "solve": {"k_used": k_used, "max_resid_est": max(r["resid_est"] for r in records),
                   "statuses": [r["status"] for r in records], "init_ms_per_instance": init_ms,
                   "solve_ms_mean": solve_ms,

@@ -208,12 +208,15 @@ OSA_API osa_status osa_set_links(osa_ctx* ctx, const void* links);
  * Newton iteration, 4 small Schur decomposition of an eigensolver restart,
  * 5 whole eigensolver restart (host wall clock, including synchronisation).
  * bytes[] counts the algorithmic HBM bytes of each launch (vectors read and
- * written once).  Enabling resets the counters; the events add a few
- * microseconds of overhead per bracketed launch. */
+ * written once).  counters[]: 0 QR sweeps and 1 plane rotations (sweeps plus
+ * reordering) of the small Schur decompositions, 2 Newton iterations of the
+ * small sign, 3 eigensolver Arnoldi steps.  Enabling resets everything; the
+ * events add a few microseconds of overhead per bracketed launch. */
 typedef struct {
     double ms[6];
     double bytes[6];
     int64_t launches[6];
+    int64_t counters[4];
 } osa_profile;
 OSA_API osa_status osa_profile_enable(osa_ctx* ctx, int32_t enable);
 OSA_API osa_status osa_profile_read(osa_ctx* ctx, osa_profile* out);

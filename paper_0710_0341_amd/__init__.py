@@ -63,14 +63,18 @@ class Info(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 6), ("bytes", ctypes.c_double * 6),
-                ("launches", ctypes.c_int64 * 6)]
+                ("launches", ctypes.c_int64 * 6), ("counters", ctypes.c_int64 * 4)]
 
     CLASSES = ("cgs_dot", "cgs_update", "stencil", "small_inverse", "small_schur",
                "eig_restart")
 
+    COUNTERS = ("schur_sweeps", "schur_rotations", "newton_iterations", "eig_arnoldi_steps")
+
     def as_dict(self):
-        return {name: dict(ms=self.ms[i], bytes=self.bytes[i], launches=self.launches[i])
-                for i, name in enumerate(self.CLASSES)}
+        d = {name: dict(ms=self.ms[i], bytes=self.bytes[i], launches=self.launches[i])
+             for i, name in enumerate(self.CLASSES)}
+        d["counters"] = {name: int(self.counters[i]) for i, name in enumerate(self.COUNTERS)}
+        return d
 
 
 class OsaError(RuntimeError):

@@ -392,6 +392,16 @@ void launch_diff_norm(const cd* s, int k, const cd* sprev, int kprev, double* ou
 // single-shift QR with Wilkinson shifts (exceptional shifts every 10
 // iterations without deflation), then reordering of the diagonal by adjacent
 // swaps.  One wavefront; T and Z live in LDS.
+// The Schur kernels below run as one 64-lane wavefront.  LDS operations of a
+// wavefront execute in issue order, so lanes exchange data through LDS with a
+// wavefront-scope fence and a wave barrier (ordering only for the compiler);
+// a workgroup barrier would also wait for every outstanding LDS access.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 static constexpr int kSchurMax = 64;
 
 __device__ __forceinline__ double sort_key(cd v, int mode) {
@@ -413,7 +423,7 @@ __device__ void apply_pair(cd* T, cd* Z, int p, int ld, int k, cd a, cd b, int c
         T[k + c * ld] = nx;
         T[k + 1 + c * ld] = ny;
     }
-    __syncthreads();
+    wave_sync();
     // right: columns k, k+1 over rows <= row1;  [x, y] Q = [a x + b y, -conj(b) x + conj(a) y]
     for (int r = l; r <= row1 && r < p; r += 64) {
         cd x = T[r + k * ld], y = T[r + (k + 1) * ld];
@@ -425,7 +435,7 @@ __device__ void apply_pair(cd* T, cd* Z, int p, int ld, int k, cd a, cd b, int c
         Z[r + k * ld] = cadd(cmul(a, x), cmul(b, y));
         Z[r + (k + 1) * ld] = csub(cmulc(a, y), cmulc(b, x));
     }
-    __syncthreads();
+    wave_sync();
 }
 
 __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, int p, cd* Tout,
@@ -453,7 +463,7 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
     if (l == 0) sanorm = amax;
-    __syncthreads();
+    wave_sync();
     const double anorm = sanorm;
     // ---- Hessenberg reduction (Householder)
     for (int j = 0; j + 2 < p; ++j) {
@@ -466,7 +476,7 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
         const double xn = sqrt(xn2);
         const cd x0 = TT(j + 1, j);
         const double tail = xn2 - cabs2(x0);
-        if (xn == 0.0 || tail <= 1e-300) { __syncthreads(); continue; }
+        if (xn == 0.0 || tail <= 1e-300) { wave_sync(); continue; }
         const double ax0 = cabsd(x0);
         const cd ph = ax0 > 0 ? cscale(x0, 1.0 / ax0) : mk(1.0, 0.0);
         const cd alpha = cscale(ph, -xn);           // -e^{i arg x0} |x|
@@ -474,7 +484,7 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
         for (int i = l; i < L; i += 64) hv[i] = (i == 0) ? csub(x0, alpha) : TT(j + 1 + i, j);
         const double vn2 = 2.0 * xn2 + 2.0 * xn * ax0;
         const double tau = 2.0 / vn2;
-        __syncthreads();
+        wave_sync();
         // left: T[j+1:, c] -= tau v (v^H T[j+1:, c]),  c >= j   (one column per lane)
         for (int c = j + l; c < p; c += 64) {
             cd sacc = mk(0.0, 0.0);
@@ -482,7 +492,7 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
             sacc = cscale(sacc, tau);
             for (int i = 0; i < L; ++i) TT(j + 1 + i, c) = csub(TT(j + 1 + i, c), cmul(hv[i], sacc));
         }
-        __syncthreads();
+        wave_sync();
         // right: T[r, j+1:] -= tau (T[r, j+1:] v) v^H, all rows; same for Z
         for (int r = l; r < p; r += 64) {
             cd sacc = mk(0.0, 0.0), sz = mk(0.0, 0.0);
@@ -497,9 +507,9 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
                 ZZ(r, j + 1 + i) = csub(ZZ(r, j + 1 + i), cmul(sz, cconj(hv[i])));
             }
         }
-        __syncthreads();
+        wave_sync();
         for (int i = l; i < L; i += 64) TT(j + 1 + i, j) = (i == 0) ? alpha : mk(0.0, 0.0);
-        __syncthreads();
+        wave_sync();
     }
     // ---- shifted QR
     const double ulp = 2.220446049250313e-16;
@@ -521,9 +531,9 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
         const unsigned long long mask = __ballot(neg);
         const int lo = mask ? 63 - __clzll(mask) : 0;
         if (lo > 0) {
-            __syncthreads();
+            wave_sync();
             if (l == 0) TT(lo, lo - 1) = mk(0.0, 0.0);
-            __syncthreads();
+            wave_sync();
         }
         if (lo == hi) { --hi; its = 0; continue; }
         if (total++ > maxtotal) { fail = true; break; }
@@ -584,7 +594,7 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
                 TT(j - 1, j - 1) = t22;
                 TT(j, j) = t11;
             }
-            __syncthreads();
+            wave_sync();
         }
     }
     for (int e = l; e < p * p; e += 64) {
@@ -637,9 +647,9 @@ __global__ __launch_bounds__(kBigThreads) void k_schur_log(const cd* __restrict_
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
     if (lane == 0) sred[wave] = amax;
-    __syncthreads();
+    wave_sync();
     const double anorm = sred[0];
-    __syncthreads();
+    wave_sync();
     // ---- Hessenberg reduction; reflectors logged for Z
     for (int j = 0; j + 2 < p; ++j) {
         const int L = p - j - 1;
@@ -648,12 +658,12 @@ __global__ __launch_bounds__(kBigThreads) void k_schur_log(const cd* __restrict_
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) xp += __shfl_xor(xp, off, 64);
         if (lane == 0) sred[wave] = xp;
-        __syncthreads();
+        wave_sync();
         const double xn2 = sred[0];
         const double xn = sqrt(xn2);
         const cd x0 = TT(j + 1, j);
         const double tail = xn2 - cabs2(x0);
-        __syncthreads();
+        wave_sync();
         if (xn == 0.0 || tail <= 1e-300) {
             if (l == 0) tlog[j] = 0.0;
             continue;
@@ -668,23 +678,23 @@ __global__ __launch_bounds__(kBigThreads) void k_schur_log(const cd* __restrict_
         }
         const double tau = 2.0 / (2.0 * xn2 + 2.0 * xn * ax0);
         if (l == 0) tlog[j] = tau;
-        __syncthreads();
+        wave_sync();
         for (int c = j + l; c < p; c += kBigThreads) {
             cd sacc = mk(0.0, 0.0);
             for (int i = 0; i < L; ++i) cfmac(sacc, hv[i], TT(j + 1 + i, c));
             sacc = cscale(sacc, tau);
             for (int i = 0; i < L; ++i) TT(j + 1 + i, c) = csub(TT(j + 1 + i, c), cmul(hv[i], sacc));
         }
-        __syncthreads();
+        wave_sync();
         for (int r = l; r < p; r += kBigThreads) {
             cd sacc = mk(0.0, 0.0);
             for (int i = 0; i < L; ++i) cfma(sacc, TT(r, j + 1 + i), hv[i]);
             sacc = cscale(sacc, tau);
             for (int i = 0; i < L; ++i) TT(r, j + 1 + i) = csub(TT(r, j + 1 + i), cmul(sacc, cconj(hv[i])));
         }
-        __syncthreads();
+        wave_sync();
         for (int i = l; i < L; i += kBigThreads) TT(j + 1 + i, j) = (i == 0) ? alpha : mk(0.0, 0.0);
-        __syncthreads();
+        wave_sync();
     }
     int nrot = 0;
     bool overflow = false;
@@ -694,7 +704,7 @@ __global__ __launch_bounds__(kBigThreads) void k_schur_log(const cd* __restrict_
             TT(k, c) = cadd(cmulc(a, x), cmulc(b, y));
             TT(k + 1, c) = (c == zero_col) ? mk(0.0, 0.0) : csub(cmul(a, y), cmul(b, x));
         }
-        __syncthreads();
+        wave_sync();
         for (int r = l; r <= row1 && r < p; r += kBigThreads) {
             const cd x = TT(r, k), y = TT(r, k + 1);
             TT(r, k) = cadd(cmul(a, x), cmul(b, y));
@@ -705,7 +715,7 @@ __global__ __launch_bounds__(kBigThreads) void k_schur_log(const cd* __restrict_
         }
         if (nrot >= rcap) overflow = true;
         ++nrot;
-        __syncthreads();
+        wave_sync();
     };
     // ---- shifted QR
     const double ulp = 2.220446049250313e-16;
@@ -727,10 +737,10 @@ __global__ __launch_bounds__(kBigThreads) void k_schur_log(const cd* __restrict_
         int lo = 0;
         if (m1) lo = 64 + 63 - __clzll(m1);
         else if (m0) lo = 63 - __clzll(m0);
-        __syncthreads();
+        wave_sync();
         if (lo > 0) {
             if (l == 0) TT(lo, lo - 1) = mk(0.0, 0.0);
-            __syncthreads();
+            wave_sync();
         }
         if (lo == hi) { --hi; its = 0; continue; }
         if (total++ > maxtotal) { fail = true; break; }
@@ -783,7 +793,7 @@ __global__ __launch_bounds__(kBigThreads) void k_schur_log(const cd* __restrict_
                 TT(j - 1, j - 1) = t22;
                 TT(j, j) = t11;
             }
-            __syncthreads();
+            wave_sync();
         }
     }
     for (int e = l; e < p * p; e += kBigThreads) Tout[e] = TT(e % p, e / p);
@@ -811,9 +821,9 @@ __global__ __launch_bounds__(64) void k_schur_build_z(int p, const cd* __restric
         const double tau = tlog[j];
         if (tau == 0.0) continue;
         const int L = p - j - 1;
-        __syncthreads();
+        wave_sync();
         for (int i = lane; i < L; i += 64) vsh[i] = hlog[(size_t)j * p + i];   // stage v_j
-        __syncthreads();
+        wave_sync();
         cd s = mk(0.0, 0.0);
         for (int i = 0; i < L; ++i) cfma(s, zs[(j + 1 + i) * 64 + lane], vsh[i]);
         s = cscale(s, tau);
@@ -825,9 +835,9 @@ __global__ __launch_bounds__(64) void k_schur_build_z(int p, const cd* __restric
     const int nrot = info[1];
     for (int base = 0; base < nrot; base += 128) {
         const int cnt = (nrot - base < 128) ? nrot - base : 128;
-        __syncthreads();
+        wave_sync();
         for (int e = lane; e < cnt; e += 64) chunk[e] = rlog[base + e];
-        __syncthreads();
+        wave_sync();
         for (int e = 0; e < cnt; ++e) {
             const RotEntry q = chunk[e];
             cd& zx = zs[q.k * 64 + lane];

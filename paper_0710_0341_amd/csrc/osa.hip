@@ -456,6 +456,7 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
         d2h_strided(c, red, c->red_stride * (int64_t)sizeof(double), 2, act, hred);
         d2h_strided(c, c->nflag.p, 4 * (int64_t)sizeof(int), 1, act, hflag);
         std::vector<int> next;
+        if (c->prof_on) c->prof.counters[2] += (int64_t)act.size();
         for (size_t i = 0; i < act.size(); ++i) {
             const int b = act[i];
             const double d2 = hred[2 * i], n2 = hred[2 * i + 1];
@@ -814,6 +815,7 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
             apply_h(c, vec(j), tv.p, fp32, adjoint);
             apply_h(c, tv.p, wv.p, fp32, adjoint);
             stats.matvecs += 2;
+            c->prof.counters[3] += c->prof_on ? 1 : 0;
             cd* scol = S.as<cd>() + (size_t)j * ldS;
             cgs2(c, wv.p, V, N, j + 1, fp32, scol, c->coef.as<cd>());
             launch_normalize(wv.p, vec(j + 1), fp32, pl, c->normp.as<double>(), scol + (j + 1),
@@ -833,8 +835,13 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
         // spike in the Schur basis: b^H Z with b^H = S[ptot, nlock:ptot]
         launch_zgemm(0, 0, 1, na, na, mk(1.0, 0.0), S.as<cd>() + ptot + (size_t)nlock * ldS, ldS,
                      Z.as<cd>(), na, mk(0.0, 0.0), bz.as<cd>(), 1, c->st);
-        int hinfo = 0;
-        d2h(c, info.p, 1, &hinfo);
+        int hinfo2[2] = {0, 0};
+        d2h(c, info.p, 2, hinfo2);
+        const int hinfo = hinfo2[0];
+        if (c->prof_on && hinfo >= 0) {
+            c->prof.counters[0] += hinfo;
+            c->prof.counters[1] += hinfo2[1];
+        }
         if (hinfo < 0)
             throw OsaError{OSA_ERR_EIG_NOCONV, "small Schur QR did not converge (active block " +
                                                    std::to_string(na) + ", restart " +
@@ -1047,6 +1054,7 @@ void deflate(osa_ctx* c, int m, osa_info* info) {
             c->prof.bytes[i] += w->prof.bytes[i];
             c->prof.launches[i] += w->prof.launches[i];
         }
+        for (int i = 0; i < 4; ++i) c->prof.counters[i] += w->prof.counters[i];
     }
     if (merr) std::rethrow_exception(merr);
     if (werr) std::rethrow_exception(werr);
