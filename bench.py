@@ -40,7 +40,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eig-prec", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--workload", choices=["dis8", "haar4"], default="dis8")
+    ap.add_argument("--eig-ncv", type=int, default=0,
+                    help="eigensolver active block (0: the library default)")
+    ap.add_argument("--workload", choices=["dis8", "haar4", "uneven64"], default="dis8",
+                    help="uneven64: 64 independent instances (6^4/8^4/10^4), solved concurrently")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--solve-only", action="store_true",
@@ -121,11 +124,11 @@ def batched_vs_plain(osa, ctx, dims, tol, m, reps=1):
     """12 point sources: one at a time (max_batch 1) vs one lockstep batch."""
     import torch
     B = torch.from_numpy(point_sources(dims)).to("cuda:0")
-    k_max, eig_prec = ctx._opts.k_max, ctx._opts.eig_prec
+    k_max, eig_prec, ncv = ctx._opts.k_max, ctx._opts.eig_prec, ctx._opts.eig_ncv
     out = {}
     ys = {}
     for name, mb in (("plain", 1), ("batched", 12)):
-        ctx.set_opts(k_max=k_max, check_every=50, max_batch=mb, eig_prec=eig_prec)
+        ctx.set_opts(k_max=k_max, check_every=50, max_batch=mb, eig_prec=eig_prec, eig_ncv=ncv)
         ctx.set_active_deflation(m)
         ctx.apply(B, tol=tol)            # warm-up (workspace growth)
         torch.cuda.synchronize()
@@ -138,12 +141,96 @@ def batched_vs_plain(osa, ctx, dims, tol, m, reps=1):
         out[name] = {"solves_per_s": 12.0 / dt, "ms": dt * 1e3, "status": int(st),
                      "k_used": [i["k_used"] for i in infos],
                      "max_resid_est": max(i["resid_est"] for i in infos)}
-    ctx.set_opts(k_max=k_max, check_every=50, eig_prec=eig_prec)
+    ctx.set_opts(k_max=k_max, check_every=50, eig_prec=eig_prec, eig_ncv=ncv)
     out["speedup"] = out["batched"]["solves_per_s"] / out["plain"]["solves_per_s"]
     out["bitwise_equal"] = bool(torch.equal(ys["plain"], ys["batched"]))
     out["sources"] = "12 spin-colour point sources at site 0"
     out["mu"], out["n_defl"], out["tol"] = ctx.mu, m, tol
     return out
+
+
+def uneven_batch(args):
+    """64 independent instances with lattices from {6^4, 8^4, 10^4}, random mu,
+    m_w, eps and 8-32 deflated pairs, one Gaussian source each.  Deflation runs
+    on 8 host threads (one stream per instance), then one osa_batch_apply solves
+    all 64 concurrently; the same 64 solved one after another give the
+    sequential reference (results must agree bitwise)."""
+    import threading
+    import torch
+
+    import lattice_inputs as LI
+    import paper_0710_0341_amd as osa
+    w = LI.WORKLOADS[4]
+    params = LI.uneven_batch_params(64)
+    ctxs, srcs = [], []
+    for p in params:
+        links = LI.make_links(p["dims"], "disordered", eps=p["eps"], cfg=4, inst=p["inst"])
+        b = LI.gaussian_source(p["dims"], cfg=4, inst=p["inst"])
+        ctxs.append(osa.Context(torch.from_numpy(links).to("cuda:0"), p["dims"], p["mu"], p["m_w"],
+                                k_max=w["k_max"], check_every=50, stream=torch.cuda.Stream()))
+        srcs.append(torch.from_numpy(b).to("cuda:0"))
+    torch.cuda.synchronize()
+    eig_ms = [0.0] * len(ctxs)
+    defl_err = [0] * len(ctxs)
+    nxt = [0]
+    lock = threading.Lock()
+
+    def deflate_worker():
+        while True:
+            with lock:
+                i = nxt[0]
+                nxt[0] += 1
+            if i >= len(ctxs):
+                return
+            t0 = time.perf_counter()
+            try:
+                ctxs[i].deflate(params[i]["n_defl"])
+            except osa.OsaError as e:      # the instance is then solved without deflation
+                defl_err[i] = e.status
+            eig_ms[i] = (time.perf_counter() - t0) * 1e3
+
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=deflate_worker) for _ in range(8)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    t_defl = time.perf_counter() - t0
+    osa.batch_apply(ctxs, srcs, tol=w["tol"])          # warm-up: workspace growth
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ys, infos, st = osa.batch_apply(ctxs, srcs, tol=w["tol"])
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    seq = [c.apply(b, tol=w["tol"])[0] for c, b in zip(ctxs, srcs)]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    lat = np.array([i["t_solve_ms"] for i in infos])
+    out = {
+        "metric": "uneven batch: instances/s and per-instance latency", "unit": "instances/s",
+        "value": len(ctxs) / t_batch, "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+        "dtype": "c128",
+        "config": {"workload": "uneven64", "instances": len(ctxs), "lattices": "6^4/8^4/10^4",
+                   "k_max": w["k_max"], "tol": w["tol"], "concurrent_instances": 8},
+        "batch_ms": t_batch * 1e3, "sequential_ms": t_seq * 1e3,
+        "speedup_vs_sequential": t_seq / t_batch,
+        "bitwise_equal": all(bool(torch.equal(a, b)) for a, b in zip(ys, seq)),
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max())},
+        "statuses": sorted(set(int(i["status"]) for i in infos)),
+        "k_used": {"min": int(min(i["k_used"] for i in infos)),
+                   "max": int(max(i["k_used"] for i in infos))},
+        "deflation": {"wall_ms": t_defl * 1e3, "host_threads": 8,
+                      "per_instance_ms_p50": float(np.percentile(eig_ms, 50)),
+                      "per_instance_ms_p99": float(np.percentile(eig_ms, 99)),
+                      "failed": [{"inst": i, "status": e, "dims": params[i]["dims"],
+                                  "n_defl": params[i]["n_defl"], "m_w": params[i]["m_w"],
+                                  "mu": params[i]["mu"]} for i, e in enumerate(defl_err) if e]},
+    }
+    print(json.dumps(out), flush=True)
+    for c in ctxs:
+        c.close()
 
 
 def main():
@@ -154,6 +241,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "uneven64":
+        uneven_batch(args)
         return
     import torch
 
@@ -169,7 +259,7 @@ def main():
     b = torch.from_numpy(b_np).to(dev)
     eig_prec = osa.FP32 if args.eig_prec == "fp32" else osa.FP64
     ctxs = [osa.Context(links, dims, mu, wl["m_w"], k_max=wl["k_max"], check_every=50,
-                        eig_prec=eig_prec) for mu in wl["mus"]]
+                        eig_prec=eig_prec, eig_ncv=args.eig_ncv) for mu in wl["mus"]]
     mmax = max(wl["ms"])
     records = []
 
@@ -195,10 +285,26 @@ def main():
         ctx = ctxs[-1]
         ctx.deflate(mmax)
         ctx.set_active_deflation(mmax)
-        for _ in range(args.steps):
-            ctx.apply(b, tol=wl["tol"])
-        torch.cuda.synchronize()
-        print(json.dumps({"solve_only": True, "mu": ctx.mu, "m": mmax}))
+        ctx.apply(b, tol=wl["tol"])
+        rec = {"solve_only": True, "mu": ctx.mu, "m": mmax}
+        for orth in (0, 1):
+            ctx.set_opts(k_max=wl["k_max"], check_every=50, orth=orth)
+            ctx.set_active_deflation(mmax)
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, infos, _ = ctx.apply(b, tol=wl["tol"])
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            prof = ctx.profile_read()
+            ctx.profile(False)
+            rec[f"orth{orth}"] = {"ms_per_solve": dt * 1e3, "k_used": infos[0]["k_used"],
+                                  "newton_iters": infos[0]["newton_iters"],
+                                  "classes": {k: (round(v["ms"] / args.steps, 2), v["launches"] // args.steps)
+                                              for k, v in prof.items() if k != "counters"},
+                                  "counters": prof["counters"]}
+        print(json.dumps(rec))
         return
     for _ in range(args.warmup):
         step(False)

@@ -81,7 +81,13 @@ typedef struct {
     double eig_tol;             /* relative Krylov-Schur residual target   (default 1e-12)    */
     int32_t max_batch;          /* sources solved together in lockstep by osa_apply, 1..64
                                    (default 16); workspace grows with it: max_batch Krylov
-                                   bases of k_max + 1 vectors of N complex128                */
+                                   bases of k_max + 2 vectors of N complex128                */
+    int32_t orth;               /* Arnoldi orthogonalisation of the solve (Eq. 7):
+                                   0 (default): classical Gram-Schmidt with the second pass
+                                   delayed by one step: one dot pass over the basis with two
+                                   vectors and one fused update pass per step (half the
+                                   basis traffic); 1: classical Gram-Schmidt applied twice
+                                   in the same step (four passes)                          */
 } osa_opts;
 
 /* Per-solve diagnostics (host struct). */
@@ -169,9 +175,15 @@ OSA_API osa_status osa_set_active_deflation(osa_ctx* ctx, int32_t m);
 OSA_API osa_status osa_apply(osa_ctx* ctx, int32_t nrhs, const void* B, void* Y, double tol,
                      osa_info* infos);
 
-/* Uneven batch: n independent contexts (different lattices, mu, m_w), one
- * source each, solved together.  B[i], Y[i] are device pointers to N_i
- * complex128; infos (host) n records. */
+/* Uneven batch: n independent contexts (different lattices, mu, m_w and
+ * deflation data), one source each, solved concurrently: up to 8 instances at
+ * a time, each on a stream of its own that waits for the work already queued
+ * on the context's stream; the call returns when all are done.  Each result is
+ * exactly what osa_apply gives for that context.  B[i], Y[i]: device pointers
+ * to N_i complex128; infos (host, may be NULL) n records, whose t_solve_ms is
+ * the instance's own wall time (the latency the instance saw once started).
+ * The contexts must be distinct (OSA_ERR_ARG otherwise).  Returns the first
+ * error in instance order, else the worst status. */
 OSA_API osa_status osa_batch_apply(int32_t n, osa_ctx* const* ctxs, const void* const* B,
                            void* const* Y, double tol, osa_info* infos);
 

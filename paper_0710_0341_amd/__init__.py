@@ -45,7 +45,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("no_reproject", ctypes.c_int32), ("eig_ncv", ctypes.c_int32),
                 ("eig_max_restarts", ctypes.c_int32), ("eig_prec", ctypes.c_int32),
-                ("eig_tol", ctypes.c_double), ("max_batch", ctypes.c_int32)]
+                ("eig_tol", ctypes.c_double), ("max_batch", ctypes.c_int32),
+                ("orth", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -163,12 +164,13 @@ def _lattice(dims, antiperiodic_t=False):
 
 
 def make_opts(k_max=0, check_every=0, no_reproject=False, eig_ncv=0, eig_max_restarts=0,
-              eig_prec=FP64, eig_tol=0.0, max_batch=0):
+              eig_prec=FP64, eig_tol=0.0, max_batch=0, orth=0):
     o = Opts()
     o.k_max, o.check_every, o.no_reproject = int(k_max), int(check_every), int(bool(no_reproject))
     o.eig_ncv, o.eig_max_restarts, o.eig_prec = int(eig_ncv), int(eig_max_restarts), int(eig_prec)
     o.eig_tol = float(eig_tol)
     o.max_batch = int(max_batch)
+    o.orth = int(orth)
     return o
 
 
@@ -203,7 +205,9 @@ sign_apply = overlap_sign_apply
 class Context:
     """Reusable context: create once, deflate once, apply to many sources."""
 
-    def __init__(self, links, dims, mu, m_w, antiperiodic_t=False, **opts):
+    def __init__(self, links, dims, mu, m_w, antiperiodic_t=False, stream=None, **opts):
+        """stream: a torch.cuda.Stream for all work of this context (default: the
+        current stream)."""
         self._h = ctypes.c_void_p(None)
         self.dims = tuple(int(d) for d in dims)
         self.V = int(np.prod(self.dims))
@@ -215,8 +219,10 @@ class Context:
             raise ValueError("links must have V*4*3*3 entries")
         self._opts = make_opts(**opts)
         lat = _lattice(dims, antiperiodic_t)
+        st = _stream() if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        self.stream = stream
         _check(lib().osa_create(ctypes.byref(self._h), ctypes.byref(lat), lp, prec, self.mu,
-                                self.m_w, ctypes.byref(self._opts), _stream()), "osa_create",
+                                self.m_w, ctypes.byref(self._opts), st), "osa_create",
                allow_not_converged=False)
 
     def close(self):
@@ -252,6 +258,7 @@ class Context:
             lpp = _dev_ptr(L, torch.complex128, "L")
         else:
             rp = lpp = ctypes.c_void_p(None)
+        self._after_current()
         _check(lib().osa_set_deflation(self._h, m, rp, lpp,
                                        lam_d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                "osa_set_deflation", False)
@@ -282,15 +289,23 @@ class Context:
         bp = _dev_ptr(B, torch.complex128, "B")
         nrhs = 1 if B.dim() == 1 else int(B.shape[0])
         Y = torch.zeros_like(B)
+        self._after_current()
         infos = (Info * nrhs)()
         st = lib().osa_apply(self._h, nrhs, bp, ctypes.c_void_p(Y.data_ptr()), float(tol), infos)
         if check:
             _check(st, "osa_apply")
         return Y, [i.as_dict() for i in infos], st
 
+    def _after_current(self):
+        """Order this context's stream after the work queued so far on the current
+        stream (inputs, output allocation)."""
+        if self.stream is not None:
+            self.stream.wait_stream(_torch().cuda.current_stream())
+
     def set_links(self, links):
         """Re-ingest new links (same lattice and precision); drops the deflation data."""
         lp = _dev_ptr(links, links.dtype, "links")
+        self._after_current()
         _check(lib().osa_set_links(self._h, lp), "osa_set_links", False)
 
     def profile(self, enable=True):
@@ -307,22 +322,28 @@ class Context:
         xp = _dev_ptr(X, torch.complex128, "X")
         nrhs = 1 if X.dim() == 1 else int(X.shape[0])
         Y = torch.empty_like(X)
+        self._after_current()
         _check(lib().osa_apply_hw(self._h, nrhs, xp, ctypes.c_void_p(Y.data_ptr())),
                "osa_apply_hw", False)
         return Y
 
 
-def batch_apply(contexts, sources, tol=1e-10):
-    """Uneven batch: one source per context.  Returns (outputs, infos, status)."""
+def batch_apply(contexts, sources, tol=1e-10, check=True):
+    """Uneven batch: one source per context, instances solved concurrently.
+    Returns (outputs, infos, status); check=False returns error statuses
+    instead of raising."""
     torch = _torch()
     n = len(contexts)
-    outs = [torch.empty_like(b) for b in sources]
+    outs = [torch.zeros_like(b) for b in sources]
+    for c in contexts:
+        c._after_current()
     hs = (ctypes.c_void_p * n)(*[c._h.value for c in contexts])
     bs = (ctypes.c_void_p * n)(*[_dev_ptr(b, torch.complex128, "B").value for b in sources])
     ys = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
     infos = (Info * n)()
     st = lib().osa_batch_apply(n, hs, bs, ys, float(tol), infos)
-    _check(st, "osa_batch_apply")
+    if check:
+        _check(st, "osa_batch_apply")
     return outs, [i.as_dict() for i in infos], st
 
 

@@ -116,6 +116,67 @@ void launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bo
     OSA_LAUNCH_CHECK();
 }
 
+// Two vectors against the same columns (one read of B): partial[c*nchunks + q]
+// for w1 and partial[(ncols + c)*nchunks + q] for w2.
+template <typename T, int C>
+__global__ __launch_bounds__(kBlock) void k_dot2_partial(const T* __restrict__ B, int64_t ldb,
+                                                         int ncols, const T* __restrict__ w1,
+                                                         const T* __restrict__ w2, int64_t n,
+                                                         int rpc, int nchunks,
+                                                         cd* __restrict__ partial, Batch bt) {
+    __shared__ double sm[kWaves * 4 * C];
+    __shared__ double so[4 * C];
+    const int pb = bt.idx[blockIdx.z];
+    B += pb * bt.basis;
+    w1 += pb * bt.basis;
+    w2 += pb * bt.vec;
+    partial += pb * bt.part;
+    const int q = blockIdx.x;
+    const int c0 = blockIdx.y * C;
+    const int64_t r0 = (int64_t)q * rpc;
+    const int64_t r1 = (r0 + rpc < n) ? r0 + rpc : n;
+    double acc[4 * C];
+#pragma unroll
+    for (int i = 0; i < 4 * C; ++i) acc[i] = 0.0;
+    const int nc = (ncols - c0 < C) ? ncols - c0 : C;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+        const cd a = tod(w1[i]), b2 = tod(w2[i]);
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+            if (cc < nc) {
+                const cd v = tod(B[(int64_t)(c0 + cc) * ldb + i]);
+                acc[4 * cc] = fma(v.x, a.x, fma(v.y, a.y, acc[4 * cc]));
+                acc[4 * cc + 1] = fma(v.x, a.y, fma(-v.y, a.x, acc[4 * cc + 1]));
+                acc[4 * cc + 2] = fma(v.x, b2.x, fma(v.y, b2.y, acc[4 * cc + 2]));
+                acc[4 * cc + 3] = fma(v.x, b2.y, fma(-v.y, b2.x, acc[4 * cc + 3]));
+            }
+        }
+    }
+    block_sum<4 * C>(acc, sm, so);
+    if (threadIdx.x < nc) {
+        const int c = c0 + threadIdx.x;
+        partial[(int64_t)c * nchunks + q] = mk(so[4 * threadIdx.x], so[4 * threadIdx.x + 1]);
+        partial[(int64_t)(ncols + c) * nchunks + q] =
+            mk(so[4 * threadIdx.x + 2], so[4 * threadIdx.x + 3]);
+    }
+}
+
+void launch_dot2_partial(const void* B, int64_t ldb, int ncols, const void* w1, const void* w2,
+                         bool fp32, const TsPlan& p, cd* partial, hipStream_t st, const Batch& bt) {
+    if (ncols <= 0 || bt.n <= 0) return;
+    constexpr int C = 8;
+    dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)bt.n), blk(kBlock);
+    if (fp32)
+        hipLaunchKernelGGL((k_dot2_partial<cf, C>), grid, blk, 0, st, (const cf*)B, ldb, ncols,
+                           (const cf*)w1, (const cf*)w2, p.n, p.rows_per_chunk, p.nchunks, partial,
+                           bt);
+    else
+        hipLaunchKernelGGL((k_dot2_partial<cd, C>), grid, blk, 0, st, (const cd*)B, ldb, ncols,
+                           (const cd*)w1, (const cd*)w2, p.n, p.rows_per_chunk, p.nchunks, partial,
+                           bt);
+    OSA_LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------- reduce
 // val[c] = sum_q partial[c*nchunks + q], one wavefront per column (lane q holds
 // chunk q, q + 64, ...; fixed shuffle tree, so the order never changes).
@@ -342,6 +403,255 @@ void launch_combine(void* y, const void* B, int64_t ldb, int ncols, const cd* co
     else
         update_impl<cd>((cd*)y, (const cd*)B, ldb, ncols, coef, n, add ? 1.0 : 0.0, 1.0, nullptr,
                         nullptr, 0, st, bt);
+}
+
+// ------------------------------------------------ delayed reorthogonalisation
+// Step j (>= 1) of the Arnoldi recurrence with delayed reorthogonalisation.
+// Column j of the basis holds u_j, orthogonalised once and not normalised; z =
+// H u_j (re-projected).  With s = V_j^H u_j, t = V_j^H z, r = |u_j - V_j s| and
+// c_j = v_j^H z (all from one dot pass over [V_j, u_j] with [u_j, z]):
+//   v_j     = (u_j - V_j s) / r
+//   u_{j+1} = (z - V_j t - c_j v_j) / r
+// one pass over V_j computes both.  coef: s at [0, j), t at [j+1, 2j+1);
+// sc: [0] = 1/r (0 after a breakdown), [1] = c_j.
+template <typename T>
+__device__ __forceinline__ void gemv2_rows(const T* __restrict__ B, int64_t ldb, int cbeg, int cend,
+                                           const cd* __restrict__ cs, const cd* __restrict__ ct,
+                                           int64_t i, cd* s1, cd* s2, cd& as, cd& at) {
+    as = mk(0.0, 0.0);
+    at = mk(0.0, 0.0);
+    for (int cb = cbeg; cb < cend; cb += kCoefTile) {
+        const int ce = (cb + kCoefTile < cend) ? cb + kCoefTile : cend;
+        __syncthreads();
+        for (int c = cb + (int)threadIdx.x; c < ce; c += kBlock) {
+            s1[c - cb] = cs[c];
+            s2[c - cb] = ct[c];
+        }
+        __syncthreads();
+        int c = cb;
+        for (; c + 2 <= ce; c += 2) {
+            const cd b0 = tod(B[(int64_t)(c + 0) * ldb + i]);
+            const cd b1 = tod(B[(int64_t)(c + 1) * ldb + i]);
+            cfma(as, b0, s1[c - cb + 0]);
+            cfma(at, b0, s2[c - cb + 0]);
+            cfma(as, b1, s1[c - cb + 1]);
+            cfma(at, b1, s2[c - cb + 1]);
+        }
+        for (; c < ce; ++c) {
+            const cd b0 = tod(B[(int64_t)c * ldb + i]);
+            cfma(as, b0, s1[c - cb]);
+            cfma(at, b0, s2[c - cb]);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void dcgs_finish_row(T* __restrict__ V, int64_t ldb, int j,
+                                                const T* __restrict__ z, const cd* sc, int64_t i,
+                                                cd as, cd at) {
+    const double ir = sc[0].x;
+    const cd cj = sc[1];
+    const cd u = tod(V[(int64_t)j * ldb + i]);
+    const cd v = cscale(csub(u, as), ir);
+    const cd v_st = tod(fromd<T>(v));
+    cd un = csub(csub(tod(z[i]), at), cmul(cj, v_st));
+    un = cscale(un, ir);
+    V[(int64_t)j * ldb + i] = fromd<T>(v);
+    V[(int64_t)(j + 1) * ldb + i] = fromd<T>(un);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dcgs_update(T* V, int64_t ldb, int j,
+                                                        const T* __restrict__ z,
+                                                        const cd* __restrict__ coef,
+                                                        const cd* __restrict__ sc, int64_t n,
+                                                        Batch bt) {
+    __shared__ cd s1[kCoefTile], s2[kCoefTile];
+    const int pb = bt.idx[blockIdx.y];
+    V += pb * bt.basis;
+    z += pb * bt.vec;
+    coef += pb * bt.small;
+    sc += pb * bt.scal;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t ii = (i < n) ? i : n - 1;
+    cd as, at;
+    gemv2_rows(V, ldb, 0, j, coef, coef + j + 1, ii, s1, s2, as, at);
+    if (i < n) dcgs_finish_row(V, ldb, j, z, sc, i, as, at);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dcgs_split(const T* __restrict__ V, int64_t ldb, int j,
+                                                       const cd* __restrict__ coef, int64_t n,
+                                                       int cpg, cd* __restrict__ scratch, int G,
+                                                       Batch bt) {
+    __shared__ cd s1[kCoefTile], s2[kCoefTile];
+    const int pb = bt.idx[blockIdx.z];
+    V += pb * bt.basis;
+    coef += pb * bt.small;
+    scratch += (int64_t)blockIdx.z * 2 * G * n;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t ii = (i < n) ? i : n - 1;
+    const int g = blockIdx.y;
+    const int cb = g * cpg;
+    const int ce = (cb + cpg < j) ? cb + cpg : j;
+    cd as, at;
+    gemv2_rows(V, ldb, cb, ce, coef, coef + j + 1, ii, s1, s2, as, at);
+    if (i < n) {
+        scratch[(int64_t)(2 * g) * n + i] = as;
+        scratch[(int64_t)(2 * g + 1) * n + i] = at;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dcgs_finish(T* V, int64_t ldb, int j,
+                                                        const T* __restrict__ z,
+                                                        const cd* __restrict__ scratch, int G,
+                                                        const cd* __restrict__ sc, int64_t n,
+                                                        Batch bt) {
+    const int pb = bt.idx[blockIdx.y];
+    V += pb * bt.basis;
+    z += pb * bt.vec;
+    sc += pb * bt.scal;
+    scratch += (int64_t)blockIdx.y * 2 * G * n;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    cd as = mk(0.0, 0.0), at = mk(0.0, 0.0);
+    for (int g = 0; g < G; ++g) {
+        as = cadd(as, scratch[(int64_t)(2 * g) * n + i]);
+        at = cadd(at, scratch[(int64_t)(2 * g + 1) * n + i]);
+    }
+    dcgs_finish_row(V, ldb, j, z, sc, i, as, at);
+}
+
+template <typename T>
+static void dcgs_impl(T* V, int64_t ldb, int j, const T* z, const cd* coef, const cd* sc,
+                      int64_t n, cd* scratch, int64_t scratch_len, hipStream_t st,
+                      const Batch& bt) {
+    if (bt.n <= 0) return;
+    const int rb = (int)ceil_div(n, kBlock);
+    // the same split rule as the plain update: it depends on rows and columns only
+    int G = 1;
+    if (j > 32 && rb < 1024 && scratch) {
+        G = (int)ceil_div(1024, rb);
+        int gmax = j / 16;
+        if (G > gmax) G = gmax;
+        if (G > 8) G = 8;
+        while (G > 1 && (int64_t)2 * G * n * bt.n > scratch_len) --G;
+    }
+    if (G <= 1) {
+        hipLaunchKernelGGL((k_dcgs_update<T>), dim3(rb, bt.n), dim3(kBlock), 0, st, V, ldb, j, z,
+                           coef, sc, n, bt);
+    } else {
+        const int cpg = (int)ceil_div(j, G);
+        G = (int)ceil_div(j, cpg);
+        hipLaunchKernelGGL((k_dcgs_split<T>), dim3(rb, G, bt.n), dim3(kBlock), 0, st,
+                           (const T*)V, ldb, j, coef, n, cpg, scratch, G, bt);
+        hipLaunchKernelGGL((k_dcgs_finish<T>), dim3(rb, bt.n), dim3(kBlock), 0, st, V, ldb, j, z,
+                           (const cd*)scratch, G, sc, n, bt);
+    }
+    OSA_LAUNCH_CHECK();
+}
+
+void launch_dcgs_update(void* V, int64_t ldb, int j, const void* z, const cd* coef, const cd* sc,
+                        bool fp32, int64_t n, cd* scratch, int64_t scratch_len, hipStream_t st,
+                        const Batch& bt) {
+    if (fp32)
+        dcgs_impl<cf>((cf*)V, ldb, j, (const cf*)z, coef, sc, n, scratch, scratch_len, st, bt);
+    else
+        dcgs_impl<cd>((cd*)V, ldb, j, (const cd*)z, coef, sc, n, scratch, scratch_len, st, bt);
+}
+
+// Small per-problem part of step j.  k_dcgs_coef (one block per problem), from
+// the reduced dot products d = [s (j), u^H u, t (j), u^H z], completes column
+// j-1 of H (H[0:j, j-1] += s, H[j, j-1] = r, with the breakdown test of the
+// plain recurrence) and sets sc = [1/r, c_j]; k_dcgs_col (one wavefront per
+// row) then writes the first-pass column j,
+//   H[0:j+1, j] = ([t; c_j] - H[0:j+1, 0:j] s) / r.
+__global__ __launch_bounds__(256) void k_dcgs_coef(int j, cd* H, int ldh, const cd* __restrict__ d,
+                                                   cd* sc, double* hfro2, int* flag, double rel,
+                                                   Batch bt) {
+    __shared__ double sred[4 * 4];
+    const int pb = bt.idx[blockIdx.x];
+    H += pb * bt.small;
+    d += pb * bt.small;
+    sc += pb * bt.scal;
+    hfro2 += 2 * pb * bt.scal;
+    flag += pb * bt.flag;
+    const cd* s = d;
+    const cd* t = d + j + 1;
+    double ss = 0, stx = 0, sty = 0, col2 = 0;
+    for (int c = threadIdx.x; c < j; c += 256) {
+        const cd sv = s[c], tv = t[c];
+        ss += cabs2(sv);
+        stx += sv.x * tv.x + sv.y * tv.y;   // conj(s) t
+        sty += sv.x * tv.y - sv.y * tv.x;
+        const cd hc = cadd(H[c + (int64_t)(j - 1) * ldh], sv);
+        H[c + (int64_t)(j - 1) * ldh] = hc;
+        col2 += cabs2(hc);
+    }
+    double v4[4] = {ss, stx, sty, col2};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double x = wave_sum(v4[q]);
+        if (lane == 0) sred[wave * 4 + q] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot[4] = {0, 0, 0, 0};
+        for (int w = 0; w < 4; ++w)
+            for (int q = 0; q < 4; ++q) tot[q] += sred[w * 4 + q];
+        const double alpha = d[j].x;
+        const double r = sqrt(fmax(alpha - tot[0], 0.0));
+        *hfro2 += tot[3];
+        const double scale = sqrt(*hfro2 + r * r);
+        int bd = (r <= rel * scale) ? 1 : 0;
+        if (!(r == r) || r > 1e300 || !(alpha == alpha)) bd = 2;   // non-finite
+        if (bd) {
+            if (flag[0] == 0) flag[1] = j - 1;
+            if (bd > flag[0]) flag[0] = bd;
+        }
+        H[j + (int64_t)(j - 1) * ldh] = mk(r, 0.0);
+        const double ir = flag[0] ? 0.0 : 1.0 / r;
+        const cd g = d[2 * j + 1];
+        const cd cj = cscale(mk(g.x - tot[1], g.y - tot[2]), ir);
+        sc[0] = mk(ir, 0.0);
+        sc[1] = cj;
+    }
+}
+
+// row = 4*blockIdx.x + wave: lanes take columns in order, then a fixed shuffle tree
+__global__ __launch_bounds__(256) void k_dcgs_col(int j, cd* H, int ldh, const cd* __restrict__ d,
+                                                  const cd* __restrict__ sc, Batch bt) {
+    const int pb = bt.idx[blockIdx.y];
+    H += pb * bt.small;
+    d += pb * bt.small;
+    sc += pb * bt.scal;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row > j) return;
+    double hx = 0, hy = 0;
+    for (int col = (row > 0 ? row - 1 : 0) + lane; col < j; col += 64) {
+        const cd hv = H[row + (int64_t)col * ldh], sv = d[col];
+        hx += hv.x * sv.x - hv.y * sv.y;
+        hy += hv.x * sv.y + hv.y * sv.x;
+    }
+    hx = wave_sum(hx);
+    hy = wave_sum(hy);
+    if (lane == 0) {
+        const cd base = (row < j) ? d[j + 1 + row] : sc[1];
+        H[row + (int64_t)j * ldh] = cscale(mk(base.x - hx, base.y - hy), sc[0].x);
+    }
+}
+
+void launch_dcgs_coef(int j, cd* H, int ldh, const cd* d, cd* sc, double* hfro2, int* flag,
+                      double rel, hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0) return;
+    hipLaunchKernelGGL(k_dcgs_coef, dim3((unsigned)bt.n), dim3(256), 0, st, j, H, ldh, d, sc,
+                       hfro2, flag, rel, bt);
+    hipLaunchKernelGGL(k_dcgs_col, dim3((unsigned)ceil_div(j + 1, 4), (unsigned)bt.n), dim3(256),
+                       0, st, j, H, ldh, d, (const cd*)sc, bt);
+    OSA_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------- norms

@@ -1,6 +1,8 @@
 // Small dense kernels: the sign of the Hessenberg matrix f(H_k) e_1 (Eq. 11,
 // Eq. 22) by the scaled Newton iteration, and the small Schur decomposition
 // used by the eigensolver restarts.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace osa {
@@ -11,9 +13,12 @@ namespace osa {
 // 1/M[p,t] and eliminates column t from every other row; column t then stores
 // the new column of the accumulated row operations.  At the end
 //   A^{-1}[t, c] = M[perm[t], pinv[c]],   pinv[perm[s]] = s.
-// Each block owns CB whole columns, so reading and writing the pivot row of a
-// column happen inside one block; the pivot column itself is handed from step
-// to step through a double-buffered copy (colbuf) written by its owner.
+// Each block owns a few whole columns, so reading and writing the pivot row of
+// a column happen inside one block; the next pivot column is handed on from
+// step to step through a double-buffered copy written by its owner.  One
+// launch per pivot: every step needs the whole previous step, and blocked
+// (panel) schedules measured no faster here, their per-step critical path on
+// one compute unit being as long as a launch.
 struct GjWs {
     cd* col;        // 2 x k
     double2* piv;   // k: (|value|, index) of the pivot chosen for step t
@@ -46,6 +51,16 @@ static GjWs gj_ws(void* ws, int k) {
     w.pinv = (int*)p;          p += (size_t)k * sizeof(int);
     w.used = (int*)p;
     return w;
+}
+
+// a * b and v - f * rp with one fixed rounding sequence (explicit fma, so that
+// contraction cannot differ between call sites)
+__device__ __forceinline__ cd gj_mul(cd a, cd b) {
+    return mk(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ cd gj_sub(cd v, cd f, cd rp) {
+    const cd q = gj_mul(f, rp);
+    return mk(v.x - q.x, v.y - q.y);
 }
 
 static constexpr int kGjThreads = 256;
@@ -120,7 +135,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_step(cd* __restrict__ M, int 
     for (int j = j0; j < j0 + kGjCols && j < k; ++j) {
         const cd r = (j == t) ? mk(1.0, 0.0) : M[p + (size_t)j * k];
         __syncthreads();   // everyone has read M[p,j] before row p is rewritten
-        const cd rp = cmul(r, ipiv);
+        const cd rp = gj_mul(r, ipiv);
         const bool nextcol = (j == t + 1);
         double bv = -1.0;
         int bi = 0x7fffffff;
@@ -128,14 +143,10 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_step(cd* __restrict__ M, int 
             const cd f = colc[i];
             cd nv;
             if (j == t) {
-                nv = (i == p) ? ipiv : mk(-(f.x * ipiv.x - f.y * ipiv.y), -(f.x * ipiv.y + f.y * ipiv.x));
+                if (i == p) nv = ipiv;
+                else { const cd q = gj_mul(f, ipiv); nv = mk(-q.x, -q.y); }
             } else {
-                if (i == p) nv = rp;
-                else {
-                    nv = M[i + (size_t)j * k];
-                    nv.x -= f.x * rp.x - f.y * rp.y;
-                    nv.y -= f.x * rp.y + f.y * rp.x;
-                }
+                nv = (i == p) ? rp : gj_sub(M[i + (size_t)j * k], f, rp);
             }
             M[i + (size_t)j * k] = nv;
             if (nextcol) {
@@ -252,16 +263,21 @@ __global__ __launch_bounds__(256) void k_newton_combine(cd* __restrict__ X, cons
     }
 }
 
-__global__ void k_sum_pairs(const double* __restrict__ part, int nb, double* red, Batch bt) {
+// red[0..1] = sums of the per-block partials: one wavefront per problem, lane q
+// takes blocks q, q + 64, ... in order, then a fixed shuffle tree.
+__global__ __launch_bounds__(64) void k_sum_pairs(const double* __restrict__ part, int nb,
+                                                  double* red, Batch bt) {
     const int pb = bt.idx[blockIdx.x];
     red += pb * bt.part;
     part = red + 2;
-    if (threadIdx.x == 0) {
-        double a = 0, b = 0;
-        for (int i = 0; i < nb; ++i) { a += part[2 * i]; b += part[2 * i + 1]; }
-        red[0] = a;
-        red[1] = b;
+    double a = 0, b = 0;
+    for (int i = threadIdx.x; i < nb; i += 64) { a += part[2 * i]; b += part[2 * i + 1]; }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
     }
+    if (threadIdx.x == 0) { red[0] = a; red[1] = b; }
 }
 
 int64_t newton_red_len(int k) { return 2 + 2 * ceil_div((int64_t)k * k, 256); }
@@ -514,6 +530,7 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
     // ---- shifted QR
     const double ulp = 2.220446049250313e-16;
     const double smlnum = 1e-300;
+    int nrot = 0;
     int hi = p - 1;
     int its = 0, total = 0;
     const int maxtotal = 60 * p;
@@ -576,6 +593,7 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
             const int col0 = (k == lo) ? lo : k - 1;
             const int row1 = (k + 2 < hi) ? k + 2 : hi;
             apply_pair(T, Z, p, ld, k, a, b, col0, row1, (k > lo) ? k - 1 : -1);
+            ++nrot;
         }
     }
     // ---- reorder the diagonal (insertion sort by adjacent swaps)
@@ -589,6 +607,7 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
             if (nx == 0.0) break;
             const cd a = cscale(x1, 1.0 / nx), b = cscale(x2, 1.0 / nx);
             apply_pair(T, Z, p, ld, j - 1, a, b, j - 1, j);
+            ++nrot;
             if (l == 0) {
                 TT(j, j - 1) = mk(0.0, 0.0);   // touched by both sides: set after them
                 TT(j - 1, j - 1) = t22;
@@ -603,7 +622,10 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
         Zout[e] = ZZ(i, j);
     }
     for (int i = l; i < p; i += 64) wout[i] = TT(i, i);
-    if (l == 0) *info = fail ? -1 : total;
+    if (l == 0) {
+        info[0] = fail ? -1 : total;
+        info[1] = nrot;
+    }
 #undef TT
 #undef ZZ
 }

@@ -86,6 +86,27 @@ void launch_update(void* w, const void* B, int64_t ldb, int ncols, const cd* coe
 // y[i] = sum_c B[c][i] coef[c] + (add ? y[i] : 0).  Batch strides as launch_update.
 void launch_combine(void* y, const void* B, int64_t ldb, int ncols, const cd* coef, bool fp32,
                     bool add, int64_t n, hipStream_t st, const Batch& bt = Batch());
+// Delayed reorthogonalisation (step j >= 1 of the Arnoldi recurrence).
+// Dots of the ncols columns of B with two vectors in one read of B:
+// partial[c*nchunks + q] for w1, partial[(ncols + c)*nchunks + q] for w2.
+// Batch strides: basis (B and w1, which is a column of the basis), vec (w2),
+// part (partial).
+void launch_dot2_partial(const void* B, int64_t ldb, int ncols, const void* w1, const void* w2,
+                         bool fp32, const TsPlan& p, cd* partial, hipStream_t st,
+                         const Batch& bt = Batch());
+// From d = [s, u^H u, t, u^H z] (2(j+1) entries): completes column j-1 of H,
+// writes the first-pass column j and sc = [1/r, c_j]; breakdown test as
+// launch_normalize (flag[1] = j - 1).  Batch strides: small (H, d), scal (sc,
+// and hfro2 in cd slots), flag.
+void launch_dcgs_coef(int j, cd* H, int ldh, const cd* d, cd* sc, double* hfro2, int* flag,
+                      double rel, hipStream_t st, const Batch& bt = Batch());
+// V[j] <- (V[j] - V_j s) / r and V[j+1] <- (z - V_j t - c_j V[j]) / r in one pass
+// over V_j (s = coef[0:j], t = coef[j+1:2j+1], sc = [1/r, c_j]).  scratch:
+// 16 n entries per problem for the column split.  Batch strides: basis (V),
+// vec (z), small (coef), scal (sc).
+void launch_dcgs_update(void* V, int64_t ldb, int j, const void* z, const cd* coef, const cd* sc,
+                        bool fp32, int64_t n, cd* scratch, int64_t scratch_len, hipStream_t st,
+                        const Batch& bt = Batch());
 // Partial sums of |w|^2 per 256 rows.  Batch strides: vec (w), part (normp).
 void launch_norm_partial(const void* w, bool fp32, const TsPlan& p, double* normp,
                          hipStream_t st, const Batch& bt = Batch());

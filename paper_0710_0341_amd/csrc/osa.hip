@@ -12,6 +12,7 @@
 // The host only sequences kernels and reads back a few scalars at
 // checkpoints; every vector and matrix operation runs on the GPU.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -87,25 +88,27 @@ struct OsaError {
 };
 
 // Per-problem block of the small data of a solve (in cd entries): the
-// Hessenberg matrix (ldh = kcap + 1 rows, kcap columns), the coefficient
-// vectors and a few scalar slots.  One stride covers all of them, so a batched
+// Hessenberg matrix (ldh = kcap + 1 rows, kcap + 1 columns: the delayed
+// reorthogonalisation writes the first pass of one column ahead), the
+// coefficient vectors, the two-vector dot products and a few scalar slots.  One stride covers all of them, so a batched
 // launch reaches any of them with the same per-problem offset.
 struct ArenaLayout {
     int ldh = 0;
     int64_t vec_len = 0;   // entries of each vector slot
-    int64_t H = 0, coef = 0, coef2 = 0, cdef = 0, tmp = 0, s_cur = 0, s_prev = 0, ds = 0;
+    int64_t H = 0, coef = 0, coef2 = 0, cdef = 0, tmp = 0, s_cur = 0, s_prev = 0, dc = 0, ds = 0;
     int64_t stride = 0;
     static ArenaLayout make(int kcap, int m) {
         ArenaLayout a;
         a.ldh = kcap + 1;
-        a.vec_len = std::max<int64_t>(std::max(kcap + 1, m + 1), 160);
-        int64_t o = (int64_t)a.ldh * kcap;
+        a.vec_len = std::max<int64_t>(std::max(kcap + 2, m + 1), 160);
+        int64_t o = (int64_t)a.ldh * (kcap + 1);
         a.coef = o;   o += a.vec_len;
         a.coef2 = o;  o += a.vec_len;
         a.cdef = o;   o += a.vec_len;
         a.tmp = o;    o += a.vec_len;
         a.s_cur = o;  o += a.vec_len;
         a.s_prev = o; o += a.vec_len;
+        a.dc = o;     o += 2 * a.vec_len;
         a.ds = o;     o += 8;
         a.stride = ceil_div(o, 16) * 16;
         return a;
@@ -115,6 +118,8 @@ struct ArenaLayout {
 }  // namespace
 
 // ============================================================== context
+constexpr int kBatchWorkers = 8;   // concurrent instances in osa_batch_apply
+
 struct osa_ctx {
     Geom g{};
     hipStream_t st = nullptr;
@@ -144,6 +149,7 @@ struct osa_ctx {
     int kcap = 0, kbatch = 0;
     DevBuf V, arena, w, x, y, coef, coef2, partial, normp, upd_scratch, dscal, flag, nflag, red;
     DevBuf sX, sM, sY, logpiv, gjws;
+    DevBuf xio, yio;   // internal-layout sources and results of osa_apply
     ArenaLayout lay;
     int64_t part_stride = 0, normp_stride = 0, red_stride = 0, gj_stride = 0;
     PinnedBuf host;
@@ -276,7 +282,8 @@ void ensure_exec(osa_ctx* c, int maxcols, int nb = 1) {
     c->normp_stride = ceil_div(N, 256) + 16;
     c->partial.ensure(sizeof(cd) * (size_t)c->part_stride * nb);
     c->normp.ensure(sizeof(double) * (size_t)c->normp_stride * nb);
-    c->upd_scratch.ensure(vb * 8 * nb);
+    // column-split scratch (16 n per problem), only where rows alone cannot fill the GPU
+    c->upd_scratch.ensure(ceil_div(N, 256) < 1024 ? vb * 16 * nb : 256);
     c->dscal.ensure(sizeof(cd) * 16);
     c->flag.ensure(sizeof(int) * 4 * nb);
     c->nflag.ensure(sizeof(int) * 4 * nb);
@@ -284,7 +291,7 @@ void ensure_exec(osa_ctx* c, int maxcols, int nb = 1) {
 }
 
 // Workspace of a lockstep solve of nb sources with Krylov size up to kcap:
-//   V      nb bases of kcap+1 vectors (problem b at b*(kcap+1)*N)
+//   V      nb bases of kcap+2 vectors (problem b at b*(kcap+2)*N)
 //   arena  nb per-problem blocks of small data, see ArenaLayout
 //   w, x   nb vectors each
 //   sX, sM, sY, logpiv, gjws, red: nb copies of the small-sign workspace
@@ -295,13 +302,13 @@ void ensure_krylov(osa_ctx* c, int kcap, int nb = 1) {
     const int64_t N = c->N();
     const size_t vb = (size_t)N * sizeof(cd);
     c->V.release();   // the largest buffer: free before growing
-    c->V.ensure(vb * (size_t)(kcap + 1) * nb);
+    c->V.ensure(vb * (size_t)(kcap + 2) * nb);
     c->lay = ArenaLayout::make(kcap, std::max(c->m_alloc, 1));
     c->arena.ensure(sizeof(cd) * (size_t)c->lay.stride * nb);
     c->w.ensure(vb * nb);
     c->x.ensure(vb * nb);
     c->y.ensure(vb);
-    ensure_exec(c, kcap + 1, nb);
+    ensure_exec(c, 2 * (kcap + 2), nb);
     c->red_stride = newton_red_len(kcap) + 16;
     c->red.ensure(sizeof(double) * (size_t)c->red_stride * nb);
     c->sX.ensure(sizeof(cd) * (size_t)kcap * kcap * nb);
@@ -547,12 +554,15 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     const int every = fixed ? kmax : std::max(1, c->opts.check_every);
     const bool reproj = !c->opts.no_reproject;
     const TsPlan p = ts_plan(N);
-    const int64_t VS = (int64_t)(c->kcap + 1) * N;   // basis stride
+    const int64_t VS = (int64_t)(c->kcap + 2) * N;   // basis stride
+    const bool dcgs = c->opts.orth == 0;           // delayed reorthogonalisation
     const int ldh = L.ldh;
     cd* V = c->V.as<cd>();
     cd* ar = c->arena.as<cd>();
     cd* H = ar + L.H;
-    cd* ds = ar + L.ds;   // [0] |b|, [1] beta, [3] |s - s'| (double), [4] hfro2 (double)
+    // ds: [0] |b|, [1] beta, [2] |y|, [3] |s - s'| (double), [4] hfro2 (double),
+    //     [5] 1/r and [6] c_j of the delayed reorthogonalisation
+    cd* ds = ar + L.ds;
     double* hfro2 = (double*)(ds + 4);
     cd* w = c->w.as<cd>();
     cd* x = c->x.as<cd>();
@@ -601,9 +611,28 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
             act.push_back(b);
         }
     }
+    const int64_t scratch_len = (int64_t)(c->upd_scratch.bytes / sizeof(cd));
     if (!act.empty()) {
         Batch b0 = bat(act);
         launch_scale_dev(x, V, false, N, ds + 1, true, c->st, b0);   // v_1 = x_ominus / beta
+        if (dcgs) {
+            // first column: one pass; u_1 = H v_1 - v_1 h_11 goes to basis column 1
+            apply_h(c, V, w, false, false, b0);
+            if (reproj && m > 0) project_out(c, w, ar + L.coef2, ar + L.tmp, b0);
+            Batch bd = b0, bu = b0;
+            bd.part = c->part_stride;
+            bu.part = 0;
+            timed(c, 0, 2.0 * N * 16.0 * b0.n, [&] {
+                launch_dot_partial(V, N, 1, w, false, p, c->partial.as<cd>(), c->st, bd);
+            });
+            launch_reduce_partial(c->partial.as<cd>(), p.nchunks, 1, H, nullptr, nullptr, nullptr,
+                                  c->st, bd);
+            timed(c, 1, 3.0 * N * 16.0 * b0.n, [&] {
+                launch_update(w, V, N, 1, H, false, p, nullptr, nullptr, 0, c->st, bu);
+            });
+            OSA_HIP(hipMemcpy2DAsync(V + N, sizeof(cd) * VS, w, sizeof(cd) * N, sizeof(cd) * N, nb,
+                                     hipMemcpyDeviceToDevice, c->st));
+        }
     }
     std::vector<int> kprev(nb, 0);
     // Check schedule.  The estimate at a check is the change since the previous
@@ -614,15 +643,33 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     std::vector<std::vector<double>> ce(nb);    // ce[i]: estimate at check i (error of check i-1)
     std::vector<int> hf;
     std::vector<double> hd;
-    for (int j = 0; j < kmax && !act.empty(); ++j) {
+    // Step j: plain CGS2 extends the decomposition to size j + 1; the delayed
+    // form (steps 1 .. kmax) completes size j and starts column j.
+    for (int j = dcgs ? 1 : 0; j < (dcgs ? kmax + 1 : kmax) && !act.empty(); ++j) {
         const Batch bt = bat(act);
         apply_h(c, V + (size_t)j * N, w, false, false, bt);
         if (reproj && m > 0) project_out(c, w, ar + L.coef2, ar + L.tmp, bt);
-        cgs2(c, w, V, N, j + 1, false, H + (size_t)j * ldh, ar + L.coef, bt);
-        launch_normalize(w, V + (size_t)(j + 1) * N, false, p, c->normp.as<double>(),
-                         H + (size_t)j * ldh + (j + 1), hfro2, 1e-14, flag, j,
-                         H + (size_t)j * ldh, j + 1, c->st, bt);
-        const int kk = j + 1;
+        if (dcgs) {
+            Batch bd = bt;
+            bd.part = c->part_stride;
+            timed(c, 0, (j + 3.0) * N * 16.0 * bt.n, [&] {
+                launch_dot2_partial(V, N, j + 1, V + (size_t)j * N, w, false, p,
+                                    c->partial.as<cd>(), c->st, bd);
+            });
+            launch_reduce_partial(c->partial.as<cd>(), p.nchunks, 2 * (j + 1), ar + L.dc, nullptr,
+                                  nullptr, nullptr, c->st, bd);
+            launch_dcgs_coef(j, H, ldh, ar + L.dc, ds + 5, hfro2, flag, 1e-14, c->st, bt);
+            timed(c, 1, (j + 4.0) * N * 16.0 * bt.n, [&] {
+                launch_dcgs_update(V, N, j, w, ar + L.dc, ds + 5, false, N,
+                                   c->upd_scratch.as<cd>(), scratch_len, c->st, bt);
+            });
+        } else {
+            cgs2(c, w, V, N, j + 1, false, H + (size_t)j * ldh, ar + L.coef, bt);
+            launch_normalize(w, V + (size_t)(j + 1) * N, false, p, c->normp.as<double>(),
+                             H + (size_t)j * ldh + (j + 1), hfro2, 1e-14, flag, j,
+                             H + (size_t)j * ldh, j + 1, c->st, bt);
+        }
+        const int kk = dcgs ? j : j + 1;
         if (kk % every != 0 && kk != kmax) continue;
         // each source follows its own schedule, as it would alone
         std::vector<int> chk, wait;
@@ -1100,6 +1147,7 @@ void deflate(osa_ctx* c, int m, osa_info* info) {
 }
 
 void fill_defaults(osa_opts& o) {
+    // orth: 0 delayed reorthogonalisation (default), 1 plain CGS2
     if (o.max_batch <= 0) o.max_batch = 16;
     if (o.k_max <= 0) o.k_max = 600;
     if (o.check_every == 0) o.check_every = 50;
@@ -1165,7 +1213,7 @@ osa_status osa_set_opts(osa_ctx* c, const osa_opts* opts) {
     if (opts) o = *opts;
     if (o.k_max < 0 || o.k_max > 4000 || o.eig_ncv < 0 || o.eig_ncv > 96 || o.eig_tol < 0 ||
         o.eig_max_restarts < 0 || (o.eig_prec != OSA_FP64 && o.eig_prec != OSA_FP32) ||
-        o.max_batch < 0 || o.max_batch > 64)
+        o.max_batch < 0 || o.max_batch > 64 || o.orth < 0 || o.orth > 1)
         return OSA_ERR_ARG;
     fill_defaults(o);
     c->opts = o;
@@ -1288,7 +1336,10 @@ osa_status osa_apply(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double to
         const int maxb = std::max(1, std::min(c->opts.max_batch, kMaxBatch));
         const int gmax = std::min<int>(nrhs, maxb);
         osa_status first_err = OSA_OK, worst = OSA_OK;
-        DevBuf xin, yint;
+        // kept in the context: a per-call allocation would make hipFree wait for
+        // the whole device, serialising concurrent contexts
+        DevBuf& xin = c->xio;
+        DevBuf& yint = c->yio;
         xin.ensure(sizeof(cd) * N * gmax);
         yint.ensure(sizeof(cd) * N * gmax);
         std::vector<SolveResult> res;
@@ -1353,11 +1404,59 @@ osa_status osa_apply(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double to
 osa_status osa_batch_apply(int32_t n, osa_ctx* const* ctxs, const void* const* B, void* const* Y,
                            double tol, osa_info* infos) {
     if (n < 1 || !ctxs || !B || !Y) return OSA_ERR_ARG;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i] || !B[i] || !Y[i]) return OSA_ERR_ARG;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return OSA_ERR_ARG;   // one context cannot run twice at once
+    }
+    // Independent instances (each its own operator, lattice and deflation data)
+    // run concurrently: a pool of host workers, each driving one context at a
+    // time on a stream of its own that first waits for the work queued on the
+    // context's stream.  Every instance computes exactly what osa_apply computes.
+    const int nw = std::min<int>(n, kBatchWorkers);
+    std::vector<hipStream_t> streams(nw, nullptr);
+    std::vector<osa_status> st(n, OSA_OK);
+    std::atomic<int> next{0};
+    osa_status setup = OSA_OK;
+    for (int w = 0; w < nw && setup == OSA_OK; ++w)
+        if (hipStreamCreateWithFlags(&streams[w], hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            setup = OSA_ERR_HIP;
+        }
+    if (setup == OSA_OK) {
+        auto work = [&](int w) {
+            hipEvent_t ev = nullptr;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                ev = nullptr;
+            }
+            for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) {
+                osa_ctx* c = ctxs[i];
+                if (!ev || hipEventRecord(ev, c->st) != hipSuccess ||
+                    hipStreamWaitEvent(streams[w], ev, 0) != hipSuccess) {
+                    (void)hipGetLastError();
+                    st[i] = OSA_ERR_HIP;
+                    continue;
+                }
+                hipStream_t own = c->st;
+                c->st = streams[w];
+                st[i] = osa_apply(c, 1, B[i], Y[i], tol, infos ? infos + i : nullptr);
+                c->st = own;   // osa_apply has synchronised the worker stream
+            }
+            if (ev) (void)hipEventDestroy(ev);
+        };
+        std::vector<std::thread> pool;
+        for (int w = 1; w < nw; ++w) pool.emplace_back(work, w);
+        work(0);
+        for (auto& t : pool) t.join();
+    }
+    for (auto s2 : streams)
+        if (s2) (void)hipStreamDestroy(s2);
+    if (setup != OSA_OK) return setup;
     osa_status worst = OSA_OK;
     for (int i = 0; i < n; ++i) {
-        osa_status s = osa_apply(ctxs[i], 1, B[i], Y[i], tol, infos ? infos + i : nullptr);
-        if (s < 0) return s;
-        if (s > worst) worst = s;
+        if (st[i] < 0) return st[i];
+        if (st[i] > worst) worst = st[i];
     }
     return worst;
 }

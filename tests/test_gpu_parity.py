@@ -101,6 +101,21 @@ def test_small_sign_matches_oracle(osa, k):
     assert rel(ref, O.small_sign_e1(hk, "eig")) < 1e-9
 
 
+@pytest.mark.parametrize("k", [700, 2100])
+def test_small_sign_large(osa, k):
+    """Krylov sizes beyond the solve's default cap (k = 700) and far beyond it
+    (k = 2100, 4 x 2100 Gauss-Jordan column blocks per pivot launch)."""
+    say(f"small sign k={k}")
+    dims = (4, 4, 4, 4)
+    links = LI.make_links(dims, "haar", cfg=9, inst=2)
+    h = O.hermitian_wilson_sparse(links, dims, 0.3, -1.5)
+    b = LI.gaussian_source(dims, cfg=9, inst=2)
+    _, hm, _, _ = O.arnoldi_cgs2(lambda x: h @ x, b, k)
+    hk = hm[:k, :k]
+    s, its = osa.small_sign(dev(hk))
+    assert rel(host(s), O.small_sign_e1(hk, "newton")) < 1e-11
+
+
 def test_small_sign_dense_nonhessenberg(osa):
     """A dense matrix with a known spectrum off the imaginary axis."""
     rng = np.random.default_rng(3)
@@ -144,12 +159,12 @@ def test_small_schur_properties(osa, p, kind, mode):
 
 
 # ------------------------------------------------- full method, fixed k
-def _fixed_k_case(osa, dims, kind, mu, m, k, inst, reproject=True, eps=0.6):
+def _fixed_k_case(osa, dims, kind, mu, m, k, inst, reproject=True, eps=0.6, orth=0):
     links = LI.make_links(dims, kind, eps=eps, cfg=9, inst=inst)
     b = LI.gaussian_source(dims, cfg=9, inst=inst)
     h = O.hermitian_wilson_sparse(links, dims, mu, -1.5)
     ctx = osa.Context(dev(links), dims, mu, -1.5, k_max=k, check_every=-1,
-                      no_reproject=not reproject)
+                      no_reproject=not reproject, orth=orth)
     defl = None
     if m:
         r, l, lam = O.critical_dense(h.toarray(), m)
@@ -172,6 +187,21 @@ def test_fixed_k_matches_oracle(osa, dims, kind, mu, m, k):
     y, yo, info, oinfo = _fixed_k_case(osa, dims, kind, mu, m, k, inst=3)
     assert info["k_used"] == oinfo["k_used"] == k
     assert rel(y, yo) < 1e-10
+
+
+@pytest.mark.parametrize("reproject", [True, False])
+def test_fixed_k_delayed_and_plain_cgs2_agree(osa, reproject):
+    """The solve's two orthogonalisations (second Gram-Schmidt pass delayed by
+    one step, default; both passes in the same step) give the same Krylov
+    approximation up to rounding, and both match the oracle's CGS2."""
+    say(f"fixed k, delayed vs plain CGS2, re-projection {reproject}")
+    y0, yo, i0, _ = _fixed_k_case(osa, (4, 4, 4, 4), "haar", 0.3, 10, 150, inst=5,
+                                  reproject=reproject, orth=0)
+    y1, _, i1, _ = _fixed_k_case(osa, (4, 4, 4, 4), "haar", 0.3, 10, 150, inst=5,
+                                 reproject=reproject, orth=1)
+    assert i0["k_used"] == i1["k_used"] == 150
+    assert rel(y0, yo) < 1e-10 and rel(y1, yo) < 1e-10
+    assert rel(y0, y1) < 1e-12
 
 
 def test_fixed_k_without_reprojection(osa):
@@ -403,3 +433,40 @@ def test_stencil_many_rhs(osa):
     for i in (0, 33, 63, 64, 69):
         assert rel(Y[i], h @ X[i]) < 1e-14, i
     ctx.close()
+
+
+# ------------------------------------------------------------- uneven batch
+def test_uneven_batch_matches_single_and_dense(osa):
+    """Instances of different lattices, mu, m_w and deflation sizes solved
+    concurrently give bitwise the single-context results; two are checked
+    against the dense oracle; a context listed twice is an argument error."""
+    import torch
+    cases = [((2, 2, 2, 4), 0.3, -1.5, 4, 0.6), ((3, 3, 3, 3), 0.1, -1.8, 6, 0.9),
+             ((2, 3, 2, 4), 0.45, -1.2, 0, 0.3), ((3, 2, 3, 2), 0.2, -1.6, 3, 0.5),
+             ((2, 2, 3, 3), 0.05, -1.9, 5, 1.0)]
+    ctxs, srcs, dense = [], [], []
+    for n, (dims, mu, mw, m, eps) in enumerate(cases):
+        links = LI.make_links(dims, "disordered", eps=eps, cfg=9, inst=30 + n)
+        b = LI.gaussian_source(dims, cfg=9, inst=30 + n)
+        c = osa.Context(dev(links), dims, mu, mw, k_max=900, check_every=20,
+                        stream=torch.cuda.Stream())
+        if m:
+            c.deflate(m)
+        ctxs.append(c)
+        srcs.append(dev(b))
+        dense.append((links, dims, mu, mw, b))
+    say("uneven batch of 5 instances")
+    ys, infos, st = osa.batch_apply(ctxs, srcs, tol=1e-10)
+    assert st == osa.OSA_OK, [i["status"] for i in infos]
+    for c, b, y in zip(ctxs, srcs, ys):
+        y1, _, _ = c.apply(b, tol=1e-10)
+        assert torch.equal(y1, y)
+    for n in (0, 1):
+        links, dims, mu, mw, b = dense[n]
+        h = O.hermitian_wilson_dense(links, dims, mu, mw)
+        assert rel(host(ys[n]), O.sign_eig_apply(h, b)) < 1e-9
+    with pytest.raises(osa.OsaError) as e:
+        osa.batch_apply([ctxs[0], ctxs[1], ctxs[0]], srcs[:3], tol=1e-10)
+    assert e.value.status == -1
+    for c in ctxs:
+        c.close()
