@@ -31,6 +31,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cgs_dot_dis8_hbm_traffic.json")
+DOT_SOURCE = os.path.join(ROOT, "paper_0710_0341_amd", "csrc", "blas.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the Gram-Schmidt dot class, from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by the copy-kernel factors it
+    records).  None once the kernels' source differs from the one measured."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(DOT_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def parse():
@@ -42,8 +61,9 @@ def parse():
     ap.add_argument("--eig-prec", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--eig-ncv", type=int, default=0,
                     help="eigensolver active block (0: the library default)")
-    ap.add_argument("--workload", choices=["dis8", "haar4", "uneven64"], default="dis8",
-                    help="uneven64: 64 independent instances (6^4/8^4/10^4), solved concurrently")
+    ap.add_argument("--workload", choices=["dis8", "haar4", "uneven64", "dis16"], default="dis8",
+                    help="uneven64: 64 independent instances (6^4/8^4/10^4), solved "
+                         "concurrently; dis16: 16^4, 12 point sources in one lockstep batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--solve-only", action="store_true",
@@ -188,6 +208,8 @@ def uneven_batch(args):
             except osa.OsaError as e:      # the instance is then solved without deflation
                 defl_err[i] = e.status
             eig_ms[i] = (time.perf_counter() - t0) * 1e3
+            print(f"deflated instance {i} {params[i]['dims']} m={params[i]['n_defl']}: "
+                  f"{eig_ms[i]:.0f} ms status {defl_err[i]}", file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
     th = [threading.Thread(target=deflate_worker) for _ in range(8)]
@@ -196,12 +218,14 @@ def uneven_batch(args):
     for t in th:
         t.join()
     t_defl = time.perf_counter() - t0
+    print("batch warm-up", file=sys.stderr, flush=True)
     osa.batch_apply(ctxs, srcs, tol=w["tol"])          # warm-up: workspace growth
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ys, infos, st = osa.batch_apply(ctxs, srcs, tol=w["tol"])
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    print("sequential reference", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     seq = [c.apply(b, tol=w["tol"])[0] for c, b in zip(ctxs, srcs)]
     torch.cuda.synchronize()
@@ -233,6 +257,74 @@ def uneven_batch(args):
         c.close()
 
 
+def batched16(args):
+    """16^4 disordered links (eps = 0.5) stored FP32, m_w = -1.5, mu = 0.2: the 40
+    critical pairs by an FP32 Krylov-Schur search refined in FP64, then the 12
+    spin-colour point sources of one site solved in one lockstep batch (k <= 500,
+    tol 1e-8), and the same 12 one at a time.  Reports the FP32-search error as
+    the difference of the result from an all-FP64 eigensearch on one source."""
+    import torch
+
+    import lattice_inputs as LI
+    import paper_0710_0341_amd as osa
+    w = LI.WORKLOADS[3]
+    dims = w["dims"]
+    links = torch.from_numpy(LI.make_links(dims, "disordered", eps=w["eps"], cfg=3, inst=0)
+                             .astype(np.complex64)).to("cuda:0")   # stored FP32
+    B = torch.from_numpy(point_sources(dims)).to("cuda:0")
+    ctx = osa.Context(links, dims, w["mu"], w["m_w"], k_max=w["k_max"], check_every=50,
+                      eig_prec=osa.FP32, max_batch=12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    print("dis16: fp32 eigensearch", file=sys.stderr, flush=True)
+    dinfo = ctx.deflate(w["n_defl"])
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    print(f"dis16: eigensearch {t_eig:.1f} s", file=sys.stderr, flush=True)
+    ctx.apply(B[:1], tol=w["tol"])                    # workspace growth, untimed
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Yb, infb, stb = ctx.apply(B, tol=w["tol"])
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"dis16: batch of 12 {t_batch:.1f} s", file=sys.stderr, flush=True)
+    ctx.set_opts(k_max=w["k_max"], check_every=50, eig_prec=osa.FP32, max_batch=1)
+    t0 = time.perf_counter()
+    Yp, infp, stp = ctx.apply(B, tol=w["tol"])
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    print(f"dis16: 12 one at a time {t_plain:.1f} s; fp64 eigensearch", file=sys.stderr, flush=True)
+    # all-FP64 eigensearch on the same (FP32-rounded) links, first source
+    ctx64 = osa.Context(links, dims, w["mu"], w["m_w"], k_max=w["k_max"], check_every=50)
+    t0 = time.perf_counter()
+    ctx64.deflate(w["n_defl"])
+    torch.cuda.synchronize()
+    t_eig64 = time.perf_counter() - t0
+    y64, _, _ = ctx64.apply(B[:1], tol=w["tol"])
+    err = float(torch.linalg.vector_norm(Yb[0] - y64[0]) / torch.linalg.vector_norm(y64[0]))
+    out = {
+        "metric": "sign(H_w(mu)) b solves/sec, 12 sources batched vs plain", "unit": "solves/s",
+        "value": 12.0 / t_batch, "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+        "dtype": "c128 (links and eigensearch c64)",
+        "config": {"workload": "dis16_12pt", "lattice": list(dims), "N": 12 * int(np.prod(dims)),
+                   "mu": w["mu"], "m_w": w["m_w"], "eps": w["eps"], "n_defl": w["n_defl"],
+                   "k_max": w["k_max"], "tol": w["tol"]},
+        "batched_ms": t_batch * 1e3, "plain_ms": t_plain * 1e3,
+        "plain_solves_per_s": 12.0 / t_plain, "speedup": t_plain / t_batch,
+        "bitwise_equal": bool(torch.equal(Yb, Yp)),
+        "statuses": sorted(set(int(i["status"]) for i in infb)),
+        "k_used": [i["k_used"] for i in infb],
+        "max_resid_est": max(i["resid_est"] for i in infb),
+        "eig": {"fp32_search_ms": t_eig * 1e3, "matvecs": dinfo["eig_matvecs"],
+                "restarts": dinfo["eig_restarts"], "max_eig_resid": dinfo["max_eig_resid"],
+                "min_abs_re_lambda": dinfo["min_abs_re_lambda"], "fp64_search_ms": t_eig64 * 1e3},
+        "fp32_search_vs_fp64_search_rel_diff": err,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    ctx64.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -244,6 +336,9 @@ def main():
         return
     if args.workload == "uneven64":
         uneven_batch(args)
+        return
+    if args.workload == "dis16":
+        batched16(args)
         return
     import torch
 
@@ -338,8 +433,8 @@ def main():
     d = agg[dom]
     avg_ms = d["ms"] / max(d["launches"], 1)
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
-    kernel_names = {"cgs_dot": "k_dot_partial", "cgs_update": "k_update_{direct,split+finish}",
-                    "stencil": "k_wilson_h"}
+    kernel_names = {"cgs_dot": "k_dot_partial + k_dot2_partial",
+                    "cgs_update": "k_update_* + k_dcgs_*", "stencil": "k_wilson_h"}
     k_used = [r["k_used"] for r in records]
     init_ms = float(np.mean([r["eig_ms"] for r in records])) if records else 0.0
     solve_ms = float(np.mean([r["t_solve_ms"] for r in records])) if records else 0.0
@@ -361,8 +456,9 @@ def main():
                    "sources_per_step": n_solves, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": kernel_names[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_us": avg_ms * 1e3,
-                     "launches": d["launches"]},
+                     "traffic": measured_traffic() if dom == "cgs_dot" else None,
+                     "algorithmic_bytes_per_launch": d["bytes"] / max(d["launches"], 1),
+                     "avg_launch_us": avg_ms * 1e3, "launches": d["launches"]},
         "kernels": {k: {"ms": v["ms"] / args.steps, "launches": v["launches"] // args.steps,
                         "GB/s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else 0.0}
                     for k, v in agg.items()},

@@ -75,7 +75,10 @@ typedef struct {
     int32_t check_every;        /* convergence check interval (default 50); < 0: run exactly
                                    k_max steps with no check (fixed-k mode)                   */
     int32_t no_reproject;       /* 1: skip the per-step oblique re-projection (default 0)     */
-    int32_t eig_ncv;            /* eigensolver active block, 8..96 (default 96)                */
+    int32_t eig_ncv;            /* eigensolver active block, 8..96 (default nev + 16 within
+                                   [64, 96], nev = wanted eigenvalues of H^2; if that run
+                                   does not converge, osa_deflate runs once more with 96
+                                   and twice the restart cap)                               */
     int32_t eig_max_restarts;   /* eigensolver restart cap                 (default 2000)     */
     osa_prec eig_prec;          /* FP32: search in FP32, then refine in FP64 (default FP64)   */
     double eig_tol;             /* relative Krylov-Schur residual target   (default 1e-12)    */

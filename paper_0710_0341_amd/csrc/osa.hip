@@ -989,8 +989,11 @@ void rayleigh_ritz(osa_ctx* c, bool adjoint, int nev, int m, cd* X, cd* Rout,
     }
 }
 
-void deflate(osa_ctx* c, int m, osa_info* info) {
-    const double t0 = now_ms();
+// ncv_req / maxr_req > 0 override the active block and the restart cap;
+// t0: start of the whole initialisation (a retry keeps counting from it)
+void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 0,
+             double t0 = -1.0) {
+    if (t0 < 0) t0 = now_ms();
     if (m == 0) {
         c->m_alloc = c->m_active = 0;
         c->lambda.clear();
@@ -1004,12 +1007,18 @@ void deflate(osa_ctx* c, int m, osa_info* info) {
     // active block of the Krylov-Schur basis (the small Schur kernels take up
     // to 96); the whole basis must fit in the 12 V dimensional space
     const int64_t dim = 12LL * c->g.V;
-    int ncv = c->opts.eig_ncv > 0 ? c->opts.eig_ncv : 96;
+    // default active block nev + 16 within [64, 96]: at 8^4 with nev = 48, 64 beats 56,
+    // 72, 80 and 96 (the Schur cost per restart grows as the cube of the block);
+    // smaller blocks failed to converge on hard instances (m_w near -1.9)
+    int ncv = ncv_req > 0 ? ncv_req
+                          : (c->opts.eig_ncv > 0 ? c->opts.eig_ncv
+                                                 : std::min(96, std::max(64, nev + 16)));
     if (ncv > 96) ncv = 96;
     if ((int64_t)nev + ncv + 1 > dim) ncv = (int)std::max<int64_t>(8, dim - nev - 1);
     if (ncv < nev + 4 || (int64_t)nev + ncv + 1 > dim) throw OsaError{OSA_ERR_ARG};
     const double tol = c->opts.eig_tol > 0 ? c->opts.eig_tol : 1e-12;
-    const int maxr = c->opts.eig_max_restarts > 0 ? c->opts.eig_max_restarts : 2000;
+    const int maxr = maxr_req > 0 ? maxr_req
+                                  : (c->opts.eig_max_restarts > 0 ? c->opts.eig_max_restarts : 2000);
     const bool fp32 = (c->opts.eig_prec == OSA_FP32);
     if (fp32 && !c->links_fp32 && !c->U32.p) {
         c->U32.ensure(sizeof(cf) * (size_t)c->g.Vp * 36);
@@ -1271,7 +1280,16 @@ osa_status osa_deflate(osa_ctx* c, int32_t n_defl, osa_info* info) {
     if (!c) return OSA_ERR_ARG;
     if (n_defl < 0 || n_defl > 48 || (int64_t)n_defl >= 12LL * c->g.V) return OSA_ERR_ARG;
     return guard([&]() -> osa_status {
-        deflate(c, n_defl, info);
+        const double t0 = now_ms();
+        try {
+            deflate(c, n_defl, info, 0, 0, t0);
+        } catch (const OsaError& e) {
+            // with the default block, a hard spectrum gets one more run with the
+            // largest block and twice the restart cap
+            if (e.s != OSA_ERR_EIG_NOCONV || c->opts.eig_ncv > 0) throw;
+            const int cap = c->opts.eig_max_restarts > 0 ? c->opts.eig_max_restarts : 2000;
+            deflate(c, n_defl, info, 96, 2 * cap, t0);
+        }
         return OSA_OK;
     }, &c->msg);
 }
