@@ -43,6 +43,26 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sm /* kWaves*
     __syncthreads();
 }
 
+// Row chunks of a dot launch: 64 chunks while that gives at least 1024 blocks
+// of (chunk x 8 columns); beyond about 128 columns, fewer and longer chunks so
+// the launch stays near 1024 blocks (measured at 8^4: more rows per thread
+// helps the long bases of the solve, 64 chunks suit the short eigensolver
+// ones).  Depends on n and ncols only (never on a batch), so a problem's
+// summation order is fixed.
+static TsPlan dot_plan(int64_t n, int ncols, int C) {
+    const int64_t groups = ceil_div(ncols > 0 ? ncols : 1, C);
+    int64_t want = ceil_div(1024, groups);
+    if (want > 64) want = 64;
+    if (want < 8) want = 8;
+    TsPlan p;
+    p.n = n;
+    int64_t rpc = ceil_div(ceil_div(n, want), kBlock) * kBlock;
+    if (rpc < kBlock) rpc = kBlock;
+    p.rows_per_chunk = (int)rpc;
+    p.nchunks = (int)ceil_div(n, rpc);
+    return p;
+}
+
 TsPlan ts_plan(int64_t n) {
     TsPlan p;
     p.n = n;
@@ -102,10 +122,11 @@ __global__ __launch_bounds__(kBlock) void k_dot_partial(const T* __restrict__ B,
         mk(so[2 * threadIdx.x], so[2 * threadIdx.x + 1]);
 }
 
-void launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bool fp32,
-                        const TsPlan& p, cd* partial, hipStream_t st, const Batch& bt) {
-    if (ncols <= 0 || bt.n <= 0) return;
+int launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bool fp32,
+                       const TsPlan& pn, cd* partial, hipStream_t st, const Batch& bt) {
     constexpr int C = 8;
+    const TsPlan p = dot_plan(pn.n, ncols, C);
+    if (ncols <= 0 || bt.n <= 0) return p.nchunks;
     dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)bt.n), blk(kBlock);
     if (fp32)
         hipLaunchKernelGGL((k_dot_partial<cf, C>), grid, blk, 0, st, (const cf*)B, ldb, ncols,
@@ -114,6 +135,7 @@ void launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bo
         hipLaunchKernelGGL((k_dot_partial<cd, C>), grid, blk, 0, st, (const cd*)B, ldb, ncols,
                            (const cd*)w, p.n, p.rows_per_chunk, p.nchunks, partial, bt);
     OSA_LAUNCH_CHECK();
+    return p.nchunks;
 }
 
 // Two vectors against the same columns (one read of B): partial[c*nchunks + q]
@@ -161,10 +183,11 @@ __global__ __launch_bounds__(kBlock) void k_dot2_partial(const T* __restrict__ B
     }
 }
 
-void launch_dot2_partial(const void* B, int64_t ldb, int ncols, const void* w1, const void* w2,
-                         bool fp32, const TsPlan& p, cd* partial, hipStream_t st, const Batch& bt) {
-    if (ncols <= 0 || bt.n <= 0) return;
+int launch_dot2_partial(const void* B, int64_t ldb, int ncols, const void* w1, const void* w2,
+                        bool fp32, const TsPlan& pn, cd* partial, hipStream_t st, const Batch& bt) {
     constexpr int C = 8;
+    const TsPlan p = dot_plan(pn.n, ncols, C);
+    if (ncols <= 0 || bt.n <= 0) return p.nchunks;
     dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)bt.n), blk(kBlock);
     if (fp32)
         hipLaunchKernelGGL((k_dot2_partial<cf, C>), grid, blk, 0, st, (const cf*)B, ldb, ncols,
@@ -175,6 +198,7 @@ void launch_dot2_partial(const void* B, int64_t ldb, int ncols, const void* w1, 
                            (const cd*)w1, (const cd*)w2, p.n, p.rows_per_chunk, p.nchunks, partial,
                            bt);
     OSA_LAUNCH_CHECK();
+    return p.nchunks;
 }
 
 // ---------------------------------------------------------------- reduce

@@ -66,10 +66,13 @@ struct TsPlan {
 TsPlan ts_plan(int64_t n);
 
 // partial[c*nchunks + q] = sum over chunk q of conj(B[c][i]) w[i], c < ncols.
-// B: ncols vectors of length n spaced by ldb; storage fp64 or fp32.
+// B: ncols vectors of length n (= p.n) spaced by ldb; storage fp64 or fp32.
+// The launch picks its row chunks from n and ncols (at most kMaxChunks) and
+// returns their number, which the following reduction takes.
 // Batch strides: basis (B), vec (w), part (partial).
-void launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bool fp32,
-                        const TsPlan& p, cd* partial, hipStream_t st, const Batch& bt = Batch());
+constexpr int kMaxChunks = 128;
+int launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bool fp32,
+                       const TsPlan& p, cd* partial, hipStream_t st, const Batch& bt = Batch());
 // out[c] = sum_q partial[c*nchunks+q] and accum[c] += out[c] (accum nullable).
 // With M != nullptr (m x m, column-major) out = M * sums instead (used for
 // G^{-1} L^dag w, M shared by the batch); tmp then holds ncols scratch entries.
@@ -91,9 +94,9 @@ void launch_combine(void* y, const void* B, int64_t ldb, int ncols, const cd* co
 // partial[c*nchunks + q] for w1, partial[(ncols + c)*nchunks + q] for w2.
 // Batch strides: basis (B and w1, which is a column of the basis), vec (w2),
 // part (partial).
-void launch_dot2_partial(const void* B, int64_t ldb, int ncols, const void* w1, const void* w2,
-                         bool fp32, const TsPlan& p, cd* partial, hipStream_t st,
-                         const Batch& bt = Batch());
+int launch_dot2_partial(const void* B, int64_t ldb, int ncols, const void* w1, const void* w2,
+                        bool fp32, const TsPlan& p, cd* partial, hipStream_t st,
+                        const Batch& bt = Batch());
 // From d = [s, u^H u, t, u^H z] (2(j+1) entries): completes column j-1 of H,
 // writes the first-pass column j and sc = [1/r, c_j]; breakdown test as
 // launch_normalize (flag[1] = j - 1).  Batch strides: small (H, d), scal (sc,

@@ -270,7 +270,7 @@ void vec_norm(osa_ctx* c, const void* v, bool fp32, cd* out) {
 
 // Work buffers of the tall-skinny kernels (Gram-Schmidt against up to maxcols
 // vectors, for up to nb problems at once), shared by the solve and the
-// eigensolver.  Per-problem strides: partial maxcols*64 (at most 64 chunks),
+// eigensolver.  Per-problem strides: partial maxcols*kMaxChunks,
 // normp ceil(N/256) + 16.
 void ensure_exec(osa_ctx* c, int maxcols, int nb = 1) {
     const int64_t N = c->N();
@@ -278,7 +278,7 @@ void ensure_exec(osa_ctx* c, int maxcols, int nb = 1) {
     maxcols = std::max(maxcols, 160);
     c->coef.ensure(sizeof(cd) * maxcols);
     c->coef2.ensure(sizeof(cd) * maxcols);
-    c->part_stride = std::max<int64_t>(c->part_stride, (int64_t)maxcols * 64);
+    c->part_stride = std::max<int64_t>(c->part_stride, (int64_t)maxcols * kMaxChunks);
     c->normp_stride = ceil_div(N, 256) + 16;
     c->partial.ensure(sizeof(cd) * (size_t)c->part_stride * nb);
     c->normp.ensure(sizeof(double) * (size_t)c->normp_stride * nb);
@@ -357,15 +357,16 @@ void cgs2(osa_ctx* c, void* wv, const void* B, int64_t ld, int ncols, bool fp32,
     const double dot_bytes = (ncols + 1.0) * n * eb;     // read V_j and w
     const double upd_bytes = (ncols + 2.0) * n * eb;     // read V_j and w, write w
     // pass 1
-    timed(c, 0, dot_bytes, [&] { launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st, bd); });
-    launch_reduce_partial(part, p.nchunks, ncols, hcol, nullptr, nullptr, nullptr, c->st, bd);
+    int nch = 0;
+    timed(c, 0, dot_bytes, [&] { nch = launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st, bd); });
+    launch_reduce_partial(part, nch, ncols, hcol, nullptr, nullptr, nullptr, c->st, bd);
     timed(c, 1, upd_bytes, [&] {
         launch_update(wv, B, ld, ncols, hcol, fp32, p, nullptr, c->upd_scratch.as<cd>(),
                       scratch_len, c->st, bu);
     });
     // pass 2
-    timed(c, 0, dot_bytes, [&] { launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st, bd); });
-    launch_reduce_partial(part, p.nchunks, ncols, co, hcol, nullptr, nullptr, c->st, bd);  // h += h2
+    timed(c, 0, dot_bytes, [&] { nch = launch_dot_partial(B, ld, ncols, wv, fp32, p, part, c->st, bd); });
+    launch_reduce_partial(part, nch, ncols, co, hcol, nullptr, nullptr, c->st, bd);  // h += h2
     timed(c, 1, upd_bytes, [&] {
         launch_update(wv, B, ld, ncols, co, fp32, p, c->normp.as<double>(),
                       c->upd_scratch.as<cd>(), scratch_len, c->st, bu);
@@ -385,8 +386,8 @@ void project_out(osa_ctx* c, void* wv, cd* cout, cd* tmp, const Batch& bt) {
     bd.basis = bu.basis = 0;   // L and R are shared
     bd.part = c->part_stride;
     bu.part = 0;
-    launch_dot_partial(c->L.p, c->N(), m, wv, false, p, part, c->st, bd);
-    launch_reduce_partial(part, p.nchunks, m, cout, nullptr, c->Ginv.as<cd>(), tmp, c->st, bd);
+    const int nch = launch_dot_partial(c->L.p, c->N(), m, wv, false, p, part, c->st, bd);
+    launch_reduce_partial(part, nch, m, cout, nullptr, c->Ginv.as<cd>(), tmp, c->st, bd);
     launch_update(wv, c->R.p, c->N(), m, cout, false, p, nullptr, c->upd_scratch.as<cd>(),
                   (int64_t)(c->upd_scratch.bytes / sizeof(cd)), c->st, bu);
 }
@@ -507,9 +508,9 @@ void build_ginv(osa_ctx* c, int m) {
     const TsPlan p = ts_plan(c->N());
     cd* G = c->sM.as<cd>();
     for (int j = 0; j < m; ++j) {
-        launch_dot_partial(c->L.p, c->N(), m, c->R.as<cd>() + (size_t)j * c->N(), false, p,
-                           c->partial.as<cd>(), c->st);
-        launch_reduce_partial(c->partial.as<cd>(), p.nchunks, m, G + (size_t)j * m, nullptr,
+        const int nch = launch_dot_partial(c->L.p, c->N(), m, c->R.as<cd>() + (size_t)j * c->N(),
+                                           false, p, c->partial.as<cd>(), c->st);
+        launch_reduce_partial(c->partial.as<cd>(), nch, m, G + (size_t)j * m, nullptr,
                               nullptr, nullptr, c->st);
     }
     OSA_HIP(hipMemsetAsync(c->flag.p, 0, sizeof(int) * 4, c->st));
@@ -622,11 +623,12 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
             Batch bd = b0, bu = b0;
             bd.part = c->part_stride;
             bu.part = 0;
+            int nch = 0;
             timed(c, 0, 2.0 * N * 16.0 * b0.n, [&] {
-                launch_dot_partial(V, N, 1, w, false, p, c->partial.as<cd>(), c->st, bd);
+                nch = launch_dot_partial(V, N, 1, w, false, p, c->partial.as<cd>(), c->st, bd);
             });
-            launch_reduce_partial(c->partial.as<cd>(), p.nchunks, 1, H, nullptr, nullptr, nullptr,
-                                  c->st, bd);
+            launch_reduce_partial(c->partial.as<cd>(), nch, 1, H, nullptr, nullptr, nullptr, c->st,
+                                  bd);
             timed(c, 1, 3.0 * N * 16.0 * b0.n, [&] {
                 launch_update(w, V, N, 1, H, false, p, nullptr, nullptr, 0, c->st, bu);
             });
@@ -652,11 +654,12 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
         if (dcgs) {
             Batch bd = bt;
             bd.part = c->part_stride;
+            int nch = 0;
             timed(c, 0, (j + 3.0) * N * 16.0 * bt.n, [&] {
-                launch_dot2_partial(V, N, j + 1, V + (size_t)j * N, w, false, p,
-                                    c->partial.as<cd>(), c->st, bd);
+                nch = launch_dot2_partial(V, N, j + 1, V + (size_t)j * N, w, false, p,
+                                          c->partial.as<cd>(), c->st, bd);
             });
-            launch_reduce_partial(c->partial.as<cd>(), p.nchunks, 2 * (j + 1), ar + L.dc, nullptr,
+            launch_reduce_partial(c->partial.as<cd>(), nch, 2 * (j + 1), ar + L.dc, nullptr,
                                   nullptr, nullptr, c->st, bd);
             launch_dcgs_coef(j, H, ldh, ar + L.dc, ds + 5, hfro2, flag, 1e-14, c->st, bt);
             timed(c, 1, (j + 4.0) * N * 16.0 * bt.n, [&] {
@@ -956,9 +959,9 @@ void rayleigh_ritz(osa_ctx* c, bool adjoint, int nev, int m, cd* X, cd* Rout,
     apply_h_contig(c, X, W.p, false, adjoint, nev);
     const TsPlan p = ts_plan(N);
     for (int j = 0; j < nev; ++j) {
-        launch_dot_partial(X, N, nev, W.as<cd>() + (size_t)j * N, false, p, c->partial.as<cd>(),
-                           c->st);
-        launch_reduce_partial(c->partial.as<cd>(), p.nchunks, nev, Mb.as<cd>() + (size_t)j * nev,
+        const int nch = launch_dot_partial(X, N, nev, W.as<cd>() + (size_t)j * N, false, p,
+                                           c->partial.as<cd>(), c->st);
+        launch_reduce_partial(c->partial.as<cd>(), nch, nev, Mb.as<cd>() + (size_t)j * nev,
                               nullptr, nullptr, nullptr, c->st);
     }
     DevBuf sws;
