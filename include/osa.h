@@ -85,7 +85,8 @@ typedef struct {
     int32_t max_batch;          /* sources solved together in lockstep by osa_apply, 1..64
                                    (default 16); workspace grows with it: max_batch Krylov
                                    bases of k_max + 2 vectors of N complex128                */
-    int32_t orth;               /* Arnoldi orthogonalisation of the solve (Eq. 7):
+    int32_t orth;               /* Arnoldi orthogonalisation of the solve (Eq. 7) and of
+                                   the eigensolver's Krylov-Schur expansion:
                                    0 (default): classical Gram-Schmidt with the second pass
                                    delayed by one step: one dot pass over the basis with two
                                    vectors and one fused update pass per step (half the

@@ -590,10 +590,13 @@ void launch_dcgs_update(void* V, int64_t ldb, int j, const void* z, const cd* co
 // j-1 of H (H[0:j, j-1] += s, H[j, j-1] = r, with the breakdown test of the
 // plain recurrence) and sets sc = [1/r, c_j]; k_dcgs_col (one wavefront per
 // row) then writes the first-pass column j,
-//   H[0:j+1, j] = ([t; c_j] - H[0:j+1, 0:j] s) / r.
+//   H[0:j+1, j] = ([t; c_j] - H[0:j+1, 0:j] s) / r,
+// using the Hessenberg band of H (hess) or all of it (a Krylov-Schur Rayleigh
+// quotient after a restart).  Without the first pass (the last step before a
+// restart: d = [s, u^H u] only) just column j-1 and 1/r are set.
 __global__ __launch_bounds__(256) void k_dcgs_coef(int j, cd* H, int ldh, const cd* __restrict__ d,
                                                    cd* sc, double* hfro2, int* flag, double rel,
-                                                   Batch bt) {
+                                                   int with_t, Batch bt) {
     __shared__ double sred[4 * 4];
     const int pb = bt.idx[blockIdx.x];
     H += pb * bt.small;
@@ -605,7 +608,7 @@ __global__ __launch_bounds__(256) void k_dcgs_coef(int j, cd* H, int ldh, const 
     const cd* t = d + j + 1;
     double ss = 0, stx = 0, sty = 0, col2 = 0;
     for (int c = threadIdx.x; c < j; c += 256) {
-        const cd sv = s[c], tv = t[c];
+        const cd sv = s[c], tv = with_t ? t[c] : mk(0.0, 0.0);
         ss += cabs2(sv);
         stx += sv.x * tv.x + sv.y * tv.y;   // conj(s) t
         sty += sv.x * tv.y - sv.y * tv.x;
@@ -637,7 +640,7 @@ __global__ __launch_bounds__(256) void k_dcgs_coef(int j, cd* H, int ldh, const 
         }
         H[j + (int64_t)(j - 1) * ldh] = mk(r, 0.0);
         const double ir = flag[0] ? 0.0 : 1.0 / r;
-        const cd g = d[2 * j + 1];
+        const cd g = with_t ? d[2 * j + 1] : mk(0.0, 0.0);
         const cd cj = cscale(mk(g.x - tot[1], g.y - tot[2]), ir);
         sc[0] = mk(ir, 0.0);
         sc[1] = cj;
@@ -646,7 +649,7 @@ __global__ __launch_bounds__(256) void k_dcgs_coef(int j, cd* H, int ldh, const 
 
 // row = 4*blockIdx.x + wave: lanes take columns in order, then a fixed shuffle tree
 __global__ __launch_bounds__(256) void k_dcgs_col(int j, cd* H, int ldh, const cd* __restrict__ d,
-                                                  const cd* __restrict__ sc, Batch bt) {
+                                                  const cd* __restrict__ sc, int hess, Batch bt) {
     const int pb = bt.idx[blockIdx.y];
     H += pb * bt.small;
     d += pb * bt.small;
@@ -655,7 +658,7 @@ __global__ __launch_bounds__(256) void k_dcgs_col(int j, cd* H, int ldh, const c
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row > j) return;
     double hx = 0, hy = 0;
-    for (int col = (row > 0 ? row - 1 : 0) + lane; col < j; col += 64) {
+    for (int col = (hess && row > 0 ? row - 1 : 0) + lane; col < j; col += 64) {
         const cd hv = H[row + (int64_t)col * ldh], sv = d[col];
         hx += hv.x * sv.x - hv.y * sv.y;
         hy += hv.x * sv.y + hv.y * sv.x;
@@ -669,12 +672,13 @@ __global__ __launch_bounds__(256) void k_dcgs_col(int j, cd* H, int ldh, const c
 }
 
 void launch_dcgs_coef(int j, cd* H, int ldh, const cd* d, cd* sc, double* hfro2, int* flag,
-                      double rel, hipStream_t st, const Batch& bt) {
+                      double rel, hipStream_t st, const Batch& bt, bool hess, bool first_pass) {
     if (bt.n <= 0) return;
     hipLaunchKernelGGL(k_dcgs_coef, dim3((unsigned)bt.n), dim3(256), 0, st, j, H, ldh, d, sc,
-                       hfro2, flag, rel, bt);
-    hipLaunchKernelGGL(k_dcgs_col, dim3((unsigned)ceil_div(j + 1, 4), (unsigned)bt.n), dim3(256),
-                       0, st, j, H, ldh, d, (const cd*)sc, bt);
+                       hfro2, flag, rel, first_pass ? 1 : 0, bt);
+    if (first_pass)
+        hipLaunchKernelGGL(k_dcgs_col, dim3((unsigned)ceil_div(j + 1, 4), (unsigned)bt.n),
+                           dim3(256), 0, st, j, H, ldh, d, (const cd*)sc, hess ? 1 : 0, bt);
     OSA_LAUNCH_CHECK();
 }
 

@@ -99,10 +99,13 @@ int launch_dot2_partial(const void* B, int64_t ldb, int ncols, const void* w1, c
                         const Batch& bt = Batch());
 // From d = [s, u^H u, t, u^H z] (2(j+1) entries): completes column j-1 of H,
 // writes the first-pass column j and sc = [1/r, c_j]; breakdown test as
-// launch_normalize (flag[1] = j - 1).  Batch strides: small (H, d), scal (sc,
-// and hfro2 in cd slots), flag.
+// launch_normalize (flag[1] = j - 1).  hess: H is upper Hessenberg (else all
+// of H[0:j+1, 0:j] enters the first-pass correction).  first_pass = false:
+// d = [s, u^H u] only; column j-1 and sc[0] = 1/r are set.
+// Batch strides: small (H, d), scal (sc, and hfro2 in cd slots), flag.
 void launch_dcgs_coef(int j, cd* H, int ldh, const cd* d, cd* sc, double* hfro2, int* flag,
-                      double rel, hipStream_t st, const Batch& bt = Batch());
+                      double rel, hipStream_t st, const Batch& bt = Batch(), bool hess = true,
+                      bool first_pass = true);
 // V[j] <- (V[j] - V_j s) / r and V[j+1] <- (z - V_j t - c_j V[j]) / r in one pass
 // over V_j (s = coef[0:j], t = coef[j+1:2j+1], sc = [1/r, c_j]).  scratch:
 // 16 n entries per problem for the column split.  Batch strides: basis (V),

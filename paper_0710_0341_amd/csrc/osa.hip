@@ -822,6 +822,73 @@ struct KsStats {
     bool converged = false;
 };
 
+// Arnoldi expansion of a Krylov-Schur basis from column kcur (a complete,
+// normalised vector) to ptot columns, with A = H^2 and the second Gram-Schmidt
+// pass delayed by one step (as in the solve): a single pass for column kcur,
+// delayed steps for kcur+1 .. ptot-1, then a last reorthogonalisation that
+// completes column ptot-1 and the normalised next vector v_ptot without a
+// further product with A.  The Rayleigh quotient S is general (triangular kept
+// block, spike row), so the first-pass correction uses all of it.
+void expand_delayed(osa_ctx* c, bool adjoint, bool fp32, char* V, int64_t N, cd* S, int ldS,
+                    int kcur, int ptot, void* wv, void* tv, cd* d, double* hfro2, int* flag,
+                    KsStats& stats) {
+    const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
+    auto vec = [&](int j) { return V + es * (size_t)N * j; };
+    const TsPlan pl = ts_plan(N);
+    const int64_t scratch_len = (int64_t)(c->upd_scratch.bytes / sizeof(cd));
+    cd* part = c->partial.as<cd>();
+    cd* sc = c->dscal.as<cd>() + 10;   // [1/r, c_j]
+    const double eb = fp32 ? 8.0 : 16.0;
+    auto matvec = [&](int j) {
+        apply_h(c, vec(j), tv, fp32, adjoint);
+        apply_h(c, tv, wv, fp32, adjoint);
+        stats.matvecs += 2;
+        c->prof.counters[3] += c->prof_on ? 1 : 0;
+    };
+    // column kcur: one pass; u_{kcur+1} -> basis column kcur + 1
+    matvec(kcur);
+    {
+        cd* scol = S + (size_t)kcur * ldS;
+        int nch = 0;
+        timed(c, 0, (kcur + 2.0) * N * eb, [&] {
+            nch = launch_dot_partial(V, N, kcur + 1, wv, fp32, pl, part, c->st);
+        });
+        launch_reduce_partial(part, nch, kcur + 1, scol, nullptr, nullptr, nullptr, c->st);
+        timed(c, 1, (kcur + 3.0) * N * eb, [&] {
+            launch_update(wv, V, N, kcur + 1, scol, fp32, pl, nullptr, nullptr, 0, c->st);
+        });
+        OSA_HIP(hipMemcpyAsync(vec(kcur + 1), wv, es * (size_t)N, hipMemcpyDeviceToDevice,
+                               c->st));
+    }
+    for (int j = kcur + 1; j < ptot; ++j) {
+        matvec(j);
+        int nch = 0;
+        timed(c, 0, (j + 3.0) * N * eb, [&] {
+            nch = launch_dot2_partial(V, N, j + 1, vec(j), wv, fp32, pl, part, c->st);
+        });
+        launch_reduce_partial(part, nch, 2 * (j + 1), d, nullptr, nullptr, nullptr, c->st);
+        launch_dcgs_coef(j, S, ldS, d, sc, hfro2, flag, 1e-300, c->st, Batch(), false, true);
+        timed(c, 1, (j + 4.0) * N * eb, [&] {
+            launch_dcgs_update(V, N, j, wv, d, sc, fp32, N, c->upd_scratch.as<cd>(), scratch_len,
+                               c->st);
+        });
+    }
+    // last reorthogonalisation: s = V^H u, |u|^2 from one pass over [V_ptot, u]
+    {
+        int nch = 0;
+        timed(c, 0, (ptot + 2.0) * N * eb, [&] {
+            nch = launch_dot_partial(V, N, ptot + 1, vec(ptot), fp32, pl, part, c->st);
+        });
+        launch_reduce_partial(part, nch, ptot + 1, d, nullptr, nullptr, nullptr, c->st);
+        launch_dcgs_coef(ptot, S, ldS, d, sc, hfro2, flag, 1e-300, c->st, Batch(), false, false);
+        timed(c, 1, (ptot + 2.0) * N * eb, [&] {
+            launch_update(vec(ptot), V, N, ptot, d, fp32, pl, nullptr, c->upd_scratch.as<cd>(),
+                          scratch_len, c->st);
+        });
+        launch_scale_dev(vec(ptot), vec(ptot), fp32, N, sc, false, c->st);
+    }
+}
+
 void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, int max_restarts,
             const cd* start /* fp64 internal vector or nullptr */, uint64_t seed, cd* Xout,
             KsStats& stats) {
@@ -830,7 +897,9 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
     const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
     const int P = nev + pa;              // basis capacity (plus the next vector)
     const int ldS = P + 1;
-    DevBuf Vb, Vt, wv, tv, S, T, Z, wr, bz, info, Spb, sws;
+    DevBuf Vb, Vt, wv, tv, S, T, Z, wr, bz, info, Spb, sws, dcb;
+    const bool dcgs = c->opts.orth == 0;   // delayed reorthogonalisation, as in the solve
+    dcb.ensure(sizeof(cd) * 2 * (size_t)(P + 2));
     Spb.ensure(sizeof(cd) * (size_t)pa * pa);
     if (pa > 64) sws.ensure(schur_ws_bytes(pa));
     Vb.ensure(es * (size_t)N * (P + 1));
@@ -861,15 +930,20 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
     for (int rs = 0; rs <= max_restarts; ++rs) {
         OSA_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, c->st));
         const int ptot = nlock + pa;
-        for (int j = kcur; j < ptot; ++j) {
-            apply_h(c, vec(j), tv.p, fp32, adjoint);
-            apply_h(c, tv.p, wv.p, fp32, adjoint);
-            stats.matvecs += 2;
-            c->prof.counters[3] += c->prof_on ? 1 : 0;
-            cd* scol = S.as<cd>() + (size_t)j * ldS;
-            cgs2(c, wv.p, V, N, j + 1, fp32, scol, c->coef.as<cd>());
-            launch_normalize(wv.p, vec(j + 1), fp32, pl, c->normp.as<double>(), scol + (j + 1),
-                             hfro2, 1e-300, flag, j, scol, j + 1, c->st);
+        if (dcgs) {
+            expand_delayed(c, adjoint, fp32, V, N, S.as<cd>(), ldS, kcur, ptot, wv.p, tv.p,
+                           dcb.as<cd>(), hfro2, flag, stats);
+        } else {
+            for (int j = kcur; j < ptot; ++j) {
+                apply_h(c, vec(j), tv.p, fp32, adjoint);
+                apply_h(c, tv.p, wv.p, fp32, adjoint);
+                stats.matvecs += 2;
+                c->prof.counters[3] += c->prof_on ? 1 : 0;
+                cd* scol = S.as<cd>() + (size_t)j * ldS;
+                cgs2(c, wv.p, V, N, j + 1, fp32, scol, c->coef.as<cd>());
+                launch_normalize(wv.p, vec(j + 1), fp32, pl, c->normp.as<double>(),
+                                 scol + (j + 1), hfro2, 1e-300, flag, j, scol, j + 1, c->st);
+            }
         }
         // Schur form of the active Rayleigh quotient, smallest |theta| first
         const double tr0 = now_ms();
