@@ -424,34 +424,70 @@ __device__ __forceinline__ double sort_key(cd v, int mode) {
     return mode == 0 ? cabsd(v) : fabs(v.x);
 }
 
-// Apply the 2x2 unitary Q (columns q0 = (a, b), q1 = (-conj b, conj a)) as a
-// similarity on rows/cols (k, k+1): T <- Q^H T Q, Z <- Z Q.
+// Unitary Q with first column (a, b) = (f, g)/|(f, g)|, so Q^H [f; g] = [|(f, g)|; 0].
+// The operands are first scaled by a power of two (exact) so that the sum of
+// squares neither overflows nor underflows; the reciprocal square root is the
+// hardware estimate refined by two Newton steps (error of a few ulp).
+__device__ __forceinline__ void unit_pair(cd f, cd g, cd& a, cd& b) {
+    const double m = fmax(fmax(fabs(f.x), fabs(f.y)), fmax(fabs(g.x), fabs(g.y)));
+    if (m == 0.0) {
+        a = mk(1.0, 0.0);
+        b = mk(0.0, 0.0);
+        return;
+    }
+    const int e = -__builtin_amdgcn_frexp_exp(m);
+    f = mk(ldexp(f.x, e), ldexp(f.y, e));
+    g = mk(ldexp(g.x, e), ldexp(g.y, e));
+    const double s2 = cabs2(f) + cabs2(g);   // in [1/4, 4)
+    double r = __builtin_amdgcn_rsq(s2);
+    r = r * fma(-0.5 * s2, r * r, 1.5);
+    r = r * fma(-0.5 * s2, r * r, 1.5);
+    a = cscale(f, r);
+    b = cscale(g, r);
+}
+
+// Value of v held by lane `src` (uniform), for every lane.
+__device__ __forceinline__ double lane_value(double v, int src) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ cd lane_value(cd v, int src) {
+    return mk(lane_value(v.x, src), lane_value(v.y, src));
+}
+
+// Similarity T <- Q^H T Q, Z <- Z Q by the 2x2 unitary Q (columns (a, b) and
+// (-conj b, conj a)) on rows/columns (k, k+1), for p <= 64: lane l owns column
+// l in the left update (columns >= col0) and row l in the right updates (T rows
+// <= row1, all rows of Z), which share one pass over LDS.
 // zero_col >= 0: the left update annihilates T[k+1, zero_col]; store an exact 0.
-__device__ void apply_pair(cd* T, cd* Z, int p, int ld, int k, cd a, cd b, int col0, int row1,
-                           int zero_col = -1) {
+// Returns this lane's updated T[l, k] (meaningful for l <= row1).
+__device__ __forceinline__ cd rotate_pair64(cd* T, cd* Z, int p, int ld, int k, cd a, cd b,
+                                            int col0, int row1, int zero_col) {
     const int l = threadIdx.x;
-    // left: rows k, k+1 over columns >= col0
-    for (int c = col0 + l; c < p; c += 64) {
-        cd x = T[k + c * ld], y = T[k + 1 + c * ld];
+    if (l >= col0 && l < p) {
+        const cd x = T[k + l * ld], y = T[k + 1 + l * ld];
         // Q^H [x; y] = [conj(a) x + conj(b) y ; -b x + a y]
-        cd nx = cadd(cmulc(a, x), cmulc(b, y));
-        cd ny = (c == zero_col) ? mk(0.0, 0.0) : csub(cmul(a, y), cmul(b, x));
-        T[k + c * ld] = nx;
-        T[k + 1 + c * ld] = ny;
+        T[k + l * ld] = cadd(cmulc(a, x), cmulc(b, y));
+        T[k + 1 + l * ld] = (l == zero_col) ? mk(0.0, 0.0) : csub(cmul(a, y), cmul(b, x));
     }
     wave_sync();
-    // right: columns k, k+1 over rows <= row1;  [x, y] Q = [a x + b y, -conj(b) x + conj(a) y]
-    for (int r = l; r <= row1 && r < p; r += 64) {
-        cd x = T[r + k * ld], y = T[r + (k + 1) * ld];
-        T[r + k * ld] = cadd(cmul(a, x), cmul(b, y));
-        T[r + (k + 1) * ld] = csub(cmulc(a, y), cmulc(b, x));
-    }
-    for (int r = l; r < p; r += 64) {
-        cd x = Z[r + k * ld], y = Z[r + (k + 1) * ld];
-        Z[r + k * ld] = cadd(cmul(a, x), cmul(b, y));
-        Z[r + (k + 1) * ld] = csub(cmulc(a, y), cmulc(b, x));
+    cd tk = mk(0.0, 0.0);
+    if (l < p) {
+        // [x, y] Q = [a x + b y, -conj(b) x + conj(a) y]
+        const cd x = T[l + k * ld], y = T[l + (k + 1) * ld];
+        const cd zx = Z[l + k * ld], zy = Z[l + (k + 1) * ld];
+        if (l <= row1) {
+            tk = cadd(cmul(a, x), cmul(b, y));
+            T[l + k * ld] = tk;
+            T[l + (k + 1) * ld] = csub(cmulc(a, y), cmulc(b, x));
+        }
+        Z[l + k * ld] = cadd(cmul(a, zx), cmul(b, zy));
+        Z[l + (k + 1) * ld] = csub(cmulc(a, zy), cmulc(b, zx));
     }
     wave_sync();
+    return tk;
 }
 
 __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, int p, cd* Tout,
@@ -468,11 +504,17 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
     const int l = threadIdx.x;
 #define TT(i, j) T[(i) + (j) * ld]
 #define ZZ(i, j) Z[(i) + (j) * ld]
+    // The QR iteration is run on B = A^H.  It tends to deflate the eigenvalues of
+    // smallest modulus first, at the bottom, so B = Z_B T_B Z_B^H comes out with
+    // the diagonal roughly descending.  Then A = W U W^H with W = Z_B J and
+    // U = J T_B^H J (J reverses the index order): U is upper triangular and its
+    // diagonal roughly ascending, which leaves the final reordering by adjacent
+    // swaps (wanted values first) little to do.
     double amax = 0;
     for (int e = l; e < p * p; e += 64) {
         const int i = e % p, j = e / p;
         const cd v = A[e];
-        TT(i, j) = v;
+        TT(j, i) = cconj(v);
         ZZ(i, j) = mk(i == j ? 1.0 : 0.0, 0.0);
         amax = fmax(amax, cabsd(v));
     }
@@ -504,20 +546,24 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
         // left: T[j+1:, c] -= tau v (v^H T[j+1:, c]),  c >= j   (one column per lane)
         for (int c = j + l; c < p; c += 64) {
             cd sacc = mk(0.0, 0.0);
+#pragma unroll 8
             for (int i = 0; i < L; ++i) cfmac(sacc, hv[i], TT(j + 1 + i, c));
             sacc = cscale(sacc, tau);
+#pragma unroll 8
             for (int i = 0; i < L; ++i) TT(j + 1 + i, c) = csub(TT(j + 1 + i, c), cmul(hv[i], sacc));
         }
         wave_sync();
         // right: T[r, j+1:] -= tau (T[r, j+1:] v) v^H, all rows; same for Z
         for (int r = l; r < p; r += 64) {
             cd sacc = mk(0.0, 0.0), sz = mk(0.0, 0.0);
+#pragma unroll 8
             for (int i = 0; i < L; ++i) {
                 cfma(sacc, TT(r, j + 1 + i), hv[i]);
                 cfma(sz, ZZ(r, j + 1 + i), hv[i]);
             }
             sacc = cscale(sacc, tau);
             sz = cscale(sz, tau);
+#pragma unroll 8
             for (int i = 0; i < L; ++i) {
                 TT(r, j + 1 + i) = csub(TT(r, j + 1 + i), cmul(sacc, cconj(hv[i])));
                 ZZ(r, j + 1 + i) = csub(ZZ(r, j + 1 + i), cmul(sz, cconj(hv[i])));
@@ -575,26 +621,43 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
                 sigma = (cabsd(csub(e1, d)) <= cabsd(csub(e2, d))) ? e1 : e2;
             }
         }
-        // bulge chase on the active block [lo, hi]
+        // bulge chase on the active block [lo, hi].  The pair (f, g) that fixes the
+        // next rotation, T[k+1, k] and the bulge T[k+2, k], comes out of the right
+        // update of rows k+1 and k+2 and is read from those lanes' registers.
+        cd f = csub(TT(lo, lo), sigma), g = TT(lo + 1, lo);
         for (int k = lo; k < hi; ++k) {
-            cd f, g;
-            if (k == lo) {
-                f = csub(TT(lo, lo), sigma);
-                g = TT(lo + 1, lo);
-            } else {
-                f = TT(k, k - 1);
-                g = TT(k + 1, k - 1);
-            }
-            // unitary with first column (f, g)/|(f, g)|: Q^H [f; g] = [|.|; 0]
-            const double nf = sqrt(cabs2(f) + cabs2(g));
             cd a, b;
-            if (nf == 0.0) { a = mk(1.0, 0.0); b = mk(0.0, 0.0); }
-            else { const double inf = 1.0 / nf; a = cscale(f, inf); b = cscale(g, inf); }
+            unit_pair(f, g, a, b);
             const int col0 = (k == lo) ? lo : k - 1;
             const int row1 = (k + 2 < hi) ? k + 2 : hi;
-            apply_pair(T, Z, p, ld, k, a, b, col0, row1, (k > lo) ? k - 1 : -1);
+            const cd tk = rotate_pair64(T, Z, p, ld, k, a, b, col0, row1, (k > lo) ? k - 1 : -1);
             ++nrot;
+            if (k + 1 < hi) {
+                f = lane_value(tk, k + 1);
+                g = lane_value(tk, k + 2);
+            }
         }
+    }
+    // ---- back to A: T <- J T^H J (pairs (i, j) <-> (p-1-j, p-1-i)), Z <- Z J
+    if (!fail) {
+        for (int e = l; e < p * p; e += 64) {
+            const int i = e % p, j = e / p;
+            const int i2 = p - 1 - j, j2 = p - 1 - i;
+            const int e2 = i2 + j2 * p;
+            if (e <= e2) {
+                const cd u = TT(i, j), v = TT(i2, j2);
+                TT(i, j) = cconj(v);
+                TT(i2, j2) = cconj(u);
+            }
+        }
+        for (int i = l; i < p; i += 64) {
+            for (int j = 0; j < p / 2; ++j) {
+                const cd u = ZZ(i, j), v = ZZ(i, p - 1 - j);
+                ZZ(i, j) = v;
+                ZZ(i, p - 1 - j) = u;
+            }
+        }
+        wave_sync();
     }
     // ---- reorder the diagonal (insertion sort by adjacent swaps)
     for (int i = 1; i < p && !fail; ++i) {
@@ -603,10 +666,10 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
             if (!(sort_key(t22, mode) < sort_key(t11, mode))) break;
             const cd t12 = TT(j - 1, j);
             const cd x1 = t12, x2 = csub(t22, t11);
-            const double nx = sqrt(cabs2(x1) + cabs2(x2));
-            if (nx == 0.0) break;
-            const cd a = cscale(x1, 1.0 / nx), b = cscale(x2, 1.0 / nx);
-            apply_pair(T, Z, p, ld, j - 1, a, b, j - 1, j);
+            if (x1.x == 0.0 && x1.y == 0.0 && x2.x == 0.0 && x2.y == 0.0) break;
+            cd a, b;
+            unit_pair(x1, x2, a, b);
+            rotate_pair64(T, Z, p, ld, j - 1, a, b, j - 1, j, -1);
             ++nrot;
             if (l == 0) {
                 TT(j, j - 1) = mk(0.0, 0.0);   // touched by both sides: set after them

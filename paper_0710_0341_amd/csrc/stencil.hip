@@ -189,79 +189,101 @@ struct StencilArgs {
     double cf[4], cb[4];
 };
 
+// One block: 64 sites of one problem, one wavefront per direction nu (both hops
+// of nu, so the direction is uniform in a wave); the four partial sums meet in
+// LDS, where each wave adds the diagonal term and gamma_5 for three of the
+// twelve components.  Four times the waves of one-thread-per-site, each with a
+// quarter of the hops: small lattices fill the GPU, large ones keep coalesced
+// site-contiguous accesses.
 template <typename R, typename ST, typename LT>
-__global__ __launch_bounds__(128) void k_wilson_h(const ST* __restrict__ in, ST* __restrict__ out,
+__global__ __launch_bounds__(256) void k_wilson_h(const ST* __restrict__ in, ST* __restrict__ out,
                                                  const LT* __restrict__ U, StencilArgs a,
                                                  Batch bt) {
+    __shared__ Cx<R> part[4][12][64];
     // consecutive blocks take the same sites for the problems of the batch, so
     // a block of links is fetched from HBM once and then served from L2
     const int entry = (int)(blockIdx.x % (unsigned)bt.n);
-    const int s = (int)(blockIdx.x / (unsigned)bt.n) * blockDim.x + threadIdx.x;
+    const int sb = (int)(blockIdx.x / (unsigned)bt.n);
     const int pb = bt.idx[entry];
     in += pb * bt.basis;
     out += pb * bt.vec;
-    if (s >= a.V) {
-        // padding sites carry zeros so that whole-vector reductions stay exact
-        if (s < a.Vp) {
-            ST z;
-            z.x = 0;
-            z.y = 0;
-#pragma unroll
-            for (int c = 0; c < 12; ++c) out[(int64_t)c * a.Vp + s] = z;
-        }
-        return;
-    }
-    const int x = s % a.lx;
-    int r = s / a.lx;
-    const int y = r % a.ly;
-    r /= a.ly;
-    const int z = r % a.lz;
-    const int t = r / a.lz;
-    const int sx = 1, sy = a.lx, sz = a.lx * a.ly, stt = a.lx * a.ly * a.lz;
-    const int xf = (x + 1 == a.lx) ? s - (a.lx - 1) * sx : s + sx;
-    const int xb = (x == 0) ? s + (a.lx - 1) * sx : s - sx;
-    const int yf = (y + 1 == a.ly) ? s - (a.ly - 1) * sy : s + sy;
-    const int yb = (y == 0) ? s + (a.ly - 1) * sy : s - sy;
-    const int zf = (z + 1 == a.lz) ? s - (a.lz - 1) * sz : s + sz;
-    const int zb = (z == 0) ? s + (a.lz - 1) * sz : s - sz;
-    const int tf = (t + 1 == a.lt) ? s - (a.lt - 1) * stt : s + stt;
-    const int tb = (t == 0) ? s + (a.lt - 1) * stt : s - stt;
-    R ctf = (R)a.cf[3], ctb = (R)a.cb[3];
-    if (a.apt) {
-        if (t + 1 == a.lt) ctf = -ctf;
-        if (t == 0) ctb = -ctb;
-    }
+    const int lane = threadIdx.x & 63;
+    const int d = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // direction of the wave
+    const int s = sb * 64 + lane;
+    const int64_t Vp = a.Vp;
     Cx<R> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = Cx<R>{0, 0};
-    const int64_t Vp = a.Vp;
-    hop<R, 0, +1>(in, U, Vp, xf, s, (R)a.cf[0], acc);
-    hop<R, 0, -1>(in, U, Vp, xb, xb, (R)a.cb[0], acc);
-    hop<R, 1, +1>(in, U, Vp, yf, s, (R)a.cf[1], acc);
-    hop<R, 1, -1>(in, U, Vp, yb, yb, (R)a.cb[1], acc);
-    hop<R, 2, +1>(in, U, Vp, zf, s, (R)a.cf[2], acc);
-    hop<R, 2, -1>(in, U, Vp, zb, zb, (R)a.cb[2], acc);
-    hop<R, 3, +1>(in, U, Vp, tf, s, ctf, acc);
-    hop<R, 3, -1>(in, U, Vp, tb, tb, ctb, acc);
+    if (s < a.V) {
+        const int x = s % a.lx;
+        int r = s / a.lx;
+        const int y = r % a.ly;
+        r /= a.ly;
+        const int z = r % a.lz;
+        const int t = r / a.lz;
+        if (d == 0) {
+            const int f = (x + 1 == a.lx) ? s - (a.lx - 1) : s + 1;
+            const int b = (x == 0) ? s + (a.lx - 1) : s - 1;
+            hop<R, 0, +1>(in, U, Vp, f, s, (R)a.cf[0], acc);
+            hop<R, 0, -1>(in, U, Vp, b, b, (R)a.cb[0], acc);
+        } else if (d == 1) {
+            const int sy = a.lx;
+            const int f = (y + 1 == a.ly) ? s - (a.ly - 1) * sy : s + sy;
+            const int b = (y == 0) ? s + (a.ly - 1) * sy : s - sy;
+            hop<R, 1, +1>(in, U, Vp, f, s, (R)a.cf[1], acc);
+            hop<R, 1, -1>(in, U, Vp, b, b, (R)a.cb[1], acc);
+        } else if (d == 2) {
+            const int sz = a.lx * a.ly;
+            const int f = (z + 1 == a.lz) ? s - (a.lz - 1) * sz : s + sz;
+            const int b = (z == 0) ? s + (a.lz - 1) * sz : s - sz;
+            hop<R, 2, +1>(in, U, Vp, f, s, (R)a.cf[2], acc);
+            hop<R, 2, -1>(in, U, Vp, b, b, (R)a.cb[2], acc);
+        } else {
+            const int stt = a.lx * a.ly * a.lz;
+            const int f = (t + 1 == a.lt) ? s - (a.lt - 1) * stt : s + stt;
+            const int b = (t == 0) ? s + (a.lt - 1) * stt : s - stt;
+            R ctf = (R)a.cf[3], ctb = (R)a.cb[3];
+            if (a.apt) {
+                if (t + 1 == a.lt) ctf = -ctf;
+                if (t == 0) ctb = -ctb;
+            }
+            hop<R, 3, +1>(in, U, Vp, f, s, ctf, acc);
+            hop<R, 3, -1>(in, U, Vp, b, b, ctb, acc);
+        }
+    }
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        Cx<R> v = ld<R>(in + (int64_t)c * Vp + s) + acc[c];
-        if (c >= 6) v = Cx<R>{-v.x, -v.y};    // gamma_5
-        ST o;
-        o.x = v.x;
-        o.y = v.y;
-        out[(int64_t)c * Vp + s] = o;
+    for (int c = 0; c < 12; ++c) part[d][c][lane] = acc[c];
+    __syncthreads();
+    if (s < a.Vp) {
+        // padding sites carry zeros so that whole-vector reductions stay exact
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int c = 3 * d + i;
+            ST o;
+            o.x = 0;
+            o.y = 0;
+            if (s < a.V) {
+                Cx<R> v = ld<R>(in + (int64_t)c * Vp + s) + part[0][c][lane] + part[1][c][lane] +
+                          part[2][c][lane] + part[3][c][lane];
+                if (c >= 6) v = Cx<R>{-v.x, -v.y};    // gamma_5
+                o.x = v.x;
+                o.y = v.y;
+            }
+            out[(int64_t)c * Vp + s] = o;
+        }
     }
 }
 
 void launch_wilson_h(const void* in, void* out, const void* U, bool links_fp32, bool spinor_fp32,
                      const Geom& g, const HopCoef& c, hipStream_t st, const Batch& bt) {
     if (bt.n <= 0) return;
+    // a block covers 64 sites and writes all of them
+    if (g.Vp % 64 != 0) throw HipError{hipErrorInvalidValue, "launch_wilson_h: Vp % 64 != 0"};
     StencilArgs a;
     a.lx = g.lx; a.ly = g.ly; a.lz = g.lz; a.lt = g.lt; a.V = g.V; a.Vp = g.Vp; a.apt = g.apt;
     for (int i = 0; i < 4; ++i) { a.cf[i] = c.fwd[i]; a.cb[i] = c.bwd[i]; }
-    // the grid covers Vp sites (padding included) for each problem
-    dim3 blk(128), grid((unsigned)(ceil_div(g.Vp, 128) * bt.n));
+    // the grid covers Vp sites (padding included; Vp is a multiple of 64) for each problem
+    dim3 blk(256), grid((unsigned)(ceil_div(g.Vp, 64) * bt.n));
     if (!spinor_fp32 && !links_fp32)
         hipLaunchKernelGGL((k_wilson_h<double, cd, cd>), grid, blk, 0, st, (const cd*)in, (cd*)out,
                            (const cd*)U, a, bt);
