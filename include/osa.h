@@ -223,18 +223,24 @@ OSA_API osa_status osa_set_links(osa_ctx* ctx, const void* links);
  * updates (w - V h), 2 stencil H_w(mu), 3 one small-matrix inversion of the
  * Newton iteration, 4 small Schur decomposition of an eigensolver restart,
  * 5 whole eigensolver restart (host wall clock, including synchronisation).
- * bytes[] counts the algorithmic HBM bytes of each launch (vectors read and
- * written once).  counters[]: 0 QR sweeps and 1 plane rotations (sweeps plus
- * reordering) of the small Schur decompositions, 2 Newton iterations of the
- * small sign, 3 eigensolver Arnoldi steps.  Enabling resets everything; the
- * events add a few microseconds of overhead per bracketed launch. */
+ * every <= 0 disables timing; every = n >= 1 brackets one launch in n of each
+ * class with events (the first, then every n-th), which keeps the overhead of
+ * the events (a few microseconds per bracketed launch) small.  ms[], bytes[]
+ * and launches[] cover the bracketed launches only, calls[] counts all of
+ * them, so ms/launches is the average duration and ms/launches*calls the
+ * estimated class total.  bytes[] counts the algorithmic HBM bytes of each
+ * launch (vectors read and written once).  counters[]: 0 QR sweeps and 1 plane
+ * rotations (sweeps plus reordering) of the small Schur decompositions,
+ * 2 Newton iterations of the small sign, 3 eigensolver Arnoldi steps.
+ * Enabling resets everything. */
 typedef struct {
     double ms[6];
     double bytes[6];
     int64_t launches[6];
     int64_t counters[4];
+    int64_t calls[6];
 } osa_profile;
-OSA_API osa_status osa_profile_enable(osa_ctx* ctx, int32_t enable);
+OSA_API osa_status osa_profile_enable(osa_ctx* ctx, int32_t every);
 OSA_API osa_status osa_profile_read(osa_ctx* ctx, osa_profile* out);
 
 /* Human-readable detail of the last error on this context ("" if none);

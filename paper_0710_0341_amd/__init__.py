@@ -64,7 +64,8 @@ class Info(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 6), ("bytes", ctypes.c_double * 6),
-                ("launches", ctypes.c_int64 * 6), ("counters", ctypes.c_int64 * 4)]
+                ("launches", ctypes.c_int64 * 6), ("counters", ctypes.c_int64 * 4),
+                ("calls", ctypes.c_int64 * 6)]
 
     CLASSES = ("cgs_dot", "cgs_update", "stencil", "small_inverse", "small_schur",
                "eig_restart")
@@ -72,7 +73,8 @@ class Profile(ctypes.Structure):
     COUNTERS = ("schur_sweeps", "schur_rotations", "newton_iterations", "eig_arnoldi_steps")
 
     def as_dict(self):
-        d = {name: dict(ms=self.ms[i], bytes=self.bytes[i], launches=self.launches[i])
+        d = {name: dict(ms=self.ms[i], bytes=self.bytes[i], launches=self.launches[i],
+                        calls=self.calls[i])
              for i, name in enumerate(self.CLASSES)}
         d["counters"] = {name: int(self.counters[i]) for i, name in enumerate(self.COUNTERS)}
         return d
@@ -308,8 +310,10 @@ class Context:
         self._after_current()
         _check(lib().osa_set_links(self._h, lp), "osa_set_links", False)
 
-    def profile(self, enable=True):
-        _check(lib().osa_profile_enable(self._h, int(bool(enable))), "osa_profile_enable", False)
+    def profile(self, enable=True, every=1):
+        """Event timing of kernel classes; every=n brackets one launch in n per class."""
+        n = max(1, int(every)) if enable else 0
+        _check(lib().osa_profile_enable(self._h, n), "osa_profile_enable", False)
 
     def profile_read(self):
         out = Profile()

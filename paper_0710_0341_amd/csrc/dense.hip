@@ -545,24 +545,37 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
         wave_sync();
         // left: T[j+1:, c] -= tau v (v^H T[j+1:, c]),  c >= j   (one column per lane)
         for (int c = j + l; c < p; c += 64) {
-            cd sacc = mk(0.0, 0.0);
-#pragma unroll 8
-            for (int i = 0; i < L; ++i) cfmac(sacc, hv[i], TT(j + 1 + i, c));
-            sacc = cscale(sacc, tau);
+            // two partial sums: independent FMA chains
+            cd s0 = mk(0.0, 0.0), s1 = mk(0.0, 0.0);
+            int i = 0;
+#pragma unroll 4
+            for (; i + 1 < L; i += 2) {
+                cfmac(s0, hv[i], TT(j + 1 + i, c));
+                cfmac(s1, hv[i + 1], TT(j + 2 + i, c));
+            }
+            if (i < L) cfmac(s0, hv[i], TT(j + 1 + i, c));
+            const cd sacc = cscale(cadd(s0, s1), tau);
 #pragma unroll 8
             for (int i = 0; i < L; ++i) TT(j + 1 + i, c) = csub(TT(j + 1 + i, c), cmul(hv[i], sacc));
         }
         wave_sync();
         // right: T[r, j+1:] -= tau (T[r, j+1:] v) v^H, all rows; same for Z
         for (int r = l; r < p; r += 64) {
-            cd sacc = mk(0.0, 0.0), sz = mk(0.0, 0.0);
-#pragma unroll 8
-            for (int i = 0; i < L; ++i) {
-                cfma(sacc, TT(r, j + 1 + i), hv[i]);
-                cfma(sz, ZZ(r, j + 1 + i), hv[i]);
+            cd s0 = mk(0.0, 0.0), s1 = mk(0.0, 0.0), z0 = mk(0.0, 0.0), z1 = mk(0.0, 0.0);
+            int i = 0;
+#pragma unroll 4
+            for (; i + 1 < L; i += 2) {
+                cfma(s0, TT(r, j + 1 + i), hv[i]);
+                cfma(z0, ZZ(r, j + 1 + i), hv[i]);
+                cfma(s1, TT(r, j + 2 + i), hv[i + 1]);
+                cfma(z1, ZZ(r, j + 2 + i), hv[i + 1]);
             }
-            sacc = cscale(sacc, tau);
-            sz = cscale(sz, tau);
+            if (i < L) {
+                cfma(s0, TT(r, j + 1 + i), hv[i]);
+                cfma(z0, ZZ(r, j + 1 + i), hv[i]);
+            }
+            const cd sacc = cscale(cadd(s0, s1), tau);
+            const cd sz = cscale(cadd(z0, z1), tau);
 #pragma unroll 8
             for (int i = 0; i < L; ++i) {
                 TT(r, j + 1 + i) = csub(TT(r, j + 1 + i), cmul(sacc, cconj(hv[i])));

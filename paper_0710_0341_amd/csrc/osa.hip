@@ -157,6 +157,7 @@ struct osa_ctx {
     // optional kernel timing (events on st, resolved at synchronisation points)
     struct Pending { hipEvent_t a, b; int cls; double bytes; };
     bool prof_on = false;
+    int prof_every = 1;   // bracket one launch in prof_every of each class
     std::vector<Pending> prof_pending;
     std::vector<hipEvent_t> prof_pool;
     osa_profile prof{};
@@ -209,6 +210,7 @@ hipEvent_t prof_event(osa_ctx* c) {
 template <typename F>
 void timed(osa_ctx* c, int cls, double bytes, F&& f) {
     if (!c->prof_on) { f(); return; }
+    if (c->prof.calls[cls]++ % c->prof_every != 0) { f(); return; }
     hipEvent_t a = prof_event(c), b = prof_event(c);
     OSA_HIP(hipEventRecord(a, c->st));
     f();
@@ -1008,7 +1010,7 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
                                  hipMemcpyDeviceToDevice, c->st));
         kcur = nlock + keep;
         nlock = nl2;
-        if (c->prof_on) {
+        if (c->prof_on && c->prof.calls[5]++ % c->prof_every == 0) {
             sync(c);
             c->prof.ms[5] += now_ms() - tr0;
             c->prof.launches[5] += 1;
@@ -1151,6 +1153,7 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
     w->u_ext = c->U.p;
     w->u32_ext = c->U32.p;
     w->prof_on = c->prof_on;
+    w->prof_every = c->prof_every;
     OSA_HIP(hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking));
     w->own_stream = true;
     ensure_exec(w.get(), nev + ncv + 1);
@@ -1186,6 +1189,7 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
             c->prof.ms[i] += w->prof.ms[i];
             c->prof.bytes[i] += w->prof.bytes[i];
             c->prof.launches[i] += w->prof.launches[i];
+            c->prof.calls[i] += w->prof.calls[i];
         }
         for (int i = 0; i < 4; ++i) c->prof.counters[i] += w->prof.counters[i];
     }
@@ -1568,12 +1572,13 @@ osa_status osa_set_links(osa_ctx* c, const void* links) {
     });
 }
 
-osa_status osa_profile_enable(osa_ctx* c, int32_t enable) {
+osa_status osa_profile_enable(osa_ctx* c, int32_t every) {
     if (!c) return OSA_ERR_ARG;
     return guard([&]() -> osa_status {
         sync(c);
         c->prof = osa_profile{};
-        c->prof_on = enable != 0;
+        c->prof_on = every > 0;
+        c->prof_every = every > 0 ? every : 1;
         return OSA_OK;
     });
 }
