@@ -490,8 +490,11 @@ __device__ __forceinline__ cd rotate_pair64(cd* T, cd* Z, int p, int ld, int k, 
     return tk;
 }
 
-__global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, int p, cd* Tout,
-                                                   cd* Zout, cd* wout, int mode, int* info) {
+static constexpr int kSchurWaves = 4;   // wavefronts of the Householder phase
+
+__global__ __launch_bounds__(64 * kSchurWaves) void k_small_schur(const cd* __restrict__ A, int p,
+                                                                 cd* Tout, cd* Zout, cd* wout,
+                                                                 int mode, int* info) {
     // T and Z in LDS, column-major with the odd leading dimension ld = p + 1 so
     // that row sweeps (stride ld) and column sweeps (stride 1) are both free of
     // bank conflicts.
@@ -500,8 +503,10 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
     cd* T = lds;
     cd* Z = lds + (size_t)p * ld;
     __shared__ cd hv[kSchurMax];
-    __shared__ double sanorm;
-    const int l = threadIdx.x;
+    __shared__ cd pt[kSchurWaves][kSchurMax], pz[kSchurWaves][kSchurMax];
+    __shared__ double sanorm[kSchurWaves];
+    const int l = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
 #define TT(i, j) T[(i) + (j) * ld]
 #define ZZ(i, j) Z[(i) + (j) * ld]
     // The QR iteration is run on B = A^H.  It tends to deflate the eigenvalues of
@@ -511,7 +516,7 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
     // diagonal roughly ascending, which leaves the final reordering by adjacent
     // swaps (wanted values first) little to do.
     double amax = 0;
-    for (int e = l; e < p * p; e += 64) {
+    for (int e = threadIdx.x; e < p * p; e += 64 * kSchurWaves) {
         const int i = e % p, j = e / p;
         const cd v = A[e];
         TT(j, i) = cconj(v);
@@ -520,10 +525,13 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
-    if (l == 0) sanorm = amax;
-    wave_sync();
-    const double anorm = sanorm;
-    // ---- Hessenberg reduction (Householder)
+    if (l == 0) sanorm[wv] = amax;
+    __syncthreads();
+    const double anorm = fmax(fmax(sanorm[0], sanorm[1]), fmax(sanorm[2], sanorm[3]));
+    // ---- Hessenberg reduction (Householder), four wavefronts: the reflector is
+    // formed redundantly by each, the products v^H T[j+1:, c] and T[r, j+1:] v
+    // are split over the wavefronts by ranges of the summation index and added
+    // in wavefront order, and each wavefront updates its own range.
     for (int j = 0; j + 2 < p; ++j) {
         const int L = p - j - 1;
         double xp = 0;
@@ -534,58 +542,63 @@ __global__ __launch_bounds__(64) void k_small_schur(const cd* __restrict__ A, in
         const double xn = sqrt(xn2);
         const cd x0 = TT(j + 1, j);
         const double tail = xn2 - cabs2(x0);
-        if (xn == 0.0 || tail <= 1e-300) { wave_sync(); continue; }
+        if (xn == 0.0 || tail <= 1e-300) { __syncthreads(); continue; }
         const double ax0 = cabsd(x0);
         const cd ph = ax0 > 0 ? cscale(x0, 1.0 / ax0) : mk(1.0, 0.0);
         const cd alpha = cscale(ph, -xn);           // -e^{i arg x0} |x|
         // v = x - alpha e1, |v|^2 = |x|^2 - 2 Re(conj(alpha) x0) + |alpha|^2, tau = 2 / |v|^2
-        for (int i = l; i < L; i += 64) hv[i] = (i == 0) ? csub(x0, alpha) : TT(j + 1 + i, j);
+        if (wv == 0)
+            for (int i = l; i < L; i += 64) hv[i] = (i == 0) ? csub(x0, alpha) : TT(j + 1 + i, j);
         const double vn2 = 2.0 * xn2 + 2.0 * xn * ax0;
         const double tau = 2.0 / vn2;
-        wave_sync();
+        // this wavefront's range of the summation index
+        const int q = (L + kSchurWaves - 1) / kSchurWaves;
+        const int i0 = wv * q, i1 = min(L, i0 + q);
+        __syncthreads();
         // left: T[j+1:, c] -= tau v (v^H T[j+1:, c]),  c >= j   (one column per lane)
-        for (int c = j + l; c < p; c += 64) {
-            // two partial sums: independent FMA chains
-            cd s0 = mk(0.0, 0.0), s1 = mk(0.0, 0.0);
-            int i = 0;
+        const int c = j + l;
+        if (c < p) {
+            cd s0 = mk(0.0, 0.0);
 #pragma unroll 4
-            for (; i + 1 < L; i += 2) {
-                cfmac(s0, hv[i], TT(j + 1 + i, c));
-                cfmac(s1, hv[i + 1], TT(j + 2 + i, c));
-            }
-            if (i < L) cfmac(s0, hv[i], TT(j + 1 + i, c));
-            const cd sacc = cscale(cadd(s0, s1), tau);
-#pragma unroll 8
-            for (int i = 0; i < L; ++i) TT(j + 1 + i, c) = csub(TT(j + 1 + i, c), cmul(hv[i], sacc));
+            for (int i = i0; i < i1; ++i) cfmac(s0, hv[i], TT(j + 1 + i, c));
+            pt[wv][l] = s0;
         }
-        wave_sync();
-        // right: T[r, j+1:] -= tau (T[r, j+1:] v) v^H, all rows; same for Z
-        for (int r = l; r < p; r += 64) {
-            cd s0 = mk(0.0, 0.0), s1 = mk(0.0, 0.0), z0 = mk(0.0, 0.0), z1 = mk(0.0, 0.0);
-            int i = 0;
+        __syncthreads();
+        if (c < p) {
+            const cd sacc = cscale(cadd(cadd(pt[0][l], pt[1][l]), cadd(pt[2][l], pt[3][l])), tau);
 #pragma unroll 4
-            for (; i + 1 < L; i += 2) {
+            for (int i = i0; i < i1; ++i) TT(j + 1 + i, c) = csub(TT(j + 1 + i, c), cmul(hv[i], sacc));
+        }
+        __syncthreads();
+        // right: T[r, j+1:] -= tau (T[r, j+1:] v) v^H, all rows; same for Z
+        const int r = l;
+        if (r < p) {
+            cd s0 = mk(0.0, 0.0), z0 = mk(0.0, 0.0);
+#pragma unroll 4
+            for (int i = i0; i < i1; ++i) {
                 cfma(s0, TT(r, j + 1 + i), hv[i]);
                 cfma(z0, ZZ(r, j + 1 + i), hv[i]);
-                cfma(s1, TT(r, j + 2 + i), hv[i + 1]);
-                cfma(z1, ZZ(r, j + 2 + i), hv[i + 1]);
             }
-            if (i < L) {
-                cfma(s0, TT(r, j + 1 + i), hv[i]);
-                cfma(z0, ZZ(r, j + 1 + i), hv[i]);
-            }
-            const cd sacc = cscale(cadd(s0, s1), tau);
-            const cd sz = cscale(cadd(z0, z1), tau);
-#pragma unroll 8
-            for (int i = 0; i < L; ++i) {
+            pt[wv][l] = s0;
+            pz[wv][l] = z0;
+        }
+        __syncthreads();
+        if (r < p) {
+            const cd sacc = cscale(cadd(cadd(pt[0][l], pt[1][l]), cadd(pt[2][l], pt[3][l])), tau);
+            const cd sz = cscale(cadd(cadd(pz[0][l], pz[1][l]), cadd(pz[2][l], pz[3][l])), tau);
+#pragma unroll 4
+            for (int i = i0; i < i1; ++i) {
                 TT(r, j + 1 + i) = csub(TT(r, j + 1 + i), cmul(sacc, cconj(hv[i])));
                 ZZ(r, j + 1 + i) = csub(ZZ(r, j + 1 + i), cmul(sz, cconj(hv[i])));
             }
         }
-        wave_sync();
-        for (int i = l; i < L; i += 64) TT(j + 1 + i, j) = (i == 0) ? alpha : mk(0.0, 0.0);
-        wave_sync();
+        __syncthreads();
+        if (wv == 0)
+            for (int i = l; i < L; i += 64) TT(j + 1 + i, j) = (i == 0) ? alpha : mk(0.0, 0.0);
+        __syncthreads();
     }
+    // the QR iteration and everything after it run on the first wavefront
+    if (wv != 0) return;
     // ---- shifted QR
     const double ulp = 2.220446049250313e-16;
     const double smlnum = 1e-300;
@@ -997,7 +1010,8 @@ void small_schur(const cd* A, int p, cd* T, cd* Z, cd* w, int mode, int* info, v
         return true;
     }();
     (void)attr_set;
-    hipLaunchKernelGGL(k_small_schur, dim3(1), dim3(64), lds, st, A, p, T, Z, w, mode, info);
+    hipLaunchKernelGGL(k_small_schur, dim3(1), dim3(64 * kSchurWaves), lds, st, A, p, T, Z, w, mode,
+                       info);
     OSA_LAUNCH_CHECK();
 }
 
