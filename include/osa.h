@@ -75,10 +75,12 @@ typedef struct {
     int32_t check_every;        /* convergence check interval (default 50); < 0: run exactly
                                    k_max steps with no check (fixed-k mode)                   */
     int32_t no_reproject;       /* 1: skip the per-step oblique re-projection (default 0)     */
-    int32_t eig_ncv;            /* eigensolver active block, 8..96 (default nev + 16 within
-                                   [64, 96], nev = wanted eigenvalues of H^2; if that run
-                                   does not converge, osa_deflate runs once more with 96
-                                   and twice the restart cap)                               */
+    int32_t eig_ncv;            /* eigensolver block, 8..96: the Krylov-Schur active block
+                                   (default nev + 16 within [64, 96], nev = wanted
+                                   eigenvalues of H^2) or the filtered block (default
+                                   nev + 48 within [64, 96], see eig_filter); if that run does not
+                                   converge, osa_deflate runs once more with 96 and twice
+                                   the restart cap                                          */
     int32_t eig_max_restarts;   /* eigensolver restart cap                 (default 2000)     */
     osa_prec eig_prec;          /* FP32: search in FP32, then refine in FP64 (default FP64)   */
     double eig_tol;             /* relative Krylov-Schur residual target   (default 1e-12)    */
@@ -92,6 +94,12 @@ typedef struct {
                                    vectors and one fused update pass per step (half the
                                    basis traffic); 1: classical Gram-Schmidt applied twice
                                    in the same step (four passes)                          */
+    int32_t eig_filter;         /* FP64 search for the critical pairs: 0 (default)
+                                   Krylov-Schur; d in 1..200: Chebyshev-filtered subspace
+                                   iteration on H^2 with a degree-d filter and a block of
+                                   eig_ncv vectors (default nev + 48 within [64, 96]);
+                                   Krylov-Schur takes over if 80 filter iterations do not
+                                   converge.  The FP32 search always uses Krylov-Schur     */
 } osa_opts;
 
 /* Per-solve diagnostics (host struct). */

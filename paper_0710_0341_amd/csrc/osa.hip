@@ -1018,6 +1018,194 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
     }
 }
 
+// ------------------------------------------------ filtered subspace iteration
+// out = alpha ay + beta y + gamma yp over n complex entries (real coefficients);
+// out may be yp.
+__global__ __launch_bounds__(256) void k_cheb_step(cd* out, const cd* __restrict__ ay,
+                                                   const cd* __restrict__ y, const cd* yp,
+                                                   int64_t n, double alpha, double beta,
+                                                   double gamma) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const cd a = ay[i], v = y[i];
+    cd r = mk(fma(alpha, a.x, beta * v.x), fma(alpha, a.y, beta * v.y));
+    if (yp) {
+        const cd q = yp[i];
+        r.x = fma(gamma, q.x, r.x);
+        r.y = fma(gamma, q.y, r.y);
+    }
+    out[i] = r;
+}
+
+void launch_cheb_step(cd* out, const cd* ay, const cd* y, const cd* yp, int64_t n, double alpha,
+                      double beta, double gamma, hipStream_t st) {
+    hipLaunchKernelGGL(k_cheb_step, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, out, ay, y,
+                       yp, n, alpha, beta, gamma);
+    OSA_LAUNCH_CHECK();
+}
+
+// Chebyshev-filtered subspace iteration for the nev eigenvalues of A = H^2 of
+// smallest modulus (A = H(mu)^2, or H(-mu)^2 for the left vectors), an
+// alternative to Krylov-Schur for the search of the critical eigenpairs.  A
+// block of s orthonormal vectors is replaced each iteration by p(A) X, where p
+// is the degree-deg Chebyshev polynomial of the first kind mapped from [a, b]
+// to [-1, 1] (so |p| <= 1 on the damped part of the spectrum and grows fast
+// below a), in the three-term recurrence scaled so that p(0) stays of order
+// one.  The filtered block is orthonormalised (CGS2, column by column) and
+// rotated by the Schur vectors of its Rayleigh quotient X^H A X, smallest
+// |theta| first.  b = 1.01 hnorm_bound^2 bounds |lambda(A)|; a is the largest
+// |theta| of the block, which for Hermitian A is at least the s-th smallest
+// eigenvalue (Courant-Fischer), so the wanted ones stay below it.  Converged
+// when the Schur residuals |A x_i - X t_i| of the first nev columns are all at
+// most tol * b; the output is then those nev columns, an orthonormal basis of
+// the wanted invariant subspace, as from ks_run.  Returns false if max_it
+// iterations do not converge.
+constexpr int kFilterMaxIt = 80;   // iterations before falling back to Krylov-Schur
+
+bool chfsi_run(osa_ctx* c, bool adjoint, int nev, int s, int deg, double tol, int max_it,
+               uint64_t seed, cd* Xout, KsStats& stats) {
+    const int64_t N = c->N();
+    ensure_exec(c, 2 * s + 2);
+    const size_t blk = sizeof(cd) * (size_t)N * s;
+    DevBuf buf[4], G, T, Z, wr, info, sws, hc, co, hs;
+    for (auto& b : buf) b.ensure(blk);
+    G.ensure(sizeof(cd) * (size_t)s * s);
+    T.ensure(sizeof(cd) * (size_t)s * s);
+    Z.ensure(sizeof(cd) * (size_t)s * s);
+    wr.ensure(sizeof(cd) * s);
+    info.ensure(sizeof(int) * 4);
+    hc.ensure(sizeof(cd) * s);
+    co.ensure(sizeof(cd) * s);
+    hs.ensure(sizeof(cd) * s);
+    if (s > 64) sws.ensure(schur_ws_bytes(s));
+    cd* X = buf[0].as<cd>();    // current orthonormal block
+    cd* Q = buf[1].as<cd>();    // rotated block / recurrence
+    cd* W = buf[2].as<cd>();    // A applied to a block
+    cd* Tm = buf[3].as<cd>();   // H applied to a block, residuals
+    auto col = [&](cd* base, int j) { return base + (size_t)N * j; };
+    const TsPlan pl = ts_plan(N);
+    const int64_t scratch_len = (int64_t)(c->upd_scratch.bytes / sizeof(cd));
+    cd* part = c->partial.as<cd>();
+    const double b = 1.01 * c->hnorm_bound * c->hnorm_bound;
+    auto apply_a = [&](const cd* in, cd* out) {
+        apply_h_contig(c, in, Tm, false, adjoint, s);
+        apply_h_contig(c, Tm, out, false, adjoint, s);
+        stats.matvecs += 2 * s;
+    };
+    auto orthonormalize = [&](cd* Y) {
+        for (int j = 0; j < s; ++j) {
+            if (j > 0) cgs2(c, col(Y, j), Y, N, j, false, hc.as<cd>(), co.as<cd>());
+            else launch_norm_partial(col(Y, 0), false, pl, c->normp.as<double>(), c->st);
+            launch_normalize(col(Y, j), col(Y, j), false, pl, c->normp.as<double>(),
+                             hs.as<cd>(), nullptr, 0.0, nullptr, 0, nullptr, 0, c->st);
+        }
+    };
+    for (int j = 0; j < s; ++j)
+        launch_random_vector(col(X, j), false, c->g, seed + 104729ULL * (uint64_t)j, c->st);
+    orthonormalize(X);
+    std::vector<cd> th(s), thp(s, mk(0.0, 0.0)), rn(nev);
+    for (int it = 0; it <= max_it; ++it) {
+        // Rayleigh quotient G = X^H A X (two columns per pass over X), Schur form
+        apply_a(X, W);
+        for (int j = 0; j < s; j += 2) {
+            int nch = 0;
+            if (j + 1 < s) {
+                timed(c, 0, (s + 2.0) * N * 16.0, [&] {
+                    nch = launch_dot2_partial(X, N, s, col(W, j), col(W, j + 1), false, pl, part,
+                                              c->st);
+                });
+                launch_reduce_partial(part, nch, 2 * s, G.as<cd>() + (size_t)j * s, nullptr,
+                                      nullptr, nullptr, c->st);
+            } else {
+                timed(c, 0, (s + 1.0) * N * 16.0, [&] {
+                    nch = launch_dot_partial(X, N, s, col(W, j), false, pl, part, c->st);
+                });
+                launch_reduce_partial(part, nch, s, G.as<cd>() + (size_t)j * s, nullptr, nullptr,
+                                      nullptr, c->st);
+            }
+        }
+        timed(c, 4, 0.0, [&] {
+            small_schur(G.as<cd>(), s, T.as<cd>(), Z.as<cd>(), wr.as<cd>(), 0, info.as<int>(),
+                        sws.p, c->st);
+        });
+        int hinfo[2] = {0, 0};
+        d2h(c, info.p, 2, hinfo);
+        if (hinfo[0] < 0) return false;
+        if (c->prof_on) {
+            c->prof.counters[0] += hinfo[0];
+            c->prof.counters[1] += hinfo[1];
+        }
+        d2h(c, wr.p, s, th.data());
+        stats.restarts = it;
+        // Schur residuals once the leading |theta| have settled (moduli: members of
+        // a pair of equal modulus may trade places between iterations), and at
+        // least every fourth iteration
+        double dth = 0;
+        for (int i = 0; i < nev; ++i)
+            dth = std::max(dth, std::fabs(cabsd(th[i]) - cabsd(thp[i])) /
+                                    std::max(cabsd(th[i]), 1e-300));
+        thp = th;
+        const bool check = (it > 0 && dth < 1e-7) || it % 4 == 3 || it == max_it;
+        // Schur basis Q = X Z (the filter runs on it: its most amplified columns
+        // come first, which keeps the column-wise orthonormalisation accurate)
+        // and A Q = W Z (into Tm)
+        launch_rotate(X, N, s, Z.as<cd>(), s, s, Q, N, false, N, c->st);
+        launch_rotate(W, N, s, Z.as<cd>(), s, s, Tm, N, false, N, c->st);
+        if (check) {
+            // residuals A q_i - Q t_i of the first nev columns, in W
+            OSA_HIP(hipMemcpyAsync(W, Tm, sizeof(cd) * (size_t)N * nev, hipMemcpyDeviceToDevice,
+                                   c->st));
+            for (int i = 0; i < nev; ++i) {
+                timed(c, 1, (i + 3.0) * N * 16.0, [&] {
+                    launch_update(col(W, i), Q, N, i + 1, T.as<cd>() + (size_t)i * s, false, pl,
+                                  c->normp.as<double>(), c->upd_scratch.as<cd>(), scratch_len,
+                                  c->st);
+                });
+                launch_normalize(col(W, i), nullptr, false, pl, c->normp.as<double>(),
+                                 hs.as<cd>() + i, nullptr, 0.0, nullptr, 0, nullptr, 0, c->st);
+            }
+            d2h(c, hs.p, nev, rn.data());
+            int nc = 0;
+            while (nc < nev && rn[nc].x <= tol * b) ++nc;
+            if (nc >= nev) {
+                OSA_HIP(hipMemcpyAsync(Xout, Q, sizeof(cd) * (size_t)N * nev,
+                                       hipMemcpyDeviceToDevice, c->st));
+                sync(c);
+                stats.converged = true;
+                return true;
+            }
+        }
+        if (it == max_it) break;
+        // filter interval [a, b]: a = the largest |theta| of the block
+        double a = 0;
+        for (int i = 0; i < s; ++i) a = std::max(a, cabsd(th[i]));
+        a = std::min(a, 0.95 * b);
+        const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
+        const double s1 = e / (0.0 - cc);   // scaling at the wanted end, 0
+        // y0 = Q, y1 = (s1/e)(A - cc) y0 (A y0 in Tm),
+        // y_{n+1} = 2(sn/e)(A - cc) y_n - s sn y_{n-1}
+        cd* prev = Q;
+        cd* cur = X;
+        const int64_t nn = N * (int64_t)s;
+        launch_cheb_step(cur, Tm, prev, nullptr, nn, s1 / e, -s1 * cc / e, 0.0, c->st);
+        double sg = s1;
+        for (int n = 2; n <= deg; ++n) {
+            const double sn = 1.0 / (2.0 / s1 - sg);
+            apply_a(cur, W);
+            launch_cheb_step(prev, W, cur, prev, nn, 2.0 * sn / e, -2.0 * sn * cc / e, -sg * sn,
+                             c->st);
+            std::swap(prev, cur);
+            sg = sn;
+        }
+        orthonormalize(cur);
+        if (cur != X) std::swap(buf[0].p, buf[1].p);   // X <- filtered block
+        X = buf[0].as<cd>();
+        Q = buf[1].as<cd>();
+    }
+    sync(c);
+    return false;
+}
+
 // Rayleigh-Ritz with H in span(X): M = X^H H X, Schur form sorted by |Re|,
 // eigenvectors Y; Rv = X Y[:, :m], lam = diag.  Residuals |H r - lam r|.
 void rayleigh_ritz(osa_ctx* c, bool adjoint, int nev, int m, cd* X, cd* Rout,
@@ -1096,6 +1284,11 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
     if ((int64_t)nev + ncv + 1 > dim) ncv = (int)std::max<int64_t>(8, dim - nev - 1);
     if (ncv < nev + 4 || (int64_t)nev + ncv + 1 > dim) throw OsaError{OSA_ERR_ARG};
     const double tol = c->opts.eig_tol > 0 ? c->opts.eig_tol : 1e-12;
+    // FP64 search with eig_filter = d > 0: Chebyshev-filtered subspace iteration of
+    // degree d (block nev + 48 within [64, 96] unless eig_ncv is set)
+    const int filter_deg = c->opts.eig_filter > 0 ? c->opts.eig_filter : 0;
+    int fblock = (ncv_req > 0 || c->opts.eig_ncv > 0) ? ncv : std::min(96, std::max(64, nev + 48));
+    if ((int64_t)fblock > dim) fblock = (int)dim;
     const int maxr = maxr_req > 0 ? maxr_req
                                   : (c->opts.eig_max_restarts > 0 ? c->opts.eig_max_restarts : 2000);
     const bool fp32 = (c->opts.eig_prec == OSA_FP32);
@@ -1132,13 +1325,22 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
             if (!s64.converged)
                 throw OsaError{OSA_ERR_EIG_NOCONV, "fp64 refinement hit the restart cap"};
         } else {
-            KsStats s64;
-            ks_run(e, adj, nev, ncv, false, tol, maxr, nullptr, seed, Xb, s64);
-            sst.matvecs += s64.matvecs;
-            sst.restarts += s64.restarts;
-            if (!s64.converged)
-                throw OsaError{OSA_ERR_EIG_NOCONV, "Krylov-Schur hit the restart cap (" +
-                                                       std::to_string(maxr) + ")"};
+            bool done = false;
+            if (filter_deg > 0) {   // filtered subspace iteration, Krylov-Schur if it fails
+                KsStats sf;
+                done = chfsi_run(e, adj, nev, fblock, filter_deg, tol, kFilterMaxIt, seed, Xb, sf);
+                sst.matvecs += sf.matvecs;
+                sst.restarts += sf.restarts;
+            }
+            if (!done) {
+                KsStats s64;
+                ks_run(e, adj, nev, ncv, false, tol, maxr, nullptr, seed, Xb, s64);
+                sst.matvecs += s64.matvecs;
+                sst.restarts += s64.restarts;
+                if (!s64.converged)
+                    throw OsaError{OSA_ERR_EIG_NOCONV, "Krylov-Schur hit the restart cap (" +
+                                                           std::to_string(maxr) + ")"};
+            }
         }
         sst.matvecs += nev;
         rayleigh_ritz(e, adj, nev, m, Xb, out, lam, res);
@@ -1303,7 +1505,8 @@ osa_status osa_set_opts(osa_ctx* c, const osa_opts* opts) {
     if (opts) o = *opts;
     if (o.k_max < 0 || o.k_max > 4000 || o.eig_ncv < 0 || o.eig_ncv > 96 || o.eig_tol < 0 ||
         o.eig_max_restarts < 0 || (o.eig_prec != OSA_FP64 && o.eig_prec != OSA_FP32) ||
-        o.max_batch < 0 || o.max_batch > 64 || o.orth < 0 || o.orth > 1)
+        o.max_batch < 0 || o.max_batch > 64 || o.orth < 0 || o.orth > 1 || o.eig_filter < 0 ||
+        o.eig_filter > 200)
         return OSA_ERR_ARG;
     fill_defaults(o);
     c->opts = o;
