@@ -462,7 +462,9 @@ __device__ __forceinline__ cd lane_value(cd v, int src) {
 // l in the left update (columns >= col0) and row l in the right updates (T rows
 // <= row1, all rows of Z), which share one pass over LDS.
 // zero_col >= 0: the left update annihilates T[k+1, zero_col]; store an exact 0.
-// Returns this lane's updated T[l, k] (meaningful for l <= row1).
+// Returns this lane's updated T[l, k] (meaningful for l <= row1).  WITH_Z =
+// false leaves Z alone (another wavefront applies the rotation to it).
+template <bool WITH_Z = true>
 __device__ __forceinline__ cd rotate_pair64(cd* T, cd* Z, int p, int ld, int k, cd a, cd b,
                                             int col0, int row1, int zero_col) {
     const int l = threadIdx.x;
@@ -477,14 +479,16 @@ __device__ __forceinline__ cd rotate_pair64(cd* T, cd* Z, int p, int ld, int k, 
     if (l < p) {
         // [x, y] Q = [a x + b y, -conj(b) x + conj(a) y]
         const cd x = T[l + k * ld], y = T[l + (k + 1) * ld];
-        const cd zx = Z[l + k * ld], zy = Z[l + (k + 1) * ld];
         if (l <= row1) {
             tk = cadd(cmul(a, x), cmul(b, y));
             T[l + k * ld] = tk;
             T[l + (k + 1) * ld] = csub(cmulc(a, y), cmulc(b, x));
         }
-        Z[l + k * ld] = cadd(cmul(a, zx), cmul(b, zy));
-        Z[l + (k + 1) * ld] = csub(cmulc(a, zy), cmulc(b, zx));
+        if (WITH_Z) {
+            const cd zx = Z[l + k * ld], zy = Z[l + (k + 1) * ld];
+            Z[l + k * ld] = cadd(cmul(a, zx), cmul(b, zy));
+            Z[l + (k + 1) * ld] = csub(cmulc(a, zy), cmulc(b, zx));
+        }
     }
     wave_sync();
     return tk;
@@ -505,8 +509,14 @@ __global__ __launch_bounds__(64 * kSchurWaves) void k_small_schur(const cd* __re
     __shared__ cd hv[kSchurMax];
     __shared__ cd pt[kSchurWaves][kSchurMax], pz[kSchurWaves][kSchurMax];
     __shared__ double sanorm[kSchurWaves];
+    // rotations of one QR sweep, handed from the first wavefront (T) to the
+    // second (Z), double buffered: (a, b) of rotation lo + i at 2i, 2i + 1
+    __shared__ cd rlog[2][2 * kSchurMax];
+    __shared__ int rsweep[2][2];   // lo, number of rotations
+    __shared__ int qr_done;
     const int l = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) qr_done = 0;
 #define TT(i, j) T[(i) + (j) * ld]
 #define ZZ(i, j) Z[(i) + (j) * ld]
     // The QR iteration is run on B = A^H.  It tends to deflate the eigenvalues of
@@ -597,8 +607,32 @@ __global__ __launch_bounds__(64 * kSchurWaves) void k_small_schur(const cd* __re
             for (int i = l; i < L; i += 64) TT(j + 1 + i, j) = (i == 0) ? alpha : mk(0.0, 0.0);
         __syncthreads();
     }
-    // the QR iteration and everything after it run on the first wavefront
-    if (wv != 0) return;
+    // The QR sweeps run on the first wavefront, which updates T and logs the
+    // rotations of each sweep; the second applies a sweep's rotations to Z while
+    // the first runs the next sweep.  One workgroup barrier per sweep hands a log
+    // over (and waits for the previous one to be applied); a last one, after
+    // qr_done is set, ends the second wavefront.  Everything after the QR
+    // iteration runs on the first wavefront.
+    if (wv >= 2) return;
+    if (wv == 1) {
+        for (int buf = 0;; buf ^= 1) {
+            __syncthreads();
+            if (qr_done) break;
+            const int lo = rsweep[buf][0], n = rsweep[buf][1];
+            if (l < p) {
+                cd zx = ZZ(l, lo);
+                for (int i = 0; i < n; ++i) {
+                    const cd a = rlog[buf][2 * i], b = rlog[buf][2 * i + 1];
+                    const cd zy = ZZ(l, lo + i + 1);
+                    ZZ(l, lo + i) = cadd(cmul(a, zx), cmul(b, zy));
+                    zx = csub(cmulc(a, zy), cmulc(b, zx));
+                }
+                ZZ(l, lo + n) = zx;
+            }
+        }
+        return;
+    }
+    int buf = 0;
     // ---- shifted QR
     const double ulp = 2.220446049250313e-16;
     const double smlnum = 1e-300;
@@ -656,14 +690,27 @@ __global__ __launch_bounds__(64 * kSchurWaves) void k_small_schur(const cd* __re
             unit_pair(f, g, a, b);
             const int col0 = (k == lo) ? lo : k - 1;
             const int row1 = (k + 2 < hi) ? k + 2 : hi;
-            const cd tk = rotate_pair64(T, Z, p, ld, k, a, b, col0, row1, (k > lo) ? k - 1 : -1);
+            const cd tk =
+                rotate_pair64<false>(T, Z, p, ld, k, a, b, col0, row1, (k > lo) ? k - 1 : -1);
+            if (l == 0) {
+                rlog[buf][2 * (k - lo)] = a;
+                rlog[buf][2 * (k - lo) + 1] = b;
+            }
             ++nrot;
             if (k + 1 < hi) {
                 f = lane_value(tk, k + 1);
                 g = lane_value(tk, k + 2);
             }
         }
+        if (l == 0) {
+            rsweep[buf][0] = lo;
+            rsweep[buf][1] = hi - lo;
+        }
+        __syncthreads();   // hand the sweep to the Z wavefront
+        buf ^= 1;
     }
+    if (l == 0) qr_done = 1;
+    __syncthreads();       // the Z wavefront has applied every sweep and leaves
     // ---- back to A: T <- J T^H J (pairs (i, j) <-> (p-1-j, p-1-i)), Z <- Z J
     if (!fail) {
         for (int e = l; e < p * p; e += 64) {
