@@ -474,7 +474,11 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
             if (hflag[i] || !std::isfinite(d2) || !std::isfinite(n2)) { iters[b] = -it; continue; }
             const double change = std::sqrt(d2 / n2);
             if (change < 1e-2) scale &= ~(1ULL << b);
-            if (change < 1e-14 || (change < 1e-8 && change > 0.5 * prev[b])) {
+            // converged: at rounding level, stagnating below 1e-8, or below 1e-8 in
+            // the quadratic regime (change <= 10 prev^2), where the new iterate's
+            // error is about change^2 and one more step would only confirm it
+            if (change < 1e-14 || (change < 1e-8 && change > 0.5 * prev[b]) ||
+                (change < 1e-8 && change <= 10.0 * prev[b] * prev[b])) {
                 ok[b] = 1;
                 continue;
             }
