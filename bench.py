@@ -40,16 +40,19 @@ DOT_SOURCE = os.path.join(ROOT, "paper_0710_0341_amd", "csrc", "blas.hip")
 def measured_traffic():
     """HBM bytes per launch of the Gram-Schmidt dot class, from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by the copy-kernel factors it
-    records).  None once the kernels' source differs from the one measured."""
+    records).  None once the source of the dot kernels and their launch plan (the
+    region of blas.hip the summary records) differs from the one measured."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        with open(DOT_SOURCE, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, ValueError):
+        with open(DOT_SOURCE) as f:
+            src = f.read()
+        reg = rec["kernel_region"]
+        a, b = src.index(reg["from"]), src.index(reg["to"])
+    except (OSError, ValueError, KeyError):
         return None
-    if rec.get("kernel_source_sha256") != sha:
+    if hashlib.sha256(src[a:b].encode()).hexdigest() != reg["sha256"]:
         return None
     return rec.get("hbm_bytes_per_launch")
 
