@@ -15,12 +15,12 @@ namespace osa {
 //   A^{-1}[t, c] = M[perm[t], pinv[c]],   pinv[perm[s]] = s.
 // Each block owns a few whole columns, so reading and writing the pivot row of
 // a column happen inside one block; the next pivot column is handed on from
-// step to step through a double-buffered copy written by its owner.  One
-// launch per pivot: every step needs the whole previous step, and blocked
-// (panel) schedules measured no faster here, their per-step critical path on
-// one compute unit being as long as a launch.
+// step to step through a double-buffered copy written by its owner.  Up to
+// k = kGjPairMax one launch takes two pivots (k_gj_step2) with the arithmetic
+// of two single steps; blocked (panel) schedules measured no faster here, their
+// per-step critical path on one compute unit being as long as a launch.
 struct GjWs {
-    cd* col;        // 2 x k
+    cd* col;        // 2 x 2 x k: two buffer sets of (column t, column t+1)
     double2* piv;   // k: (|value|, index) of the pivot chosen for step t
     int* perm;      // k
     int* pinv;      // k
@@ -28,7 +28,7 @@ struct GjWs {
 };
 
 size_t gj_ws_bytes(int k) {
-    return (size_t)k * (2 * sizeof(cd) + sizeof(double2) + 3 * sizeof(int)) + 256;
+    return (size_t)k * (4 * sizeof(cd) + sizeof(double2) + 3 * sizeof(int)) + 256;
 }
 
 // the workspace of problem pb of a batch (byte stride bt.ws)
@@ -45,7 +45,7 @@ __device__ __forceinline__ GjWs gj_at(GjWs w, const Batch& bt, int pb) {
 static GjWs gj_ws(void* ws, int k) {
     char* p = (char*)ws;
     GjWs w;
-    w.col = (cd*)p;            p += (size_t)2 * k * sizeof(cd);
+    w.col = (cd*)p;            p += (size_t)4 * k * sizeof(cd);
     w.piv = (double2*)p;       p += (size_t)k * sizeof(double2);
     w.perm = (int*)p;          p += (size_t)k * sizeof(int);
     w.pinv = (int*)p;          p += (size_t)k * sizeof(int);
@@ -65,6 +65,7 @@ __device__ __forceinline__ cd gj_sub(cd v, cd f, cd rp) {
 
 static constexpr int kGjThreads = 256;
 static constexpr int kGjCols = 4;
+static constexpr int kGjPairMax = 2048;   // two pivots per launch up to this k (LDS column)
 
 __device__ __forceinline__ void argmax_pair(double& v, int& idx, double ov, int oi) {
     if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
@@ -102,6 +103,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_init(const cd* __restrict__ M
     for (int i = threadIdx.x; i < k; i += kGjThreads) {
         cd v = M[i];
         w.col[i] = v;
+        if (k > 1) w.col[k + i] = M[i + (size_t)k];
         w.used[i] = 0;
         w.perm[i] = i;
         w.pinv[i] = i;
@@ -113,8 +115,8 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_init(const cd* __restrict__ M
     if (threadIdx.x == 0) w.piv[0] = make_double2(ov, (double)oi);
 }
 
-__global__ __launch_bounds__(kGjThreads) void k_gj_step(cd* __restrict__ M, int k, int t, GjWs w,
-                                                       double* logpiv, int* flag, Batch bt) {
+__global__ __launch_bounds__(kGjThreads) void k_gj_step(cd* __restrict__ M, int k, int t, int rb,
+                                                       GjWs w, double* logpiv, int* flag, Batch bt) {
     __shared__ double sv[kGjThreads / 64];
     __shared__ int si[kGjThreads / 64];
     const int pb = bt.idx[blockIdx.y];
@@ -122,8 +124,8 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_step(cd* __restrict__ M, int 
     w = gj_at(w, bt, pb);
     logpiv += pb * bt.small;
     flag += pb * bt.flag;
-    const cd* colc = w.col + (size_t)(t & 1) * k;
-    cd* coln = w.col + (size_t)((t + 1) & 1) * k;
+    const cd* colc = w.col + (size_t)(2 * rb) * k;   // column t, from buffer set rb
+    cd* coln = w.col + (size_t)(2 * (rb ^ 1)) * k;   // column t+1, for the next launch
     // A column of NaNs selects no pivot; keep every index in range and flag it.
     const double pf = w.piv[t].y;
     const bool badp = !(pf >= 0.0 && pf < (double)k);
@@ -169,6 +171,115 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_step(cd* __restrict__ M, int 
     }
 }
 
+// Steps t and t+1 in one launch, with the arithmetic of two k_gj_step
+// launches: every block forms column t+1 after step t (from the buffered
+// columns t and t+1) and the pivot of step t+1, then applies both steps to its
+// columns in one pass over them.  The owners of columns t+2 and t+3 buffer them
+// for the next launch; the owner of column t+2 also picks its pivot.
+__global__ __launch_bounds__(kGjThreads) void k_gj_step2(cd* __restrict__ M, int k, int t, int rb,
+                                                        GjWs w, double* logpiv, int* flag,
+                                                        Batch bt) {
+    extern __shared__ cd c1[];   // column t+1 after step t
+    __shared__ double sv[kGjThreads / 64];
+    __shared__ int si[kGjThreads / 64];
+    __shared__ int sp1;
+    const int pb = bt.idx[blockIdx.y];
+    M += pb * bt.mat;
+    w = gj_at(w, bt, pb);
+    logpiv += pb * bt.small;
+    flag += pb * bt.flag;
+    const cd* colA = w.col + (size_t)(2 * rb) * k;   // column t before step t
+    const cd* colB = colA + k;                        // column t+1 before step t
+    cd* outA = w.col + (size_t)(2 * (rb ^ 1)) * k;    // column t+2 after step t+1
+    cd* outB = outA + k;                              // column t+3 after step t+1
+    const double pf = w.piv[t].y;
+    const bool badp = !(pf >= 0.0 && pf < (double)k);
+    const int p = badp ? t : (int)pf;
+    const cd piv = colA[p];
+    const bool zero = badp || (piv.x == 0.0 && piv.y == 0.0);
+    const cd ipiv = zero ? mk(0.0, 0.0) : cinv(piv);
+    {
+        const cd rp = gj_mul(colB[p], ipiv);
+        double bv = -1.0;
+        int bi = 0x7fffffff;
+        for (int i = threadIdx.x; i < k; i += kGjThreads) {
+            const cd nv = (i == p) ? rp : gj_sub(colB[i], colA[i], rp);
+            c1[i] = nv;
+            if (i != p && !w.used[i]) argmax_pair(bv, bi, cabsd(nv), i);
+        }
+        double ov = 0.0;
+        int oi = 0;
+        block_argmax(bv, bi, sv, si, ov, oi);
+        if (threadIdx.x == 0) {
+            sp1 = oi;
+            if (blockIdx.x == 0) w.piv[t + 1] = make_double2(ov, (double)oi);
+        }
+        __syncthreads();
+    }
+    const int q1 = sp1;
+    const bool badp1 = !(q1 >= 0 && q1 < k);
+    const int p1 = badp1 ? t + 1 : q1;
+    const cd piv1 = c1[p1];
+    const bool zero1 = badp1 || (piv1.x == 0.0 && piv1.y == 0.0);
+    const cd ipiv1 = zero1 ? mk(0.0, 0.0) : cinv(piv1);
+    const int j0 = blockIdx.x * kGjCols;
+    for (int j = j0; j < j0 + kGjCols && j < k; ++j) {
+        // pivot-row values: step t reads row p, step t+1 row p1 after step t
+        const cd r0 = (j == t) ? mk(1.0, 0.0) : M[p + (size_t)j * k];
+        const cd rp0 = gj_mul(r0, ipiv);
+        cd r1 = mk(1.0, 0.0);
+        if (j == t) {
+            if (p1 == p) r1 = ipiv;
+            else { const cd q = gj_mul(colA[p1], ipiv); r1 = mk(-q.x, -q.y); }
+        } else if (j != t + 1) {
+            r1 = (p1 == p) ? rp0 : gj_sub(M[p1 + (size_t)j * k], colA[p1], rp0);
+        }
+        __syncthreads();   // everyone has read rows p and p1 of column j before it is rewritten
+        const cd rp1 = gj_mul(r1, ipiv1);
+        const bool nextA = (j == t + 2), nextB = (j == t + 3);
+        double bv = -1.0;
+        int bi = 0x7fffffff;
+        for (int i = threadIdx.x; i < k; i += kGjThreads) {
+            cd nv;
+            if (j == t + 1) {   // the pivot column of step t+1
+                if (i == p1) nv = ipiv1;
+                else { const cd q = gj_mul(c1[i], ipiv1); nv = mk(-q.x, -q.y); }
+            } else {
+                cd v;   // column j after step t
+                if (j == t) {
+                    if (i == p) v = ipiv;
+                    else { const cd q = gj_mul(colA[i], ipiv); v = mk(-q.x, -q.y); }
+                } else {
+                    v = (i == p) ? rp0 : gj_sub(M[i + (size_t)j * k], colA[i], rp0);
+                }
+                nv = (i == p1) ? rp1 : gj_sub(v, c1[i], rp1);
+            }
+            M[i + (size_t)j * k] = nv;
+            if (nextA) {
+                outA[i] = nv;
+                if (i != p && i != p1 && !w.used[i]) argmax_pair(bv, bi, cabsd(nv), i);
+            }
+            if (nextB) outB[i] = nv;
+        }
+        if (nextA) {
+            double ov;
+            int oi;
+            block_argmax(bv, bi, sv, si, ov, oi);
+            if (threadIdx.x == 0) w.piv[t + 2] = make_double2(ov, (double)oi);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        w.perm[t] = p;
+        w.used[p] = 1;
+        logpiv[t] = zero ? -1e300 : log(cabsd(piv));
+        if (zero || !(piv.x == piv.x) || !(piv.y == piv.y)) *flag = 1;
+        w.perm[t + 1] = p1;
+        w.used[p1] = 1;
+        logpiv[t + 1] = zero1 ? -1e300 : log(cabsd(piv1));
+        if (zero1 || !(piv1.x == piv1.x) || !(piv1.y == piv1.y)) *flag = 1;
+    }
+}
+
 __global__ void k_gj_pinv(int k, GjWs w, Batch bt) {
     w = gj_at(w, bt, bt.idx[blockIdx.y]);
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < k; s += gridDim.x * blockDim.x) {
@@ -199,9 +310,14 @@ void gj_invert(cd* M, cd* Y, int k, double* logpiv, int* flag, void* ws, hipStre
     const unsigned nbt = (unsigned)bt.n;
     hipLaunchKernelGGL(k_gj_init, dim3(nbt), dim3(kGjThreads), 0, st, (const cd*)M, k, w, bt);
     const int nb = (int)ceil_div(k, kGjCols);
-    for (int t = 0; t < k; ++t)
-        hipLaunchKernelGGL(k_gj_step, dim3(nb, nbt), dim3(kGjThreads), 0, st, M, k, t, w, logpiv,
-                           flag, bt);
+    int t = 0, rb = 0;
+    if (k <= kGjPairMax)
+        for (; t + 1 < k; t += 2, rb ^= 1)
+            hipLaunchKernelGGL(k_gj_step2, dim3(nb, nbt), dim3(kGjThreads), sizeof(cd) * (size_t)k,
+                               st, M, k, t, rb, w, logpiv, flag, bt);
+    for (; t < k; ++t, rb ^= 1)
+        hipLaunchKernelGGL(k_gj_step, dim3(nb, nbt), dim3(kGjThreads), 0, st, M, k, t, rb, w,
+                           logpiv, flag, bt);
     hipLaunchKernelGGL(k_gj_pinv, dim3((unsigned)ceil_div(k, 256), nbt), dim3(256), 0, st, k, w,
                        bt);
     if (Y) {
