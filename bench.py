@@ -288,16 +288,32 @@ def batched16(args):
     print(f"dis16: eigensearch {t_eig:.1f} s", file=sys.stderr, flush=True)
     ctx.apply(B[:1], tol=w["tol"])                    # workspace growth, untimed
     torch.cuda.synchronize()
+
+    def classes(prof):
+        """per kernel class: launches, average event-timed duration, algorithmic GB/s"""
+        out = {}
+        for k, v in prof.items():
+            if k == "counters" or not v["launches"]:
+                continue
+            out[k] = {"launches": v["calls"], "avg_us": v["ms"] / v["launches"] * 1e3,
+                      "GB/s": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] else 0.0}
+        return out
+
+    ctx.profile(True, every=PROF_EVERY)
     t0 = time.perf_counter()
     Yb, infb, stb = ctx.apply(B, tol=w["tol"])
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    kb = classes(ctx.profile_read())
     print(f"dis16: batch of 12 {t_batch:.1f} s", file=sys.stderr, flush=True)
     ctx.set_opts(k_max=w["k_max"], check_every=50, eig_prec=osa.FP32, max_batch=1)
+    ctx.profile(True, every=PROF_EVERY)
     t0 = time.perf_counter()
     Yp, infp, stp = ctx.apply(B, tol=w["tol"])
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    kp = classes(ctx.profile_read())
+    ctx.profile(False)
     print(f"dis16: 12 one at a time {t_plain:.1f} s; fp64 eigensearch", file=sys.stderr, flush=True)
     # all-FP64 eigensearch on the same (FP32-rounded) links, first source
     ctx64 = osa.Context(links, dims, w["mu"], w["m_w"], k_max=w["k_max"], check_every=50)
@@ -324,6 +340,9 @@ def batched16(args):
                 "restarts": dinfo["eig_restarts"], "max_eig_resid": dinfo["max_eig_resid"],
                 "min_abs_re_lambda": dinfo["min_abs_re_lambda"], "fp64_search_ms": t_eig64 * 1e3},
         "fp32_search_vs_fp64_search_rel_diff": err,
+        "kernels_batched": kb, "kernels_plain": kp,
+        "profiling": f"HIP events on one launch in {PROF_EVERY} of each class; GB/s from "
+                     "algorithmic bytes (peak 8000)",
     }
     print(json.dumps(out), flush=True)
     ctx.close()
