@@ -187,6 +187,23 @@ OSA_API osa_status osa_set_active_deflation(osa_ctx* ctx, int32_t m);
 OSA_API osa_status osa_apply(osa_ctx* ctx, int32_t nrhs, const void* B, void* Y, double tol,
                      osa_info* infos);
 
+/* Y = sign(H_w(mu))^dag B for nrhs sources, with the same arguments, batching
+ * and statuses as osa_apply.  Since H_w(mu)^dag = H_w(-mu) (the adjoint
+ * identity behind Eq. 20), sign(H)^dag = sign(H(-mu)): the Arnoldi runs on
+ * H(-mu), and the deflation data of H(mu) serves unchanged with the roles of
+ * the left and right eigenvectors exchanged and lambda -> conj(lambda) (the
+ * same signs of Re lambda); the remark on sign(H) and sign(H)^dag in the
+ * results section. */
+OSA_API osa_status osa_apply_adjoint(osa_ctx* ctx, int32_t nrhs, const void* B, void* Y,
+                                     double tol, osa_info* infos);
+
+/* Y = D_ov B = B + gamma_5 sign(H_w(mu)) B, the overlap operator of Eq. 1, for
+ * nrhs sources (gamma_5 = diag(1, 1, -1, -1) in spin, chiral basis).  Same
+ * arguments, batching and statuses as osa_apply; resid_est refers to the sign
+ * part. */
+OSA_API osa_status osa_apply_overlap(osa_ctx* ctx, int32_t nrhs, const void* B, void* Y,
+                                     double tol, osa_info* infos);
+
 /* Uneven batch: n independent contexts (different lattices, mu, m_w and
  * deflation data), one source each, solved concurrently: up to 8 instances at
  * a time, each on a stream of its own that waits for the work already queued

@@ -12,6 +12,7 @@ Everything is plain numpy / scipy in float64 / complex128:
 * ``free_field`` -- closed form of sign(H) b at U = 1 (derived from Eq. 2)
 * ``krylov``     -- Arnoldi + LR deflation, step by step            (Eq. 7, 11, 20-22)
 * ``eigen``      -- critical left/right eigenpairs                  (Eq. 20)
+* ``overlap``    -- D_ov = 1 + gamma_5 sign(H_w) and sign(H)^dag      (Eq. 1)
 """
 from .dirac import (gamma_matrices, kappa_of, wilson_dirac_sparse, hermitian_wilson_sparse,
                     hermitian_wilson_dense, gamma5_diag)
@@ -20,5 +21,6 @@ from .free_field import (free_field_sign_apply, free_field_h_apply, free_field_s
                          free_field_h_of_p)
 from .krylov import arnoldi_cgs2, lr_arnoldi_sign, small_sign_e1, Deflation
 from .eigen import critical_dense, critical_sparse, critical_order, eig_residuals
+from .overlap import overlap_apply, sign_adjoint_apply
 
 __all__ = [n for n in dir() if not n.startswith("_")]

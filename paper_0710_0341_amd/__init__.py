@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "OSA_OK", 1: "OSA_NOT_CONVERGED", -1: "OSA_ERR_ARG", -2: "OSA
 FP64, FP32 = 0, 1
 
 EXPORTS = ["overlap_sign_apply", "osa_create", "osa_deflate", "osa_set_deflation",
-           "osa_get_deflation", "osa_set_active_deflation", "osa_apply", "osa_batch_apply",
+           "osa_get_deflation", "osa_set_active_deflation", "osa_apply", "osa_apply_adjoint",
+           "osa_apply_overlap", "osa_batch_apply",
            "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_small_schur", "osa_set_links",
            "osa_profile_enable", "osa_profile_read", "osa_last_message", "osa_destroy",
            "osa_status_string",
@@ -107,6 +108,8 @@ def lib() -> ctypes.CDLL:
     L.osa_get_deflation.argtypes = [vp, ctypes.POINTER(i32), vp, vp, ctypes.POINTER(dbl)]
     L.osa_set_active_deflation.argtypes = [vp, i32]
     L.osa_apply.argtypes = [vp, i32, vp, vp, dbl, ctypes.POINTER(Info)]
+    L.osa_apply_adjoint.argtypes = [vp, i32, vp, vp, dbl, ctypes.POINTER(Info)]
+    L.osa_apply_overlap.argtypes = [vp, i32, vp, vp, dbl, ctypes.POINTER(Info)]
     L.osa_batch_apply.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   dbl, ctypes.POINTER(Info)]
     L.osa_set_opts.argtypes = [vp, ctypes.POINTER(Opts)]
@@ -288,15 +291,27 @@ class Context:
         """Y = sign(H) B for B of shape (N,) or (nrhs, N).  Returns (Y, infos, status).
         Up to max_batch sources run in lockstep.  check=False returns error
         statuses instead of raising (per-source statuses are in infos)."""
+        return self._apply("osa_apply", B, tol, check)
+
+    def apply_adjoint(self, B, tol=1e-10, check=True):
+        """Y = sign(H)^dag B = sign(H(-mu)) B, with the same deflation data."""
+        return self._apply("osa_apply_adjoint", B, tol, check)
+
+    def apply_overlap(self, B, tol=1e-10, check=True):
+        """Y = D_ov B = B + gamma_5 sign(H) B (the overlap operator)."""
+        return self._apply("osa_apply_overlap", B, tol, check)
+
+    def _apply(self, name, B, tol, check):
         torch = _torch()
         bp = _dev_ptr(B, torch.complex128, "B")
         nrhs = 1 if B.dim() == 1 else int(B.shape[0])
         Y = torch.zeros_like(B)
         self._after_current()
         infos = (Info * nrhs)()
-        st = lib().osa_apply(self._h, nrhs, bp, ctypes.c_void_p(Y.data_ptr()), float(tol), infos)
+        st = getattr(lib(), name)(self._h, nrhs, bp, ctypes.c_void_p(Y.data_ptr()), float(tol),
+                                  infos)
         if check:
-            _check(st, "osa_apply")
+            _check(st, name)
         return Y, [i.as_dict() for i in infos], st
 
     def _after_current(self):

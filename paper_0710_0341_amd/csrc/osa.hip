@@ -139,6 +139,11 @@ struct osa_ctx {
     // deflation data (internal layout, m_alloc vectors each)
     int m_alloc = 0, m_active = 0;
     DevBuf R, L, Ginv, lam_dev, sgnc;
+    // adjoint solves, sign(H(mu))^dag = sign(H(-mu)): the stencil of H(-mu), and
+    // the deflation data with the left and right vectors swapped and G^{-1}
+    // replaced by its conjugate transpose (GinvH)
+    bool adj = false;
+    DevBuf GinvH;
     std::vector<cd> lambda;
     double max_eig_resid = 0, min_abs_re = 0;
     int64_t eig_matvecs = 0;
@@ -388,9 +393,12 @@ void project_out(osa_ctx* c, void* wv, cd* cout, cd* tmp, const Batch& bt) {
     bd.basis = bu.basis = 0;   // L and R are shared
     bd.part = c->part_stride;
     bu.part = 0;
-    const int nch = launch_dot_partial(c->L.p, c->N(), m, wv, false, p, part, c->st, bd);
-    launch_reduce_partial(part, nch, m, cout, nullptr, c->Ginv.as<cd>(), tmp, c->st, bd);
-    launch_update(wv, c->R.p, c->N(), m, cout, false, p, nullptr, c->upd_scratch.as<cd>(),
+    const void* Lp = c->adj ? c->R.p : c->L.p;
+    const void* Rp = c->adj ? c->L.p : c->R.p;
+    const cd* Gi = c->adj ? c->GinvH.as<cd>() : c->Ginv.as<cd>();
+    const int nch = launch_dot_partial(Lp, c->N(), m, wv, false, p, part, c->st, bd);
+    launch_reduce_partial(part, nch, m, cout, nullptr, Gi, tmp, c->st, bd);
+    launch_update(wv, Rp, c->N(), m, cout, false, p, nullptr, c->upd_scratch.as<cd>(),
                   (int64_t)(c->upd_scratch.bytes / sizeof(cd)), c->st, bu);
 }
 
@@ -624,7 +632,7 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
         launch_scale_dev(x, V, false, N, ds + 1, true, c->st, b0);   // v_1 = x_ominus / beta
         if (dcgs) {
             // first column: one pass; u_1 = H v_1 - v_1 h_11 goes to basis column 1
-            apply_h(c, V, w, false, false, b0);
+            apply_h(c, V, w, false, c->adj, b0);
             if (reproj && m > 0) project_out(c, w, ar + L.coef2, ar + L.tmp, b0);
             Batch bd = b0, bu = b0;
             bd.part = c->part_stride;
@@ -655,7 +663,7 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     // form (steps 1 .. kmax) completes size j and starts column j.
     for (int j = dcgs ? 1 : 0; j < (dcgs ? kmax + 1 : kmax) && !act.empty(); ++j) {
         const Batch bt = bat(act);
-        apply_h(c, V + (size_t)j * N, w, false, false, bt);
+        apply_h(c, V + (size_t)j * N, w, false, c->adj, bt);
         if (reproj && m > 0) project_out(c, w, ar + L.coef2, ar + L.tmp, bt);
         if (dcgs) {
             Batch bd = bt;
@@ -780,7 +788,8 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
                                ar + L.coef, bo);
             Batch br = bo;
             br.basis = 0;   // R is shared
-            launch_combine(yout, c->R.p, N, m, ar + L.coef, false, false, N, c->st, br);
+            launch_combine(yout, c->adj ? c->L.p : c->R.p, N, m, ar + L.coef, false, false, N,
+                           c->st, br);
         } else {
             OSA_HIP(hipMemsetAsync(yout, 0, sizeof(cd) * N * nb, c->st));
         }
@@ -1478,6 +1487,123 @@ osa_status guard(F&& f, std::string* msg = nullptr) {
     }
 }
 
+// What an apply call computes from the sign: sign(H) B, sign(H)^dag B, or the
+// overlap operator B + gamma_5 sign(H) B.
+enum class ApplyMode { kSign, kAdjoint, kOverlap };
+
+// GinvH = (G^{-1})^H, m x m column-major
+__global__ void k_conj_transpose(int m, const cd* __restrict__ A, cd* __restrict__ B) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * m) return;
+    const int i = e % m, j = e / m;
+    B[e] = cconj(A[j + (int64_t)i * m]);
+}
+
+// Y = B + gamma_5 Y in the boundary layout (index (site*4 + spin)*3 + color;
+// chiral basis, gamma_5 = diag(1, 1, -1, -1) in spin)
+__global__ void k_overlap_finish(const cd* __restrict__ B, cd* Y, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int spin = (int)((e / 3) % 4);
+    const cd b = B[e], y = Y[e];
+    Y[e] = spin < 2 ? cadd(b, y) : csub(b, y);
+}
+
+osa_status apply_impl(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double tol,
+                      osa_info* infos, ApplyMode mode) {
+    if (!c || nrhs < 1 || !B || !Y) return OSA_ERR_ARG;
+    const bool fixed = c->opts.check_every < 0;
+    if (!fixed && !(tol > 0)) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        struct AdjScope {   // the adjoint flag holds for this call only
+            osa_ctx* c;
+            ~AdjScope() { c->adj = false; }
+        } scope{c};
+        c->adj = (mode == ApplyMode::kAdjoint);
+        if (c->adj && c->m_active > 0) {
+            const int m = c->m_active;
+            c->GinvH.ensure(sizeof(cd) * (size_t)m * m + 16);
+            hipLaunchKernelGGL(k_conj_transpose, dim3((unsigned)ceil_div((int64_t)m * m, 256)),
+                               dim3(256), 0, c->st, m, c->Ginv.as<cd>(), c->GinvH.as<cd>());
+            OSA_LAUNCH_CHECK();
+        }
+        const int64_t N = c->N();
+        const int64_t nbnd = 12LL * c->g.V;
+        const int maxb = std::max(1, std::min(c->opts.max_batch, kMaxBatch));
+        const int gmax = std::min<int>(nrhs, maxb);
+        osa_status first_err = OSA_OK, worst = OSA_OK;
+        // kept in the context: a per-call allocation would make hipFree wait for
+        // the whole device, serialising concurrent contexts
+        DevBuf& xin = c->xio;
+        DevBuf& yint = c->yio;
+        xin.ensure(sizeof(cd) * N * gmax);
+        yint.ensure(sizeof(cd) * N * gmax);
+        std::vector<SolveResult> res;
+        for (int r0 = 0; r0 < nrhs; r0 += maxb) {
+            const int nb = std::min(maxb, nrhs - r0);
+            const double t0 = now_ms();
+            launch_vec_to_internal((const cd*)B + r0 * nbnd, xin.p, false, c->g, nb, c->st);
+            solve_batch(c, nb, xin.as<cd>(), yint.as<cd>(), tol, res);
+            // |y| of each result, for the relative estimate
+            std::vector<int> okp;
+            for (int b = 0; b < nb; ++b)
+                if (res[b].st == OSA_OK || res[b].st == OSA_NOT_CONVERGED) okp.push_back(b);
+            std::vector<cd> yn;
+            if (!okp.empty()) {
+                Batch bt = batch_of(okp);
+                bt.vec = N;
+                bt.part = c->normp_stride;
+                bt.scal = c->lay.stride;
+                const TsPlan p = ts_plan(N);
+                cd* slot = c->arena.as<cd>() + c->lay.ds + 2;
+                launch_norm_partial(yint.p, false, p, c->normp.as<double>(), c->st, bt);
+                launch_normalize(yint.p, nullptr, false, p, c->normp.as<double>(), slot, nullptr,
+                                 0.0, nullptr, 0, nullptr, 0, c->st, bt);
+                for (int b : okp) {
+                    launch_vec_from_internal(yint.as<cd>() + (size_t)b * N, false,
+                                             (cd*)Y + (r0 + b) * nbnd, c->g, 1, c->st);
+                    if (mode == ApplyMode::kOverlap) {
+                        hipLaunchKernelGGL(k_overlap_finish, dim3((unsigned)ceil_div(nbnd, 256)),
+                                           dim3(256), 0, c->st, (const cd*)B + (r0 + b) * nbnd,
+                                           (cd*)Y + (r0 + b) * nbnd, nbnd);
+                        OSA_LAUNCH_CHECK();
+                    }
+                }
+                d2h_strided(c, slot, c->lay.stride * (int64_t)sizeof(cd), 1, okp, yn);
+            }
+            sync(c);
+            const double t1 = now_ms();
+            for (int b = 0; b < nb; ++b) {
+                const SolveResult& sr = res[b];
+                double ynorm = 1.0;
+                for (size_t i = 0; i < okp.size(); ++i)
+                    if (okp[i] == b) ynorm = yn[i].x;
+                if (infos) {
+                    osa_info& in = infos[r0 + b];
+                    std::memset(&in, 0, sizeof(in));
+                    in.resid_est = std::isnan(sr.est) ? sr.est
+                                                      : sr.est * sr.bnorm / std::max(ynorm, 1e-300);
+                    in.k_used = sr.k_used;
+                    in.n_defl = c->m_active;
+                    in.status = sr.st;
+                    in.newton_iters = sr.newton_iters;
+                    in.breakdown = sr.breakdown;
+                    in.min_abs_re_lambda = c->m_active ? c->min_abs_re : NAN;
+                    in.max_eig_resid = c->max_eig_resid;
+                    in.t_init_ms = c->t_init_ms;
+                    in.t_solve_ms = t1 - t0;
+                    in.eig_matvecs = c->eig_matvecs;
+                    in.eig_restarts = c->eig_restarts;
+                    in.batch = nb;
+                }
+                if (sr.st < 0 && first_err == OSA_OK) first_err = sr.st;
+                if (sr.st > worst) worst = sr.st;
+            }
+        }
+        return first_err != OSA_OK ? first_err : worst;
+    });
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -1633,78 +1759,17 @@ osa_status osa_set_active_deflation(osa_ctx* c, int32_t m) {
 
 osa_status osa_apply(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double tol,
                      osa_info* infos) {
-    if (!c || nrhs < 1 || !B || !Y) return OSA_ERR_ARG;
-    const bool fixed = c->opts.check_every < 0;
-    if (!fixed && !(tol > 0)) return OSA_ERR_ARG;
-    return guard([&]() -> osa_status {
-        const int64_t N = c->N();
-        const int64_t nbnd = 12LL * c->g.V;
-        const int maxb = std::max(1, std::min(c->opts.max_batch, kMaxBatch));
-        const int gmax = std::min<int>(nrhs, maxb);
-        osa_status first_err = OSA_OK, worst = OSA_OK;
-        // kept in the context: a per-call allocation would make hipFree wait for
-        // the whole device, serialising concurrent contexts
-        DevBuf& xin = c->xio;
-        DevBuf& yint = c->yio;
-        xin.ensure(sizeof(cd) * N * gmax);
-        yint.ensure(sizeof(cd) * N * gmax);
-        std::vector<SolveResult> res;
-        for (int r0 = 0; r0 < nrhs; r0 += maxb) {
-            const int nb = std::min(maxb, nrhs - r0);
-            const double t0 = now_ms();
-            launch_vec_to_internal((const cd*)B + r0 * nbnd, xin.p, false, c->g, nb, c->st);
-            solve_batch(c, nb, xin.as<cd>(), yint.as<cd>(), tol, res);
-            // |y| of each result, for the relative estimate
-            std::vector<int> okp;
-            for (int b = 0; b < nb; ++b)
-                if (res[b].st == OSA_OK || res[b].st == OSA_NOT_CONVERGED) okp.push_back(b);
-            std::vector<cd> yn;
-            if (!okp.empty()) {
-                Batch bt = batch_of(okp);
-                bt.vec = N;
-                bt.part = c->normp_stride;
-                bt.scal = c->lay.stride;
-                const TsPlan p = ts_plan(N);
-                cd* slot = c->arena.as<cd>() + c->lay.ds + 2;
-                launch_norm_partial(yint.p, false, p, c->normp.as<double>(), c->st, bt);
-                launch_normalize(yint.p, nullptr, false, p, c->normp.as<double>(), slot, nullptr,
-                                 0.0, nullptr, 0, nullptr, 0, c->st, bt);
-                for (int b : okp)
-                    launch_vec_from_internal(yint.as<cd>() + (size_t)b * N, false,
-                                             (cd*)Y + (r0 + b) * nbnd, c->g, 1, c->st);
-                d2h_strided(c, slot, c->lay.stride * (int64_t)sizeof(cd), 1, okp, yn);
-            }
-            sync(c);
-            const double t1 = now_ms();
-            for (int b = 0; b < nb; ++b) {
-                const SolveResult& sr = res[b];
-                double ynorm = 1.0;
-                for (size_t i = 0; i < okp.size(); ++i)
-                    if (okp[i] == b) ynorm = yn[i].x;
-                if (infos) {
-                    osa_info& in = infos[r0 + b];
-                    std::memset(&in, 0, sizeof(in));
-                    in.resid_est = std::isnan(sr.est) ? sr.est
-                                                      : sr.est * sr.bnorm / std::max(ynorm, 1e-300);
-                    in.k_used = sr.k_used;
-                    in.n_defl = c->m_active;
-                    in.status = sr.st;
-                    in.newton_iters = sr.newton_iters;
-                    in.breakdown = sr.breakdown;
-                    in.min_abs_re_lambda = c->m_active ? c->min_abs_re : NAN;
-                    in.max_eig_resid = c->max_eig_resid;
-                    in.t_init_ms = c->t_init_ms;
-                    in.t_solve_ms = t1 - t0;
-                    in.eig_matvecs = c->eig_matvecs;
-                    in.eig_restarts = c->eig_restarts;
-                    in.batch = nb;
-                }
-                if (sr.st < 0 && first_err == OSA_OK) first_err = sr.st;
-                if (sr.st > worst) worst = sr.st;
-            }
-        }
-        return first_err != OSA_OK ? first_err : worst;
-    });
+    return apply_impl(c, nrhs, B, Y, tol, infos, ApplyMode::kSign);
+}
+
+osa_status osa_apply_adjoint(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double tol,
+                             osa_info* infos) {
+    return apply_impl(c, nrhs, B, Y, tol, infos, ApplyMode::kAdjoint);
+}
+
+osa_status osa_apply_overlap(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double tol,
+                             osa_info* infos) {
+    return apply_impl(c, nrhs, B, Y, tol, infos, ApplyMode::kOverlap);
 }
 
 osa_status osa_batch_apply(int32_t n, osa_ctx* const* ctxs, const void* const* B, void* const* Y,

@@ -477,3 +477,35 @@ def test_uneven_batch_matches_single_and_dense(osa):
     assert e.value.status == -1
     for c in ctxs:
         c.close()
+
+
+# -------------------------------------------------- adjoint and overlap operator
+def test_adjoint_and_overlap_match_oracle(osa, haar4_dense):
+    """osa_apply_adjoint reuses the deflation data of H(mu) for sign(H)^dag =
+    sign(H(-mu)) (left and right vectors swapped, lambda -> conj lambda);
+    osa_apply_overlap returns b + gamma_5 sign(H) b (Eq. 1)."""
+    dims, links, b, h, yref = haar4_dense
+    say("adjoint and overlap, haar4, m = 10 and m = 0")
+    rng = np.random.default_rng(21)
+    a = rng.standard_normal(b.shape) + 1j * rng.standard_normal(b.shape)
+    a /= np.linalg.norm(a)
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=500, check_every=25)
+    ctx.deflate(10)
+    ref_adj = O.sign_adjoint_apply(h, a)
+    ya, ia, st = ctx.apply_adjoint(dev(a), tol=1e-11)
+    assert st == osa.OSA_OK and rel(host(ya), ref_adj) < 1e-9
+    yo, io, st = ctx.apply_overlap(dev(b), tol=1e-11)
+    assert st == osa.OSA_OK and rel(host(yo), O.overlap_apply(h, b)) < 1e-9
+    # the adjoint identity on the GPU results: <a, sign(H) b> = <sign(H)^dag a, b>
+    ys, _, _ = ctx.apply(dev(b), tol=1e-11)
+    lhs, rhs = np.vdot(a, host(ys)), np.vdot(host(ya), b)
+    assert abs(lhs - rhs) < 1e-9 * abs(lhs)
+    # a batch of adjoint solves is bitwise the single-source result
+    A2 = np.stack([a, b])
+    Y2, _, st = ctx.apply_adjoint(dev(A2), tol=1e-11)
+    assert st == osa.OSA_OK and np.array_equal(host(Y2)[0], host(ya))
+    # without deflation
+    ctx.set_active_deflation(0)
+    ya0, _, st = ctx.apply_adjoint(dev(a), tol=1e-10)
+    assert st == osa.OSA_OK and rel(host(ya0), ref_adj) < 1e-8
+    ctx.close()

@@ -330,3 +330,48 @@ def test_planted_dropped_diagonal_is_caught(monkeypatch):
     h = O.hermitian_wilson_sparse(u, dims, mu, -1.5)
     monkeypatch.undo()
     assert rel(h @ b, O.free_field_h_apply(dims, mu, -1.5, b)) > 1e-3
+
+
+# ------------------------------------------------- overlap operator and adjoint
+def _tiny(mu):
+    dims = (2, 2, 2, 2)
+    links = LI.make_links(dims, "haar", cfg=7, inst=3)
+    return dims, links, O.hermitian_wilson_dense(links, dims, mu, -1.5)
+
+
+def _as_matrix(apply, n):
+    return apply(np.eye(n, dtype=complex))
+
+
+def test_adjoint_sign_is_the_adjoint():
+    """<a, sign(H) b> = <sign(H)^dag a, b>, sign(H)^dag from an eigendecomposition of
+    H^dag independent of the one of H; and H(mu)^dag = H(-mu) gives the same vector."""
+    dims, links, h = _tiny(0.4)
+    rng = np.random.default_rng(11)
+    n = h.shape[0]
+    a = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    lhs = np.vdot(a, O.sign_eig_apply(h, b))
+    rhs = np.vdot(O.sign_adjoint_apply(h, a), b)
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+    h_minus = O.hermitian_wilson_dense(links, dims, -0.4, -1.5)
+    assert rel(O.sign_adjoint_apply(h, a), O.sign_eig_apply(h_minus, a)) < 1e-11
+
+
+def test_overlap_ginsparg_wilson_circle_and_gamma5_hermiticity():
+    """At mu = 0 sign(H) is Hermitian and unitary, so the spectrum of D_ov lies on
+    |z - 1| = 1; at any mu, D_ov(mu)^dag = gamma_5 D_ov(-mu) gamma_5."""
+    dims, links, h0 = _tiny(0.0)
+    n = h0.shape[0]
+    d0 = _as_matrix(lambda x: O.overlap_apply(h0, x), n)
+    ev = np.linalg.eigvals(d0)
+    assert np.max(np.abs(np.abs(ev - 1.0) - 1.0)) < 1e-10
+    _, _, hp = _tiny(0.3)
+    _, _, hm = _tiny(-0.3)
+    dp = _as_matrix(lambda x: O.overlap_apply(hp, x), n)
+    dm = _as_matrix(lambda x: O.overlap_apply(hm, x), n)
+    g5 = np.diag(OD.gamma5_diag(n // 12))
+    assert np.abs(dp.conj().T - g5 @ dm @ g5).max() < 1e-10
+    # (gamma_5 (D_ov - 1))^2 = sign(H)^2 = 1 (the property after Eq. 6)
+    q = g5 @ (dp - np.eye(n))
+    assert np.abs(q @ q - np.eye(n)).max() < 1e-9
