@@ -66,9 +66,11 @@ def parse():
     ap.add_argument("--eig-prec", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--eig-ncv", type=int, default=0,
                     help="eigensolver active block (0: the library default)")
-    ap.add_argument("--workload", choices=["dis8", "haar4", "uneven64", "dis16"], default="dis8",
+    ap.add_argument("--workload", choices=["dis8", "haar4", "uneven64", "dis16", "fig1"],
+                    default="dis8",
                     help="uneven64: 64 independent instances (6^4/8^4/10^4), solved "
-                         "concurrently; dis16: 16^4, 12 point sources in one lockstep batch")
+                         "concurrently; dis16: 16^4, 12 point sources in one lockstep batch; "
+                         "fig1: the error-vs-Krylov-size study of the results section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--solve-only", action="store_true",
@@ -349,6 +351,66 @@ def batched16(args):
     ctx64.close()
 
 
+FIG1_LATTICES = [((4, 4, 4, 4), [0, 5, 10, 15, 25]), ((6, 6, 6, 6), [0, 12, 24, 36, 48])]
+FIG1_KS = list(range(25, 801, 25))
+
+
+def fig1_study(args):
+    """The convergence study of the results section (Fig. 1): relative error of
+    the LR-deflated approximation (Eq. 22) against the Krylov size k, for several
+    deflation sizes m, at mu = 0.3 with the source x = (1, ..., 1) on 4^4 and 6^4
+    lattices.  Synthetic links (m_w = -1.5) stand in for the paper's gauge
+    configurations: Haar-random links, and disordered links (eps = 0.6) whose
+    spectrum has fewer eigenvalues near the imaginary axis.  Each point is one fixed-k solve (no convergence check); the
+    reference y is the converged solve with the largest m at tol 1e-12.  The m
+    values cover the paper's m ~ 0.008 N at 4^4; at 6^4 the eigensolver's limit
+    of 48 pairs reaches 0.003 N."""
+    import torch
+
+    import lattice_inputs as LI
+    import paper_0710_0341_amd as osa
+    mu, m_w, eps_target = 0.3, -1.5, 1e-8
+    out = {}
+    t_all = time.perf_counter()
+    for (dims, ms), (kind, leps) in [(a, b) for b in (("haar", 0.0), ("disordered", 0.6))
+                                     for a in FIG1_LATTICES]:
+        N = 12 * int(np.prod(dims))
+        tag = kind + "_" + "x".join(str(d) for d in dims)
+        links = torch.from_numpy(LI.make_links(dims, kind, eps=leps, cfg=5, inst=0)).to("cuda:0")
+        x = torch.from_numpy(LI.ones_source(dims)).to("cuda:0")
+        ctx = osa.Context(links, dims, mu, m_w, k_max=1500, check_every=25)
+        dinfo = ctx.deflate(max(ms))
+        yref, info, st = ctx.apply(x, tol=1e-12, check=False)
+        print(f"fig1 {tag}: m={max(ms)} eigensearch {dinfo['t_init_ms'] / 1e3:.1f} s, reference "
+              f"k={info[0]['k_used']} est={info[0]['resid_est']:.1e} status={st}",
+              file=sys.stderr, flush=True)
+        nref = torch.linalg.vector_norm(yref).item()
+        curves = {}
+        for m in ms:
+            ctx.set_active_deflation(m)
+            errs = []
+            for k in FIG1_KS:
+                ctx.set_opts(k_max=k, check_every=-1)
+                y, inf, st = ctx.apply(x, tol=1e-12, check=False)
+                err = torch.linalg.vector_norm(y - yref).item() / nref if st >= 0 else float("nan")
+                errs.append(err)
+            curves[m] = errs
+            hit = [k for k, e in zip(FIG1_KS, errs) if e <= eps_target]
+            print(f"fig1 {tag}: m={m} ({m / N:.4f} N) eps(k={FIG1_KS[-1]})={errs[-1]:.1e} "
+                  f"k(1e-8)={hit[0] if hit else None}", file=sys.stderr, flush=True)
+            ctx.set_opts(k_max=1500, check_every=25)
+        ctx.close()
+        out[tag] = {"N": N, "m": ms, "k": FIG1_KS,
+                    "eps": {str(m): [float("%.3e" % e) for e in curves[m]] for m in ms},
+                    "k_at_1e-8": {str(m): next((k for k, e in zip(FIG1_KS, curves[m])
+                                                if e <= eps_target), None) for m in ms},
+                    "reference": {"m": max(ms), "k": info[0]["k_used"],
+                                  "resid_est": info[0]["resid_est"]}}
+    print(json.dumps({"study": "fig1_eps_vs_k", "mu": mu, "m_w": m_w, "links": "synthetic",
+                      "source": "ones", "eps_target": eps_target,
+                      "seconds": round(time.perf_counter() - t_all, 1), "lattices": out}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -363,6 +425,9 @@ def main():
         return
     if args.workload == "dis16":
         batched16(args)
+        return
+    if args.workload == "fig1":
+        fig1_study(args)
         return
     import torch
 

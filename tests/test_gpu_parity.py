@@ -509,3 +509,31 @@ def test_adjoint_and_overlap_match_oracle(osa, haar4_dense):
     ya0, _, st = ctx.apply_adjoint(dev(a), tol=1e-10)
     assert st == osa.OSA_OK and rel(host(ya0), ref_adj) < 1e-8
     ctx.close()
+
+
+# -------------------------------------------------- Fig. 1 convergence trends
+def test_fig1_trends_haar4(osa, haar4_dense):
+    """The results section's study at 4^4, mu = 0.3, x = (1, ..., 1): the error of
+    fixed-k GPU solves against the dense sign falls with the Krylov size k and with
+    the number m of deflated pairs (LR deflation)."""
+    dims, links, _, h, _ = haar4_dense
+    say("fig1 trends 4^4: dense sign of the ones source")
+    x = LI.ones_source(dims)
+    yx = O.sign_eig_apply(h, x)
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=400, check_every=25)
+    ctx.deflate(25)
+    ks, ms = (50, 100, 200, 300), (0, 10, 25)
+    eps = {}
+    for m in ms:
+        ctx.set_active_deflation(m)
+        for k in ks:
+            ctx.set_opts(k_max=k, check_every=-1)
+            y, _, st = ctx.apply(dev(x), tol=1e-12)
+            eps[m, k] = rel(host(y), yx)
+    say("  " + "  ".join(f"m={m},k={k}:{e:.1e}" for (m, k), e in eps.items()))
+    for m in ms:
+        assert eps[m, 300] < eps[m, 100] < eps[m, 50]
+    for k in (100, 200, 300):
+        assert eps[25, k] < eps[10, k] < eps[0, k]
+    assert eps[25, 300] < 1e-9 and eps[0, 300] > 10 * eps[25, 300]
+    ctx.close()
