@@ -13,6 +13,7 @@ Everything is plain numpy / scipy in float64 / complex128:
 * ``krylov``     -- Arnoldi + LR deflation, step by step            (Eq. 7, 11, 20-22)
 * ``eigen``      -- critical left/right eigenpairs                  (Eq. 20)
 * ``overlap``    -- D_ov = 1 + gamma_5 sign(H_w) and sign(H)^dag      (Eq. 1)
+* ``schur``      -- Arnoldi with Schur deflation, Sylvester coupling    (Eq. 13-19)
 """
 from .dirac import (gamma_matrices, kappa_of, wilson_dirac_sparse, hermitian_wilson_sparse,
                     hermitian_wilson_dense, gamma5_diag)
@@ -22,5 +23,6 @@ from .free_field import (free_field_sign_apply, free_field_h_apply, free_field_s
 from .krylov import arnoldi_cgs2, lr_arnoldi_sign, small_sign_e1, Deflation
 from .eigen import critical_dense, critical_sparse, critical_order, eig_residuals
 from .overlap import overlap_apply, sign_adjoint_apply
+from .schur import schur_basis, schur_arnoldi, schur_arnoldi_sign, coupling_y
 
 __all__ = [n for n in dir() if not n.startswith("_")]

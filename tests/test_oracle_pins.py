@@ -375,3 +375,98 @@ def test_overlap_ginsparg_wilson_circle_and_gamma5_hermiticity():
     # (gamma_5 (D_ov - 1))^2 = sign(H)^2 = 1 (the property after Eq. 6)
     q = g5 @ (dp - np.eye(n))
     assert np.abs(q @ q - np.eye(n)).max() < 1e-9
+
+
+# ------------------------------------------------------------ Schur deflation
+def test_schur_basis_relation(haar3):
+    """Eq. 13: S_m orthonormal, A S_m = S_m T_m, T_m upper triangular with the
+    critical eigenvalues on its diagonal; it agrees with scipy's sorted complex
+    Schur form up to a unitary diagonal (its eigenvalues are distinct)."""
+    dims, u, h, b, y = haar3
+    r, l, lam = O.critical_dense(h, 10)
+    s, t = O.schur_basis(r, lambda x: h @ x)
+    assert np.abs(s.conj().T @ s - np.eye(10)).max() < 1e-12
+    assert np.abs(h @ s - s @ t).max() < 1e-11
+    assert np.abs(np.tril(t, -1)).max() < 1e-11
+    assert np.abs(np.diag(t) - lam).max() < 1e-11
+    # the same invariant subspace from an independent Schur factorisation of A
+    thr = np.max(np.abs(lam.real))
+    ts, zs, sdim = sla.schur(h, output="complex", sort=lambda z: abs(z.real) <= thr + 1e-13)
+    assert sdim == 10
+    zs = zs[:, :10]
+    assert np.abs(zs @ (zs.conj().T @ s) - s).max() < 1e-10
+
+
+def test_schur_full_space_is_exact(haar2):
+    """With the Krylov space filling the orthogonal complement (k = N - m) the
+    Eq. 19 approximation is sign(A) b to rounding, for several m."""
+    dims, u, h = haar2
+    rng = np.random.default_rng(5)
+    n = h.shape[0]
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    yx = O.sign_eig_apply(h, b)
+    for m in (0, 4, 12):
+        r = O.critical_dense(h, m)[0] if m else np.zeros((n, 0), complex)
+        s, t = O.schur_basis(r, lambda x: h @ x)
+        y, info = O.schur_arnoldi_sign(lambda x: h @ x, b, s, t, k=n - m)
+        assert rel(y, yx) < 1e-9, m
+
+
+def test_schur_block_sign_and_sylvester(haar3):
+    """Eq. 17-18: the sign of the block matrix H = [[T, X], [0, H_k]], taken whole
+    by its eigendecomposition, has f(T), Y and f(H_k) as its blocks."""
+    dims, u, h, b, y = haar3
+    r = O.critical_dense(h, 8)[0]
+    s, t = O.schur_basis(r, lambda x: h @ x)
+    yk, info = O.schur_arnoldi_sign(lambda x: h @ x, b, s, t, k=40)
+    k = info["k_used"]
+    big = np.block([[t, info["x"]], [np.zeros((k, 8)), info["hk"][:k, :k]]])
+    fb = O.sign_eig(big)
+    assert np.abs(fb[:8, :8] - info["fT"]).max() < 1e-9
+    assert np.abs(fb[8:, 8:] - info["fH"]).max() < 1e-9
+    assert np.abs(fb[:8, 8:] - info["y_coupling"]).max() < 1e-9
+    assert np.abs(fb[8:, :8]).max() < 1e-12
+    # the Arnoldi relation of Eq. 14 with the composite basis
+    vmat, hm, xm, beta, c0, kd = O.schur_arnoldi(lambda x: h @ x, b, s, 40)
+    q = np.concatenate([s, vmat[:, :kd]], axis=1)
+    hq = np.block([[t, xm], [np.zeros((kd, 8)), hm[:kd, :kd]]])
+    resid = h @ q - q @ hq
+    resid[:, -1] -= hm[kd, kd - 1] * vmat[:, kd]
+    assert np.abs(resid).max() < 1e-11
+    assert np.abs(q.conj().T @ q - np.eye(8 + kd)).max() < 1e-12
+
+
+def test_schur_basis_invariance_and_special_cases(haar3):
+    """Eq. 19 depends on Omega_m, not on the basis: S -> S W, T -> W^dag T W with W
+    unitary (T no longer triangular) gives the same vector.  m = 0 reduces to the
+    plain Arnoldi approximation; a source inside Omega_m is mapped exactly."""
+    dims, u, h, b, y = haar3
+    mv = lambda x: h @ x  # noqa: E731
+    r, l, lam = O.critical_dense(h, 8)
+    s, t = O.schur_basis(r, mv)
+    y1, _ = O.schur_arnoldi_sign(mv, b, s, t, k=50)
+    w, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((8, 8))
+                        + 1j * np.random.default_rng(4).standard_normal((8, 8)))
+    y2, _ = O.schur_arnoldi_sign(mv, b, s @ w, w.conj().T @ t @ w, k=50)
+    assert rel(y2, y1) < 1e-10
+    n = h.shape[0]
+    y0, _ = O.schur_arnoldi_sign(mv, b, np.zeros((n, 0), complex), np.zeros((0, 0)), k=50)
+    assert rel(y0, O.lr_arnoldi_sign(mv, b, None, k=50)[0]) < 1e-11
+    xin = r @ np.arange(1, 9)
+    yin, info = O.schur_arnoldi_sign(mv, xin, s, t, k=10)
+    assert info["k_used"] == 0 and rel(yin, O.sign_eig_apply(h, xin)) < 1e-10
+
+
+def test_schur_accuracy_close_to_lr(haar3):
+    """Results section: Schur deflation is about as accurate as LR deflation at
+    equal (m, k); both improve on no deflation."""
+    dims, u, h, b, y = haar3
+    mv = lambda x: h @ x  # noqa: E731
+    r, l, lam = O.critical_dense(h, 16)
+    s, t = O.schur_basis(r, mv)
+    for k in (60, 120):
+        es = rel(O.schur_arnoldi_sign(mv, b, s, t, k=k)[0], y)
+        el = rel(O.lr_arnoldi_sign(mv, b, O.Deflation(r, l, lam), k=k)[0], y)
+        e0 = rel(O.lr_arnoldi_sign(mv, b, None, k=k)[0], y)
+        assert es < e0 and el < e0
+        assert 0.1 < es / el < 10.0, (k, es, el)
