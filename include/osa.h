@@ -100,6 +100,17 @@ typedef struct {
                                    eig_ncv vectors (default nev + 48 within [64, 96]);
                                    Krylov-Schur takes over if 80 filter iterations do not
                                    converge.  The FP32 search always uses Krylov-Schur     */
+    int32_t deflation;          /* deflation scheme of the solve:
+                                   0 (default): LR deflation (Eq. 20-22) with the left and
+                                   right critical eigenvectors;
+                                   1: Schur deflation (Eq. 13-19): right eigenvectors only
+                                   (osa_deflate then skips the left ones), an orthonormal
+                                   Schur basis S_m with A S_m = S_m T_m, Arnoldi vectors
+                                   orthogonalised against S_m as well (plain CGS2, orth is
+                                   ignored) and the coupling block Y of Eq. 17 taken from the
+                                   sign of the block matrix of Eq. 15.  Data from a Schur-mode
+                                   osa_deflate serves only Schur-mode solves: an LR solve or
+                                   osa_apply_adjoint on it returns OSA_ERR_STATE            */
 } osa_opts;
 
 /* Per-solve diagnostics (host struct). */
@@ -155,6 +166,8 @@ OSA_API osa_status osa_create(osa_ctx** out, const osa_lattice* lat, const void*
  * H_w(mu) and left ones as right eigenvectors of H_w(-mu) = H_w(mu)^dag, by
  * Krylov-Schur on H^2 followed by a Rayleigh-Ritz step with H; selects the
  * n_defl eigenvalues of smallest |Re lambda| among the converged ones.
+ * With opts.deflation = 1 (Schur deflation) only the right eigenvectors are
+ * computed: the paper's remark that Schur deflation halves the set-up cost.
  * info (host, may be NULL) receives eigensolver statistics.
  * Errors: OSA_ERR_EIG_NOCONV, OSA_ERR_IMAG_AXIS (|Re lambda| < 1e-12 |H|). */
 OSA_API osa_status osa_deflate(osa_ctx* ctx, int32_t n_defl, osa_info* info);
@@ -162,12 +175,15 @@ OSA_API osa_status osa_deflate(osa_ctx* ctx, int32_t n_defl, osa_info* info);
 /* Import deflation data: R, L are m vectors each (m*N complex128, vector j at
  * offset j*N, boundary layout); lambda (host) holds m complex128 values
  * (re, im interleaved).  Only the projector R (L^dag R)^{-1} L^dag and the
- * eigenvalues matter; scale and phase of the vectors are free. */
+ * eigenvalues matter; scale and phase of the vectors are free.  Under Schur
+ * deflation (opts.deflation = 1) L may be NULL: only span(R) is used. */
 OSA_API osa_status osa_set_deflation(osa_ctx* ctx, int32_t m, const void* R, const void* L,
                              const double* lambda);
 
 /* Export the current deflation data in the same layout (buffers of m*N
- * complex128; lambda (host) 2m doubles).  m_out (host) receives m. */
+ * complex128; lambda (host) 2m doubles).  m_out (host) receives m.  L must
+ * be NULL when the data holds no left vectors (a Schur-mode deflation):
+ * OSA_ERR_STATE otherwise. */
 OSA_API osa_status osa_get_deflation(const osa_ctx* ctx, int32_t* m_out, void* R, void* L,
                              double* lambda);
 

@@ -24,10 +24,12 @@ LIB_PATH = os.path.join(HERE, "libosa.so")
 
 OSA_OK = 0
 OSA_NOT_CONVERGED = 1
+OSA_ERR_STATE = -8
 STATUS_NAMES = {0: "OSA_OK", 1: "OSA_NOT_CONVERGED", -1: "OSA_ERR_ARG", -2: "OSA_ERR_HIP",
                 -3: "OSA_ERR_OOM", -4: "OSA_ERR_NONFINITE", -5: "OSA_ERR_IMAG_AXIS",
                 -6: "OSA_ERR_EIG_NOCONV", -7: "OSA_ERR_NEWTON_NOCONV", -8: "OSA_ERR_STATE"}
 FP64, FP32 = 0, 1
+LR, SCHUR = 0, 1   # osa_opts.deflation
 
 EXPORTS = ["overlap_sign_apply", "osa_create", "osa_deflate", "osa_set_deflation",
            "osa_get_deflation", "osa_set_active_deflation", "osa_apply", "osa_apply_adjoint",
@@ -47,7 +49,8 @@ class Opts(ctypes.Structure):
                 ("no_reproject", ctypes.c_int32), ("eig_ncv", ctypes.c_int32),
                 ("eig_max_restarts", ctypes.c_int32), ("eig_prec", ctypes.c_int32),
                 ("eig_tol", ctypes.c_double), ("max_batch", ctypes.c_int32),
-                ("orth", ctypes.c_int32), ("eig_filter", ctypes.c_int32)]
+                ("orth", ctypes.c_int32), ("eig_filter", ctypes.c_int32),
+                ("deflation", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -169,7 +172,7 @@ def _lattice(dims, antiperiodic_t=False):
 
 
 def make_opts(k_max=0, check_every=0, no_reproject=False, eig_ncv=0, eig_max_restarts=0,
-              eig_prec=FP64, eig_tol=0.0, max_batch=0, orth=0, eig_filter=0):
+              eig_prec=FP64, eig_tol=0.0, max_batch=0, orth=0, eig_filter=0, deflation=LR):
     o = Opts()
     o.k_max, o.check_every, o.no_reproject = int(k_max), int(check_every), int(bool(no_reproject))
     o.eig_ncv, o.eig_max_restarts, o.eig_prec = int(eig_ncv), int(eig_max_restarts), int(eig_prec)
@@ -177,6 +180,7 @@ def make_opts(k_max=0, check_every=0, no_reproject=False, eig_ncv=0, eig_max_res
     o.max_batch = int(max_batch)
     o.orth = int(orth)
     o.eig_filter = int(eig_filter)
+    o.deflation = int(deflation)
     return o
 
 
@@ -254,14 +258,15 @@ class Context:
         return info.as_dict()
 
     def set_deflation(self, R, L, lam):
-        """R, L: complex128 GPU tensors (m, N); lam: m complex numbers (host)."""
+        """R, L: complex128 GPU tensors (m, N); lam: m complex numbers (host).
+        L may be None under Schur deflation."""
         torch = _torch()
         m = int(R.shape[0]) if R is not None else 0
         lam = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128))
         lam_d = lam.view(np.float64)
         if m:
             rp = _dev_ptr(R, torch.complex128, "R")
-            lpp = _dev_ptr(L, torch.complex128, "L")
+            lpp = _dev_ptr(L, torch.complex128, "L") if L is not None else ctypes.c_void_p(None)
         else:
             rp = lpp = ctypes.c_void_p(None)
         self._after_current()
@@ -269,17 +274,19 @@ class Context:
                                        lam_d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                "osa_set_deflation", False)
 
-    def get_deflation(self, device="cuda"):
+    def get_deflation(self, device="cuda", left=True):
+        """(R, L, lambda); left=False skips L (returned as None), which a
+        Schur-mode deflation does not hold."""
         torch = _torch()
         m = ctypes.c_int32(0)
         _check(lib().osa_get_deflation(self._h, ctypes.byref(m), None, None, None),
                "osa_get_deflation", False)
         mm = m.value
         R = torch.empty((mm, self.N), dtype=torch.complex128, device=device)
-        L = torch.empty((mm, self.N), dtype=torch.complex128, device=device)
+        L = torch.empty((mm, self.N), dtype=torch.complex128, device=device) if left else None
         lam = np.zeros(2 * max(mm, 1))
         _check(lib().osa_get_deflation(self._h, ctypes.byref(m), ctypes.c_void_p(R.data_ptr()),
-                                       ctypes.c_void_p(L.data_ptr()),
+                                       ctypes.c_void_p(L.data_ptr() if left else None),
                                        lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                "osa_get_deflation", False)
         return R, L, lam[: 2 * mm].view(np.complex128)

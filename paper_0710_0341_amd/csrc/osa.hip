@@ -96,11 +96,15 @@ struct ArenaLayout {
     int ldh = 0;
     int64_t vec_len = 0;   // entries of each vector slot
     int64_t H = 0, coef = 0, coef2 = 0, cdef = 0, tmp = 0, s_cur = 0, s_prev = 0, dc = 0, ds = 0;
+    int64_t xs = 0;   // Schur deflation: X = S^dag H V_k (m x (kcap + 1), ld m)
+    int m = 0;
     int64_t stride = 0;
     static ArenaLayout make(int kcap, int m) {
         ArenaLayout a;
         a.ldh = kcap + 1;
-        a.vec_len = std::max<int64_t>(std::max(kcap + 2, m + 1), 160);
+        a.m = m;
+        // vectors of the small problem: Schur deflation solves it at size m + k
+        a.vec_len = std::max<int64_t>(kcap + m + 2, 160);
         int64_t o = (int64_t)a.ldh * (kcap + 1);
         a.coef = o;   o += a.vec_len;
         a.coef2 = o;  o += a.vec_len;
@@ -110,6 +114,7 @@ struct ArenaLayout {
         a.s_prev = o; o += a.vec_len;
         a.dc = o;     o += 2 * a.vec_len;
         a.ds = o;     o += 8;
+        a.xs = o;     o += (int64_t)m * (kcap + 1);
         a.stride = ceil_div(o, 16) * 16;
         return a;
     }
@@ -144,6 +149,11 @@ struct osa_ctx {
     // replaced by its conjugate transpose (GinvH)
     bool adj = false;
     DevBuf GinvH;
+    // Schur deflation (Eq. 13): orthonormal basis S of the first schur_m right
+    // vectors and T = S^dag H S; have_left: L holds left vectors (an LR deflation)
+    bool have_left = true;
+    int schur_m = 0;
+    DevBuf Sch, Tsch;
     std::vector<cd> lambda;
     double max_eig_resid = 0, min_abs_re = 0;
     int64_t eig_matvecs = 0;
@@ -152,6 +162,7 @@ struct osa_ctx {
 
     // Krylov workspace, for up to kbatch sources solved in lockstep
     int kcap = 0, kbatch = 0;
+    int scap = 0;   // size cap of the small sign problem (kcap, + m under Schur deflation)
     DevBuf V, arena, w, x, y, coef, coef2, partial, normp, upd_scratch, dscal, flag, nflag, red;
     DevBuf sX, sM, sY, logpiv, gjws;
     DevBuf xio, yio;   // internal-layout sources and results of osa_apply
@@ -303,9 +314,13 @@ void ensure_exec(osa_ctx* c, int maxcols, int nb = 1) {
 //   w, x   nb vectors each
 //   sX, sM, sY, logpiv, gjws, red: nb copies of the small-sign workspace
 void ensure_krylov(osa_ctx* c, int kcap, int nb = 1) {
-    if (kcap <= c->kcap && nb <= c->kbatch && c->V.p) return;
+    // Schur deflation solves the small sign at size m + k
+    const int extra = c->opts.deflation == 1 ? c->m_alloc : 0;
+    if (kcap <= c->kcap && nb <= c->kbatch && c->V.p && std::max(kcap, c->kcap) + extra <= c->scap)
+        return;
     kcap = std::max(kcap, c->kcap);
     nb = std::max(nb, c->kbatch);
+    const int scap = std::max(kcap + extra, c->scap);
     const int64_t N = c->N();
     const size_t vb = (size_t)N * sizeof(cd);
     c->V.release();   // the largest buffer: free before growing
@@ -316,15 +331,16 @@ void ensure_krylov(osa_ctx* c, int kcap, int nb = 1) {
     c->x.ensure(vb * nb);
     c->y.ensure(vb);
     ensure_exec(c, 2 * (kcap + 2), nb);
-    c->red_stride = newton_red_len(kcap) + 16;
+    c->red_stride = newton_red_len(scap) + 16;
     c->red.ensure(sizeof(double) * (size_t)c->red_stride * nb);
-    c->sX.ensure(sizeof(cd) * (size_t)kcap * kcap * nb);
-    c->sM.ensure(sizeof(cd) * (size_t)kcap * kcap * nb);
-    c->sY.ensure(sizeof(cd) * (size_t)kcap * kcap * nb);
-    c->logpiv.ensure(sizeof(double) * (size_t)kcap * nb);
-    c->gj_stride = (int64_t)ceil_div((int64_t)gj_ws_bytes(kcap), 256) * 256;
+    c->sX.ensure(sizeof(cd) * (size_t)scap * scap * nb);
+    c->sM.ensure(sizeof(cd) * (size_t)scap * scap * nb);
+    c->sY.ensure(sizeof(cd) * (size_t)scap * scap * nb);
+    c->logpiv.ensure(sizeof(double) * (size_t)scap * nb);
+    c->gj_stride = (int64_t)ceil_div((int64_t)gj_ws_bytes(scap), 256) * 256;
     c->gjws.ensure((size_t)c->gj_stride * nb);
     c->kcap = kcap;
+    c->scap = scap;
     c->kbatch = nb;
 }
 
@@ -382,7 +398,8 @@ void cgs2(osa_ctx* c, void* wv, const void* B, int64_t ld, int ncols, bool fp32,
 
 // Oblique projection w <- w - R G^{-1} L^dag w (Eq. 21) with the active pairs,
 // shared by every problem of the batch.  The coefficients G^{-1} L^dag w are
-// left in cout; tmp is m scratch entries.  Batch strides: vec (w), small (cout,
+// left in cout; tmp is m scratch entries.  Under Schur deflation the
+// projection is orthogonal, w <- w - S S^dag w, and cout = S^dag w.  Batch strides: vec (w), small (cout,
 // tmp).
 void project_out(osa_ctx* c, void* wv, cd* cout, cd* tmp, const Batch& bt) {
     const int m = c->m_active;
@@ -393,9 +410,11 @@ void project_out(osa_ctx* c, void* wv, cd* cout, cd* tmp, const Batch& bt) {
     bd.basis = bu.basis = 0;   // L and R are shared
     bd.part = c->part_stride;
     bu.part = 0;
-    const void* Lp = c->adj ? c->R.p : c->L.p;
-    const void* Rp = c->adj ? c->L.p : c->R.p;
-    const cd* Gi = c->adj ? c->GinvH.as<cd>() : c->Ginv.as<cd>();
+    // Schur deflation: the orthogonal projector 1 - S S^dag (Eq. 14)
+    const bool sch = c->opts.deflation == 1;
+    const void* Lp = sch ? c->Sch.p : (c->adj ? c->R.p : c->L.p);
+    const void* Rp = sch ? c->Sch.p : (c->adj ? c->L.p : c->R.p);
+    const cd* Gi = sch ? nullptr : (c->adj ? c->GinvH.as<cd>() : c->Ginv.as<cd>());
     const int nch = launch_dot_partial(Lp, c->N(), m, wv, false, p, part, c->st, bd);
     launch_reduce_partial(part, nch, m, cout, nullptr, Gi, tmp, c->st, bd);
     launch_update(wv, Rp, c->N(), m, cout, false, p, nullptr, c->upd_scratch.as<cd>(),
@@ -432,17 +451,73 @@ namespace {
 // the group share every launch; each stops on its own.
 // iters[b] > 0: iterations used, ok[b] = 1 on convergence; iters[b] < 0: a
 // singular or non-finite iterate at iteration -iters[b].
+// The small problem of Schur deflation (Eq. 15-19): the block matrix
+// [[T, X], [0, H_k]] of size m + k.  T is shared; X (ld m), the coefficients
+// c0 = S^dag b and the slot holding beta sit in each problem's arena block.
+struct SchurBlock {
+    int m = 0;
+    const cd* T = nullptr;
+    const cd* X = nullptr;
+    const cd* c0 = nullptr;
+    const cd* beta = nullptr;
+    int64_t stride = 0;   // arena stride
+};
+
+// out = [[T, X], [0, H]] (n = m + k, ld n).  Batch strides: small (X, H), mat (out).
+__global__ void k_schur_block(int m, int k, const cd* __restrict__ T, const cd* __restrict__ X,
+                              const cd* __restrict__ H, int ldh, cd* __restrict__ out, Batch bt) {
+    const int pb = bt.idx[blockIdx.y];
+    X += pb * bt.small;
+    H += pb * bt.small;
+    out += pb * bt.mat;
+    const int n = m + k;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * n) return;
+    const int i = (int)(e % n), j = (int)(e / n);
+    cd v = mk(0.0, 0.0);
+    if (j < m) {
+        if (i < m) v = T[i + (int64_t)j * m];
+    } else if (i < m) {
+        v = X[i + (int64_t)(j - m) * m];
+    } else {
+        v = H[(i - m) + (int64_t)(j - m) * ldh];
+    }
+    out[e] = v;
+}
+
+// s = F [c0; beta e_1] for F = sign of the block matrix (n = m + k, ld n); the
+// beta column only when k > 0.  Eq. 19 is then y = S s[0:m] + V_k s[m:n].
+// Batch strides: mat (F), small (c0, s), scal (beta).
+__global__ void k_schur_rhs(int m, int k, const cd* __restrict__ F, const cd* __restrict__ c0,
+                            const cd* __restrict__ beta, cd* __restrict__ s, Batch bt) {
+    const int pb = bt.idx[blockIdx.y];
+    F += pb * bt.mat;
+    c0 += pb * bt.small;
+    s += pb * bt.small;
+    beta += pb * bt.scal;
+    const int n = m + k;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cd a = k > 0 ? cscale(F[i + (int64_t)m * n], beta->x) : mk(0.0, 0.0);
+    for (int j = 0; j < m; ++j) a = cadd(a, cmul(F[i + (int64_t)j * n], c0[j]));
+    s[i] = a;
+}
+
+// sign of the k x k matrices A (or, with sb, of the Schur block matrices of
+// size m + k); s_out receives the first column (with sb: sign times [c0; beta e_1])
 void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd* A, int lda,
                       int64_t a_stride, cd* s_out, int64_t s_stride, std::vector<int>& iters,
-                      std::vector<char>& ok) {
-    const int64_t ms = (int64_t)c->kcap * c->kcap;
+                      std::vector<char>& ok, const SchurBlock* sb = nullptr) {
+    const int n = sb ? sb->m + k : k;
+    if (n > c->scap) throw OsaError{OSA_ERR_ARG, "small sign beyond its workspace"};
+    const int64_t ms = (int64_t)c->scap * c->scap;
     cd* X = c->sX.as<cd>();
     cd* M = c->sM.as<cd>();
     cd* Y = c->sY.as<cd>();
     Batch bt;   // strides of the Newton workspace
     bt.basis = a_stride;
     bt.mat = ms;
-    bt.small = c->kcap;   // logpiv (doubles)
+    bt.small = c->scap;   // logpiv (doubles)
     bt.flag = 4;
     bt.ws = c->gj_stride;
     bt.part = c->red_stride;
@@ -452,7 +527,17 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
         Batch b0 = bt;
         b0.n = (int)act.size();
         for (int i = 0; i < b0.n; ++i) b0.idx[i] = (int16_t)act[i];
-        launch_copy_square(A, lda, X, k, c->st, b0);
+        if (sb) {
+            Batch bb = b0;
+            bb.small = sb->stride;
+            if (b0.n > 0) {
+                hipLaunchKernelGGL(k_schur_block, dim3((unsigned)ceil_div((int64_t)n * n, 256), b0.n),
+                                   dim3(256), 0, c->st, sb->m, k, sb->T, sb->X, A, lda, X, bb);
+                OSA_LAUNCH_CHECK();
+            }
+        } else {
+            launch_copy_square(A, lda, X, k, c->st, b0);
+        }
     }
     OSA_HIP(hipMemsetAsync(c->nflag.p, 0, c->nflag.bytes, c->st));
     uint64_t scale = ~0ULL;
@@ -464,13 +549,13 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
         Batch ba = bt;
         ba.n = (int)act.size();
         for (int i = 0; i < ba.n; ++i) ba.idx[i] = (int16_t)act[i];
-        Batch bc = ba;   // M <- X: X has leading dimension k
+        Batch bc = ba;   // M <- X: X has leading dimension n
         bc.basis = ms;
-        launch_copy_square(X, k, M, k, c->st, bc);
-        timed(c, 3, 2.0 * 16.0 * k * (double)k * ba.n, [&] {
-            gj_invert(M, Y, k, c->logpiv.as<double>(), c->nflag.as<int>(), c->gjws.p, c->st, ba);
+        launch_copy_square(X, n, M, n, c->st, bc);
+        timed(c, 3, 2.0 * 16.0 * n * (double)n * ba.n, [&] {
+            gj_invert(M, Y, n, c->logpiv.as<double>(), c->nflag.as<int>(), c->gjws.p, c->st, ba);
         });
-        launch_newton_combine(X, Y, k, c->logpiv.as<double>(), scale, red, c->st, ba);
+        launch_newton_combine(X, Y, n, c->logpiv.as<double>(), scale, red, c->st, ba);
         d2h_strided(c, red, c->red_stride * (int64_t)sizeof(double), 2, act, hred);
         d2h_strided(c, c->nflag.p, 4 * (int64_t)sizeof(int), 1, act, hflag);
         std::vector<int> next;
@@ -502,7 +587,16 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
     bs.n = (int)good.size();
     for (int i = 0; i < bs.n; ++i) bs.idx[i] = (int16_t)good[i];
     bs.small = s_stride;
-    launch_copy_col0(X, k, s_out, c->st, bs);
+    if (sb) {
+        bs.scal = sb->stride;
+        if (bs.n > 0) {
+            hipLaunchKernelGGL(k_schur_rhs, dim3((unsigned)ceil_div(n, 256), bs.n), dim3(256), 0,
+                               c->st, sb->m, k, X, sb->c0, sb->beta, s_out, bs);
+            OSA_LAUNCH_CHECK();
+        }
+    } else {
+        launch_copy_col0(X, k, s_out, c->st, bs);
+    }
 }
 
 // ------------------------------------------------------------- set deflation
@@ -536,7 +630,54 @@ void build_ginv(osa_ctx* c, int m) {
 
 void set_active(osa_ctx* c, int m) {
     c->m_active = m;
-    if (m > 0) build_ginv(c, m);
+    if (m > 0 && c->have_left) build_ginv(c, m);
+}
+
+// Schur basis of the active deflation space (Eq. 13): classical Gram-Schmidt,
+// applied twice, over the right eigenvectors in their order gives R = S U with
+// U upper triangular, so T = S^dag H S = U Lambda U^{-1} is upper triangular
+// (to the accuracy of the eigenvectors) with the eigenvalues on its diagonal.
+void ensure_schur(osa_ctx* c) {
+    const int m = c->m_active;
+    if (m == 0 || c->schur_m == m) return;
+    if ((int64_t)(c->kcap + 2) * c->kbatch < m) throw OsaError{OSA_ERR_ARG, "basis storage"};
+    const int64_t N = c->N();
+    const TsPlan p = ts_plan(N);
+    c->Sch.ensure(sizeof(cd) * (size_t)N * m);
+    c->Tsch.ensure(sizeof(cd) * (size_t)m * m + 16);
+    cd* S = c->Sch.as<cd>();
+    cd* w = c->w.as<cd>();
+    for (int j = 0; j < m; ++j) {
+        OSA_HIP(hipMemcpyAsync(w, c->R.as<cd>() + (size_t)j * N, sizeof(cd) * N,
+                               hipMemcpyDeviceToDevice, c->st));
+        if (j > 0)
+            cgs2(c, w, S, N, j, false, c->coef.as<cd>(), c->coef2.as<cd>());
+        else
+            launch_norm_partial(w, false, p, c->normp.as<double>(), c->st);
+        launch_normalize(w, S + (size_t)j * N, false, p, c->normp.as<double>(), c->dscal.as<cd>(),
+                         nullptr, 0.0, nullptr, 0, nullptr, 0, c->st);
+    }
+    // T = S^dag (H S), H S in the Krylov basis storage (free between solves)
+    cd* W = c->V.as<cd>();
+    apply_h_contig(c, S, W, false, false, m);
+    for (int j = 0; j < m; ++j) {
+        const int nch = launch_dot_partial(S, N, m, W + (size_t)j * N, false, p,
+                                           c->partial.as<cd>(), c->st);
+        launch_reduce_partial(c->partial.as<cd>(), nch, m, c->Tsch.as<cd>() + (size_t)j * m,
+                              nullptr, nullptr, nullptr, c->st);
+    }
+    c->schur_m = m;
+}
+
+// The deflation data has to fit the scheme of the solve: LR deflation and the
+// adjoint need left vectors, and Schur deflation has no adjoint form here.
+void check_deflation_state(osa_ctx* c) {
+    if (c->m_active == 0) return;
+    if (c->opts.deflation == 1 && c->adj)
+        throw OsaError{OSA_ERR_STATE, "the adjoint solve needs LR deflation (deflation = 0)"};
+    if (c->opts.deflation != 1 && !c->have_left)
+        throw OsaError{OSA_ERR_STATE, "LR deflation needs left eigenvectors; this deflation "
+                                      "data has none (computed for Schur deflation)"};
 }
 
 // ------------------------------------------------------------- solve
@@ -559,18 +700,24 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     res.assign(nb, SolveResult{});
     const int64_t N = c->N();
     const int kmax = c->opts.k_max;
-    ensure_krylov(c, kmax, nb);
-    if (c->lay.vec_len < std::max(kmax + 1, c->m_active + 1)) {
+    check_deflation_state(c);
+    const bool schur = c->opts.deflation == 1 && c->m_active > 0;   // Eq. 13-19
+    // the Schur basis set-up uses m columns of the basis storage as scratch
+    ensure_krylov(c, schur ? std::max(kmax, c->m_active) : kmax, nb);
+    if (c->lay.vec_len < kmax + c->m_alloc + 2 || c->lay.m < c->m_alloc) {
         c->lay = ArenaLayout::make(c->kcap, std::max(c->m_alloc, 1));
         c->arena.ensure(sizeof(cd) * (size_t)c->lay.stride * c->kbatch);
     }
+    if (schur) ensure_schur(c);
     const ArenaLayout& L = c->lay;
     const bool fixed = c->opts.check_every < 0;
     const int every = fixed ? kmax : std::max(1, c->opts.check_every);
-    const bool reproj = !c->opts.no_reproject;
+    // Schur deflation keeps the S coefficients of every H v_j (the block X of
+    // Eq. 15), so it projects at every step, after H v_j with v_j final (plain CGS2)
+    const bool reproj = !c->opts.no_reproject || schur;
     const TsPlan p = ts_plan(N);
     const int64_t VS = (int64_t)(c->kcap + 2) * N;   // basis stride
-    const bool dcgs = c->opts.orth == 0;           // delayed reorthogonalisation
+    const bool dcgs = c->opts.orth == 0 && !schur;  // delayed reorthogonalisation
     const int ldh = L.ldh;
     cd* V = c->V.as<cd>();
     cd* ar = c->arena.as<cd>();
@@ -583,6 +730,15 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     cd* x = c->x.as<cd>();
     int* flag = c->flag.as<int>();
     const int m = c->m_active;
+    SchurBlock sblk;
+    sblk.m = m;
+    sblk.T = c->Tsch.as<cd>();
+    sblk.X = ar + L.xs;
+    sblk.c0 = ar + L.cdef;
+    sblk.beta = ds + 1;
+    sblk.stride = L.stride;
+    const SchurBlock* sbp = schur ? &sblk : nullptr;
+    const int ms0 = schur ? m : 0;   // leading S part of the small solution vector
     Batch base;   // strides of the solve workspace
     base.basis = VS;
     base.vec = N;
@@ -664,7 +820,8 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     for (int j = dcgs ? 1 : 0; j < (dcgs ? kmax + 1 : kmax) && !act.empty(); ++j) {
         const Batch bt = bat(act);
         apply_h(c, V + (size_t)j * N, w, false, c->adj, bt);
-        if (reproj && m > 0) project_out(c, w, ar + L.coef2, ar + L.tmp, bt);
+        if (reproj && m > 0)   // Schur deflation: column j of X = S^dag H v_j
+            project_out(c, w, schur ? ar + L.xs + (size_t)j * m : ar + L.coef2, ar + L.tmp, bt);
         if (dcgs) {
             Batch bd = bt;
             bd.part = c->part_stride;
@@ -726,7 +883,8 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
             std::vector<int> grp;
             for (int b : live)
                 if (kcheck[b] == kc) grp.push_back(b);
-            small_sign_batch(c, grp, kc, H, ldh, L.stride, ar + L.s_cur, L.stride, iters, okv);
+            small_sign_batch(c, grp, kc, H, ldh, L.stride, ar + L.s_cur, L.stride, iters, okv,
+                             sbp);
             std::vector<int> good, withprev;
             for (int b : grp) {
                 res[b].newton_iters = iters[b];
@@ -746,11 +904,13 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
                 for (int b : withprev) (kprev[b] == kp ? sub : rest).push_back(b);
                 Batch bd = bat(sub);
                 bd.scal = 2 * L.stride;   // counted in doubles
-                launch_diff_norm(ar + L.s_cur, kc, ar + L.s_prev, kp, (double*)(ds + 3), c->st, bd);
+                launch_diff_norm(ar + L.s_cur, kc + ms0, ar + L.s_prev, kp + ms0, (double*)(ds + 3),
+                                 c->st, bd);
                 d2h_strided(c, (double*)(ds + 3), L.stride * (int64_t)sizeof(cd), 1, sub, hd);
                 for (size_t i = 0; i < sub.size(); ++i) {
                     const int b = sub[i];
-                    res[b].est = beta[b] * hd[i] / bnorm[b];
+                    // s carries beta under Schur deflation (s = sign(H) [c0; beta e_1])
+                    res[b].est = (schur ? 1.0 : beta[b]) * hd[i] / bnorm[b];
                 }
                 withprev.swap(rest);
             }
@@ -768,7 +928,7 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
             if (!cont.empty()) {   // keep the latest sign in s_prev for the next difference
                 Batch bcp = bat(cont);
                 bcp.mat = L.stride;
-                launch_copy_col0(ar + L.s_cur, kc, ar + L.s_prev, c->st, bcp);
+                launch_copy_col0(ar + L.s_cur, kc + ms0, ar + L.s_prev, c->st, bcp);
             }
             next.insert(next.end(), cont.begin(), cont.end());
         }
@@ -780,7 +940,35 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     std::vector<int> okp;
     for (int b = 0; b < nb; ++b)
         if (res[b].st >= 0) okp.push_back(b);
-    if (!okp.empty()) {
+    if (schur) {
+        // Eq. 19: y = S s[0:m] + V_k s[m:m+k] with s = sign(H) [c0; beta e_1];
+        // a source inside Omega_m (no Krylov step) needs sign(T) c0 only
+        std::vector<int> z, it0(nb, 0);
+        std::vector<char> ok0(nb, 0);
+        for (int b : okp)
+            if (res[b].k_used == 0) z.push_back(b);
+        if (!z.empty()) {
+            small_sign_batch(c, z, 0, H, ldh, L.stride, ar + L.s_cur, L.stride, it0, ok0, sbp);
+            for (int b : z) {
+                res[b].newton_iters = it0[b];
+                if (it0[b] < 0 || !ok0[b]) res[b].st = OSA_ERR_NEWTON_NOCONV;
+            }
+        }
+        std::vector<int> ks;
+        for (int b : okp)
+            if (res[b].st >= 0 && std::find(ks.begin(), ks.end(), res[b].k_used) == ks.end())
+                ks.push_back(res[b].k_used);
+        for (int ku : ks) {
+            std::vector<int> grp;
+            for (int b : okp)
+                if (res[b].st >= 0 && res[b].k_used == ku) grp.push_back(b);
+            const Batch bg = bat(grp);
+            Batch bs = bg;
+            bs.basis = 0;   // S is shared
+            launch_combine(yout, c->Sch.p, N, m, ar + L.s_cur, false, false, N, c->st, bs);
+            if (ku > 0) launch_combine(yout, V, N, ku, ar + L.s_cur + m, false, true, N, c->st, bg);
+        }
+    } else if (!okp.empty()) {
         const Batch bo = bat(okp);
         if (m > 0) {
             hipLaunchKernelGGL(k_sign_coef, dim3((unsigned)ceil_div(m, 64), bo.n), dim3(64), 0,
@@ -1309,11 +1497,13 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
         c->U32.ensure(sizeof(cf) * (size_t)c->g.Vp * 36);
         launch_convert(c->U.p, false, c->U32.p, true, (int64_t)c->g.Vp * 36, c->st);
     }
+    // Schur deflation needs the right eigenvectors only
+    const bool right_only = c->opts.deflation == 1;
     DevBuf X, Rn, Ln, Xs;
     X.ensure(sizeof(cd) * (size_t)N * nev);
     Xs.ensure(sizeof(cd) * N);
     Rn.ensure(sizeof(cd) * (size_t)N * m);
-    Ln.ensure(sizeof(cd) * (size_t)N * m);
+    if (!right_only) Ln.ensure(sizeof(cd) * (size_t)N * m);
     KsStats st;
     std::vector<cd> lam_r, lam_l;
     double res_r = 0, res_l = 0;
@@ -1381,11 +1571,14 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
         (void)hipEventDestroy(ready);
     }
     DevBuf X2, Xs2;
-    X2.ensure(sizeof(cd) * (size_t)N * nev);
-    Xs2.ensure(sizeof(cd) * N);
+    if (!right_only) {
+        X2.ensure(sizeof(cd) * (size_t)N * nev);
+        Xs2.ensure(sizeof(cd) * N);
+    }
     KsStats st_l;
     std::exception_ptr werr;
     std::thread worker([&] {
+        if (right_only) return;
         try {
             side(w.get(), true, X2.as<cd>(), Xs2.as<cd>(), Ln.as<cd>(), lam_l, res_l, st_l);
         } catch (...) {
@@ -1414,9 +1607,14 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
     st.restarts += st_l.restarts;
     // install
     c->R.ensure(sizeof(cd) * (size_t)N * m);
-    c->L.ensure(sizeof(cd) * (size_t)N * m);
     OSA_HIP(hipMemcpyAsync(c->R.p, Rn.p, sizeof(cd) * (size_t)N * m, hipMemcpyDeviceToDevice, c->st));
-    OSA_HIP(hipMemcpyAsync(c->L.p, Ln.p, sizeof(cd) * (size_t)N * m, hipMemcpyDeviceToDevice, c->st));
+    if (!right_only) {
+        c->L.ensure(sizeof(cd) * (size_t)N * m);
+        OSA_HIP(hipMemcpyAsync(c->L.p, Ln.p, sizeof(cd) * (size_t)N * m, hipMemcpyDeviceToDevice,
+                               c->st));
+    }
+    c->have_left = !right_only;
+    c->schur_m = 0;
     c->lambda = lam_r;
     c->lam_dev.ensure(sizeof(cd) * m);
     h2d(c, c->lam_dev.p, c->lambda.data(), m);
@@ -1520,6 +1718,7 @@ osa_status apply_impl(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double t
             ~AdjScope() { c->adj = false; }
         } scope{c};
         c->adj = (mode == ApplyMode::kAdjoint);
+        check_deflation_state(c);
         if (c->adj && c->m_active > 0) {
             const int m = c->m_active;
             c->GinvH.ensure(sizeof(cd) * (size_t)m * m + 16);
@@ -1711,14 +1910,18 @@ osa_status osa_deflate(osa_ctx* c, int32_t n_defl, osa_info* info) {
 osa_status osa_set_deflation(osa_ctx* c, int32_t m, const void* R, const void* L,
                              const double* lambda) {
     if (!c || m < 0 || m > 64 || (int64_t)m >= 12LL * c->g.V) return OSA_ERR_ARG;
-    if (m > 0 && (!R || !L || !lambda)) return OSA_ERR_ARG;
+    if (m > 0 && (!R || !lambda || (!L && c->opts.deflation != 1))) return OSA_ERR_ARG;
     return guard([&]() -> osa_status {
         const int64_t N = c->N();
         if (m == 0) { c->m_alloc = c->m_active = 0; c->lambda.clear(); return OSA_OK; }
         c->R.ensure(sizeof(cd) * (size_t)N * m);
-        c->L.ensure(sizeof(cd) * (size_t)N * m);
         launch_vec_to_internal((const cd*)R, c->R.p, false, c->g, m, c->st);
-        launch_vec_to_internal((const cd*)L, c->L.p, false, c->g, m, c->st);
+        if (L) {
+            c->L.ensure(sizeof(cd) * (size_t)N * m);
+            launch_vec_to_internal((const cd*)L, c->L.p, false, c->g, m, c->st);
+        }
+        c->have_left = L != nullptr;
+        c->schur_m = 0;
         c->lambda.resize(m);
         for (int i = 0; i < m; ++i) c->lambda[i] = mk(lambda[2 * i], lambda[2 * i + 1]);
         c->lam_dev.ensure(sizeof(cd) * m);
@@ -1741,6 +1944,7 @@ osa_status osa_get_deflation(const osa_ctx* cc, int32_t* m_out, void* R, void* L
         const int m = c->m_alloc;
         if (m == 0) return OSA_OK;
         if (R) launch_vec_from_internal(c->R.p, false, (cd*)R, c->g, m, c->st);
+        if (L && !c->have_left) return OSA_ERR_STATE;
         if (L) launch_vec_from_internal(c->L.p, false, (cd*)L, c->g, m, c->st);
         if (lambda)
             for (int i = 0; i < m; ++i) { lambda[2 * i] = c->lambda[i].x; lambda[2 * i + 1] = c->lambda[i].y; }
@@ -1889,6 +2093,7 @@ osa_status osa_small_sign(int32_t k, const void* A, void* s, int32_t* iters, voi
         c.g.Vp = 64;
         c.host.ensure(1 << 16);
         c.kcap = k;
+        c.scap = k;
         c.kbatch = 1;
         c.sX.ensure(sizeof(cd) * (size_t)k * k);
         c.sM.ensure(sizeof(cd) * (size_t)k * k);

@@ -537,3 +537,75 @@ def test_fig1_trends_haar4(osa, haar4_dense):
         assert eps[25, k] < eps[10, k] < eps[0, k]
     assert eps[25, 300] < 1e-9 and eps[0, 300] > 10 * eps[25, 300]
     ctx.close()
+
+
+# -------------------------------------------------- Schur deflation (Eq. 13-19)
+@pytest.fixture(scope="module")
+def haar3_schur():
+    """3^4 Haar links, mu = 0.3, m_w = -1.5: the oracle's Schur data for m = 10 (a
+    gap in |Re lambda| after the 10th eigenvalue) and the dense sign."""
+    dims = (3, 3, 3, 3)
+    links = LI.make_links(dims, "haar", cfg=0, inst=11)
+    b = LI.gaussian_source(dims, cfg=0, inst=11)
+    h = O.hermitian_wilson_dense(links, dims, 0.3, -1.5)
+    say("dense oracle 3^4: sign and critical eigenpairs")
+    r, l, lam = O.critical_dense(h, 10)
+    s, t = O.schur_basis(r, lambda x: h @ x)
+    return dims, links, b, h, r, s, t, O.sign_eig_apply(h, b)
+
+
+def test_schur_deflation_matches_oracle(osa, haar3_schur):
+    """Fixed-k Schur-deflated solves equal the oracle's Eq. 19 at the same (m, k);
+    the converged solve equals the dense sign; the eigensolver ran one side only."""
+    dims, links, b, h, r, s, t, yx = haar3_schur
+    say("schur 3^4: deflate (right vectors only), fixed k, converged")
+    mv = lambda x: h @ x  # noqa: E731
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=400, check_every=20,
+                      deflation=osa.SCHUR)
+    dinfo = ctx.deflate(10)
+    assert dinfo["max_eig_resid"] < 1e-10
+    for k in (30, 60, 120):
+        ctx.set_opts(k_max=k, check_every=-1, deflation=osa.SCHUR)
+        y, _, st = ctx.apply(dev(b))
+        yo, info = O.schur_arnoldi_sign(mv, b, s, t, k=k)
+        assert st == osa.OSA_OK and rel(host(y), yo) < 1e-9, k
+    ctx.set_opts(k_max=400, check_every=20, deflation=osa.SCHUR)
+    y, infos, st = ctx.apply(dev(b), tol=1e-11)
+    assert st == osa.OSA_OK and rel(host(y), yx) < 1e-9
+    # a batch: the source, a source inside Omega_m (from the oracle's vectors) and
+    # zero (no Krylov step: sign(T) c0 alone); the first bitwise as alone
+    xin = r @ (np.arange(1, 11) + 0.5j)
+    B = np.stack([b, xin, np.zeros_like(b)])
+    Y, infs, st = ctx.apply(dev(B), tol=1e-11)
+    Y = host(Y)
+    assert st == osa.OSA_OK
+    assert np.array_equal(Y[0], host(y))
+    assert rel(Y[1], O.sign_eig_apply(h, xin)) < 1e-9
+    assert not Y[2].any() and infs[2]["k_used"] == 0
+    ctx.close()
+
+
+def test_schur_vs_lr_and_state_errors(osa, haar3_schur):
+    """Results section: Schur deflation needs only right eigenvectors (about half
+    the eigensolver's stencil applications of LR) at about LR's accuracy.  Data
+    without left vectors refuses LR and adjoint solves with OSA_ERR_STATE."""
+    dims, links, b, h, r, s, t, yx = haar3_schur
+    say("schur vs lr 3^4")
+    cs = osa.Context(dev(links), dims, 0.3, -1.5, k_max=60, check_every=-1, deflation=osa.SCHUR)
+    cl = osa.Context(dev(links), dims, 0.3, -1.5, k_max=60, check_every=-1)
+    ds, dl = cs.deflate(10), cl.deflate(10)
+    assert ds["eig_matvecs"] < 0.7 * dl["eig_matvecs"]
+    es = rel(host(cs.apply(dev(b))[0]), yx)
+    el = rel(host(cl.apply(dev(b))[0]), yx)
+    assert 0.1 < es / el < 10.0, (es, el)
+    _, _, st = cs.apply_adjoint(dev(b), check=False)
+    assert st == osa.OSA_ERR_STATE
+    cs.set_opts(k_max=60, check_every=-1)          # LR solve on right-only data
+    _, _, st = cs.apply(dev(b), check=False)
+    assert st == osa.OSA_ERR_STATE
+    # LR data serves Schur solves as well (only R is used)
+    cl.set_opts(k_max=60, check_every=-1, deflation=osa.SCHUR)
+    ys = host(cl.apply(dev(b))[0])
+    assert rel(ys, O.schur_arnoldi_sign(lambda x: h @ x, b, s, t, k=60)[0]) < 1e-9
+    cs.close()
+    cl.close()
