@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--solve-only", action="store_true",
                     help="only the solves of one instance (eigenpairs computed untimed first)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain record")
+    ap.add_argument("--deflation", choices=["lr", "schur"], default="lr",
+                    help="deflation scheme: LR (Eq. 20-22, the default) or Schur (Eq. 13-19)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the 12-source lockstep batch (eigenpairs computed untimed first)")
     return ap.parse_args()
@@ -152,10 +154,12 @@ def batched_vs_plain(osa, ctx, dims, tol, m, reps=1):
     import torch
     B = torch.from_numpy(point_sources(dims)).to("cuda:0")
     k_max, eig_prec, ncv = ctx._opts.k_max, ctx._opts.eig_prec, ctx._opts.eig_ncv
+    defl = ctx._opts.deflation
     out = {}
     ys = {}
     for name, mb in (("plain", 1), ("batched", 12)):
-        ctx.set_opts(k_max=k_max, check_every=50, max_batch=mb, eig_prec=eig_prec, eig_ncv=ncv)
+        ctx.set_opts(k_max=k_max, check_every=50, max_batch=mb, eig_prec=eig_prec, eig_ncv=ncv,
+                     deflation=defl)
         ctx.set_active_deflation(m)
         ctx.apply(B, tol=tol)            # warm-up (workspace growth)
         torch.cuda.synchronize()
@@ -168,7 +172,7 @@ def batched_vs_plain(osa, ctx, dims, tol, m, reps=1):
         out[name] = {"solves_per_s": 12.0 / dt, "ms": dt * 1e3, "status": int(st),
                      "k_used": [i["k_used"] for i in infos],
                      "max_resid_est": max(i["resid_est"] for i in infos)}
-    ctx.set_opts(k_max=k_max, check_every=50, eig_prec=eig_prec, eig_ncv=ncv)
+    ctx.set_opts(k_max=k_max, check_every=50, eig_prec=eig_prec, eig_ncv=ncv, deflation=defl)
     out["speedup"] = out["batched"]["solves_per_s"] / out["plain"]["solves_per_s"]
     out["bitwise_equal"] = bool(torch.equal(ys["plain"], ys["batched"]))
     out["sources"] = "12 spin-colour point sources at site 0"
@@ -442,8 +446,10 @@ def main():
     links = torch.from_numpy(links_np).to(dev)
     b = torch.from_numpy(b_np).to(dev)
     eig_prec = osa.FP32 if args.eig_prec == "fp32" else osa.FP64
+    scheme = osa.SCHUR if args.deflation == "schur" else osa.LR
     ctxs = [osa.Context(links, dims, mu, wl["m_w"], k_max=wl["k_max"], check_every=50,
-                        eig_prec=eig_prec, eig_ncv=args.eig_ncv) for mu in wl["mus"]]
+                        eig_prec=eig_prec, eig_ncv=args.eig_ncv, deflation=scheme)
+            for mu in wl["mus"]]
     mmax = max(wl["ms"])
     records = []
 
@@ -472,7 +478,7 @@ def main():
         ctx.apply(b, tol=wl["tol"])
         rec = {"solve_only": True, "mu": ctx.mu, "m": mmax}
         for orth in (0, 1):
-            ctx.set_opts(k_max=wl["k_max"], check_every=50, orth=orth)
+            ctx.set_opts(k_max=wl["k_max"], check_every=50, orth=orth, deflation=scheme)
             ctx.set_active_deflation(mmax)
             torch.cuda.synchronize()
             ctx.profile(True)
@@ -546,7 +552,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "lattice": list(dims), "N": 12 * int(np.prod(dims)),
                    "mu": wl["mus"], "n_defl": wl["ms"], "k_max": wl["k_max"], "tol": wl["tol"],
-                   "sources_per_step": n_solves, "parallelism": "single GPU"},
+                   "sources_per_step": n_solves, "deflation": args.deflation,
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": kernel_names[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if dom == "cgs_dot" else None,

@@ -503,6 +503,46 @@ __global__ void k_schur_rhs(int m, int k, const cd* __restrict__ F, const cd* __
     s[i] = a;
 }
 
+// Delayed reorthogonalisation under Schur deflation: H was applied to the
+// tentative column u_j = r v_j + V_{<j} s, so the projection left S^dag H u_j
+// in column j of X; S^dag H v_j = (X_j - X_{<j} s) / r, with s = d[0:j] and
+// 1/r in sc[0].  One block per (row i, problem): 256 threads split the j
+// terms, then a fixed-order block reduction.  Batch strides: small (X, d),
+// scal (sc).
+__global__ __launch_bounds__(256) void k_schur_x_fix(int m, int j, cd* __restrict__ X,
+                                                     const cd* __restrict__ d,
+                                                     const cd* __restrict__ sc, Batch bt) {
+    __shared__ double red[2][4];
+    const int pb = bt.idx[blockIdx.y];
+    const int i = blockIdx.x;
+    X += pb * bt.small;
+    d += pb * bt.small;
+    sc += pb * bt.scal;
+    double ax = 0.0, ay = 0.0;
+    for (int l = threadIdx.x; l < j; l += 256) {
+        const cd p = cmul(X[i + (int64_t)l * m], d[l]);
+        ax += p.x;
+        ay += p.y;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        ax += __shfl_xor(ax, off, 64);
+        ay += __shfl_xor(ay, off, 64);
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wave] = ax;
+        red[1][wave] = ay;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const cd acc = mk(red[0][0] + red[0][1] + red[0][2] + red[0][3],
+                          red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+        const cd a = csub(X[i + (int64_t)j * m], acc);
+        X[i + (int64_t)j * m] = cscale(a, sc[0].x);
+    }
+}
+
 // sign of the k x k matrices A (or, with sb, of the Schur block matrices of
 // size m + k); s_out receives the first column (with sb: sign times [c0; beta e_1])
 void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd* A, int lda,
@@ -713,11 +753,11 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     const bool fixed = c->opts.check_every < 0;
     const int every = fixed ? kmax : std::max(1, c->opts.check_every);
     // Schur deflation keeps the S coefficients of every H v_j (the block X of
-    // Eq. 15), so it projects at every step, after H v_j with v_j final (plain CGS2)
+    // Eq. 15), so it projects at every step
     const bool reproj = !c->opts.no_reproject || schur;
     const TsPlan p = ts_plan(N);
     const int64_t VS = (int64_t)(c->kcap + 2) * N;   // basis stride
-    const bool dcgs = c->opts.orth == 0 && !schur;  // delayed reorthogonalisation
+    const bool dcgs = c->opts.orth == 0;           // delayed reorthogonalisation
     const int ldh = L.ldh;
     cd* V = c->V.as<cd>();
     cd* ar = c->arena.as<cd>();
@@ -789,7 +829,7 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
         if (dcgs) {
             // first column: one pass; u_1 = H v_1 - v_1 h_11 goes to basis column 1
             apply_h(c, V, w, false, c->adj, b0);
-            if (reproj && m > 0) project_out(c, w, ar + L.coef2, ar + L.tmp, b0);
+            if (reproj && m > 0) project_out(c, w, schur ? ar + L.xs : ar + L.coef2, ar + L.tmp, b0);
             Batch bd = b0, bu = b0;
             bd.part = c->part_stride;
             bu.part = 0;
@@ -833,6 +873,12 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
             launch_reduce_partial(c->partial.as<cd>(), nch, 2 * (j + 1), ar + L.dc, nullptr,
                                   nullptr, nullptr, c->st, bd);
             launch_dcgs_coef(j, H, ldh, ar + L.dc, ds + 5, hfro2, flag, 1e-14, c->st, bt);
+            if (schur) {
+                hipLaunchKernelGGL(k_schur_x_fix, dim3((unsigned)m, (unsigned)bt.n), dim3(256), 0,
+                                   c->st, m, j, ar + L.xs, (const cd*)(ar + L.dc),
+                                   (const cd*)(ds + 5), bt);
+                OSA_LAUNCH_CHECK();
+            }
             timed(c, 1, (j + 4.0) * N * 16.0 * bt.n, [&] {
                 launch_dcgs_update(V, N, j, w, ar + L.dc, ds + 5, false, N,
                                    c->upd_scratch.as<cd>(), scratch_len, c->st, bt);

@@ -564,11 +564,11 @@ def test_schur_deflation_matches_oracle(osa, haar3_schur):
                       deflation=osa.SCHUR)
     dinfo = ctx.deflate(10)
     assert dinfo["max_eig_resid"] < 1e-10
-    for k in (30, 60, 120):
-        ctx.set_opts(k_max=k, check_every=-1, deflation=osa.SCHUR)
+    for k, orth in ((30, 0), (60, 0), (120, 0), (60, 1)):   # delayed and plain CGS2
+        ctx.set_opts(k_max=k, check_every=-1, deflation=osa.SCHUR, orth=orth)
         y, _, st = ctx.apply(dev(b))
         yo, info = O.schur_arnoldi_sign(mv, b, s, t, k=k)
-        assert st == osa.OSA_OK and rel(host(y), yo) < 1e-9, k
+        assert st == osa.OSA_OK and rel(host(y), yo) < 1e-9, (k, orth)
     ctx.set_opts(k_max=400, check_every=20, deflation=osa.SCHUR)
     y, infos, st = ctx.apply(dev(b), tol=1e-11)
     assert st == osa.OSA_OK and rel(host(y), yx) < 1e-9
