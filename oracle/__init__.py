@@ -14,6 +14,7 @@ Everything is plain numpy / scipy in float64 / complex128:
 * ``eigen``      -- critical left/right eigenpairs                  (Eq. 20)
 * ``overlap``    -- D_ov = 1 + gamma_5 sign(H_w) and sign(H)^dag      (Eq. 1)
 * ``schur``      -- Arnoldi with Schur deflation, Sylvester coupling    (Eq. 13-19)
+* ``block_krylov`` -- block Arnoldi for several sources (not the paper's; Eq. 11, 22 per block)
 """
 from .dirac import (gamma_matrices, kappa_of, wilson_dirac_sparse, hermitian_wilson_sparse,
                     hermitian_wilson_dense, gamma5_diag)
@@ -24,5 +25,6 @@ from .krylov import arnoldi_cgs2, lr_arnoldi_sign, small_sign_e1, Deflation
 from .eigen import critical_dense, critical_sparse, critical_order, eig_residuals
 from .overlap import overlap_apply, sign_adjoint_apply
 from .schur import schur_basis, schur_arnoldi, schur_arnoldi_sign, coupling_y
+from .block_krylov import block_arnoldi, block_lr_sign
 
 __all__ = [n for n in dir() if not n.startswith("_")]

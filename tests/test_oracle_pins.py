@@ -470,3 +470,47 @@ def test_schur_accuracy_close_to_lr(haar3):
         e0 = rel(O.lr_arnoldi_sign(mv, b, None, k=k)[0], y)
         assert es < e0 and el < e0
         assert 0.1 < es / el < 10.0, (k, es, el)
+
+
+# ------------------------------------------------------------ block Krylov
+def test_block_arnoldi_relation_and_single_source(haar2):
+    """Block Arnoldi: A V_K = V_K H_K + V_{K+1} H_{K+1,K} E_K^T with orthonormal V and
+    block upper Hessenberg H; with one source the block method is Eq. 22."""
+    dims, u, h = haar2
+    n = h.shape[0]
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    mvb = lambda x: h @ x  # noqa: E731
+    vmat, hmat, r0, kd = O.block_arnoldi(mvb, b, 12)
+    s = 3
+    assert kd == 12
+    assert np.abs(vmat.conj().T @ vmat - np.eye((kd + 1) * s)).max() < 1e-12
+    resid = h @ vmat[:, : kd * s] - vmat @ hmat
+    assert np.abs(resid).max() < 1e-11
+    assert np.abs(np.tril(hmat, -s - 1)).max() == 0.0            # block Hessenberg
+    assert np.abs(vmat[:, :s] @ r0 - b).max() < 1e-12
+    r, l, lam = O.critical_dense(h, 6)
+    defl = O.Deflation(r, l, lam)
+    y1, _ = O.block_lr_sign(lambda x: h @ x, b[:, :1], defl, 30)
+    y2, _ = O.lr_arnoldi_sign(lambda x: h @ x, b[:, 0], defl, k=30)
+    assert rel(y1[:, 0], y2) < 1e-10
+
+
+def test_block_krylov_exact_on_full_space_and_contains_single_spaces(haar2):
+    """When K s reaches the complement's dimension the block result is the exact
+    sign; the block space of K steps contains each source's own Krylov space of K
+    steps, so its error at K is no worse than the single-source error at K."""
+    dims, u, h = haar2
+    n = h.shape[0]
+    rng = np.random.default_rng(9)
+    b = rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4))
+    yx = O.sign_eig_apply(h, b)
+    r, l, lam = O.critical_dense(h, 8)
+    defl = O.Deflation(r, l, lam)
+    yb, info = O.block_lr_sign(lambda x: h @ x, b, defl, (n - 8) // 4)
+    assert rel(yb, yx) < 1e-9
+    for k in (6, 12):
+        yb, _ = O.block_lr_sign(lambda x: h @ x, b, defl, k)
+        for i in range(4):
+            ys, _ = O.lr_arnoldi_sign(lambda x: h @ x, b[:, i], defl, k=k)
+            assert rel(yb[:, i], yx[:, i]) < 3 * rel(ys, yx[:, i]), (k, i)
