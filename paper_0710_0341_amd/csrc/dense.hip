@@ -24,7 +24,7 @@ struct GjWs {
     double2* piv;   // k: (|value|, index) of the pivot chosen for step t
     int* perm;      // k
     int* pinv;      // k
-    int* used;      // k
+    int* used;      // k: 0, or s + 1 for the pivot row of step s
 };
 
 size_t gj_ws_bytes(int k) {
@@ -41,6 +41,12 @@ __device__ __forceinline__ GjWs gj_at(GjWs w, const Batch& bt, int pb) {
     w.used = (int*)((char*)w.used + off);
     return w;
 }
+
+// Row i was the pivot of a step before step t.  Block 0 marks the pivot rows
+// of a launch at its end, while other blocks of the same launch may still be
+// choosing pivots: marks of step t or later must not count, or a block that
+// runs after block 0 would skip the row the others chose.
+__device__ __forceinline__ bool used_before(int u, int t) { return u != 0 && u <= t; }
 
 static GjWs gj_ws(void* ws, int k) {
     char* p = (char*)ws;
@@ -153,7 +159,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_step(cd* __restrict__ M, int 
             M[i + (size_t)j * k] = nv;
             if (nextcol) {
                 coln[i] = nv;
-                if (i != p && !w.used[i]) argmax_pair(bv, bi, cabsd(nv), i);
+                if (i != p && !used_before(w.used[i], t)) argmax_pair(bv, bi, cabsd(nv), i);
             }
         }
         if (nextcol) {
@@ -165,7 +171,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_step(cd* __restrict__ M, int 
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         w.perm[t] = p;
-        w.used[p] = 1;
+        w.used[p] = t + 1;
         logpiv[t] = zero ? -1e300 : log(cabsd(piv));
         if (zero || !(piv.x == piv.x) || !(piv.y == piv.y)) *flag = 1;
     }
@@ -205,7 +211,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_step2(cd* __restrict__ M, int
         for (int i = threadIdx.x; i < k; i += kGjThreads) {
             const cd nv = (i == p) ? rp : gj_sub(colB[i], colA[i], rp);
             c1[i] = nv;
-            if (i != p && !w.used[i]) argmax_pair(bv, bi, cabsd(nv), i);
+            if (i != p && !used_before(w.used[i], t)) argmax_pair(bv, bi, cabsd(nv), i);
         }
         double ov = 0.0;
         int oi = 0;
@@ -257,7 +263,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_step2(cd* __restrict__ M, int
             M[i + (size_t)j * k] = nv;
             if (nextA) {
                 outA[i] = nv;
-                if (i != p && i != p1 && !w.used[i]) argmax_pair(bv, bi, cabsd(nv), i);
+                if (i != p && i != p1 && !used_before(w.used[i], t)) argmax_pair(bv, bi, cabsd(nv), i);
             }
             if (nextB) outB[i] = nv;
         }
@@ -270,11 +276,11 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_step2(cd* __restrict__ M, int
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         w.perm[t] = p;
-        w.used[p] = 1;
+        w.used[p] = t + 1;
         logpiv[t] = zero ? -1e300 : log(cabsd(piv));
         if (zero || !(piv.x == piv.x) || !(piv.y == piv.y)) *flag = 1;
         w.perm[t + 1] = p1;
-        w.used[p1] = 1;
+        w.used[p1] = t + 2;
         logpiv[t + 1] = zero1 ? -1e300 : log(cabsd(piv1));
         if (zero1 || !(piv1.x == piv1.x) || !(piv1.y == piv1.y)) *flag = 1;
     }

@@ -582,6 +582,13 @@ def test_schur_deflation_matches_oracle(osa, haar3_schur):
     assert np.array_equal(Y[0], host(y))
     assert rel(Y[1], O.sign_eig_apply(h, xin)) < 1e-9
     assert not Y[2].any() and infs[2]["k_used"] == 0
+    # fewer active pairs rebuild S and T from the leading right vectors
+    ctx.set_active_deflation(6)
+    ctx.set_opts(k_max=60, check_every=-1, deflation=osa.SCHUR)
+    y6, _, st = ctx.apply(dev(b))
+    s6, t6 = O.schur_basis(r[:, :6], mv)
+    assert st == osa.OSA_OK
+    assert rel(host(y6), O.schur_arnoldi_sign(mv, b, s6, t6, k=60)[0]) < 1e-9
     ctx.close()
 
 
