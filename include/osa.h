@@ -209,7 +209,8 @@ OSA_API osa_status osa_apply(osa_ctx* ctx, int32_t nrhs, const void* B, void* Y,
  * H(-mu), and the deflation data of H(mu) serves unchanged with the roles of
  * the left and right eigenvectors exchanged and lambda -> conj(lambda) (the
  * same signs of Re lambda); the remark on sign(H) and sign(H)^dag in the
- * results section. */
+ * results section.  Needs LR deflation data (left vectors): under Schur
+ * deflation (opts.deflation = 1) it returns OSA_ERR_STATE. */
 OSA_API osa_status osa_apply_adjoint(osa_ctx* ctx, int32_t nrhs, const void* B, void* Y,
                                      double tol, osa_info* infos);
 
