@@ -374,6 +374,7 @@ def fig1_study(args):
     import lattice_inputs as LI
     import paper_0710_0341_amd as osa
     mu, m_w, eps_target = 0.3, -1.5, 1e-8
+    scheme = osa.SCHUR if args.deflation == "schur" else osa.LR
     out = {}
     t_all = time.perf_counter()
     for (dims, ms), (kind, leps) in [(a, b) for b in (("haar", 0.0), ("disordered", 0.6))
@@ -382,7 +383,7 @@ def fig1_study(args):
         tag = kind + "_" + "x".join(str(d) for d in dims)
         links = torch.from_numpy(LI.make_links(dims, kind, eps=leps, cfg=5, inst=0)).to("cuda:0")
         x = torch.from_numpy(LI.ones_source(dims)).to("cuda:0")
-        ctx = osa.Context(links, dims, mu, m_w, k_max=1500, check_every=25)
+        ctx = osa.Context(links, dims, mu, m_w, k_max=1500, check_every=25, deflation=scheme)
         dinfo = ctx.deflate(max(ms))
         yref, info, st = ctx.apply(x, tol=1e-12, check=False)
         print(f"fig1 {tag}: m={max(ms)} eigensearch {dinfo['t_init_ms'] / 1e3:.1f} s, reference "
@@ -394,7 +395,7 @@ def fig1_study(args):
             ctx.set_active_deflation(m)
             errs = []
             for k in FIG1_KS:
-                ctx.set_opts(k_max=k, check_every=-1)
+                ctx.set_opts(k_max=k, check_every=-1, deflation=scheme)
                 y, inf, st = ctx.apply(x, tol=1e-12, check=False)
                 err = torch.linalg.vector_norm(y - yref).item() / nref if st >= 0 else float("nan")
                 errs.append(err)
@@ -402,7 +403,7 @@ def fig1_study(args):
             hit = [k for k, e in zip(FIG1_KS, errs) if e <= eps_target]
             print(f"fig1 {tag}: m={m} ({m / N:.4f} N) eps(k={FIG1_KS[-1]})={errs[-1]:.1e} "
                   f"k(1e-8)={hit[0] if hit else None}", file=sys.stderr, flush=True)
-            ctx.set_opts(k_max=1500, check_every=25)
+            ctx.set_opts(k_max=1500, check_every=25, deflation=scheme)
         ctx.close()
         out[tag] = {"N": N, "m": ms, "k": FIG1_KS,
                     "eps": {str(m): [float("%.3e" % e) for e in curves[m]] for m in ms},
@@ -410,7 +411,8 @@ def fig1_study(args):
                                                 if e <= eps_target), None) for m in ms},
                     "reference": {"m": max(ms), "k": info[0]["k_used"],
                                   "resid_est": info[0]["resid_est"]}}
-    print(json.dumps({"study": "fig1_eps_vs_k", "mu": mu, "m_w": m_w, "links": "synthetic",
+    print(json.dumps({"study": "fig1_eps_vs_k", "deflation": args.deflation, "mu": mu,
+                      "m_w": m_w, "links": "synthetic",
                       "source": "ones", "eps_target": eps_target,
                       "seconds": round(time.perf_counter() - t_all, 1), "lattices": out}))
 
