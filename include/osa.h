@@ -289,6 +289,22 @@ OSA_API osa_status osa_profile_read(osa_ctx* ctx, osa_profile* out);
  * valid until the next call on the context. */
 OSA_API const char* osa_last_message(const osa_ctx* ctx);
 
+/* Device workspace allocator (process-wide).  With alloc and dealloc set, every
+ * workspace buffer created afterwards comes from alloc(bytes, stream, user)
+ * and returns through dealloc(ptr, stream, user) (stream is always NULL: the
+ * workspace lives as long as its context, outside stream order).  The library
+ * synchronises the device after each alloc and before each dealloc, so the
+ * allocator may hand out blocks last used on any stream (a caching allocator
+ * such as PyTorch's).  A buffer is returned through the hook that allocated
+ * it, so the hook's functions must stay callable until every context created
+ * under it is destroyed.  alloc returning NULL makes the calling entry point
+ * fail with OSA_ERR_OOM.  Both NULL restores hipMalloc/hipFree; exactly one NULL
+ * is OSA_ERR_ARG.  Pinned host staging buffers always use hipHostMalloc.
+ * Not safe to call while another thread is inside the library. */
+OSA_API osa_status osa_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* user),
+                                     void (*dealloc)(void* ptr, void* stream, void* user),
+                                     void* user);
+
 OSA_API void osa_destroy(osa_ctx* ctx);
 OSA_API const char* osa_status_string(osa_status s);
 OSA_API const char* osa_version(void);

@@ -36,8 +36,13 @@ EXPORTS = ["overlap_sign_apply", "osa_create", "osa_deflate", "osa_set_deflation
            "osa_apply_overlap", "osa_batch_apply",
            "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_small_schur", "osa_set_links",
            "osa_profile_enable", "osa_profile_read", "osa_last_message", "osa_destroy",
-           "osa_status_string",
+           "osa_status_string", "osa_set_allocator",
            "osa_version"]
+
+# device workspace allocator hook: alloc(bytes, stream, user), dealloc(ptr, stream, user)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+DEALLOC_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_hooks = []   # every registered callback pair stays alive: buffers return through their own
 
 
 class Lattice(ctypes.Structure):
@@ -129,11 +134,36 @@ def lib() -> ctypes.CDLL:
     L.osa_status_string.argtypes = [i32]
     L.osa_status_string.restype = ctypes.c_char_p
     L.osa_version.restype = ctypes.c_char_p
+    L.osa_set_allocator.argtypes = [ALLOC_FN, DEALLOC_FN, vp]
     for name in EXPORTS:
         if name not in ("osa_destroy", "osa_status_string", "osa_version", "osa_last_message"):
             getattr(L, name).restype = i32
     _lib = L
     return L
+
+
+def use_torch_allocator(enable=True):
+    """Route the library's device workspace through PyTorch's caching allocator
+    (osa_set_allocator), or back to hipMalloc with enable=False.  Contexts keep
+    the allocator they were given buffers from."""
+    L = lib()
+    if not enable:
+        _check(L.osa_set_allocator(ALLOC_FN(), DEALLOC_FN(), None), "osa_set_allocator", False)
+        return
+    torch = _torch()
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:   # out of memory: the library reports OSA_ERR_OOM
+            return None
+
+    def _free(ptr, stream, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    pair = (ALLOC_FN(_alloc), DEALLOC_FN(_free))
+    _hooks.append(pair)
+    _check(L.osa_set_allocator(pair[0], pair[1], None), "osa_set_allocator", False)
 
 
 def _check(status, where, allow_not_converged=True):

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <exception>
 #include <string>
@@ -30,22 +31,64 @@ using namespace osa;
 
 namespace {
 
+// Process-wide allocation hook for device workspace (osa_set_allocator); each
+// buffer keeps the hook that allocated it, so a later change of the hook does
+// not mix allocators.
+struct AllocHook {
+    void* (*alloc)(size_t, void*, void*) = nullptr;   // (bytes, stream, user)
+    void (*dealloc)(void*, void*, void*) = nullptr;   // (ptr, stream, user)
+    void* user = nullptr;
+};
+std::mutex g_alloc_mu;
+AllocHook g_alloc;
+
+AllocHook current_alloc_hook() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    AllocHook hook{};
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (hook.dealloc) {
+                // the hook's allocator may hand the block out again at once: let
+                // every queued kernel finish first (hipFree does the same)
+                (void)hipDeviceSynchronize();
+                hook.dealloc(p, nullptr, hook.user);
+            } else {
+                (void)hipFree(p);
+            }
+        }
         p = nullptr;
         bytes = 0;
+        hook = AllocHook{};
     }
     void ensure(size_t b) {
         if (b <= bytes && p) return;
         release();
         if (b == 0) b = 16;
+        const AllocHook h = current_alloc_hook();
+        if (h.alloc) {
+            p = h.alloc(b, nullptr, h.user);
+            if (!p) throw std::bad_alloc();
+            // the block may come from work still queued on another stream
+            if (hipDeviceSynchronize() != hipSuccess) {
+                (void)hipGetLastError();
+                h.dealloc(p, nullptr, h.user);
+                p = nullptr;
+                throw std::bad_alloc();
+            }
+            hook = h;
+            bytes = b;
+            return;
+        }
         hipError_t e = hipMalloc(&p, b);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -1855,6 +1898,16 @@ osa_status apply_impl(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double t
 extern "C" {
 
 const char* osa_version(void) { return "osa 0.1 (gfx950)"; }
+
+osa_status osa_set_allocator(void* (*alloc)(size_t, void*, void*),
+                             void (*dealloc)(void*, void*, void*), void* user) {
+    if ((alloc == nullptr) != (dealloc == nullptr)) return OSA_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.dealloc = dealloc;
+    g_alloc.user = alloc ? user : nullptr;
+    return OSA_OK;
+}
 
 const char* osa_last_message(const osa_ctx* c) { return c ? c->msg.c_str() : ""; }
 

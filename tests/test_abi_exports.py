@@ -67,3 +67,13 @@ def test_argument_errors_before_device_work():
     # null context
     assert lib.osa_apply(None, 1, dummy, dummy, 1e-8, None) == -1
     assert lib.osa_deflate(None, 4, None) == -1
+
+
+def test_allocator_hook_arguments():
+    """osa_set_allocator: exactly one null function is an argument error; both
+    null (the default, hipMalloc) is accepted.  No device work on either path."""
+    L = osa.lib()
+    alloc = osa.ALLOC_FN(lambda n, s, u: None)
+    assert L.osa_set_allocator(alloc, osa.DEALLOC_FN(), None) == -1
+    assert L.osa_set_allocator(osa.ALLOC_FN(), osa.DEALLOC_FN(lambda p, s, u: None), None) == -1
+    assert L.osa_set_allocator(osa.ALLOC_FN(), osa.DEALLOC_FN(), None) == 0

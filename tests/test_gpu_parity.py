@@ -616,3 +616,35 @@ def test_schur_vs_lr_and_state_errors(osa, haar3_schur):
     assert rel(ys, O.schur_arnoldi_sign(lambda x: h @ x, b, s, t, k=60)[0]) < 1e-9
     cs.close()
     cl.close()
+
+
+def test_torch_allocator_hook(osa):
+    """Workspace from PyTorch's caching allocator (osa_set_allocator): the same
+    solve gives bitwise the hipMalloc result; torch accounts for the workspace
+    while the context lives and gets it back when the context is destroyed."""
+    import torch
+    dims = (3, 3, 3, 3)
+    links = dev(LI.make_links(dims, "haar", cfg=0, inst=11))
+    b = dev(LI.gaussian_source(dims, cfg=0, inst=11))
+    say("allocator hook: hipMalloc run, then torch caching allocator run")
+    c0 = osa.Context(links, dims, 0.3, -1.5, k_max=300, check_every=20)
+    c0.deflate(8)
+    y0, _, st0 = c0.apply(b, tol=1e-10)
+    c0.close()
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    osa.use_torch_allocator(True)
+    try:
+        c1 = osa.Context(links, dims, 0.3, -1.5, k_max=300, check_every=20)
+        c1.deflate(8)
+        y1, _, st1 = c1.apply(b, tol=1e-10)
+        torch.cuda.synchronize()
+        held = torch.cuda.memory_allocated() - base
+        assert st0 == st1 == osa.OSA_OK
+        assert torch.equal(y0, y1)
+        assert held > 300 * 12 * 81 * 16          # at least the Krylov basis
+        c1.close()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() - base < held
+    finally:
+        osa.use_torch_allocator(False)
