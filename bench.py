@@ -66,11 +66,12 @@ def parse():
     ap.add_argument("--eig-prec", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--eig-ncv", type=int, default=0,
                     help="eigensolver active block (0: the library default)")
-    ap.add_argument("--workload", choices=["dis8", "haar4", "uneven64", "dis16", "fig1"],
+    ap.add_argument("--workload", choices=["dis8", "haar4", "uneven64", "dis16", "fig1", "haar12"],
                     default="dis8",
                     help="uneven64: 64 independent instances (6^4/8^4/10^4), solved "
                          "concurrently; dis16: 16^4, 12 point sources in one lockstep batch; "
-                         "fig1: the error-vs-Krylov-size study of the results section")
+                         "fig1: the error-vs-Krylov-size study of the results section; "
+                         "haar12: 12^4 with FP32 links, FP32 vs FP64 eigensearch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--solve-only", action="store_true",
@@ -359,6 +360,53 @@ FIG1_LATTICES = [((4, 4, 4, 4), [0, 5, 10, 15, 25]), ((6, 6, 6, 6), [0, 12, 24, 
 FIG1_KS = list(range(25, 801, 25))
 
 
+def mixed12(args):
+    """12^4 Haar links stored FP32 (rounded once: that array is the instance),
+    m_w = -1.8, mu = 0.3, m = 30, Gaussian source.  The critical pairs from an
+    FP32 Krylov-Schur search refined in FP64 and from an all-FP64 search; one
+    solve with each (k <= 2000, tol 1e-8), their difference, and the Krylov
+    size this operator needs."""
+    import torch
+
+    import lattice_inputs as LI
+    import paper_0710_0341_amd as osa
+    w = LI.WORKLOADS[2]
+    dims = w["dims"]
+    links = torch.from_numpy(LI.make_links(dims, "haar", cfg=2, inst=0)
+                             .astype(np.complex64)).to("cuda:0")
+    b = torch.from_numpy(LI.gaussian_source(dims, cfg=2, inst=0)).to("cuda:0")
+    kmax = 2000
+    out = {"workload": "haar12_fp32links", "lattice": list(dims), "m_w": w["m_w"], "mu": w["mu"],
+           "n_defl": w["n_defl"], "tol": w["tol"], "k_max": kmax,
+           "deflation": args.deflation}
+    scheme = osa.SCHUR if args.deflation == "schur" else osa.LR
+    ys = {}
+    for name, prec in (("fp32_search", osa.FP32), ("fp64_search", osa.FP64)):
+        ctx = osa.Context(links, dims, w["mu"], w["m_w"], k_max=kmax, check_every=50,
+                          eig_prec=prec, deflation=scheme)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dinfo = ctx.deflate(w["n_defl"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        y, infos, st = ctx.apply(b, tol=w["tol"], check=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ys[name] = y
+        out[name] = {"eig_s": round(t1 - t0, 2), "eig_matvecs": dinfo["eig_matvecs"],
+                     "min_abs_re_lambda": dinfo["min_abs_re_lambda"],
+                     "max_eig_resid": dinfo["max_eig_resid"], "solve_s": round(t2 - t1, 3),
+                     "k_used": infos[0]["k_used"], "resid_est": infos[0]["resid_est"],
+                     "status": int(st)}
+        print(f"haar12 {name}: eig {t1 - t0:.1f} s, k_used {infos[0]['k_used']}, "
+              f"est {infos[0]['resid_est']:.1e}, solve {t2 - t1:.2f} s", file=sys.stderr,
+              flush=True)
+        ctx.close()
+    d = torch.linalg.vector_norm(ys["fp32_search"] - ys["fp64_search"]).item()
+    out["rel_diff_fp32_vs_fp64_search"] = d / torch.linalg.vector_norm(ys["fp64_search"]).item()
+    print(json.dumps(out))
+
+
 def fig1_study(args):
     """The convergence study of the results section (Fig. 1): relative error of
     the LR-deflated approximation (Eq. 22) against the Krylov size k, for several
@@ -434,6 +482,9 @@ def main():
         return
     if args.workload == "fig1":
         fig1_study(args)
+        return
+    if args.workload == "haar12":
+        mixed12(args)
         return
     import torch
 
