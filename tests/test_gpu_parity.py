@@ -248,14 +248,16 @@ def test_converged_matches_dense_haar4(osa, haar4_dense):
     ctx.close()
 
 
-@pytest.mark.parametrize("ncv,filt", [(96, 0), (32, 0), (0, 128), (32, 40)])
-def test_deflation_matches_oracle_eigenpairs(osa, haar4_dense, ncv, filt):
+@pytest.mark.parametrize("ncv,filt,prec", [(96, 0, 0), (32, 0, 0), (0, 128, 0), (32, 40, 0),
+                                           (0, 0, 1)])
+def test_deflation_matches_oracle_eigenpairs(osa, haar4_dense, ncv, filt, prec):
     """Krylov-Schur (filt 0) with both Schur kernels: the LDS one (active block
     <= 64) and the logged one (<= 96); the Chebyshev-filtered subspace iteration
-    (degree filt) with its default block and with a 32-vector block."""
+    (degree filt) with its default block and with a 32-vector block; an FP32
+    Krylov-Schur search (prec 1) whose subspace is refined in FP64."""
     dims, links, b, h, _ = haar4_dense
-    say(f"haar4 eigenpairs vs dense oracle, block {ncv}, filter {filt}")
-    ctx = osa.Context(dev(links), dims, 0.3, -1.5, eig_ncv=ncv, eig_filter=filt)
+    say(f"haar4 eigenpairs vs dense oracle, block {ncv}, filter {filt}, prec {prec}")
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, eig_ncv=ncv, eig_filter=filt, eig_prec=prec)
     ctx.deflate(10)
     R, L, lam = ctx.get_deflation()
     R, L = host(R).T, host(L).T
