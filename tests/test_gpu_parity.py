@@ -594,6 +594,11 @@ def test_schur_deflation_matches_oracle(osa, haar3_schur):
     ctx.close()
 
 
+def torch_equal(a, b):
+    import torch
+    return bool(torch.equal(a, b))
+
+
 def test_schur_vs_lr_and_state_errors(osa, haar3_schur):
     """Results section: Schur deflation needs only right eigenvectors (about half
     the eigensolver's stencil applications of LR) at about LR's accuracy.  Data
@@ -612,6 +617,15 @@ def test_schur_vs_lr_and_state_errors(osa, haar3_schur):
     cs.set_opts(k_max=60, check_every=-1)          # LR solve on right-only data
     _, _, st = cs.apply(dev(b), check=False)
     assert st == osa.OSA_ERR_STATE
+    # right-only data moves between contexts: export without L, import with L = None
+    with pytest.raises(osa.OsaError):
+        cs.get_deflation()                          # no left vectors to export
+    R, _, lam = cs.get_deflation(left=False)
+    cs.set_opts(k_max=60, check_every=-1, deflation=osa.SCHUR)
+    c2 = osa.Context(dev(links), dims, 0.3, -1.5, k_max=60, check_every=-1, deflation=osa.SCHUR)
+    c2.set_deflation(R, None, lam)
+    assert torch_equal(cs.apply(dev(b))[0], c2.apply(dev(b))[0])
+    c2.close()
     # LR data serves Schur solves as well (only R is used)
     cl.set_opts(k_max=60, check_every=-1, deflation=osa.SCHUR)
     ys = host(cl.apply(dev(b))[0])
