@@ -35,7 +35,9 @@ def build(verbose: bool = False) -> str:
     """Compile all HIP sources into one shared library; returns its path."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-o", tmp] + srcs
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = [hipcc()] + FLAGS + ["-o", tmp] + srcs + [f"-L{rocm}/lib", "-lrocblas",
+                                                    f"-Wl,-rpath,{rocm}/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)

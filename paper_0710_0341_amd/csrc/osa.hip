@@ -25,6 +25,8 @@
 #include <thread>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "kernels.hpp"
 
 using namespace osa;
@@ -221,7 +223,9 @@ struct osa_ctx {
     std::vector<hipEvent_t> prof_pool;
     osa_profile prof{};
     std::string msg;
+    rocblas_handle blas = nullptr;   // Newton-Schulz GEMMs of the small sign
     ~osa_ctx() {
+        if (blas) (void)rocblas_destroy_handle(blas);
         for (auto& p : prof_pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
         for (auto e : prof_pool) (void)hipEventDestroy(e);
         if (own_stream && st) (void)hipStreamDestroy(st);
@@ -586,6 +590,9 @@ __global__ __launch_bounds__(256) void k_schur_x_fix(int m, int j, cd* __restric
     }
 }
 
+// Newton change below which the small sign continues by Newton-Schulz steps
+constexpr double kNsSwitch = 1e-2;
+
 // sign of the k x k matrices A (or, with sb, of the Schur block matrices of
 // size m + k); s_out receives the first column (with sb: sign times [c0; beta e_1])
 void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd* A, int lda,
@@ -625,6 +632,12 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
     OSA_HIP(hipMemsetAsync(c->nflag.p, 0, c->nflag.bytes, c->st));
     uint64_t scale = ~0ULL;
     std::vector<double> prev(c->kbatch, INFINITY);
+    // problems in the Newton-Schulz phase: X <- (3X - X^3)/2 by two GEMMs instead
+    // of an inverse, once the unscaled Newton change is below kNsSwitch.  With
+    // X = S(1 + E) (every iterate is a function of H, so E commutes with S) the
+    // error maps to E' = -(3/2)E^2 - E^3/2, quadratic as in Newton's E^2/(2(1+E)).
+    // A step that does not halve the change returns the problem to Newton.
+    std::vector<char> nsm(c->kbatch, 0);
     double* red = c->red.as<double>();
     std::vector<double> hred;
     std::vector<int> hflag;
@@ -632,12 +645,48 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
         Batch ba = bt;
         ba.n = (int)act.size();
         for (int i = 0; i < ba.n; ++i) ba.idx[i] = (int16_t)act[i];
-        Batch bc = ba;   // M <- X: X has leading dimension n
-        bc.basis = ms;
-        launch_copy_square(X, n, M, n, c->st, bc);
-        timed(c, 3, 2.0 * 16.0 * n * (double)n * ba.n, [&] {
-            gj_invert(M, Y, n, c->logpiv.as<double>(), c->nflag.as<int>(), c->gjws.p, c->st, ba);
-        });
+        std::vector<int> gjl, nsl;
+        for (int b : act) (nsm[b] ? nsl : gjl).push_back(b);
+        if (!gjl.empty()) {
+            Batch bg = bt;
+            bg.n = (int)gjl.size();
+            for (int i = 0; i < bg.n; ++i) bg.idx[i] = (int16_t)gjl[i];
+            Batch bc = bg;   // M <- X: X has leading dimension n
+            bc.basis = ms;
+            launch_copy_square(X, n, M, n, c->st, bc);
+            timed(c, 3, 2.0 * 16.0 * n * (double)n * bg.n, [&] {
+                gj_invert(M, Y, n, c->logpiv.as<double>(), c->nflag.as<int>(), c->gjws.p, c->st,
+                          bg);
+            });
+        }
+        if (!nsl.empty()) {
+            // Y = 2X - X (X X), so that the combine (X + Y)/2 is the Newton-Schulz step
+            if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
+                c->blas = nullptr;
+                throw OsaError{OSA_ERR_HIP, "rocblas_create_handle"};
+            }
+            if (rocblas_set_stream(c->blas, c->st) != rocblas_status_success)
+                throw OsaError{OSA_ERR_HIP, "rocblas_set_stream"};
+            const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0), two(2.0, 0.0),
+                mone(-1.0, 0.0);
+            timed(c, 3, 3.0 * 16.0 * n * (double)n * nsl.size(), [&] {
+                for (int b : nsl) {
+                    auto* Xb = reinterpret_cast<rocblas_double_complex*>(X + b * ms);
+                    auto* Mb = reinterpret_cast<rocblas_double_complex*>(M + b * ms);
+                    auto* Yb = reinterpret_cast<rocblas_double_complex*>(Y + b * ms);
+                    rocblas_status r1 = rocblas_zgemm(c->blas, rocblas_operation_none,
+                                                      rocblas_operation_none, n, n, n, &one, Xb, n,
+                                                      Xb, n, &zero, Mb, n);
+                    OSA_HIP(hipMemcpyAsync(Yb, Xb, sizeof(cd) * (size_t)n * n,
+                                           hipMemcpyDeviceToDevice, c->st));
+                    rocblas_status r2 = rocblas_zgemm(c->blas, rocblas_operation_none,
+                                                      rocblas_operation_none, n, n, n, &mone, Xb,
+                                                      n, Mb, n, &two, Yb, n);
+                    if (r1 != rocblas_status_success || r2 != rocblas_status_success)
+                        throw OsaError{OSA_ERR_HIP, "rocblas_zgemm"};
+                }
+            });
+        }
         launch_newton_combine(X, Y, n, c->logpiv.as<double>(), scale, red, c->st, ba);
         d2h_strided(c, red, c->red_stride * (int64_t)sizeof(double), 2, act, hred);
         d2h_strided(c, c->nflag.p, 4 * (int64_t)sizeof(int), 1, act, hflag);
@@ -650,6 +699,8 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
             if (hflag[i] || !std::isfinite(d2) || !std::isfinite(n2)) { iters[b] = -it; continue; }
             const double change = std::sqrt(d2 / n2);
             if (change < 1e-2) scale &= ~(1ULL << b);
+            if (nsm[b] && !(change < 0.5 * prev[b])) nsm[b] = 0;   // back to Newton
+            else if (!nsm[b] && change < kNsSwitch && !((scale >> b) & 1ULL)) nsm[b] = 1;
             // converged: at rounding level, stagnating below 1e-8, or below 1e-8 in
             // the quadratic regime (change <= 10 prev^2), where the new iterate's
             // error is about change^2 and one more step would only confirm it
