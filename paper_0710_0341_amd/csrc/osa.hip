@@ -591,7 +591,7 @@ __global__ __launch_bounds__(256) void k_schur_x_fix(int m, int j, cd* __restric
 }
 
 // Newton change below which the small sign continues by Newton-Schulz steps
-constexpr double kNsSwitch = 1e-2;
+constexpr double kNsSwitch = 5e-2;
 
 // sign of the k x k matrices A (or, with sb, of the Schur block matrices of
 // size m + k); s_out receives the first column (with sb: sign times [c0; beta e_1])
@@ -698,7 +698,7 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
             iters[b] = it;
             if (hflag[i] || !std::isfinite(d2) || !std::isfinite(n2)) { iters[b] = -it; continue; }
             const double change = std::sqrt(d2 / n2);
-            if (change < 1e-2) scale &= ~(1ULL << b);
+            if (change < std::max(1e-2, kNsSwitch)) scale &= ~(1ULL << b);
             if (nsm[b] && !(change < 0.5 * prev[b])) nsm[b] = 0;   // back to Newton
             else if (!nsm[b] && change < kNsSwitch && !((scale >> b) & 1ULL)) nsm[b] = 1;
             // converged: at rounding level, stagnating below 1e-8, or below 1e-8 in
