@@ -590,6 +590,12 @@ __global__ __launch_bounds__(256) void k_schur_x_fix(int m, int j, cd* __restric
     }
 }
 
+// M <- M - I (n x n, ld n)
+__global__ void k_sub_identity(cd* M, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) M[i + (int64_t)i * n].x -= 1.0;
+}
+
 // Newton change below which the small sign continues by Newton-Schulz steps
 constexpr double kNsSwitch = 5e-2;
 
@@ -645,8 +651,43 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
         Batch ba = bt;
         ba.n = (int)act.size();
         for (int i = 0; i < ba.n; ++i) ba.idx[i] = (int16_t)act[i];
-        std::vector<int> gjl, nsl;
-        for (int b : act) (nsm[b] ? nsl : gjl).push_back(b);
+        std::vector<int> gjl, nsc, nsl;
+        for (int b : act) (nsm[b] ? nsc : gjl).push_back(b);
+        const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0), mone(-1.0, 0.0);
+        if (!nsc.empty()) {
+            // Newton-Schulz candidates: D = X X - I.  The step converges to sign(X)
+            // when |I - X^2| < 1 (Frobenius norm here, with margin 0.5); otherwise an
+            // eigenvalue of X may lie where (3x - x^3)/2 flips its sign, and the
+            // problem takes a Newton step instead.
+            if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
+                c->blas = nullptr;
+                throw OsaError{OSA_ERR_HIP, "rocblas_create_handle"};
+            }
+            if (rocblas_set_stream(c->blas, c->st) != rocblas_status_success ||
+                rocblas_set_pointer_mode(c->blas, rocblas_pointer_mode_host) !=
+                    rocblas_status_success)
+                throw OsaError{OSA_ERR_HIP, "rocblas_set_stream"};
+            for (int b : nsc) {
+                auto* Xb = reinterpret_cast<rocblas_double_complex*>(X + b * ms);
+                auto* Mb = reinterpret_cast<rocblas_double_complex*>(M + b * ms);
+                double dn = INFINITY;
+                rocblas_status r1 = rocblas_zgemm(c->blas, rocblas_operation_none,
+                                                  rocblas_operation_none, n, n, n, &one, Xb, n, Xb,
+                                                  n, &zero, Mb, n);
+                hipLaunchKernelGGL(k_sub_identity, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0,
+                                   c->st, M + b * ms, n);
+                OSA_LAUNCH_CHECK();
+                rocblas_status r2 = rocblas_dznrm2(c->blas, n * n, Mb, 1, &dn);   // synchronous
+                if (r1 != rocblas_status_success || r2 != rocblas_status_success)
+                    throw OsaError{OSA_ERR_HIP, "rocblas_zgemm / rocblas_dznrm2"};
+                if (dn < 0.5) {
+                    nsl.push_back(b);
+                } else {
+                    nsm[b] = 0;
+                    gjl.push_back(b);
+                }
+            }
+        }
         if (!gjl.empty()) {
             Batch bg = bt;
             bg.n = (int)gjl.size();
@@ -660,29 +701,18 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
             });
         }
         if (!nsl.empty()) {
-            // Y = 2X - X (X X), so that the combine (X + Y)/2 is the Newton-Schulz step
-            if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
-                c->blas = nullptr;
-                throw OsaError{OSA_ERR_HIP, "rocblas_create_handle"};
-            }
-            if (rocblas_set_stream(c->blas, c->st) != rocblas_status_success)
-                throw OsaError{OSA_ERR_HIP, "rocblas_set_stream"};
-            const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0), two(2.0, 0.0),
-                mone(-1.0, 0.0);
+            // Y = X - X D = 2X - X (X X), so that the combine (X + Y)/2 is the
+            // Newton-Schulz step (3X - X^3)/2
             timed(c, 3, 3.0 * 16.0 * n * (double)n * nsl.size(), [&] {
                 for (int b : nsl) {
                     auto* Xb = reinterpret_cast<rocblas_double_complex*>(X + b * ms);
                     auto* Mb = reinterpret_cast<rocblas_double_complex*>(M + b * ms);
                     auto* Yb = reinterpret_cast<rocblas_double_complex*>(Y + b * ms);
-                    rocblas_status r1 = rocblas_zgemm(c->blas, rocblas_operation_none,
-                                                      rocblas_operation_none, n, n, n, &one, Xb, n,
-                                                      Xb, n, &zero, Mb, n);
                     OSA_HIP(hipMemcpyAsync(Yb, Xb, sizeof(cd) * (size_t)n * n,
                                            hipMemcpyDeviceToDevice, c->st));
-                    rocblas_status r2 = rocblas_zgemm(c->blas, rocblas_operation_none,
-                                                      rocblas_operation_none, n, n, n, &mone, Xb,
-                                                      n, Mb, n, &two, Yb, n);
-                    if (r1 != rocblas_status_success || r2 != rocblas_status_success)
+                    if (rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, n,
+                                      n, n, &mone, Xb, n, Mb, n, &one, Yb, n) !=
+                        rocblas_status_success)
                         throw OsaError{OSA_ERR_HIP, "rocblas_zgemm"};
                 }
             });
