@@ -514,3 +514,22 @@ def test_block_krylov_exact_on_full_space_and_contains_single_spaces(haar2):
         for i in range(4):
             ys, _ = O.lr_arnoldi_sign(lambda x: h @ x, b[:, i], defl, k=k)
             assert rel(yb[:, i], yx[:, i]) < 3 * rel(ys, yx[:, i]), (k, i)
+
+
+def test_newton_schulz_tail_reading(haar2):
+    """The small-sign reading used on the GPU: once |X^2 - I|_F < 0.5, Newton-Schulz
+    steps X <- (3X - X^3)/2 from a Newton iterate converge to the same sign as the
+    spectral definition; without that condition an eigenvalue beyond sqrt(3) is
+    flipped (2 -> -1), which is why the check is needed."""
+    dims, u, h = haar2
+    x = np.array(h, dtype=complex)
+    eye = np.eye(len(h))
+    for _ in range(60):                       # plain Newton until the condition holds
+        if np.linalg.norm(x @ x - eye) < 0.5:
+            break
+        x = 0.5 * (x + np.linalg.inv(x))
+    assert np.linalg.norm(x @ x - eye) < 0.5
+    for _ in range(30):
+        x = 0.5 * (3 * x - x @ x @ x)
+    assert np.abs(x - O.sign_eig(h)).max() < 1e-10
+    assert 0.5 * (3 * 2.0 - 2.0 ** 3) == -1.0
