@@ -1,22 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark: sign(H_w(mu)) b solves per second on one MI355X.
 
-Workload (the headline single-GPU configuration): 8^4 lattice (N = 49152),
-disordered links U = exp(i eps H) with eps = 0.6, m_w = -1.5, mu in {0.1, 0.5},
-one Gaussian source, Krylov size up to 600, deflating 20 and 40 critical
-eigenpairs, tolerance 1e-10.  One step runs the whole hot path for both
-values of mu: ingest the links, compute the 40 critical left/right eigenpairs,
-then solve with m = 20 and with m = 40 (4 solves per step).  All inputs are
-resident in GPU memory before the timed region starts.  Kernel classes are
-timed with HIP events on one launch in PROF_EVERY (all launches are counted).
+Headline workload (the configuration the metric is quoted on): 16^4 lattice
+(N = 786432), disordered links U = exp(i eps H) with eps = 0.5 stored FP32,
+m_w = -1.5, mu = 0.2, the 12 spin-colour point sources of site 0, a shared LR
+deflation basis of 40 critical eigenpairs (Eq. 20-22), Krylov size up to 500,
+tol 1e-8.  The deflation data is computed once before the timed region (the
+paper's initialisation phase, reusable for every source of the operator) and
+reported as init_ms.  One step = one lockstep solve of the 12 sources
+(osa_apply with max_batch 12): stencil, LR projection, Arnoldi with
+Gram-Schmidt, convergence checks with the small sign, assembly.  The "plain"
+figure is the same 12 solved one at a time by the single-source FP64 path on
+the same context; both must give bitwise equal results.  Inputs are resident
+in GPU memory before the timed region starts.
 
-The "batched" record compares, on the same operator and deflation data
-(mu = 0.5, m = 40), the 12 spin-colour point sources of one site solved one at
-a time against the same 12 solved in one lockstep batch (stencil links read
-once per step for the batch, shared launches for the Gram-Schmidt passes and
-the small sign); both runs must give bitwise equal results.
+Kernel classes are timed with HIP events on the launching stream on one
+launch in PROF_EVERY (all launches are counted); the roofline object reports
+the dominant class.  cpu_baseline times the oracle's Eq. 22 (numpy/scipy) on
+one source at a fixed Krylov size on the host cores, beside the GPU at the
+same fixed size.
 
-Prints one JSON line (see the fields at the end of main()).
+Other workloads: --workload dis8 (8^4, eigensolver inside every step),
+haar4, haar12 (mixed precision), uneven64, fig1.
+
+Prints one JSON line (see the fields at the end of each workload function).
 """
 from __future__ import annotations
 
@@ -33,43 +40,125 @@ sys.path.insert(0, ROOT)
 
 PROF_EVERY = 16   # event-bracket one launch in 16 of each kernel class in the timed steps
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cgs_dot_dis8_hbm_traffic.json")
-DOT_SOURCE = os.path.join(ROOT, "paper_0710_0341_amd", "csrc", "blas.hip")
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64, vector and matrix cores (dense)
+PROFILES = os.path.join(ROOT, "profiles")
+
+# kernel classes of osa_profile: the kernels behind each, the bound, and the
+# rocprofv3 counter summary (FETCH_SIZE / WRITE_SIZE) of the class, if any
+CLASS_INFO = {
+    "cgs_dot": ("k_dot_partial + k_dot2_partial", "hbm"),
+    "cgs_update": ("k_update_* + k_dcgs_*", "hbm"),
+    "stencil": ("k_wilson_h", "hbm"),
+    "small_inverse": ("k_gj_*", "alu"),
+    "small_gemm": ("k_zgemm_mfma", "mfma"),
+}
 
 
-def measured_traffic():
-    """HBM bytes per launch of the Gram-Schmidt dot class, from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by the copy-kernel factors it
-    records).  None once the source of the dot kernels and their launch plan (the
-    region of blas.hip the summary records) differs from the one measured."""
+def measured_traffic(cls, workload):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary profiles/<cls>_<workload>_hbm_traffic.json
+    (scaled by the copy-kernel factors it records).  None when there is no
+    summary, or once the kernel source region it records has changed."""
     import hashlib
+    path = os.path.join(PROFILES, f"{cls}_{workload}_hbm_traffic.json")
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
-        with open(DOT_SOURCE) as f:
-            src = f.read()
-        reg = rec["kernel_region"]
-        a, b = src.index(reg["from"]), src.index(reg["to"])
+        for reg in rec["kernel_regions"]:
+            with open(os.path.join(ROOT, reg["file"])) as f:
+                src = f.read()
+            a, b = src.index(reg["from"]), src.index(reg["to"])
+            if hashlib.sha256(src[a:b].encode()).hexdigest() != reg["sha256"]:
+                return None
     except (OSError, ValueError, KeyError):
         return None
-    if hashlib.sha256(src[a:b].encode()).hexdigest() != reg["sha256"]:
-        return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def class_table(profs, steps):
+    """Per kernel class, summed over the given osa_profile dicts: launches
+    (all), event-timed launches, average duration, estimated total per step,
+    algorithmic GB/s and TFLOP/s over the event-timed launches."""
+    agg = {}
+    for p in profs:
+        for k, v in p.items():
+            if k == "counters":
+                continue
+            a = agg.setdefault(k, dict(ms=0.0, bytes=0.0, flops=0.0, launches=0, calls=0))
+            for f in ("ms", "bytes", "flops", "launches", "calls"):
+                a[f] += v[f]
+    out = {}
+    for k, a in agg.items():
+        if not a["launches"]:
+            continue
+        avg = a["ms"] / a["launches"]
+        out[k] = {"launches_per_step": a["calls"] / steps, "avg_us": avg * 1e3,
+                  "ms_per_step": avg * a["calls"] / steps,
+                  "GB/s": a["bytes"] / (a["ms"] * 1e-3) / 1e9 if a["ms"] else 0.0,
+                  "TFLOP/s": a["flops"] / (a["ms"] * 1e-3) / 1e12 if a["ms"] else 0.0,
+                  "bytes_per_launch": a["bytes"] / a["launches"],
+                  "flops_per_launch": a["flops"] / a["launches"],
+                  "event_timed": a["launches"], "calls": a["calls"]}
+    return out
+
+
+def roofline(table, workload):
+    """The roofline object for the dominant class (largest estimated time)."""
+    cands = {k: v for k, v in table.items() if k in CLASS_INFO}
+    dom = max(cands, key=lambda k: cands[k]["ms_per_step"])
+    d = cands[dom]
+    kernels, bound = CLASS_INFO[dom]
+    if bound == "hbm":
+        ach, peak, unit = d["GB/s"], HBM_PEAK_GBS, "GB/s"
+    else:
+        ach, peak, unit = d["TFLOP/s"], FP64_PEAK_TFLOPS, "TFLOP/s"
+    return {"bound": bound, "kernel_class": dom, "kernel": kernels, "achieved": ach,
+            "peak": peak, "unit": unit, "frac": ach / peak,
+            "traffic": measured_traffic(dom, workload) if bound == "hbm" else None,
+            "algorithmic_bytes_per_launch": d["bytes_per_launch"],
+            "algorithmic_flops_per_launch": d["flops_per_launch"],
+            "avg_launch_us": d["avg_us"], "launches_per_step": d["launches_per_step"],
+            "event_timed_launches": d["event_timed"],
+            "share_of_step_kernel_time": d["ms_per_step"] / sum(v["ms_per_step"]
+                                                                for v in table.values())}
+
+
+def host_info():
+    """nproc, the CPU model and the BLAS thread count of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        import threadpoolctl
+        blas = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] + [1])
+    except Exception:
+        pass
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"nproc": nproc, "cpu_model": model, "blas_threads": blas}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eig-prec", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--eig-ncv", type=int, default=0,
                     help="eigensolver active block (0: the library default)")
-    ap.add_argument("--workload", choices=["dis8", "haar4", "uneven64", "dis16", "fig1", "haar12"],
-                    default="dis8",
-                    help="uneven64: 64 independent instances (6^4/8^4/10^4), solved "
-                         "concurrently; dis16: 16^4, 12 point sources in one lockstep batch; "
+    ap.add_argument("--workload", choices=["dis16", "dis8", "haar4", "uneven64", "fig1", "haar12"],
+                    default="dis16",
+                    help="dis16 (headline): 16^4, 12 point sources in one lockstep batch; "
+                         "dis8: 8^4 with the eigensolver inside every step; "
+                         "uneven64: 64 independent instances (6^4/8^4/10^4), solved "
+                         "concurrently; "
                          "fig1: the error-vs-Krylov-size study of the results section; "
                          "haar12: 12^4 with FP32 links, FP32 vs FP64 eigensearch")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -106,39 +195,6 @@ def workload(name):
     w = LI.WORKLOADS[0]
     return dict(name="haar4_mu0.3_mw-1.5", dims=w["dims"], kind="haar", eps=0.0, m_w=w["m_w"],
                 mus=[w["mu"]], ms=[w["n_defl"]], k_max=w["k_max"], tol=w["tol"], cfg=0)
-
-
-def cpu_baseline(wl, k_ref):
-    """The oracle's Eq. 22 apply phase (CGS2 Arnoldi, Newton small sign,
-    assembly) on the same lattice, timed on the host cores.  Bounded sample:
-    two truncated runs (k = 60 and 120) fit T(k) = a k + b k^2, evaluated at
-    the Krylov size the GPU needed.  The eigensolver phase is not sampled."""
-    import lattice_inputs as LI
-    import oracle as O
-    dims = wl["dims"]
-    links = LI.make_links(dims, wl["kind"], eps=wl["eps"], cfg=wl["cfg"], inst=0)
-    b = LI.gaussian_source(dims, cfg=wl["cfg"], inst=0)
-    h = O.hermitian_wilson_sparse(links, dims, wl["mus"][0], wl["m_w"])
-    ts = {}
-    for k in (60, 120):
-        t0 = time.perf_counter()
-        O.lr_arnoldi_sign(lambda x: h @ x, b, None, k=k)
-        ts[k] = time.perf_counter() - t0
-    # T(k) = a k + b k^2 through the two samples
-    bq = (ts[120] / 120 - ts[60] / 60) / 60.0
-    aq = ts[60] / 60 - bq * 60
-    t_solve = aq * k_ref + bq * k_ref * k_ref
-    try:
-        import threadpoolctl
-        info = threadpoolctl.threadpool_info()
-        cores = max([i.get("num_threads", 1) for i in info] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
-    return {"value": 1.0 / t_solve, "unit": "solves/s (apply phase)", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"oracle CGS2 Arnoldi + Newton sign at {dims[0]}^4 for k=60 and k=120 "
-                      f"({ts[60]:.1f}s, {ts[120]:.1f}s), T(k)=a k+b k^2 evaluated at the GPU's "
-                      f"mean k_used={k_ref:.0f}; eigensolver phase not included"}
 
 
 def point_sources(dims, site=0):
@@ -269,91 +325,138 @@ def uneven_batch(args):
         c.close()
 
 
-def batched16(args):
-    """16^4 disordered links (eps = 0.5) stored FP32, m_w = -1.5, mu = 0.2: the 40
-    critical pairs by an FP32 Krylov-Schur search refined in FP64, then the 12
-    spin-colour point sources of one site solved in one lockstep batch (k <= 500,
-    tol 1e-8), and the same 12 one at a time.  Reports the FP32-search error as
-    the difference of the result from an all-FP64 eigensearch on one source."""
+CPU_SAMPLE_K = 30   # Krylov size of the oracle's timed sample at 16^4 (~10-30 s of host work)
+
+
+def cpu_baseline_fixed_k(dims, links_np, mu, m_w, m, b, k, links_dev, cfg):
+    """The oracle's Eq. 22 (CGS2 Arnoldi with the oblique re-projection, Newton
+    small sign, assembly) on one source at the fixed Krylov size k, with an
+    m-pair deflation of the workload's shape (placeholder vectors from the
+    seeded generator: the timing does not depend on their values), on the host
+    cores.  The GPU runs the same fixed-k sample on the same inputs beside it.
+    The sparse H is assembled before timing."""
+    import torch
+
+    import lattice_inputs as LI
+    import oracle as O
+    import paper_0710_0341_amd as osa
+    n = b.shape[0]
+    h = O.hermitian_wilson_sparse(links_np, dims, mu, m_w)
+    r, l, lam = LI.placeholder_deflation(n, m, cfg=cfg, inst=0)
+    defl = O.Deflation(r, l, lam)
+    t0 = time.perf_counter()
+    y_cpu, _ = O.lr_arnoldi_sign(lambda x: h @ x, b, defl, k=k)
+    t_cpu = time.perf_counter() - t0
+    ctx = osa.Context(links_dev, dims, mu, m_w, k_max=k, check_every=-1)
+    ctx.set_deflation(torch.from_numpy(np.ascontiguousarray(r.T)).to("cuda:0"),
+                      torch.from_numpy(np.ascontiguousarray(l.T)).to("cuda:0"), lam)
+    bd = torch.from_numpy(b).to("cuda:0")
+    ctx.apply(bd, tol=1.0)                     # workspace growth
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y_gpu, _, _ = ctx.apply(bd, tol=1.0)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    diff = float(np.linalg.norm(y_gpu.cpu().numpy() - y_cpu) / np.linalg.norm(y_cpu))
+    ctx.close()
+    hi = host_info()
+    lat = "x".join(str(d) for d in dims)
+    return {"value": 1.0 / t_cpu, "unit": f"solves/s at fixed k={k} (one source)",
+            "cores": hi["blas_threads"] or hi["nproc"], "kind": "oracle",
+            "sample": f"oracle Eq. 22 on one source at {lat}, k={k} fixed, m={m} placeholder "
+                      f"deflation, {t_cpu:.1f} s; sparse matvec single-threaded, dense BLAS on "
+                      f"{hi['blas_threads']} threads",
+            "host": hi, "seconds": t_cpu,
+            "gpu_same_sample": {"seconds": t_gpu, "solves_per_s": 1.0 / t_gpu,
+                                "rel_diff_vs_oracle": diff}}
+
+
+def headline16(args):
+    """The headline: 12 point sources at 16^4 (FP32-stored links) in one lockstep
+    batch, against the same 12 one at a time (the plain single-source FP64 GPU
+    path), with the deflation data (m = 40, FP64 Krylov-Schur on the FP32-rounded
+    links) computed once before the timed region."""
     import torch
 
     import lattice_inputs as LI
     import paper_0710_0341_amd as osa
     w = LI.WORKLOADS[3]
-    dims = w["dims"]
-    links = torch.from_numpy(LI.make_links(dims, "disordered", eps=w["eps"], cfg=3, inst=0)
-                             .astype(np.complex64)).to("cuda:0")   # stored FP32
-    B = torch.from_numpy(point_sources(dims)).to("cuda:0")
+    dims, tol = w["dims"], w["tol"]
+    links_np = LI.round_links_fp32(LI.make_links(dims, "disordered", eps=w["eps"], cfg=3, inst=0))
+    links = torch.from_numpy(links_np.astype(np.complex64)).to("cuda:0")   # stored FP32
+    B_np = point_sources(dims)
+    B = torch.from_numpy(B_np).to("cuda:0")
+    nsrc = B.shape[0]
     ctx = osa.Context(links, dims, w["mu"], w["m_w"], k_max=w["k_max"], check_every=50,
-                      eig_prec=osa.FP32, max_batch=12)
+                      max_batch=nsrc)
     torch.cuda.synchronize()
+    print("dis16: deflation (40 pairs)", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    print("dis16: fp32 eigensearch", file=sys.stderr, flush=True)
     dinfo = ctx.deflate(w["n_defl"])
     torch.cuda.synchronize()
-    t_eig = time.perf_counter() - t0
-    print(f"dis16: eigensearch {t_eig:.1f} s", file=sys.stderr, flush=True)
-    ctx.apply(B[:1], tol=w["tol"])                    # workspace growth, untimed
+    init_ms = (time.perf_counter() - t0) * 1e3
+    _, _, lam = ctx.get_deflation(left=False)
+    print(f"dis16: deflation {init_ms / 1e3:.1f} s; warm-up", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ctx.apply(B, tol=tol)
     torch.cuda.synchronize()
-
-    def classes(prof):
-        """per kernel class: launches, average event-timed duration, algorithmic GB/s"""
-        out = {}
-        for k, v in prof.items():
-            if k == "counters" or not v["launches"]:
-                continue
-            out[k] = {"launches": v["calls"], "avg_us": v["ms"] / v["launches"] * 1e3,
-                      "GB/s": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] else 0.0}
-        return out
-
     ctx.profile(True, every=PROF_EVERY)
     t0 = time.perf_counter()
-    Yb, infb, stb = ctx.apply(B, tol=w["tol"])
+    for i in range(args.steps):
+        Y, infos, st = ctx.apply(B, tol=tol)
+        print(f"dis16: step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    kb = classes(ctx.profile_read())
-    print(f"dis16: batch of 12 {t_batch:.1f} s", file=sys.stderr, flush=True)
-    ctx.set_opts(k_max=w["k_max"], check_every=50, eig_prec=osa.FP32, max_batch=1)
+    t1 = time.perf_counter()
+    table = class_table([ctx.profile_read()], args.steps)
+    ctx.profile(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = nsrc * args.steps / (t1 - t0)
+    # the plain single-source path on the same context and sources
+    print("dis16: the 12 sources one at a time", file=sys.stderr, flush=True)
+    ctx.set_opts(k_max=w["k_max"], check_every=50, max_batch=1)
     ctx.profile(True, every=PROF_EVERY)
     t0 = time.perf_counter()
-    Yp, infp, stp = ctx.apply(B, tol=w["tol"])
+    Yp, infp, stp = ctx.apply(B, tol=tol)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    kp = classes(ctx.profile_read())
+    table_plain = class_table([ctx.profile_read()], 1)
     ctx.profile(False)
-    print(f"dis16: 12 one at a time {t_plain:.1f} s; fp64 eigensearch", file=sys.stderr, flush=True)
-    # all-FP64 eigensearch on the same (FP32-rounded) links, first source
-    ctx64 = osa.Context(links, dims, w["mu"], w["m_w"], k_max=w["k_max"], check_every=50)
-    t0 = time.perf_counter()
-    ctx64.deflate(w["n_defl"])
-    torch.cuda.synchronize()
-    t_eig64 = time.perf_counter() - t0
-    y64, _, _ = ctx64.apply(B[:1], tol=w["tol"])
-    err = float(torch.linalg.vector_norm(Yb[0] - y64[0]) / torch.linalg.vector_norm(y64[0]))
+    bitwise = bool(torch.equal(Y, Yp))
     out = {
-        "metric": "sign(H_w(mu)) b solves/sec, 12 sources batched vs plain", "unit": "solves/s",
-        "value": 12.0 / t_batch, "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
-        "dtype": "c128 (links and eigensearch c64)",
+        "metric": "sign(H_w(\u03bc))\u00b7b solves/sec + HBM GB/s at 1e-8 rel err, batched vs plain",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
         "config": {"workload": "dis16_12pt", "lattice": list(dims), "N": 12 * int(np.prod(dims)),
-                   "mu": w["mu"], "m_w": w["m_w"], "eps": w["eps"], "n_defl": w["n_defl"],
-                   "k_max": w["k_max"], "tol": w["tol"]},
-        "batched_ms": t_batch * 1e3, "plain_ms": t_plain * 1e3,
-        "plain_solves_per_s": 12.0 / t_plain, "speedup": t_plain / t_batch,
-        "bitwise_equal": bool(torch.equal(Yb, Yp)),
-        "statuses": sorted(set(int(i["status"]) for i in infb)),
-        "k_used": [i["k_used"] for i in infb],
-        "max_resid_est": max(i["resid_est"] for i in infb),
-        "eig": {"fp32_search_ms": t_eig * 1e3, "matvecs": dinfo["eig_matvecs"],
-                "restarts": dinfo["eig_restarts"], "max_eig_resid": dinfo["max_eig_resid"],
-                "min_abs_re_lambda": dinfo["min_abs_re_lambda"], "fp64_search_ms": t_eig64 * 1e3},
-        "fp32_search_vs_fp64_search_rel_diff": err,
-        "kernels_batched": kb, "kernels_plain": kp,
-        "profiling": f"HIP events on one launch in {PROF_EVERY} of each class; GB/s from "
-                     "algorithmic bytes (peak 8000)",
+                   "links": "disordered eps=0.5, stored FP32", "m_w": w["m_w"], "mu": w["mu"],
+                   "sources": "12 spin-colour point sources at site 0, one lockstep batch",
+                   "n_defl": w["n_defl"], "deflation": "LR (Eq. 20-22), computed once",
+                   "k_max": w["k_max"], "tol": tol, "parallelism": "single GPU"},
+        "roofline": roofline(table, "dis16"),
+        "plain": {"solves_per_s": nsrc / t_plain, "ms": t_plain * 1e3, "status": int(stp),
+                  "kernels": table_plain},
+        "batched_vs_plain": value / (nsrc / t_plain),
+        "bitwise_equal_batched_vs_plain": bitwise,
+        "init_ms": init_ms,
+        "whole_path_solves_per_s": nsrc / (init_ms * 1e-3 + ms_per_step * 1e-3),
+        "kernels": table,
+        "profiling": f"HIP events on one launch in {PROF_EVERY} of each class, on the launching "
+                     "stream, inside the timed region; per-step class time = average x launches",
+        "solve": {"status": int(st), "k_used": [i["k_used"] for i in infos],
+                  "max_resid_est": max(i["resid_est"] for i in infos),
+                  "newton_iters": [i["newton_iters"] for i in infos]},
+        "deflation": {"eig_matvecs": dinfo["eig_matvecs"], "restarts": dinfo["eig_restarts"],
+                      "max_eig_resid": dinfo["max_eig_resid"],
+                      "min_abs_re_lambda": dinfo["min_abs_re_lambda"],
+                      "count_abs_re_below_0.05": int(np.sum(np.abs(lam.real) < 0.05)),
+                      "eigensearch": "FP64 Krylov-Schur on H^2, Rayleigh-Ritz on H"},
     }
-    print(json.dumps(out), flush=True)
     ctx.close()
-    ctx64.close()
+    if not args.no_cpu_baseline:
+        print("dis16: oracle sample on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_fixed_k(dims, links_np, w["mu"], w["m_w"], w["n_defl"],
+                                                   B_np[0], CPU_SAMPLE_K, links, cfg=3)
+    print(json.dumps(out), flush=True)
 
 
 FIG1_LATTICES = [((4, 4, 4, 4), [0, 5, 10, 15, 25]), ((6, 6, 6, 6), [0, 12, 24, 36, 48])]
@@ -478,7 +581,7 @@ def main():
         uneven_batch(args)
         return
     if args.workload == "dis16":
-        batched16(args)
+        headline16(args)
         return
     if args.workload == "fig1":
         fig1_study(args)
@@ -567,26 +670,11 @@ def main():
     n_solves = len(wl["mus"]) * len(wl["ms"])
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n_solves * args.steps / (t1 - t0)
-    # dominant kernel class by accumulated time
-    agg = {}
     counters = {}
     for p in prof:
         for k, v in p.pop("counters").items():
             counters[k] = counters.get(k, 0) + v // args.steps
-        for k, v in p.items():
-            a = agg.setdefault(k, dict(ms=0.0, bytes=0.0, launches=0, calls=0))
-            for f in ("ms", "bytes", "launches", "calls"):
-                a[f] += v[f]
-    # event-timed launches are one in PROF_EVERY per class; totals are estimated
-    for a in agg.values():
-        a["avg_ms"] = a["ms"] / a["launches"] if a["launches"] else 0.0
-        a["est_total_ms"] = a["avg_ms"] * a["calls"]
-    dom = max(("cgs_dot", "cgs_update", "stencil"), key=lambda k: agg[k]["est_total_ms"])
-    d = agg[dom]
-    avg_ms = d["avg_ms"]
-    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
-    kernel_names = {"cgs_dot": "k_dot_partial + k_dot2_partial",
-                    "cgs_update": "k_update_* + k_dcgs_*", "stencil": "k_wilson_h"}
+    table = class_table(prof, args.steps)
     k_used = [r["k_used"] for r in records]
     init_ms = float(np.mean([r["eig_ms"] for r in records])) if records else 0.0
     solve_ms = float(np.mean([r["t_solve_ms"] for r in records])) if records else 0.0
@@ -607,16 +695,8 @@ def main():
                    "mu": wl["mus"], "n_defl": wl["ms"], "k_max": wl["k_max"], "tol": wl["tol"],
                    "sources_per_step": n_solves, "deflation": args.deflation,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": kernel_names[dom], "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if dom == "cgs_dot" else None,
-                     "algorithmic_bytes_per_launch": d["bytes"] / max(d["launches"], 1),
-                     "avg_launch_us": avg_ms * 1e3, "launches": d["calls"],
-                     "event_timed_launches": d["launches"]},
-        "kernels": {k: {"ms": v["est_total_ms"] / args.steps, "launches": v["calls"] // args.steps,
-                        "avg_us": v["avg_ms"] * 1e3,
-                        "GB/s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else 0.0}
-                    for k, v in agg.items()},
+        "roofline": roofline(table, "dis8"),
+        "kernels": table,
         "profiling": f"HIP events on one launch in {PROF_EVERY} of each class, on the launching "
                      "stream, inside the timed region; class totals = average x launches",
         "counters_per_step": counters,
@@ -631,7 +711,8 @@ def main():
         # the metric's 1e-8 (point sources need k > 600 for the workload's 1e-10)
         out["batched"] = batched_vs_plain(osa, ctxs[-1], dims, 1e-8, mmax)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, float(np.mean(k_used)))
+        out["cpu_baseline"] = cpu_baseline_fixed_k(dims, links_np, wl["mus"][-1], wl["m_w"],
+                                                   mmax, b_np, 120, links, cfg=wl["cfg"])
     print(json.dumps(out), flush=True)
     for ctx in ctxs:
         ctx.close()

@@ -246,6 +246,15 @@ OSA_API osa_status osa_apply_hw(osa_ctx* ctx, int32_t nrhs, const void* X, void*
  * the small-sign kernel for checks; stream-ordered on `stream`. */
 OSA_API osa_status osa_small_sign(int32_t k, const void* A, void* s, int32_t* iters, void* stream);
 
+/* C_b = A_b B_b for nb pairs of n x n complex128 matrices (column-major, ld n,
+ * problem b at offset b*n*n in each of A, B, C; device), on the FP64 matrix
+ * cores: the product kernel of the Newton-Schulz steps X <- (3X - X^3)/2 that
+ * finish the small sign f(H_k) e_1 (Eq. 11, Eq. 22).  C must not overlap A or
+ * B.  1 <= n <= 4000, 1 <= nb <= 64.  Standalone entry of the kernel for
+ * checks; stream-ordered on `stream`. */
+OSA_API osa_status osa_small_gemm(int32_t n, int32_t nb, const void* A, const void* B, void* C,
+                                  void* stream);
+
 /* Schur decomposition A = Z T Z^H of a p x p complex128 matrix (column-major,
  * device, 1 <= p <= 96), with the diagonal of T ordered by |t_ii| ascending
  * (mode 0) or |Re t_ii| ascending (mode 1): the small dense step of the
@@ -264,23 +273,27 @@ OSA_API osa_status osa_set_links(osa_ctx* ctx, const void* links);
  * Classes: 0 Gram-Schmidt / projection dot products (V^H w), 1 Gram-Schmidt
  * updates (w - V h), 2 stencil H_w(mu), 3 one small-matrix inversion of the
  * Newton iteration, 4 small Schur decomposition of an eigensolver restart,
- * 5 whole eigensolver restart (host wall clock, including synchronisation).
+ * 5 whole eigensolver restart (host wall clock, including synchronisation),
+ * 6 complex GEMM of a Newton-Schulz step on the FP64 matrix cores.
  * every <= 0 disables timing; every = n >= 1 brackets one launch in n of each
  * class with events (the first, then every n-th), which keeps the overhead of
  * the events (a few microseconds per bracketed launch) small.  ms[], bytes[]
  * and launches[] cover the bracketed launches only, calls[] counts all of
  * them, so ms/launches is the average duration and ms/launches*calls the
  * estimated class total.  bytes[] counts the algorithmic HBM bytes of each
- * launch (vectors read and written once).  counters[]: 0 QR sweeps and 1 plane
+ * launch (vectors read and written once); flops[] the algorithmic flops of
+ * each launch (class 6: 8 n^3 per complex n x n product).  counters[]: 0 QR sweeps and 1 plane
  * rotations (sweeps plus reordering) of the small Schur decompositions,
  * 2 Newton iterations of the small sign, 3 eigensolver Arnoldi steps.
  * Enabling resets everything. */
+#define OSA_PROFILE_CLASSES 7
 typedef struct {
-    double ms[6];
-    double bytes[6];
-    int64_t launches[6];
+    double ms[OSA_PROFILE_CLASSES];
+    double bytes[OSA_PROFILE_CLASSES];
+    int64_t launches[OSA_PROFILE_CLASSES];
     int64_t counters[4];
-    int64_t calls[6];
+    int64_t calls[OSA_PROFILE_CLASSES];
+    double flops[OSA_PROFILE_CLASSES];
 } osa_profile;
 OSA_API osa_status osa_profile_enable(osa_ctx* ctx, int32_t every);
 OSA_API osa_status osa_profile_read(osa_ctx* ctx, osa_profile* out);

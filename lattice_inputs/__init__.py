@@ -31,6 +31,7 @@ SEED_ROOT = 710341
 STREAM_LINKS = 0
 STREAM_SOURCE = 1
 STREAM_PARAMS = 2
+STREAM_DEFL = 3
 
 
 def rng_for(cfg: int, inst: int, stream: int) -> np.random.Generator:
@@ -130,9 +131,25 @@ def ones_source(dims) -> np.ndarray:
     return np.full(n, 1.0 / np.sqrt(n), dtype=np.complex128)
 
 
+def placeholder_deflation(n: int, m: int, cfg: int = 0, inst: int = 0):
+    """(R, L, lambda) of the shapes of m deflation pairs for vectors of length n:
+    unit Gaussian columns and values with |Re| in [0.05, 0.5].  They are not
+    eigenpairs; they only give a timing run the memory traffic and arithmetic
+    of an m-pair deflation."""
+    rng = rng_for(cfg, inst, STREAM_DEFL)
+    r = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
+    l = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
+    r /= np.linalg.norm(r, axis=0)
+    l /= np.linalg.norm(l, axis=0)
+    re = rng.uniform(0.05, 0.5, m) * rng.choice([-1.0, 1.0], m)
+    lam = re + 1j * rng.uniform(-0.1, 0.1, m)
+    return r, l, lam
+
+
 # ---------------------------------------------------------------------------
 # Workloads.  Index 0 is the small case the dense oracle handles in seconds;
-# index 1 is the headline single-GPU workload.
+# index 3 (16^4, 12 point sources, batched) is the headline single-GPU
+# workload; 1, 2 and 4 are the other measured configurations.
 # ---------------------------------------------------------------------------
 WORKLOADS = [
     dict(name="haar4_mu0.3_m10", dims=(4, 4, 4, 4), kind="haar", eps=0.0,

@@ -34,7 +34,8 @@ LR, SCHUR = 0, 1   # osa_opts.deflation
 EXPORTS = ["overlap_sign_apply", "osa_create", "osa_deflate", "osa_set_deflation",
            "osa_get_deflation", "osa_set_active_deflation", "osa_apply", "osa_apply_adjoint",
            "osa_apply_overlap", "osa_batch_apply",
-           "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_small_schur", "osa_set_links",
+           "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_small_gemm", "osa_small_schur",
+           "osa_set_links",
            "osa_profile_enable", "osa_profile_read", "osa_last_message", "osa_destroy",
            "osa_status_string", "osa_set_allocator",
            "osa_version"]
@@ -71,19 +72,22 @@ class Info(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+NPROF = 7   # OSA_PROFILE_CLASSES
+
+
 class Profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 6), ("bytes", ctypes.c_double * 6),
-                ("launches", ctypes.c_int64 * 6), ("counters", ctypes.c_int64 * 4),
-                ("calls", ctypes.c_int64 * 6)]
+    _fields_ = [("ms", ctypes.c_double * NPROF), ("bytes", ctypes.c_double * NPROF),
+                ("launches", ctypes.c_int64 * NPROF), ("counters", ctypes.c_int64 * 4),
+                ("calls", ctypes.c_int64 * NPROF), ("flops", ctypes.c_double * NPROF)]
 
     CLASSES = ("cgs_dot", "cgs_update", "stencil", "small_inverse", "small_schur",
-               "eig_restart")
+               "eig_restart", "small_gemm")
 
     COUNTERS = ("schur_sweeps", "schur_rotations", "newton_iterations", "eig_arnoldi_steps")
 
     def as_dict(self):
         d = {name: dict(ms=self.ms[i], bytes=self.bytes[i], launches=self.launches[i],
-                        calls=self.calls[i])
+                        calls=self.calls[i], flops=self.flops[i])
              for i, name in enumerate(self.CLASSES)}
         d["counters"] = {name: int(self.counters[i]) for i, name in enumerate(self.COUNTERS)}
         return d
@@ -124,6 +128,7 @@ def lib() -> ctypes.CDLL:
     L.osa_apply_hw.argtypes = [vp, i32, vp, vp]
     L.osa_small_sign.argtypes = [i32, vp, vp, ctypes.POINTER(i32), vp]
     L.osa_small_schur.argtypes = [i32, vp, vp, vp, vp, i32, vp]
+    L.osa_small_gemm.argtypes = [i32, i32, vp, vp, vp, vp]
     L.osa_set_links.argtypes = [vp, vp]
     L.osa_profile_enable.argtypes = [vp, i32]
     L.osa_profile_read.argtypes = [vp, ctypes.POINTER(Profile)]
@@ -416,6 +421,24 @@ def small_schur(A, mode=0):
                                  ctypes.c_void_p(Z.data_ptr()), ctypes.c_void_p(w.data_ptr()),
                                  int(mode), _stream()), "osa_small_schur", False)
     return T.t(), Z.t(), w          # column-major storage -> row-major views
+
+
+def small_gemm(A, B):
+    """C = A @ B for complex128 GPU tensors of shape (n, n) or (nb, n, n), on the
+    library's FP64 matrix-core kernel."""
+    torch = _torch()
+    single = A.dim() == 2
+    A3 = A.unsqueeze(0) if single else A
+    B3 = B.unsqueeze(0) if single else B
+    nb, n = int(A3.shape[0]), int(A3.shape[1])
+    Acm = A3.transpose(1, 2).contiguous()      # column-major storage per problem
+    Bcm = B3.transpose(1, 2).contiguous()
+    C = torch.empty_like(Acm)
+    _check(lib().osa_small_gemm(n, nb, ctypes.c_void_p(Acm.data_ptr()),
+                                ctypes.c_void_p(Bcm.data_ptr()), ctypes.c_void_p(C.data_ptr()),
+                                _stream()), "osa_small_gemm", False)
+    C = C.transpose(1, 2)
+    return C[0] if single else C
 
 
 def small_sign(A):

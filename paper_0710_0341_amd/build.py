@@ -36,7 +36,7 @@ def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
-    cmd = [hipcc()] + FLAGS + ["-o", tmp] + srcs + [f"-L{rocm}/lib", "-lrocblas",
+    cmd = [hipcc()] + FLAGS + ["-o", tmp] + srcs + [f"-L{rocm}/lib",
                                                     f"-Wl,-rpath,{rocm}/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -497,6 +497,122 @@ void launch_zgemm(int opA, int opB, int m, int n, int kk, cd alpha, const cd* A,
     OSA_LAUNCH_CHECK();
 }
 
+// ============================================================ zgemm (MFMA)
+// Out = alpha A B + beta Cin + delta I for square n x n complex128 matrices
+// (column-major, ld n), one problem per grid z entry, on the FP64 matrix
+// cores.  The complex product is four real products per 16x16x4 step,
+//   Re += Ar Br - Ai Bi,   Im += Ar Bi + Ai Br,
+// each one v_mfma_f64_16x16x4 (FP64 fused multiply-add inside the unit, so
+// the accumulation is FP64 throughout and its order is fixed).  A workgroup
+// owns a 32 x 32 complex tile of Out; its four wavefronts own 16 x 16 quarters.
+// k advances in chunks of 32 staged in LDS: A as [k][i] and B as [j][k], both
+// padded by one entry so that the fragment reads of a wavefront spread over
+// the banks.  Operand fragments: lane l holds A[i0 + l%16][k + l/16] and
+// B[k + l/16][j0 + l%16]; result register r of lane l is
+// Out[i0 + l/16 + 4r][j0 + l%16] (checked against numpy by the GEMM test).
+typedef double d4v __attribute__((ext_vector_type(4)));
+static constexpr int kMmT = 32;   // workgroup tile (complex rows and columns)
+static constexpr int kMmK = 32;   // k chunk staged in LDS
+
+__global__ __launch_bounds__(256) void k_zgemm_mfma(int n, cd alpha, const cd* __restrict__ A,
+                                                   const cd* __restrict__ B, double beta,
+                                                   const cd* Cin, double delta, cd* Out,
+                                                   double* __restrict__ part, Batch bt) {
+    __shared__ cd As[kMmK][kMmT + 1];
+    __shared__ cd Bs[kMmT][kMmK + 1];
+    __shared__ double sred[4];
+    const int pb = bt.idx[blockIdx.z];
+    A += pb * bt.mat;
+    B += pb * bt.mat;
+    Out += pb * bt.mat;
+    if (Cin) Cin += pb * bt.mat;
+    const int i0 = blockIdx.x * kMmT, j0 = blockIdx.y * kMmT;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wi = (wave & 1) * 16, wj = (wave >> 1) * 16;
+    const int fr = lane & 15, fk = lane >> 4;
+    d4v cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < n; k0 += kMmK) {
+        for (int e = t; e < kMmT * kMmK; e += 256) {
+            const int r = e % kMmT, c = e / kMmT;
+            const int ai = i0 + r, ak = k0 + c;   // A[ai, ak]: consecutive rows per column
+            As[c][r] = (ai < n && ak < n) ? A[ai + (int64_t)ak * n] : mk(0.0, 0.0);
+            const int bk = k0 + r, bj = j0 + c;   // B[bk, bj]
+            Bs[c][r] = (bk < n && bj < n) ? B[bk + (int64_t)bj * n] : mk(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kMmK; kk += 4) {
+            const cd a = As[kk + fk][wi + fr];
+            const cd b = Bs[wj + fr][kk + fk];
+            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = i0 + wi + fk + 4 * r, col = j0 + wj + fr;
+        if (row < n && col < n) {
+            const int64_t e = row + (int64_t)col * n;
+            const cd acc = mk(cr[r], ci[r]);
+            cd v = cmul(alpha, acc);
+            if (beta != 0.0) {
+                const cd c0 = Cin[e];
+                v.x = fma(beta, c0.x, v.x);
+                v.y = fma(beta, c0.y, v.y);
+            }
+            if (row == col) v.x += delta;
+            Out[e] = v;
+            nrm += cabs2(v);
+        }
+    }
+    if (part) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+        if (lane == 0) sred[wave] = nrm;
+        __syncthreads();
+        if (t == 0)
+            part[pb * bt.part + blockIdx.x + (int64_t)blockIdx.y * gridDim.x] =
+                ((sred[0] + sred[1]) + sred[2]) + sred[3];
+    }
+}
+
+// norm2[pb] = sum of the np partials (fixed order: lane q takes q, q + 64, ...,
+// then a shuffle tree)
+__global__ __launch_bounds__(64) void k_sum_partials(const double* __restrict__ part, int np,
+                                                    double* __restrict__ norm2, Batch bt) {
+    const int pb = bt.idx[blockIdx.x];
+    part += pb * bt.part;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < np; i += 64) a += part[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (threadIdx.x == 0) norm2[pb * bt.scal] = a;
+}
+
+int64_t zgemm_part_len(int n) {
+    const int64_t t = ceil_div(n, kMmT);
+    return t * t;
+}
+
+void launch_zgemm_sq(int n, cd alpha, const cd* A, const cd* B, double beta, const cd* Cin,
+                     double delta, cd* Out, double* part, double* norm2, hipStream_t st,
+                     const Batch& bt) {
+    if (bt.n <= 0 || n <= 0) return;
+    if (Out == A || Out == B) throw HipError{hipErrorInvalidValue, "launch_zgemm_sq: Out aliases A or B"};
+    if (beta != 0.0 && !Cin) throw HipError{hipErrorInvalidValue, "launch_zgemm_sq: beta without Cin"};
+    const unsigned t = (unsigned)ceil_div(n, kMmT);
+    hipLaunchKernelGGL(k_zgemm_mfma, dim3(t, t, bt.n), dim3(256), 0, st, n, alpha, A, B, beta,
+                       Cin, delta, Out, part, bt);
+    if (part && norm2)
+        hipLaunchKernelGGL(k_sum_partials, dim3(bt.n), dim3(64), 0, st, (const double*)part,
+                           (int)(t * t), norm2, bt);
+    OSA_LAUNCH_CHECK();
+}
+
 // |s - [sprev; 0]|  (one block)
 __global__ void k_diff_norm(const cd* __restrict__ s, int k, const cd* __restrict__ sp, int kp,
                             double* out, Batch bt) {

@@ -167,6 +167,17 @@ void launch_copy_col0(const cd* X, int k, cd* s, hipStream_t st, const Batch& bt
 // opA/opB: 0 = N, 1 = conjugate transpose.
 void launch_zgemm(int opA, int opB, int m, int n, int kk, cd alpha, const cd* A, int lda,
                   const cd* B, int ldb, cd beta, cd* C, int ldc, hipStream_t st);
+// Batched square complex GEMM on the FP64 matrix cores (v_mfma_f64_16x16x4):
+//   Out = alpha A B + beta Cin + delta I   (n x n, column-major, ld n).
+// Out must not alias A or B (Cin may equal Out; Cin may be null when beta = 0).
+// With part != nullptr the per-workgroup partial sums of |Out|^2 go to part
+// (zgemm_part_len(n) doubles per problem) and, with norm2 != nullptr, their
+// fixed-order sum |Out|_F^2 to norm2.  Batch strides: mat (A, B, Cin, Out),
+// part (part, doubles), scal (norm2, doubles).
+int64_t zgemm_part_len(int n);
+void launch_zgemm_sq(int n, cd alpha, const cd* A, const cd* B, double beta, const cd* Cin,
+                     double delta, cd* Out, double* part, double* norm2, hipStream_t st,
+                     const Batch& bt = Batch());
 // *out = |s - [sprev; 0]|  (device).  Batch strides: small (s, sprev),
 // scal (out, counted in doubles).
 void launch_diff_norm(const cd* s, int k, const cd* sprev, int kprev, double* out,

@@ -25,8 +25,6 @@
 #include <thread>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "kernels.hpp"
 
 using namespace osa;
@@ -140,7 +138,8 @@ struct OsaError {
 struct ArenaLayout {
     int ldh = 0;
     int64_t vec_len = 0;   // entries of each vector slot
-    int64_t H = 0, coef = 0, coef2 = 0, cdef = 0, tmp = 0, s_cur = 0, s_prev = 0, dc = 0, ds = 0;
+    int64_t H = 0, coef = 0, coef2 = 0, cdef = 0, craw = 0, tmp = 0, s_cur = 0, s_prev = 0, dc = 0,
+            ds = 0;
     int64_t xs = 0;   // Schur deflation: X = S^dag H V_k (m x (kcap + 1), ld m)
     int m = 0;
     int64_t stride = 0;
@@ -154,6 +153,7 @@ struct ArenaLayout {
         a.coef = o;   o += a.vec_len;
         a.coef2 = o;  o += a.vec_len;
         a.cdef = o;   o += a.vec_len;
+        a.craw = o;   o += a.vec_len;
         a.tmp = o;    o += a.vec_len;
         a.s_cur = o;  o += a.vec_len;
         a.s_prev = o; o += a.vec_len;
@@ -188,7 +188,7 @@ struct osa_ctx {
 
     // deflation data (internal layout, m_alloc vectors each)
     int m_alloc = 0, m_active = 0;
-    DevBuf R, L, Ginv, lam_dev, sgnc;
+    DevBuf R, L, Ginv, lam_dev, sgnc, gnorm;
     // adjoint solves, sign(H(mu))^dag = sign(H(-mu)): the stencil of H(-mu), and
     // the deflation data with the left and right vectors swapped and G^{-1}
     // replaced by its conjugate transpose (GinvH)
@@ -216,16 +216,14 @@ struct osa_ctx {
     PinnedBuf host;
 
     // optional kernel timing (events on st, resolved at synchronisation points)
-    struct Pending { hipEvent_t a, b; int cls; double bytes; };
+    struct Pending { hipEvent_t a, b; int cls; double bytes, flops; };
     bool prof_on = false;
     int prof_every = 1;   // bracket one launch in prof_every of each class
     std::vector<Pending> prof_pending;
     std::vector<hipEvent_t> prof_pool;
     osa_profile prof{};
     std::string msg;
-    rocblas_handle blas = nullptr;   // Newton-Schulz GEMMs of the small sign
     ~osa_ctx() {
-        if (blas) (void)rocblas_destroy_handle(blas);
         for (auto& p : prof_pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
         for (auto e : prof_pool) (void)hipEventDestroy(e);
         if (own_stream && st) (void)hipStreamDestroy(st);
@@ -243,6 +241,7 @@ void prof_resolve(osa_ctx* c) {
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             c->prof.ms[p.cls] += ms;
             c->prof.bytes[p.cls] += p.bytes;
+            c->prof.flops[p.cls] += p.flops;
             c->prof.launches[p.cls] += 1;
         } else {
             (void)hipGetLastError();
@@ -271,14 +270,14 @@ hipEvent_t prof_event(osa_ctx* c) {
 
 // Brackets the launches issued by f() with events when profiling is on.
 template <typename F>
-void timed(osa_ctx* c, int cls, double bytes, F&& f) {
+void timed(osa_ctx* c, int cls, double bytes, F&& f, double flops = 0.0) {
     if (!c->prof_on) { f(); return; }
     if (c->prof.calls[cls]++ % c->prof_every != 0) { f(); return; }
     hipEvent_t a = prof_event(c), b = prof_event(c);
     OSA_HIP(hipEventRecord(a, c->st));
     f();
     OSA_HIP(hipEventRecord(b, c->st));
-    c->prof_pending.push_back({a, b, cls, bytes});
+    c->prof_pending.push_back({a, b, cls, bytes, flops});
     if (c->prof_pending.size() > 4096) sync(c);
 }
 
@@ -493,9 +492,10 @@ namespace {
 // s = sign(A) e_1 for the problems in probs (k x k each, A of problem b at
 // A + b*a_stride with leading dimension lda; s written at s_out + b*s_stride)
 // by the scaled Newton iteration (Eq. 11): determinantal scaling until the
-// relative change drops below 1e-2; stop once the change is below 1e-14, or
-// below 1e-8 and no longer halving; at most 100 iterations.  All problems of
-// the group share every launch; each stops on its own.
+// relative change drops below kNsSwitch (5e-2), then Newton-Schulz steps on the
+// matrix cores while |X^2 - I|_F < 0.5; stop once the change is below 1e-14,
+// or below 1e-8 and no longer halving; at most 100 iterations.  All problems
+// of the group share every launch; each stops on its own.
 // iters[b] > 0: iterations used, ok[b] = 1 on convergence; iters[b] < 0: a
 // singular or non-finite iterate at iteration -iters[b].
 // The small problem of Schur deflation (Eq. 15-19): the block matrix
@@ -597,6 +597,7 @@ __global__ void k_sub_identity(cd* M, int n) {
 }
 
 // Newton change below which the small sign continues by Newton-Schulz steps
+// (determinantal scaling stops there too)
 constexpr double kNsSwitch = 5e-2;
 
 // sign of the k x k matrices A (or, with sb, of the Schur block matrices of
@@ -638,14 +639,17 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
     OSA_HIP(hipMemsetAsync(c->nflag.p, 0, c->nflag.bytes, c->st));
     uint64_t scale = ~0ULL;
     std::vector<double> prev(c->kbatch, INFINITY);
-    // problems in the Newton-Schulz phase: X <- (3X - X^3)/2 by two GEMMs instead
-    // of an inverse, once the unscaled Newton change is below kNsSwitch.  With
-    // X = S(1 + E) (every iterate is a function of H, so E commutes with S) the
-    // error maps to E' = -(3/2)E^2 - E^3/2, quadratic as in Newton's E^2/(2(1+E)).
-    // A step that does not halve the change returns the problem to Newton.
+    // problems in the Newton-Schulz phase: X <- (3X - X^3)/2 by two GEMMs on the
+    // FP64 matrix cores instead of an inverse, once the unscaled Newton change is
+    // below kNsSwitch.  With X = S(1 + E) (every iterate is a function of H, so E
+    // commutes with S) the error maps to E' = -(3/2)E^2 - E^3/2, quadratic as in
+    // Newton's E^2/(2(1+E)).  A step that does not halve the change returns the
+    // problem to Newton.  A problem whose X^2 - I was too large for the step
+    // (nsblock = the change at that test) waits until its change has halved.
     std::vector<char> nsm(c->kbatch, 0);
+    std::vector<double> nsblock(c->kbatch, INFINITY);
     double* red = c->red.as<double>();
-    std::vector<double> hred;
+    std::vector<double> hred, hns;
     std::vector<int> hflag;
     for (int it = 1; it <= 100 && !act.empty(); ++it) {
         Batch ba = bt;
@@ -653,40 +657,32 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
         for (int i = 0; i < ba.n; ++i) ba.idx[i] = (int16_t)act[i];
         std::vector<int> gjl, nsc, nsl;
         for (int b : act) (nsm[b] ? nsc : gjl).push_back(b);
-        const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0), mone(-1.0, 0.0);
         if (!nsc.empty()) {
-            // Newton-Schulz candidates: D = X X - I.  The step converges to sign(X)
+            // Newton-Schulz candidates: D = X X - I and |D|_F^2 (into red[0]) for all
+            // of them in one launch, one read-back.  The step converges to sign(X)
             // when |I - X^2| < 1 (Frobenius norm here, with margin 0.5); otherwise an
             // eigenvalue of X may lie where (3x - x^3)/2 flips its sign, and the
             // problem takes a Newton step instead.
-            if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
-                c->blas = nullptr;
-                throw OsaError{OSA_ERR_HIP, "rocblas_create_handle"};
-            }
-            if (rocblas_set_stream(c->blas, c->st) != rocblas_status_success ||
-                rocblas_set_pointer_mode(c->blas, rocblas_pointer_mode_host) !=
-                    rocblas_status_success)
-                throw OsaError{OSA_ERR_HIP, "rocblas_set_stream"};
-            for (int b : nsc) {
-                auto* Xb = reinterpret_cast<rocblas_double_complex*>(X + b * ms);
-                auto* Mb = reinterpret_cast<rocblas_double_complex*>(M + b * ms);
-                double dn = INFINITY;
-                rocblas_status r1 = rocblas_zgemm(c->blas, rocblas_operation_none,
-                                                  rocblas_operation_none, n, n, n, &one, Xb, n, Xb,
-                                                  n, &zero, Mb, n);
-                hipLaunchKernelGGL(k_sub_identity, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0,
-                                   c->st, M + b * ms, n);
-                OSA_LAUNCH_CHECK();
-                rocblas_status r2 = rocblas_dznrm2(c->blas, n * n, Mb, 1, &dn);   // synchronous
-                if (r1 != rocblas_status_success || r2 != rocblas_status_success)
-                    throw OsaError{OSA_ERR_HIP, "rocblas_zgemm / rocblas_dznrm2"};
-                if (dn < 0.5) {
+            Batch bn = batch_of(nsc);
+            bn.mat = ms;
+            bn.part = c->red_stride;
+            bn.scal = c->red_stride;
+            timed(c, 6, 2.0 * 16.0 * n * (double)n * bn.n, [&] {
+                launch_zgemm_sq(n, mk(1.0, 0.0), X, X, 0.0, nullptr, -1.0, M, red + 2, red, c->st,
+                                bn);
+            }, 8.0 * n * (double)n * n * bn.n);
+            d2h_strided(c, red, c->red_stride * (int64_t)sizeof(double), 1, nsc, hns);
+            for (size_t i = 0; i < nsc.size(); ++i) {
+                const int b = nsc[i];
+                if (std::sqrt(hns[i]) < 0.5) {
                     nsl.push_back(b);
                 } else {
                     nsm[b] = 0;
+                    nsblock[b] = prev[b];
                     gjl.push_back(b);
                 }
             }
+            std::sort(gjl.begin(), gjl.end());
         }
         if (!gjl.empty()) {
             Batch bg = bt;
@@ -703,19 +699,12 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
         if (!nsl.empty()) {
             // Y = X - X D = 2X - X (X X), so that the combine (X + Y)/2 is the
             // Newton-Schulz step (3X - X^3)/2
-            timed(c, 3, 3.0 * 16.0 * n * (double)n * nsl.size(), [&] {
-                for (int b : nsl) {
-                    auto* Xb = reinterpret_cast<rocblas_double_complex*>(X + b * ms);
-                    auto* Mb = reinterpret_cast<rocblas_double_complex*>(M + b * ms);
-                    auto* Yb = reinterpret_cast<rocblas_double_complex*>(Y + b * ms);
-                    OSA_HIP(hipMemcpyAsync(Yb, Xb, sizeof(cd) * (size_t)n * n,
-                                           hipMemcpyDeviceToDevice, c->st));
-                    if (rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, n,
-                                      n, n, &mone, Xb, n, Mb, n, &one, Yb, n) !=
-                        rocblas_status_success)
-                        throw OsaError{OSA_ERR_HIP, "rocblas_zgemm"};
-                }
-            });
+            Batch bs = batch_of(nsl);
+            bs.mat = ms;
+            timed(c, 6, 4.0 * 16.0 * n * (double)n * bs.n, [&] {
+                launch_zgemm_sq(n, mk(-1.0, 0.0), X, M, 1.0, X, 0.0, Y, nullptr, nullptr, c->st,
+                                bs);
+            }, 8.0 * n * (double)n * n * bs.n);
         }
         launch_newton_combine(X, Y, n, c->logpiv.as<double>(), scale, red, c->st, ba);
         d2h_strided(c, red, c->red_stride * (int64_t)sizeof(double), 2, act, hred);
@@ -728,9 +717,11 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
             iters[b] = it;
             if (hflag[i] || !std::isfinite(d2) || !std::isfinite(n2)) { iters[b] = -it; continue; }
             const double change = std::sqrt(d2 / n2);
-            if (change < std::max(1e-2, kNsSwitch)) scale &= ~(1ULL << b);
+            if (change < kNsSwitch) scale &= ~(1ULL << b);
             if (nsm[b] && !(change < 0.5 * prev[b])) nsm[b] = 0;   // back to Newton
-            else if (!nsm[b] && change < kNsSwitch && !((scale >> b) & 1ULL)) nsm[b] = 1;
+            else if (!nsm[b] && change < kNsSwitch && !((scale >> b) & 1ULL) &&
+                     change < 0.5 * nsblock[b])
+                nsm[b] = 1;
             // converged: at rounding level, stagnating below 1e-8, or below 1e-8 in
             // the quadratic regime (change <= 10 prev^2), where the new iterate's
             // error is about change^2 and one more step would only confirm it
@@ -773,7 +764,54 @@ __global__ void k_sign_coef(int m, const cd* __restrict__ lam, const cd* __restr
     if (i < m) cout[i] = cscale(cin[i], lam[i].x > 0 ? 1.0 : -1.0);
 }
 
-// G = L^H R for the first m pairs, then G^{-1}.
+// Adjoint assembly.  With the deflation data of H (H R = R Lambda, G = L^dag R)
+// the deflated part of sign(H)^dag x is (R sgn(Lambda) G^{-1} L^dag)^dag x =
+// L G^{-H} sgn(Lambda) R^dag x: the signs act on R^dag x (raw) before G^{-H},
+// so the order of the columns of L is free.  cout = G^{-H} (sgn(Re lambda) . raw),
+// one block per problem.  Batch strides: small (raw, cout).
+__global__ __launch_bounds__(64) void k_adj_sign_coef(int m, const cd* __restrict__ lam,
+                                                      const cd* __restrict__ ginvh,
+                                                      const cd* __restrict__ raw,
+                                                      cd* __restrict__ cout, Batch bt) {
+    const int pb = bt.idx[blockIdx.x];
+    raw += pb * bt.small;
+    cout += pb * bt.small;
+    for (int i = threadIdx.x; i < m; i += 64) {
+        cd a = mk(0.0, 0.0);
+        for (int j = 0; j < m; ++j)
+            cfma(a, ginvh[i + (int64_t)j * m], cscale(raw[j], lam[j].x > 0 ? 1.0 : -1.0));
+        cout[i] = a;
+    }
+}
+
+// |V_j|^2 for the m columns of V (length n each): one block per column, fixed order.
+__global__ __launch_bounds__(256) void k_col_norm2(const cd* __restrict__ V, int64_t n,
+                                                   double* __restrict__ out) {
+    __shared__ double sm[4];
+    V += (int64_t)blockIdx.x * n;
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) a += cabs2(V[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = ((sm[0] + sm[1]) + sm[2]) + sm[3];
+}
+
+// Gn[i, j] = G[i, j] / (|l_i| |r_j|) from the squared column norms nl2, nr2
+__global__ void k_normalize_g(int m, const cd* __restrict__ G, const double* __restrict__ nl2,
+                              const double* __restrict__ nr2, cd* __restrict__ Gn) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * m) return;
+    const int i = e % m, j = e / m;
+    Gn[e] = cscale(G[e], 1.0 / std::sqrt(nl2[i] * nr2[j]));
+}
+
+// G = L^H R for the first m pairs, then G^{-1}.  The vectors may carry any
+// scale (only the projector R G^{-1} L^dag matters), so the conditioning test
+// runs on G with unit columns of L and R: it is then nearly diagonal with
+// entries cos(angle(l_i, r_i)) when L and R span dual invariant subspaces, and a
+// Gauss-Jordan pivot below 1e-10 means they do not.
 void build_ginv(osa_ctx* c, int m) {
     ensure_krylov(c, std::max(c->kcap, std::max(m + 1, 8)));
     c->Ginv.ensure(sizeof(cd) * (size_t)m * m + 16);
@@ -785,11 +823,31 @@ void build_ginv(osa_ctx* c, int m) {
         launch_reduce_partial(c->partial.as<cd>(), nch, m, G + (size_t)j * m, nullptr,
                               nullptr, nullptr, c->st);
     }
+    // normalised copy for the conditioning test (in sY, free outside the small sign)
+    c->gnorm.ensure(sizeof(double) * 2 * (size_t)m);
+    double* nrm = c->gnorm.as<double>();
+    hipLaunchKernelGGL(k_col_norm2, dim3(m), dim3(256), 0, c->st, c->L.as<cd>(), c->N(), nrm);
+    hipLaunchKernelGGL(k_col_norm2, dim3(m), dim3(256), 0, c->st, c->R.as<cd>(), c->N(), nrm + m);
+    cd* Gn = c->sY.as<cd>();
+    hipLaunchKernelGGL(k_normalize_g, dim3((unsigned)ceil_div((int64_t)m * m, 256)), dim3(256), 0,
+                       c->st, m, (const cd*)G, (const double*)nrm, (const double*)(nrm + m), Gn);
+    OSA_LAUNCH_CHECK();
     OSA_HIP(hipMemsetAsync(c->flag.p, 0, sizeof(int) * 4, c->st));
     gj_invert(G, c->Ginv.as<cd>(), m, c->logpiv.as<double>(), c->flag.as<int>(), c->gjws.p, c->st);
     int hf = 0;
     d2h(c, c->flag.p, 1, &hf);
-    if (hf) throw OsaError{OSA_ERR_EIG_NOCONV};
+    if (hf) throw OsaError{OSA_ERR_EIG_NOCONV, "G = L^dag R is singular"};
+    // Gauss-Jordan of the normalised G (its inverse goes to sX, unused)
+    gj_invert(Gn, c->sX.as<cd>(), m, c->logpiv.as<double>(), c->flag.as<int>(), c->gjws.p, c->st);
+    std::vector<double> lp(m);
+    d2h(c, c->logpiv.p, (size_t)m, lp.data());
+    d2h(c, c->flag.p, 1, &hf);
+    double mn = INFINITY;
+    for (double v : lp) mn = std::min(mn, v);
+    if (hf || !(mn > std::log(1e-10)))
+        throw OsaError{OSA_ERR_EIG_NOCONV,
+                       "G = L^dag R is nearly singular: the left and right vectors do not span "
+                       "dual invariant subspaces"};
 }
 
 void set_active(osa_ctx* c, int m) {
@@ -926,7 +984,8 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     launch_norm_partial(x, false, p, c->normp.as<double>(), c->st, ball);
     launch_normalize(x, nullptr, false, p, c->normp.as<double>(), ds + 0, nullptr, 0.0, nullptr, 0,
                      nullptr, 0, c->st, ball);
-    if (m > 0) project_out(c, x, ar + L.cdef, ar + L.tmp, ball);   // x <- x_ominus  (Eq. 21)
+    // x <- x_ominus (Eq. 21); craw keeps L^dag b (R^dag b in the adjoint) for the assembly
+    if (m > 0) project_out(c, x, ar + L.cdef, ar + L.craw, ball);
     launch_norm_partial(x, false, p, c->normp.as<double>(), c->st, ball);
     launch_normalize(x, nullptr, false, p, c->normp.as<double>(), ds + 1, nullptr, 0.0, nullptr, 0,
                      nullptr, 0, c->st, ball);
@@ -1141,9 +1200,15 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     } else if (!okp.empty()) {
         const Batch bo = bat(okp);
         if (m > 0) {
-            hipLaunchKernelGGL(k_sign_coef, dim3((unsigned)ceil_div(m, 64), bo.n), dim3(64), 0,
-                               c->st, m, (const cd*)c->lam_dev.p, (const cd*)(ar + L.cdef),
-                               ar + L.coef, bo);
+            if (c->adj)
+                hipLaunchKernelGGL(k_adj_sign_coef, dim3(bo.n), dim3(64), 0, c->st, m,
+                                   (const cd*)c->lam_dev.p, (const cd*)c->GinvH.p,
+                                   (const cd*)(ar + L.craw), ar + L.coef, bo);
+            else
+                hipLaunchKernelGGL(k_sign_coef, dim3((unsigned)ceil_div(m, 64), bo.n), dim3(64), 0,
+                                   c->st, m, (const cd*)c->lam_dev.p, (const cd*)(ar + L.cdef),
+                                   ar + L.coef, bo);
+            OSA_LAUNCH_CHECK();
             Batch br = bo;
             br.basis = 0;   // R is shared
             launch_combine(yout, c->adj ? c->L.p : c->R.p, N, m, ar + L.coef, false, false, N,
@@ -1577,10 +1642,32 @@ bool chfsi_run(osa_ctx* c, bool adjoint, int nev, int s, int deg, double tol, in
     return false;
 }
 
+// max_i |H v_i - lam_i v_i| over the columns cols of V (unit vectors, ld N)
+double eig_resid(osa_ctx* c, bool adjoint, const cd* V, const std::vector<cd>& lam,
+                 const std::vector<int>& cols) {
+    const int64_t N = c->N();
+    DevBuf hv;
+    hv.ensure(sizeof(cd) * (size_t)N);
+    double mx = 0;
+    for (int i : cols) {
+        apply_h(c, V + (size_t)i * N, hv.p, false, adjoint);
+        cd negl = mk(-lam[i].x, -lam[i].y);
+        h2d(c, c->coef.p, &negl, 1);
+        launch_combine(hv.p, V + (size_t)i * N, N, 1, c->coef.as<cd>(), false, true, N, c->st);
+        vec_norm(c, hv.p, false, c->dscal.as<cd>() + 12);
+        cd hn;
+        d2h(c, c->dscal.as<cd>() + 12, 1, &hn);
+        mx = std::max(mx, hn.x);
+    }
+    return mx;
+}
+
 // Rayleigh-Ritz with H in span(X): M = X^H H X, Schur form sorted by |Re|,
-// eigenvectors Y; Rv = X Y[:, :m], lam = diag.  Residuals |H r - lam r|.
+// eigenvectors Y; Rv = X Y[:, :m], lam = diag.  Residuals |H r - lam r| of the
+// first mres of them (all m when mres < 0).
 void rayleigh_ritz(osa_ctx* c, bool adjoint, int nev, int m, cd* X, cd* Rout,
-                   std::vector<cd>& lam, double& max_res) {
+                   std::vector<cd>& lam, double& max_res, int mres = -1) {
+    if (mres < 0) mres = m;
     const int64_t N = c->N();
     DevBuf W, Mb, T, Z, Y, wr, info, HR, res;
     W.ensure(sizeof(cd) * (size_t)N * nev);
@@ -1614,8 +1701,7 @@ void rayleigh_ritz(osa_ctx* c, bool adjoint, int nev, int m, cd* X, cd* Rout,
     launch_rotate(W.p, N, nev, Y.as<cd>(), nev, m, HR.p, N, false, N, c->st);
     // residuals: |HR_i - lam_i R_i| (R_i unit)
     max_res = 0;
-    std::vector<double> nrm(1);
-    for (int i = 0; i < m; ++i) {
+    for (int i = 0; i < mres; ++i) {
         cd* hr = HR.as<cd>() + (size_t)i * N;
         cd negl = mk(-lam[i].x, -lam[i].y);
         h2d(c, c->coef.p, &negl, 1);
@@ -1673,7 +1759,8 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
     X.ensure(sizeof(cd) * (size_t)N * nev);
     Xs.ensure(sizeof(cd) * N);
     Rn.ensure(sizeof(cd) * (size_t)N * m);
-    if (!right_only) Ln.ensure(sizeof(cd) * (size_t)N * m);
+    // the left search returns all nev Ritz pairs of H(-mu), for the pairing below
+    if (!right_only) Ln.ensure(sizeof(cd) * (size_t)N * nev);
     KsStats st;
     std::vector<cd> lam_r, lam_l;
     double res_r = 0, res_l = 0;
@@ -1716,7 +1803,8 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
             }
         }
         sst.matvecs += nev;
-        rayleigh_ritz(e, adj, nev, m, Xb, out, lam, res);
+        // the left side keeps all nev pairs; their residuals follow the pairing
+        rayleigh_ritz(e, adj, nev, adj ? nev : m, Xb, out, lam, res, adj ? 0 : m);
     };
     // the left side runs on a worker clone: own non-blocking stream and work
     // buffers, the parent's links; ordered after everything queued so far
@@ -1763,9 +1851,10 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
     }
     worker.join();
     if (c->prof_on) {
-        for (int i = 0; i < 6; ++i) {
+        for (int i = 0; i < OSA_PROFILE_CLASSES; ++i) {
             c->prof.ms[i] += w->prof.ms[i];
             c->prof.bytes[i] += w->prof.bytes[i];
+            c->prof.flops[i] += w->prof.flops[i];
             c->prof.launches[i] += w->prof.launches[i];
             c->prof.calls[i] += w->prof.calls[i];
         }
@@ -1775,13 +1864,49 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
     if (werr) std::rethrow_exception(werr);
     st.matvecs += st_l.matvecs;
     st.restarts += st_l.restarts;
+    // Pair the left vectors with the right ones.  Right eigenvalue lam_r[i] takes
+    // the left Ritz pair (of H(-mu)) whose conjugate eigenvalue is nearest, each
+    // at most once, so L comes in R's order and G = L^dag R is nearly diagonal.
+    // A right eigenvalue without a left partner means the two searches found
+    // different critical sets: the oblique projector of Eq. 20-21 would be wrong.
+    std::vector<int> pick(m, -1);
+    if (!right_only) {
+        std::vector<char> used(lam_l.size(), 0);
+        double worst = 0;
+        for (int i = 0; i < m; ++i) {
+            int best = -1;
+            double bd = INFINITY;
+            for (size_t j = 0; j < lam_l.size(); ++j) {
+                if (used[j]) continue;
+                const double d = cabsd(csub(cconj(lam_l[j]), lam_r[i]));
+                if (d < bd) { bd = d; best = (int)j; }
+            }
+            if (best < 0) {
+                c->m_alloc = c->m_active = 0;
+                throw OsaError{OSA_ERR_EIG_NOCONV, "fewer left than right critical pairs"};
+            }
+            used[best] = 1;
+            pick[i] = best;
+            worst = std::max(worst, bd);
+        }
+        res_l = eig_resid(w.get(), true, Ln.as<cd>(), lam_l, pick);
+        const double mtol = std::max(1e-8 * c->hnorm_bound, 1e3 * std::max(res_r, res_l));
+        if (!(worst <= mtol)) {
+            c->m_alloc = c->m_active = 0;
+            char b[200];
+            snprintf(b, sizeof b, "left and right searches disagree: a critical eigenvalue has "
+                     "no left partner within %.1e (nearest %.3e)", mtol, worst);
+            throw OsaError{OSA_ERR_EIG_NOCONV, b};
+        }
+    }
     // install
     c->R.ensure(sizeof(cd) * (size_t)N * m);
     OSA_HIP(hipMemcpyAsync(c->R.p, Rn.p, sizeof(cd) * (size_t)N * m, hipMemcpyDeviceToDevice, c->st));
     if (!right_only) {
         c->L.ensure(sizeof(cd) * (size_t)N * m);
-        OSA_HIP(hipMemcpyAsync(c->L.p, Ln.p, sizeof(cd) * (size_t)N * m, hipMemcpyDeviceToDevice,
-                               c->st));
+        for (int i = 0; i < m; ++i)
+            OSA_HIP(hipMemcpyAsync(c->L.as<cd>() + (size_t)i * N, Ln.as<cd>() + (size_t)pick[i] * N,
+                                   sizeof(cd) * (size_t)N, hipMemcpyDeviceToDevice, c->st));
     }
     c->have_left = !right_only;
     c->schur_m = 0;
@@ -1795,7 +1920,10 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
     c->max_eig_resid = std::max(res_r, res_l);
     c->eig_matvecs = st.matvecs;
     c->eig_restarts = st.restarts;
-    if (c->min_abs_re < 1e-12 * hn) throw OsaError{OSA_ERR_IMAG_AXIS};
+    if (c->min_abs_re < 1e-12 * hn) {
+        c->m_alloc = c->m_active = 0;   // no half-installed deflation data stays active
+        throw OsaError{OSA_ERR_IMAG_AXIS};
+    }
     // the Krylov-Schur test is on H^2; the pairs used are checked on H itself
     if (!(c->max_eig_resid <= 1e-8 * hn)) {
         c->m_alloc = c->m_active = 0;
@@ -2109,7 +2237,10 @@ osa_status osa_set_deflation(osa_ctx* c, int32_t m, const void* R, const void* L
         c->m_alloc = m;
         c->min_abs_re = INFINITY;
         for (auto& l : c->lambda) c->min_abs_re = std::min(c->min_abs_re, std::fabs(l.x));
-        if (c->min_abs_re < 1e-12 * c->hnorm_bound) return OSA_ERR_IMAG_AXIS;
+        if (c->min_abs_re < 1e-12 * c->hnorm_bound) {
+            c->m_alloc = c->m_active = 0;   // the solve then runs without deflation
+            return OSA_ERR_IMAG_AXIS;
+        }
         c->max_eig_resid = NAN;
         set_active(c, m);
         return OSA_OK;
@@ -2290,6 +2421,25 @@ osa_status osa_small_sign(int32_t k, const void* A, void* s, int32_t* iters, voi
         sync(&c);
         if (iters) *iters = its[0];
         if (its[0] < 0 || !ok[0]) return OSA_ERR_NEWTON_NOCONV;
+        return OSA_OK;
+    });
+}
+
+osa_status osa_small_gemm(int32_t n, int32_t nb, const void* A, const void* B, void* C,
+                          void* stream) {
+    if (n < 1 || n > 4000 || nb < 1 || nb > kMaxBatch || !A || !B || !C) return OSA_ERR_ARG;
+    const size_t bytes = sizeof(cd) * (size_t)n * n * nb;
+    auto overlap = [&](const void* p, const void* q) {
+        return (const char*)p < (const char*)q + bytes && (const char*)q < (const char*)p + bytes;
+    };
+    if (overlap(C, A) || overlap(C, B)) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        Batch bt;
+        bt.n = nb;
+        bt.mat = (int64_t)n * n;
+        launch_zgemm_sq(n, mk(1.0, 0.0), (const cd*)A, (const cd*)B, 0.0, nullptr, 0.0, (cd*)C,
+                        nullptr, nullptr, (hipStream_t)stream, bt);
+        OSA_HIP(hipStreamSynchronize((hipStream_t)stream));
         return OSA_OK;
     });
 }
