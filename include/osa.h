@@ -111,6 +111,15 @@ typedef struct {
                                    sign of the block matrix of Eq. 15.  Data from a Schur-mode
                                    osa_deflate serves only Schur-mode solves: an LR solve or
                                    osa_apply_adjoint on it returns OSA_ERR_STATE            */
+    int32_t stop_rule;          /* convergence estimate resid_est (the paper gives no stopping
+                                   rule; est = beta |s_k - s_k'| / |b| is the change since the
+                                   previous check k', about the error of check k'):
+                                   0 (default): twice the geometric tail est rho^d /
+                                   (1 - rho^d), d = k - k', with rho the per-step rate from
+                                   the last two
+                                   changes (the slower of the last two rates); the first
+                                   estimate is the change itself;
+                                   1: the change itself                                    */
 } osa_opts;
 
 /* Per-solve diagnostics (host struct). */

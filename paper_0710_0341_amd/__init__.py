@@ -56,7 +56,7 @@ class Opts(ctypes.Structure):
                 ("eig_max_restarts", ctypes.c_int32), ("eig_prec", ctypes.c_int32),
                 ("eig_tol", ctypes.c_double), ("max_batch", ctypes.c_int32),
                 ("orth", ctypes.c_int32), ("eig_filter", ctypes.c_int32),
-                ("deflation", ctypes.c_int32)]
+                ("deflation", ctypes.c_int32), ("stop_rule", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -207,7 +207,8 @@ def _lattice(dims, antiperiodic_t=False):
 
 
 def make_opts(k_max=0, check_every=0, no_reproject=False, eig_ncv=0, eig_max_restarts=0,
-              eig_prec=FP64, eig_tol=0.0, max_batch=0, orth=0, eig_filter=0, deflation=LR):
+              eig_prec=FP64, eig_tol=0.0, max_batch=0, orth=0, eig_filter=0, deflation=LR,
+              stop_rule=0):
     o = Opts()
     o.k_max, o.check_every, o.no_reproject = int(k_max), int(check_every), int(bool(no_reproject))
     o.eig_ncv, o.eig_max_restarts, o.eig_prec = int(eig_ncv), int(eig_max_restarts), int(eig_prec)
@@ -216,6 +217,7 @@ def make_opts(k_max=0, check_every=0, no_reproject=False, eig_ncv=0, eig_max_res
     o.orth = int(orth)
     o.eig_filter = int(eig_filter)
     o.deflation = int(deflation)
+    o.stop_rule = int(stop_rule)
     return o
 
 

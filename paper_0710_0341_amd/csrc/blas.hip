@@ -429,6 +429,131 @@ void launch_combine(void* y, const void* B, int64_t ldb, int ncols, const cd* co
                         nullptr, 0, st, bt);
 }
 
+// ------------------------------------------- shared basis, several vectors
+// The LR projection of a lockstep batch applies the same R, L (m columns) to
+// every source's vector.  These kernels read the shared columns once for a
+// group of sources instead of once per source, and give every source exactly
+// the arithmetic of the one-source kernels above (same row chunks, the same
+// fma sequence per (column, source), the same block reduction), so batched
+// results stay bitwise those of single-source solves.
+
+// Dots of 8 shared columns with kMdotR vectors: block (chunk q, column group,
+// vector group); partial of problem b, column c at b*bt.part + c*nchunks + q.
+static constexpr int kMdotR = 4;
+
+__global__ __launch_bounds__(kBlock) void k_mdot_partial(const cd* __restrict__ B, int64_t ldb,
+                                                         int ncols, const cd* __restrict__ w,
+                                                         int64_t n, int rpc, int nchunks,
+                                                         cd* __restrict__ partial, Batch bt) {
+    constexpr int C = 8, R = kMdotR, NV = 2 * C * R;
+    __shared__ double sm[kWaves * NV];
+    __shared__ double so[NV];
+    const int q = blockIdx.x;
+    const int c0 = blockIdx.y * C;
+    const int g0 = blockIdx.z * R;
+    const int nr = (bt.n - g0 < R) ? bt.n - g0 : R;
+    const int nc = (ncols - c0 < C) ? ncols - c0 : C;
+    const int64_t r0 = (int64_t)q * rpc;
+    const int64_t r1 = (r0 + rpc < n) ? r0 + rpc : n;
+    const cd* wv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) wv[r] = w + (int64_t)bt.idx[g0 + (r < nr ? r : 0)] * bt.vec;
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+        cd wi[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) wi[r] = wv[r][i];
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+            if (cc < nc) {
+                const cd b = B[(int64_t)(c0 + cc) * ldb + i];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    double* a = acc + 2 * (r * C + cc);
+                    a[0] = fma(b.x, wi[r].x, fma(b.y, wi[r].y, a[0]));
+                    a[1] = fma(b.x, wi[r].y, fma(-b.y, wi[r].x, a[1]));
+                }
+            }
+        }
+    }
+    block_sum<NV>(acc, sm, so);
+    if (threadIdx.x < nc * R) {
+        const int r = threadIdx.x / nc, cc = threadIdx.x % nc;
+        if (r < nr) {
+            const int pb = bt.idx[g0 + r];
+            partial[pb * bt.part + (int64_t)(c0 + cc) * nchunks + q] =
+                mk(so[2 * (r * C + cc)], so[2 * (r * C + cc) + 1]);
+        }
+    }
+}
+
+int launch_mdot_partial(const cd* B, int64_t ldb, int ncols, const cd* w, const TsPlan& pn,
+                        cd* partial, hipStream_t st, const Batch& bt) {
+    constexpr int C = 8;
+    const TsPlan p = dot_plan(pn.n, ncols, C);   // the one-source plan: same chunks
+    if (ncols <= 0 || bt.n <= 0) return p.nchunks;
+    dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)ceil_div(bt.n, kMdotR));
+    hipLaunchKernelGGL(k_mdot_partial, grid, dim3(kBlock), 0, st, B, ldb, ncols, w, p.n,
+                       p.rows_per_chunk, p.nchunks, partial, bt);
+    OSA_LAUNCH_CHECK();
+    return p.nchunks;
+}
+
+// w_b[i] -= sum_c B[c][i] coef_b[c] for up to kMupdR problems per launch
+// entry, B read once: the arithmetic of k_update_direct (alpha = 1, no norm
+// partials) for every problem.  Batch strides: vec (w), small (coef).
+static constexpr int kMupdR = 16;
+static constexpr int kMupdCols = 64;
+
+__global__ __launch_bounds__(kBlock) void k_mupdate(cd* w, const cd* __restrict__ B, int64_t ldb,
+                                                    int ncols, const cd* __restrict__ coef,
+                                                    int64_t n, Batch bt) {
+    __shared__ cd scoef[kMupdR][kMupdCols];
+    const int g0 = blockIdx.y * kMupdR;
+    const int nr = (bt.n - g0 < kMupdR) ? bt.n - g0 : kMupdR;
+    for (int e = threadIdx.x; e < nr * ncols; e += kBlock) {
+        const int r = e / ncols, c = e % ncols;
+        scoef[r][c] = coef[(int64_t)bt.idx[g0 + r] * bt.small + c];
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    cd acc[kMupdR];
+#pragma unroll
+    for (int r = 0; r < kMupdR; ++r) acc[r] = mk(0.0, 0.0);
+    for (int c = 0; c < ncols; ++c) {
+        const cd b = B[(int64_t)c * ldb + i];
+#pragma unroll
+        for (int r = 0; r < kMupdR; ++r)
+            if (r < nr) cfma(acc[r], b, scoef[r][c]);
+    }
+#pragma unroll
+    for (int r = 0; r < kMupdR; ++r) {
+        if (r < nr) {
+            cd* wp = w + (int64_t)bt.idx[g0 + r] * bt.vec + i;
+            const cd base = *wp;
+            *wp = mk(base.x + -1.0 * acc[r].x, base.y + -1.0 * acc[r].y);
+        }
+    }
+}
+
+bool mupdate_matches_single(int64_t n, int ncols) {
+    // k_update_direct is the one-source kernel exactly when update_impl does not
+    // split the columns: at most 32 columns, or rows enough to fill the GPU
+    return ncols <= kMupdCols && (ncols <= 32 || ceil_div(n, kBlock) >= 1024);
+}
+
+void launch_mupdate(cd* w, const cd* B, int64_t ldb, int ncols, const cd* coef, int64_t n,
+                    hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0 || ncols <= 0) return;
+    if (ncols > kMupdCols) throw HipError{hipErrorInvalidValue, "launch_mupdate: ncols > 64"};
+    dim3 grid((unsigned)ceil_div(n, kBlock), (unsigned)ceil_div(bt.n, kMupdR));
+    hipLaunchKernelGGL(k_mupdate, grid, dim3(kBlock), 0, st, w, B, ldb, ncols, coef, n, bt);
+    OSA_LAUNCH_CHECK();
+}
+
 // ------------------------------------------------ delayed reorthogonalisation
 // Step j (>= 1) of the Arnoldi recurrence with delayed reorthogonalisation.
 // Column j of the basis holds u_j, orthogonalised once and not normalised; z =

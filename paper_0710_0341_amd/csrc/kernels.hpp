@@ -89,6 +89,18 @@ void launch_update(void* w, const void* B, int64_t ldb, int ncols, const cd* coe
 // y[i] = sum_c B[c][i] coef[c] + (add ? y[i] : 0).  Batch strides as launch_update.
 void launch_combine(void* y, const void* B, int64_t ldb, int ncols, const cd* coef, bool fp32,
                     bool add, int64_t n, hipStream_t st, const Batch& bt = Batch());
+// Shared columns B (fp64) against the vectors of several problems, B read once
+// per group of problems, with the per-problem arithmetic of launch_dot_partial
+// (same plan, same summation order: bitwise equal results).  Returns nchunks.
+// Batch strides: vec (w), part (partial).
+int launch_mdot_partial(const cd* B, int64_t ldb, int ncols, const cd* w, const TsPlan& p,
+                        cd* partial, hipStream_t st, const Batch& bt);
+// w_b -= B coef_b for every problem b (fp64, ncols <= 64), B read once per 16
+// problems; bitwise what launch_update does for each problem alone whenever
+// mupdate_matches_single(n, ncols).  Batch strides: vec (w), small (coef).
+bool mupdate_matches_single(int64_t n, int ncols);
+void launch_mupdate(cd* w, const cd* B, int64_t ldb, int ncols, const cd* coef, int64_t n,
+                    hipStream_t st, const Batch& bt);
 // Delayed reorthogonalisation (step j >= 1 of the Arnoldi recurrence).
 // Dots of the ncols columns of B with two vectors in one read of B:
 // partial[c*nchunks + q] for w1, partial[(ncols + c)*nchunks + q] for w2.

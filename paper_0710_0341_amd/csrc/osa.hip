@@ -461,10 +461,18 @@ void project_out(osa_ctx* c, void* wv, cd* cout, cd* tmp, const Batch& bt) {
     const void* Lp = sch ? c->Sch.p : (c->adj ? c->R.p : c->L.p);
     const void* Rp = sch ? c->Sch.p : (c->adj ? c->L.p : c->R.p);
     const cd* Gi = sch ? nullptr : (c->adj ? c->GinvH.as<cd>() : c->Ginv.as<cd>());
-    const int nch = launch_dot_partial(Lp, c->N(), m, wv, false, p, part, c->st, bd);
+    // several sources: the shared L and R are read once per group of sources
+    // (kernels with the one-source arithmetic, so results stay bitwise equal)
+    const bool multi = bt.n > 1;
+    const int nch = multi ? launch_mdot_partial((const cd*)Lp, c->N(), m, (const cd*)wv, p, part,
+                                                c->st, bd)
+                          : launch_dot_partial(Lp, c->N(), m, wv, false, p, part, c->st, bd);
     launch_reduce_partial(part, nch, m, cout, nullptr, Gi, tmp, c->st, bd);
-    launch_update(wv, Rp, c->N(), m, cout, false, p, nullptr, c->upd_scratch.as<cd>(),
-                  (int64_t)(c->upd_scratch.bytes / sizeof(cd)), c->st, bu);
+    if (multi && mupdate_matches_single(c->N(), m))
+        launch_mupdate((cd*)wv, (const cd*)Rp, c->N(), m, cout, c->N(), c->st, bu);
+    else
+        launch_update(wv, Rp, c->N(), m, cout, false, p, nullptr, c->upd_scratch.as<cd>(),
+                      (int64_t)(c->upd_scratch.bytes / sizeof(cd)), c->st, bu);
 }
 
 // Strided device-to-host copy of `width` bytes from each of the problems in
@@ -903,6 +911,25 @@ void check_deflation_state(osa_ctx* c) {
 }
 
 // ------------------------------------------------------------- solve
+// Per-step rate rho of an error e_k = C rho^k from two successive checkpoint
+// changes: est1 over a span of d1 steps, then est2 over the next d2 steps.
+// With e_k geometric, est ~ e_{k-d} - e_k, so est2 / est1 =
+// rho^d1 (1 - rho^d2) / (1 - rho^d1), increasing in rho from 0 to d2/d1;
+// solved by bisection.  1 when the changes do not contract.
+double geometric_rate(double est1, int d1, double est2, int d2) {
+    if (!(est1 > 0) || !(est2 >= 0) || d1 <= 0 || d2 <= 0) return 1.0;
+    if (est2 == 0) return 0.0;
+    const double R = est2 / est1;
+    if (!(R < 0.999 * (double)d2 / (double)d1)) return 1.0;
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 80; ++it) {
+        const double r = 0.5 * (lo + hi);
+        const double f = std::pow(r, d1) * (1.0 - std::pow(r, d2)) / (1.0 - std::pow(r, d1));
+        (f < R ? lo : hi) = r;
+    }
+    return hi;
+}
+
 struct SolveResult {
     osa_status st = OSA_OK;
     int k_used = 0;
@@ -1030,12 +1057,23 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
         }
     }
     std::vector<int> kprev(nb, 0);
-    // Check schedule.  The estimate at a check is the change since the previous
-    // check, i.e. about the error of the previous check.  After two estimates
-    // the geometric rate predicts where the error crosses tol; checks far
-    // before that point are skipped (at most 3 in a row).
+    // Convergence estimate and check schedule (the paper gives no stopping rule).
+    // The change est = beta |s_k - [s_k'; 0]| / |b| since the previous check k'
+    // is about the error of check k'.  stop_rule 0 (default): once two changes
+    // are known, their ratio gives the per-step rate rho of a geometric error
+    // (the slower of the last two rates is used), and the error of the current
+    // iterate is estimated by twice the geometric tail est rho^d / (1 - rho^d),
+    // d = k - k';
+    // the solve stops when that is <= tol (with only one change: when the
+    // change is).  stop_rule 1: stop when the change itself is <= tol, i.e. when
+    // the previous check was accurate enough.  The rate also predicts where the
+    // estimate crosses tol; checks far before that point are skipped (at most 3
+    // in a row).
+    const bool tail_rule = c->opts.stop_rule == 0;
     std::vector<std::vector<int>> cj(nb);       // performed checks
-    std::vector<std::vector<double>> ce(nb);    // ce[i]: estimate at check i (error of check i-1)
+    std::vector<std::vector<double>> ce(nb);    // ce[i]: change at check i (error of check i-1)
+    std::vector<std::vector<double>> crate(nb); // per-step rates from consecutive changes
+    std::vector<double> ctail(nb, INFINITY);    // estimated error at the last check
     std::vector<int> hf;
     std::vector<double> hd;
     // Step j: plain CGS2 extends the decomposition to size j + 1; the delayed
@@ -1078,13 +1116,10 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
         std::vector<int> chk, wait;
         for (int b : act) {
             bool want = true;
-            if (!fixed && kk != kmax && ce[b].size() >= 3) {
-                const size_t q = ce[b].size() - 1;
-                const double e1 = ce[b][q - 1], e2 = ce[b][q];
-                const int j1 = cj[b][q - 2], j2 = cj[b][q - 1];
-                const double r = (e1 > 0 && e2 > 0) ? std::log(e2 / e1) / (double)(j2 - j1) : 0.0;
-                const double pred = e2 * std::exp(r * (double)(kk - j2));
-                const bool near = !(r < 0) || pred <= 3.0 * tol;
+            if (!fixed && kk != kmax && !crate[b].empty()) {
+                const double rho = crate[b].back();
+                const double pred = ctail[b] * std::pow(rho, (double)(kk - cj[b].back()));
+                const bool near = !(rho < 1.0) || !(pred > 3.0 * tol);
                 if (!near && kk - cj[b].back() < 4 * every) want = false;
             }
             (want ? chk : wait).push_back(b);
@@ -1146,9 +1181,30 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
             std::vector<int> cont;
             for (int b : good) {
                 bool stop = res[b].breakdown != 0;
-                if (kprev[b] > 0 && !fixed && res[b].est <= tol) stop = true;
+                if (kprev[b] > 0 && !fixed) {
+                    const double change = res[b].est;
+                    double tail = change;
+                    if (ce[b].size() >= 2 && std::isfinite(ce[b].back())) {
+                        const int d1 = cj[b].back() - cj[b][cj[b].size() - 2];
+                        const int d2 = kc - cj[b].back();
+                        const double rho = geometric_rate(ce[b].back(), d1, change, d2);
+                        const double rho_use = crate[b].empty() ? rho
+                                                                : std::max(rho, crate[b].back());
+                        crate[b].push_back(rho);
+                        if (tail_rule) {
+                            const double q = std::pow(rho_use, (double)d2);
+                            // factor 2: margin for a rate that drifts between checks
+                            tail = q < 1.0 ? 2.0 * change * q / (1.0 - q) : INFINITY;
+                        }
+                    }
+                    if (tail_rule) res[b].est = tail;
+                    ctail[b] = tail;
+                    if (res[b].est <= tol) stop = true;
+                    ce[b].push_back(change);
+                } else {
+                    ce[b].push_back(NAN);
+                }
                 cj[b].push_back(kc);
-                ce[b].push_back(kprev[b] > 0 ? res[b].est : NAN);
                 if (res[b].breakdown) res[b].est = 0.0;
                 if (stop) { done[b] = 1; continue; }
                 kprev[b] = kc;
@@ -2142,7 +2198,8 @@ osa_status osa_set_opts(osa_ctx* c, const osa_opts* opts) {
     if (opts) o = *opts;
     if (o.k_max < 0 || o.k_max > 4000 || o.eig_ncv < 0 || o.eig_ncv > 96 || o.eig_tol < 0 ||
         o.eig_max_restarts < 0 || (o.eig_prec != OSA_FP64 && o.eig_prec != OSA_FP32) ||
-        o.max_batch < 0 || o.max_batch > 64 || o.orth < 0 || o.orth > 1 || o.eig_filter < 0 ||
+        o.max_batch < 0 || o.max_batch > 64 || o.orth < 0 || o.orth > 1 || o.stop_rule < 0 ||
+        o.stop_rule > 1 || o.eig_filter < 0 ||
         o.eig_filter > 200)
         return OSA_ERR_ARG;
     fill_defaults(o);

@@ -533,3 +533,72 @@ def test_newton_schulz_tail_reading(haar2):
         x = 0.5 * (3 * x - x @ x @ x)
     assert np.abs(x - O.sign_eig(h)).max() < 1e-10
     assert 0.5 * (3 * 2.0 - 2.0 ** 3) == -1.0
+
+
+def _geometric_rate(e1, d1, e2, d2):
+    """The rate the GPU's stopping rule solves for: e2 / e1 = r^d1 (1 - r^d2) / (1 - r^d1)."""
+    if not (e1 > 0) or e2 < 0:
+        return 1.0
+    if e2 == 0:
+        return 0.0
+    ratio = e2 / e1
+    if not ratio < 0.999 * d2 / d1:
+        return 1.0
+    lo, hi = 0.0, 1.0
+    for _ in range(80):
+        r = 0.5 * (lo + hi)
+        f = r ** d1 * (1 - r ** d2) / (1 - r ** d1)
+        lo, hi = (r, hi) if f < ratio else (lo, r)
+    return hi
+
+
+@pytest.mark.parametrize("kind,eps", [("haar", 0.0), ("disordered", 0.9)])
+def test_geometric_tail_estimate_reading(kind, eps):
+    """The GPU's default convergence estimate (the paper gives no stopping rule):
+    at checks every d Arnoldi steps the change c_k = beta |s_k - [s_{k-d}; 0]| / |b|
+    of the Krylov iterate (Eq. 22) is about the error of check k - d.  Two
+    successive changes give the per-step rate r of a geometric error, and twice
+    the tail c_k r^d / (1 - r^d), with the slower of the last two rates, is the
+    estimate of the error of check k.  On the oracle's own iterates it must not
+    fall below the true error (against the spectral sign, Eq. 4-6) once the
+    error is in the asymptotic regime (below 1e-4, where stopping decisions for
+    practical tolerances are taken; far from convergence the error can stall
+    for a check while the change is large) and above rounding, and the first
+    check where it is <= 1e-8 must have a true error <= 1e-8."""
+    dims = (2, 3, 3, 4)
+    links = LI.make_links(dims, kind, eps=eps, cfg=9, inst=40)
+    b = LI.gaussian_source(dims, cfg=9, inst=40)
+    h = O.hermitian_wilson_dense(links, dims, 0.3, -1.5)
+    yex = O.sign_eig_apply(h, b)
+    defl = O.Deflation(*O.critical_dense(h, 6))
+    c, xo = defl.split(b)
+    vmat, hmat, beta, kd = O.arnoldi_cgs2(lambda x: h @ x, xo, 500, project=defl.project_out)
+    bn = np.linalg.norm(b)
+    ys, ss = {}, {}
+    for d in (10, 25):
+        prev_s, changes, rates, stop_err = None, [], [], None
+        for k in range(d, kd + 1, d):
+            if k not in ss:
+                ss[k] = O.small_sign_e1(hmat[:k, :k], "eig")
+                ys[k] = defl.exact_part(c) + beta * (vmat[:, :k] @ ss[k])
+            s, y = ss[k], ys[k]
+            err = rel(y, yex)
+            if prev_s is not None:
+                ds = s.copy()
+                ds[: prev_s.size] -= prev_s
+                ch = beta * np.linalg.norm(ds) / bn
+                tail = ch
+                if changes:
+                    r = _geometric_rate(changes[-1], d, ch, d)
+                    r_use = max([r] + rates[-1:])
+                    rates.append(r)
+                    q = r_use ** d
+                    tail = 2 * ch * q / (1 - q) if q < 1 else np.inf
+                changes.append(ch)
+                est = tail * bn / np.linalg.norm(y)
+                if 1e-12 < err < 1e-4 and len(changes) >= 2:
+                    assert est >= err, (d, k, est, err)
+                if stop_err is None and est <= 1e-8:
+                    stop_err = err
+            prev_s = s
+        assert stop_err is not None and stop_err <= 1e-8, d
