@@ -255,6 +255,23 @@ OSA_API osa_status osa_apply_hw(osa_ctx* ctx, int32_t nrhs, const void* X, void*
  * the small-sign kernel for checks; stream-ordered on `stream`. */
 OSA_API osa_status osa_small_sign(int32_t k, const void* A, void* s, int32_t* iters, void* stream);
 
+/* Allocation-free form of osa_small_sign, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same result, bit for bit, with every work array
+ * in one file-scope device array of the library instead of hipMalloc'd
+ * buffers.  Each GPU holds its own copy of that array (about 3.2 MB) until the
+ * process ends; its device address is looked up once per device, on the first
+ * call with that device current.  The caller passes A and s as for
+ * osa_small_sign.  Limit: 1 <= k <= OSA_NOALLOC_MAX_K (256), else OSA_ERR_ARG
+ * before any device work.  No hipMalloc, hipFree or hipMemset is issued (the
+ * flags are cleared by a kernel); the host staging of the read-backs is a
+ * per-thread static buffer.  All calls on one GPU share the array and it keeps
+ * the last call's contents: calls that overlap in time on one GPU (several
+ * streams or host threads) race and must be serialised by the caller. */
+#define OSA_NOALLOC_MAX_K 256
+OSA_API osa_status osa_small_sign_noalloc(int32_t k, const void* A, void* s, int32_t* iters,
+                                          void* stream);
+
 /* C_b = A_b B_b for nb pairs of n x n complex128 matrices (column-major, ld n,
  * problem b at offset b*n*n in each of A, B, C; device), on the FP64 matrix
  * cores: the product kernel of the Newton-Schulz steps X <- (3X - X^3)/2 that

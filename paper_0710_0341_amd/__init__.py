@@ -34,7 +34,8 @@ LR, SCHUR = 0, 1   # osa_opts.deflation
 EXPORTS = ["overlap_sign_apply", "osa_create", "osa_deflate", "osa_set_deflation",
            "osa_get_deflation", "osa_set_active_deflation", "osa_apply", "osa_apply_adjoint",
            "osa_apply_overlap", "osa_batch_apply",
-           "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_small_gemm", "osa_small_schur",
+           "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_small_sign_noalloc",
+           "osa_small_gemm", "osa_small_schur",
            "osa_set_links",
            "osa_profile_enable", "osa_profile_read", "osa_last_message", "osa_destroy",
            "osa_status_string", "osa_set_allocator",
@@ -129,6 +130,7 @@ def lib() -> ctypes.CDLL:
     L.osa_small_sign.argtypes = [i32, vp, vp, ctypes.POINTER(i32), vp]
     L.osa_small_schur.argtypes = [i32, vp, vp, vp, vp, i32, vp]
     L.osa_small_gemm.argtypes = [i32, i32, vp, vp, vp, vp]
+    L.osa_small_sign_noalloc.argtypes = [i32, vp, vp, ctypes.POINTER(i32), vp]
     L.osa_set_links.argtypes = [vp, vp]
     L.osa_profile_enable.argtypes = [vp, i32]
     L.osa_profile_read.argtypes = [vp, ctypes.POINTER(Profile)]
@@ -443,13 +445,16 @@ def small_gemm(A, B):
     return C[0] if single else C
 
 
-def small_sign(A):
-    """s = sign(A) e_1 for a square complex128 GPU tensor A (the Newton kernel)."""
+def small_sign(A, noalloc=False):
+    """s = sign(A) e_1 for a square complex128 GPU tensor A (the Newton kernel).
+    noalloc=True calls osa_small_sign_noalloc (workspace in the library's static
+    device array, k <= 256)."""
     torch = _torch()
     k = int(A.shape[0])
     Acm = A.t().contiguous()          # column-major storage
     s = torch.empty(k, dtype=torch.complex128, device=A.device)
     it = ctypes.c_int32(0)
-    _check(lib().osa_small_sign(k, ctypes.c_void_p(Acm.data_ptr()), ctypes.c_void_p(s.data_ptr()),
-                                ctypes.byref(it), _stream()), "osa_small_sign", False)
+    name = "osa_small_sign_noalloc" if noalloc else "osa_small_sign"
+    _check(getattr(lib(), name)(k, ctypes.c_void_p(Acm.data_ptr()), ctypes.c_void_p(s.data_ptr()),
+                                ctypes.byref(it), _stream()), name, False)
     return s, it.value

@@ -1024,6 +1024,21 @@ void launch_convert(const void* src, bool src_fp32, void* dst, bool dst_fp32, in
     OSA_LAUNCH_CHECK();
 }
 
+// Zero `bytes` bytes (a multiple of 4) with a kernel: unlike hipMemsetAsync it
+// records as an ordinary kernel node when a caller captures the stream.
+__global__ __launch_bounds__(kBlock) void k_fill_zero(uint32_t* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+void launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, st,
+                       (uint32_t*)p, n);
+    OSA_LAUNCH_CHECK();
+}
+
 // splitmix64 finaliser as a counter-based generator
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z += 0x9E3779B97F4A7C15ULL;

@@ -150,6 +150,8 @@ void launch_rotate(const void* B, int64_t ldb, int ncols_in, const cd* Z, int ld
 // fp32 <-> fp64 vector copies
 void launch_convert(const void* src, bool src_fp32, void* dst, bool dst_fp32, int64_t n,
                     hipStream_t st);
+// Zero bytes (a multiple of 4) of device memory with a kernel.
+void launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 // Deterministic pseudo-random unit-variance complex vector (counter-based hash),
 // zero on padding sites.
 void launch_random_vector(void* v, bool fp32, const Geom& g, uint64_t seed, hipStream_t st);

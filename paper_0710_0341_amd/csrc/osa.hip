@@ -21,6 +21,7 @@
 #include <mutex>
 #include <new>
 #include <exception>
+#include <stdexcept>
 #include <string>
 #include <thread>
 #include <vector>
@@ -51,11 +52,24 @@ struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
     AllocHook hook{};
+    bool borrowed = false;   // memory owned elsewhere: never freed, never grown
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
+    void borrow(void* q, size_t b) {
+        release();
+        p = q;
+        bytes = b;
+        borrowed = true;
+    }
     void release() {
+        if (borrowed) {
+            p = nullptr;
+            bytes = 0;
+            borrowed = false;
+            return;
+        }
         if (p) {
             if (hook.dealloc) {
                 // the hook's allocator may hand the block out again at once: let
@@ -72,6 +86,7 @@ struct DevBuf {
     }
     void ensure(size_t b) {
         if (b <= bytes && p) return;
+        if (borrowed) throw std::length_error("borrowed workspace too small");
         release();
         if (b == 0) b = 16;
         const AllocHook h = current_alloc_hook();
@@ -103,11 +118,19 @@ struct DevBuf {
 struct PinnedBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;   // ordinary host memory owned elsewhere
     ~PinnedBuf() {
-        if (p) (void)hipHostFree(p);
+        if (p && !borrowed) (void)hipHostFree(p);
+    }
+    void borrow(void* q, size_t b) {
+        if (p && !borrowed) (void)hipHostFree(p);
+        p = q;
+        bytes = b;
+        borrowed = true;
     }
     void ensure(size_t b) {
         if (b <= bytes && p) return;
+        if (borrowed) throw std::length_error("borrowed host staging too small");
         if (p) (void)hipHostFree(p);
         p = nullptr;
         if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
@@ -644,7 +667,7 @@ void small_sign_batch(osa_ctx* c, const std::vector<int>& probs, int k, const cd
             launch_copy_square(A, lda, X, k, c->st, b0);
         }
     }
-    OSA_HIP(hipMemsetAsync(c->nflag.p, 0, c->nflag.bytes, c->st));
+    launch_fill_zero(c->nflag.p, c->nflag.bytes, c->st);   // a kernel, not a memset node
     uint64_t scale = ~0ULL;
     std::vector<double> prev(c->kbatch, INFINITY);
     // problems in the Newton-Schulz phase: X <- (3X - X^3)/2 by two GEMMs on the
@@ -2034,6 +2057,9 @@ osa_status guard(F&& f, std::string* msg = nullptr) {
     } catch (const std::bad_alloc&) {
         if (msg) *msg = "device allocation failed";
         return OSA_ERR_OOM;
+    } catch (const std::length_error& e) {
+        if (msg) *msg = e.what();
+        return OSA_ERR_ARG;
     } catch (...) {
         return OSA_ERR_HIP;
     }
@@ -2158,6 +2184,41 @@ osa_status apply_impl(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double t
 }
 
 }  // namespace
+
+// ====================================================== allocation-free scratch
+// Workspace of osa_small_sign_noalloc: one file-scope device array (each GPU
+// the library runs on holds its own copy until the process ends).  Its size
+// covers the small sign of one k x k problem for k <= OSA_NOALLOC_MAX_K: three
+// k x k matrices, the pivot logs, the Gauss-Jordan work arrays, the flags and
+// the reduction slots, each rounded up to 256 bytes.
+static constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+static constexpr size_t kNoallocScratchBytes =
+    3 * round256(16ull * OSA_NOALLOC_MAX_K * OSA_NOALLOC_MAX_K) +   // X, M, Y
+    round256(8ull * OSA_NOALLOC_MAX_K) +                            // log |pivot|
+    round256(92ull * OSA_NOALLOC_MAX_K + 256) +                     // Gauss-Jordan (gj_ws_bytes)
+    256 +                                                           // flags
+    round256(8ull * (2 + 2 * ((OSA_NOALLOC_MAX_K * OSA_NOALLOC_MAX_K + 255) / 256) + 16));
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[64] = {};   // device address of scratch per device ordinal
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current.  In host code the array's name is only a
+// host-side stand-in, so kernels get this address, never the name.
+static void* noalloc_scratch() {
+    int dev = 0;
+    OSA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) throw OsaError{OSA_ERR_HIP, "device ordinal beyond 63"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        OSA_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw OsaError{OSA_ERR_HIP, "hipGetSymbolAddress(scratch) gave NULL"};
+        g_scratch_dev[dev] = ptr;
+    }
+    return g_scratch_dev[dev];
+}
 
 // ================================================================ C ABI
 extern "C" {
@@ -2497,6 +2558,53 @@ osa_status osa_small_gemm(int32_t n, int32_t nb, const void* A, const void* B, v
         launch_zgemm_sq(n, mk(1.0, 0.0), (const cd*)A, (const cd*)B, 0.0, nullptr, 0.0, (cd*)C,
                         nullptr, nullptr, (hipStream_t)stream, bt);
         OSA_HIP(hipStreamSynchronize((hipStream_t)stream));
+        return OSA_OK;
+    });
+}
+
+osa_status osa_small_sign_noalloc(int32_t k, const void* A, void* s, int32_t* iters,
+                                  void* stream) {
+    if (k < 1 || !A || !s) return OSA_ERR_ARG;
+    if (k > OSA_NOALLOC_MAX_K) return OSA_ERR_ARG;   // the scratch array holds k <= 256
+    return guard([&]() -> osa_status {
+        char* base = (char*)noalloc_scratch();
+        // carve the workspace of one problem of size k, with the strides
+        // osa_small_sign uses, so both run the same launches on the same layout
+        const size_t mat = sizeof(cd) * (size_t)k * k;
+        const int64_t gj_stride = (int64_t)ceil_div((int64_t)gj_ws_bytes(k), 256) * 256;
+        const int64_t red_stride = newton_red_len(k) + 16;
+        size_t off = 0;
+        auto take = [&](size_t b) {
+            char* q = base + off;
+            off += (size_t)ceil_div((int64_t)b, 256) * 256;
+            return q;
+        };
+        osa_ctx c;
+        c.st = (hipStream_t)stream;
+        c.g.lx = c.g.ly = c.g.lz = c.g.lt = 2;
+        c.g.V = 16;
+        c.g.Vp = 64;
+        c.kcap = k;
+        c.scap = k;
+        c.kbatch = 1;
+        c.gj_stride = gj_stride;
+        c.red_stride = red_stride;
+        c.sX.borrow(take(mat), mat);
+        c.sM.borrow(take(mat), mat);
+        c.sY.borrow(take(mat), mat);
+        c.logpiv.borrow(take(sizeof(double) * k), sizeof(double) * k);
+        c.gjws.borrow(take((size_t)gj_stride), (size_t)gj_stride);
+        c.nflag.borrow(take(sizeof(int) * 4), sizeof(int) * 4);
+        c.red.borrow(take(sizeof(double) * (size_t)red_stride), sizeof(double) * (size_t)red_stride);
+        if (off > kNoallocScratchBytes) throw OsaError{OSA_ERR_ARG, "scratch too small"};
+        thread_local char staging[1 << 12];   // ordinary host memory for the read-backs
+        c.host.borrow(staging, sizeof staging);
+        std::vector<int> its(1, 0);
+        std::vector<char> ok(1, 0);
+        small_sign_batch(&c, std::vector<int>{0}, k, (const cd*)A, k, 0, (cd*)s, 0, its, ok);
+        sync(&c);
+        if (iters) *iters = its[0];
+        if (its[0] < 0 || !ok[0]) return OSA_ERR_NEWTON_NOCONV;
         return OSA_OK;
     });
 }
