@@ -124,6 +124,81 @@ def roofline(table, workload):
                                                                 for v in table.values())}
 
 
+class roctx_range:
+    """A named ROCTx range (rocprofv3 --marker-trace records it) around a block;
+    a no-op where the ROCTx library is not found."""
+    _lib = None
+
+    def __init__(self, name):
+        self.name = name.encode()
+        if roctx_range._lib is None:
+            import ctypes
+            roctx_range._lib = False
+            for so in ("librocprofiler-sdk-roctx.so.1", "libroctx64.so.4"):
+                try:
+                    lib = ctypes.CDLL(so)
+                    lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+                    roctx_range._lib = lib
+                    break
+                except OSError:
+                    continue
+
+    def __enter__(self):
+        if roctx_range._lib:
+            roctx_range._lib.roctxRangePushA(self.name)
+        return self
+
+    def __exit__(self, *exc):
+        if roctx_range._lib:
+            roctx_range._lib.roctxRangePop()
+        return False
+
+
+def summarize_trace(trace_dir, out_md):
+    """Per-kernel statistics of the dispatches inside the 'timed_steps' ROCTx range
+    of a rocprofv3 --kernel-trace --marker-trace run of this benchmark."""
+    import csv
+    import glob
+    import re
+    kt = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    mk = glob.glob(os.path.join(trace_dir, "**", "*marker_api_trace.csv"), recursive=True)
+    t0 = t1 = None
+    with open(mk[0]) as f:
+        for r in csv.DictReader(f):
+            if r.get("Function", "").find("timed_steps") >= 0 or \
+                    r.get("Operation", "").find("timed_steps") >= 0 or \
+                    any("timed_steps" in str(v) for v in r.values()):
+                t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+    stats = {}
+    with open(kt[0]) as f:
+        for r in csv.DictReader(f):
+            a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            if t0 is None or a < t0 or b > t1:
+                continue
+            name = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "").replace("osa::", "")
+            name = name.replace("HIP_vector_type<double, 2u>", "cd").replace(
+                "HIP_vector_type<float, 2u>", "cf")
+            st = stats.setdefault(name, [0, 0])
+            st[0] += 1
+            st[1] += b - a
+    tot = sum(v[1] for v in stats.values())
+    rows = sorted(stats.items(), key=lambda kv: -kv[1][1])
+    lines = ["| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for name, (n, ns) in rows:
+        lines.append(f"| {name} | {n} | {ns / 1e6:.1f} | {ns / n / 1e3:.2f} | "
+                     f"{100.0 * ns / tot:.2f} |")
+    classes = {}
+    for cls, pat in CLASS_KERNELS.items():
+        rx = re.compile(pat)
+        n = sum(v[0] for k, v in stats.items() if rx.search(k))
+        ns = sum(v[1] for k, v in stats.items() if rx.search(k))
+        if n:
+            classes[cls] = {"dispatches": n, "avg_us": ns / n / 1e3, "total_ms": ns / 1e6}
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps({"range_ns": [t0, t1], "kernels": len(stats), "classes": classes}, indent=1))
+
+
 def host_info():
     """nproc, the CPU model and the BLAS thread count of this host."""
     model = "unknown"
@@ -162,6 +237,19 @@ def parse():
                          "concurrently; "
                          "fig1: the error-vs-Krylov-size study of the results section; "
                          "haar12: 12^4 with FP32 links, FP32 vs FP64 eigensearch")
+    ap.add_argument("--counters-sample", action="store_true",
+                    help="dis16 kernel-counter sample: one 12-source lockstep solve at the "
+                         "headline's Krylov size (fixed k = 225, m = 40 placeholder deflation "
+                         "data, no eigensolver), every launch event-timed; prints the class "
+                         "table (for rocprofv3 --pmc runs)")
+    ap.add_argument("--summarize-counters", nargs=5,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR",
+                             "SAMPLE_JSON"),
+                    help="reduce rocprofv3 --pmc outputs of --counters-sample and "
+                         "--copy-calibration to profiles/<class>_dis16_hbm_traffic.json")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
+                    help="per-kernel statistics of the timed steps from a rocprofv3 "
+                         "--kernel-trace --marker-trace run of this benchmark")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--solve-only", action="store_true",
@@ -184,6 +272,120 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n * 16, "copy_bytes_written": n * 16, "launches": 5}))
+
+
+COUNTER_K = 225   # the headline's Krylov size (k_used of every source)
+
+# kernels behind each profiled class (rocprofv3 kernel names), and the source
+# regions whose hash dates a counter summary
+CLASS_KERNELS = {
+    "cgs_dot": r"k_dot_partial|k_dot2_partial",
+    "cgs_update": r"k_update_direct|k_update_split|k_update_finish|k_dcgs_update|k_dcgs_split|"
+                  r"k_dcgs_finish",
+    "stencil": r"k_wilson_h",
+}
+CLASS_REGIONS = {
+    "cgs_dot": [("paper_0710_0341_amd/csrc/blas.hip", "static TsPlan dot_plan(",
+                 "// ---------------------------------------------------------------- reduce")],
+    "cgs_update": [("paper_0710_0341_amd/csrc/blas.hip",
+                    "// ---------------------------------------------------------------- update",
+                    "// ---------------------------------------------------------------- norms")],
+    "stencil": [("paper_0710_0341_amd/csrc/stencil.hip",
+                 "// ------------------------------------------------------------------ stencil",
+                 "void launch_wilson_h_contig(")],
+}
+
+
+def counters_sample(args):
+    """One 12-source lockstep solve with the headline's shapes, for counter runs."""
+    import torch
+
+    import lattice_inputs as LI
+    import paper_0710_0341_amd as osa
+    w = LI.WORKLOADS[3]
+    dims = w["dims"]
+    links_np = LI.round_links_fp32(LI.make_links(dims, "disordered", eps=w["eps"], cfg=3, inst=0))
+    links = torch.from_numpy(links_np.astype(np.complex64)).to("cuda:0")
+    B = torch.from_numpy(point_sources(dims)).to("cuda:0")
+    n = B.shape[1]
+    r, l, lam = LI.placeholder_deflation(n, w["n_defl"], cfg=3, inst=0)
+    ctx = osa.Context(links, dims, w["mu"], w["m_w"], k_max=COUNTER_K, check_every=-1,
+                      max_batch=B.shape[0])
+    ctx.set_deflation(torch.from_numpy(np.ascontiguousarray(r.T)).to("cuda:0"),
+                      torch.from_numpy(np.ascontiguousarray(l.T)).to("cuda:0"), lam)
+    ctx.profile(True, every=1)
+    ctx.apply(B, tol=1.0)
+    torch.cuda.synchronize()
+    table = class_table([ctx.profile_read()], 1)
+    ctx.close()
+    print(json.dumps({"counters_sample": "dis16_12pt", "k": COUNTER_K, "classes": table}))
+
+
+def summarize_counters(args):
+    """HBM traffic per launch of each class from rocprofv3 --pmc FETCH_SIZE and
+    WRITE_SIZE runs of --counters-sample, scaled by the same counters' readings
+    for the plain 1 GiB copy of --copy-calibration (bytes per KiB reading)."""
+    import csv
+    import glob
+    import hashlib
+    import re
+    fetch_dir, write_dir, cf_dir, cw_dir, sample_json = args.summarize_counters
+
+    def rows(d, counter):
+        out = []
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as f:
+                for r in csv.DictReader(f):
+                    if r.get("Counter_Name") == counter:
+                        out.append((r["Kernel_Name"], float(r["Counter_Value"]), r["Dispatch_Id"]))
+        return out
+
+    def per_dispatch(rs):
+        acc = {}
+        for name, v, did in rs:   # a counter can come in several rows per dispatch
+            key = (did, name)
+            acc[key] = acc.get(key, 0.0) + v
+        return acc
+
+    cf = per_dispatch(rows(cf_dir, "FETCH_SIZE"))
+    cw = per_dispatch(rows(cw_dir, "WRITE_SIZE"))
+    copy_f = [v for (d, n), v in cf.items() if "copy" in n.lower()]
+    copy_w = [v for (d, n), v in cw.items() if "copy" in n.lower()]
+    gib = float(1 << 30)
+    fetch_factor = gib / float(np.median(copy_f))    # bytes per unit of FETCH_SIZE
+    write_factor = gib / float(np.median(copy_w))
+    fetch = per_dispatch(rows(fetch_dir, "FETCH_SIZE"))
+    write = per_dispatch(rows(write_dir, "WRITE_SIZE"))
+    with open(sample_json) as f:
+        sample = json.loads(f.read().strip().splitlines()[-1])
+    out = {}
+    for cls, pat in CLASS_KERNELS.items():
+        rx = re.compile(pat)
+        fs = [v for (d, n), v in fetch.items() if rx.search(n)]
+        ws = [v for (d, n), v in write.items() if rx.search(n)]
+        if not fs or not ws:
+            continue
+        hbm = (np.sum(fs) * fetch_factor + np.sum(ws) * write_factor) / len(fs)
+        alg = sample["classes"][cls]["bytes_per_launch"]
+        regions = []
+        for fn, a, b in CLASS_REGIONS[cls]:
+            with open(os.path.join(ROOT, fn)) as f:
+                src = f.read()
+            i, j = src.index(a), src.index(b)
+            regions.append({"file": fn, "from": a, "to": b,
+                            "sha256": hashlib.sha256(src[i:j].encode()).hexdigest()})
+        rec = {"kernel_class": cls, "kernels": pat, "workload": "dis16_12pt counters sample "
+               f"(12 sources, fixed k = {COUNTER_K}, m = 40)",
+               "dispatches": len(fs), "fetch_factor": fetch_factor, "write_factor": write_factor,
+               "hbm_bytes_per_launch": float(hbm), "algorithmic_bytes_per_launch": alg,
+               "measured_over_algorithmic": float(hbm / alg), "kernel_regions": regions}
+        with open(os.path.join(PROFILES, f"{cls}_dis16_hbm_traffic.json"), "w") as f:
+            json.dump(rec, f, indent=1)
+        out[cls] = rec
+    print(json.dumps({k: {"hbm_MB": v["hbm_bytes_per_launch"] / 1e6,
+                          "alg_MB": v["algorithmic_bytes_per_launch"] / 1e6,
+                          "ratio": v["measured_over_algorithmic"], "dispatches": v["dispatches"]}
+                      for k, v in out.items()}, indent=1))
 
 
 def workload(name):
@@ -402,12 +604,13 @@ def headline16(args):
         ctx.apply(B, tol=tol)
     torch.cuda.synchronize()
     ctx.profile(True, every=PROF_EVERY)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        Y, infos, st = ctx.apply(B, tol=tol)
-        print(f"dis16: step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with roctx_range("timed_steps"):
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            Y, infos, st = ctx.apply(B, tol=tol)
+            print(f"dis16: step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     table = class_table([ctx.profile_read()], args.steps)
     ctx.profile(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -590,6 +793,15 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.summarize_counters:
+        summarize_counters(args)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.counters_sample:
+        counters_sample(args)
         return
     if args.workload == "uneven64":
         uneven_batch(args)

@@ -187,28 +187,66 @@ struct StencilArgs {
     int64_t Vp;
     int apt;
     double cf[4], cb[4];
+    // work order (see block_work): total = site blocks x problems, per_xcd =
+    // ceil(total / 8); bps > 0: site blocks per time slice (time slices in pairs)
+    int total, per_xcd, bps;
 };
 
-// One block: 64 sites of one problem, one wavefront per direction nu (both hops
-// of nu, so the direction is uniform in a wave); the four partial sums meet in
-// LDS, where each wave adds the diagonal term and gamma_5 for three of the
-// twelve components.  Four times the waves of one-thread-per-site, each with a
-// quarter of the hops: small lattices fill the GPU, large ones keep coalesced
-// site-contiguous accesses.
+static constexpr int kStGroup = 4;   // problems sharing one pass over a pair of slices
+
+// Which (site block, problem) a workgroup takes.  Workgroups go to the eight
+// XCDs of the chip round-robin (workgroup b to XCD b % 8), and each XCD has its
+// own L2.  Giving XCD x the contiguous stretch [x per_xcd, (x+1) per_xcd) of
+// the work order keeps a neighbourhood of the lattice in one L2.  The order runs
+// over pairs of time slices; within a pair, over groups of up to four
+// problems, and within a group over the site blocks of a slice, then the two
+// slices, then the problems of the group: the time neighbour inside a pair, the
+// z and y neighbours and the links (shared by a group) are all read a few
+// dozen workgroups apart, so they come from that XCD's L2 rather than HBM.
+// Without whole 64-site blocks per slice (bps = 0) the order is site block
+// major, problem minor.  Returns false for the padding workgroups.
+__device__ __forceinline__ bool block_work(const StencilArgs& a, int nprob, int& sb, int& entry) {
+    const int b = (int)blockIdx.x;
+    const int L = (b & 7) * a.per_xcd + (b >> 3);
+    if (L >= a.total) return false;
+    if (a.bps > 0) {
+        // problems in groups of kStGroup: within a pair of slices, group by group
+        const int per_pair = a.bps * 2 * nprob;
+        const int tp = L / per_pair;
+        int r = L - tp * per_pair;
+        const int g0 = (r / (a.bps * 2 * kStGroup)) * kStGroup;
+        const int gn = (nprob - g0 < kStGroup) ? nprob - g0 : kStGroup;
+        r -= g0 * a.bps * 2;
+        const int q = r / (2 * gn);
+        const int r2 = r - q * 2 * gn;
+        const int dt = r2 / gn;
+        entry = g0 + (r2 - dt * gn);
+        sb = (2 * tp + dt) * a.bps + q;
+    } else {
+        entry = L % nprob;
+        sb = L / nprob;
+    }
+    return true;
+}
+
+// One block: 64 sites of one problem and two wavefronts, each with both hops of
+// two directions (x and y; z and t), so the direction is uniform in a wave.  The
+// two partial sums meet in LDS (24 KB per block at FP64, so six blocks fit a
+// compute unit), where each wave adds the diagonal term and gamma_5 for six of
+// the twelve components.  Small lattices still fill the GPU (two waves per 64
+// sites), large ones keep coalesced, site-contiguous accesses.
 template <typename R, typename ST, typename LT>
-__global__ __launch_bounds__(256) void k_wilson_h(const ST* __restrict__ in, ST* __restrict__ out,
+__global__ __launch_bounds__(128) void k_wilson_h(const ST* __restrict__ in, ST* __restrict__ out,
                                                  const LT* __restrict__ U, StencilArgs a,
                                                  Batch bt) {
-    __shared__ Cx<R> part[4][12][64];
-    // consecutive blocks take the same sites for the problems of the batch, so
-    // a block of links is fetched from HBM once and then served from L2
-    const int entry = (int)(blockIdx.x % (unsigned)bt.n);
-    const int sb = (int)(blockIdx.x / (unsigned)bt.n);
+    __shared__ Cx<R> part[2][12][64];
+    int sb = 0, entry = 0;
+    if (!block_work(a, bt.n, sb, entry)) return;   // uniform over the block
     const int pb = bt.idx[entry];
     in += pb * bt.basis;
     out += pb * bt.vec;
     const int lane = threadIdx.x & 63;
-    const int d = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // direction of the wave
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // 0: x, y; 1: z, t
     const int s = sb * 64 + lane;
     const int64_t Vp = a.Vp;
     Cx<R> acc[12];
@@ -221,50 +259,47 @@ __global__ __launch_bounds__(256) void k_wilson_h(const ST* __restrict__ in, ST*
         r /= a.ly;
         const int z = r % a.lz;
         const int t = r / a.lz;
-        if (d == 0) {
-            const int f = (x + 1 == a.lx) ? s - (a.lx - 1) : s + 1;
-            const int b = (x == 0) ? s + (a.lx - 1) : s - 1;
-            hop<R, 0, +1>(in, U, Vp, f, s, (R)a.cf[0], acc);
-            hop<R, 0, -1>(in, U, Vp, b, b, (R)a.cb[0], acc);
-        } else if (d == 1) {
+        if (w == 0) {
+            const int fx = (x + 1 == a.lx) ? s - (a.lx - 1) : s + 1;
+            const int bx = (x == 0) ? s + (a.lx - 1) : s - 1;
+            hop<R, 0, +1>(in, U, Vp, fx, s, (R)a.cf[0], acc);
+            hop<R, 0, -1>(in, U, Vp, bx, bx, (R)a.cb[0], acc);
             const int sy = a.lx;
-            const int f = (y + 1 == a.ly) ? s - (a.ly - 1) * sy : s + sy;
-            const int b = (y == 0) ? s + (a.ly - 1) * sy : s - sy;
-            hop<R, 1, +1>(in, U, Vp, f, s, (R)a.cf[1], acc);
-            hop<R, 1, -1>(in, U, Vp, b, b, (R)a.cb[1], acc);
-        } else if (d == 2) {
-            const int sz = a.lx * a.ly;
-            const int f = (z + 1 == a.lz) ? s - (a.lz - 1) * sz : s + sz;
-            const int b = (z == 0) ? s + (a.lz - 1) * sz : s - sz;
-            hop<R, 2, +1>(in, U, Vp, f, s, (R)a.cf[2], acc);
-            hop<R, 2, -1>(in, U, Vp, b, b, (R)a.cb[2], acc);
+            const int fy = (y + 1 == a.ly) ? s - (a.ly - 1) * sy : s + sy;
+            const int by = (y == 0) ? s + (a.ly - 1) * sy : s - sy;
+            hop<R, 1, +1>(in, U, Vp, fy, s, (R)a.cf[1], acc);
+            hop<R, 1, -1>(in, U, Vp, by, by, (R)a.cb[1], acc);
         } else {
+            const int sz = a.lx * a.ly;
+            const int fz = (z + 1 == a.lz) ? s - (a.lz - 1) * sz : s + sz;
+            const int bz = (z == 0) ? s + (a.lz - 1) * sz : s - sz;
+            hop<R, 2, +1>(in, U, Vp, fz, s, (R)a.cf[2], acc);
+            hop<R, 2, -1>(in, U, Vp, bz, bz, (R)a.cb[2], acc);
             const int stt = a.lx * a.ly * a.lz;
-            const int f = (t + 1 == a.lt) ? s - (a.lt - 1) * stt : s + stt;
-            const int b = (t == 0) ? s + (a.lt - 1) * stt : s - stt;
+            const int ft = (t + 1 == a.lt) ? s - (a.lt - 1) * stt : s + stt;
+            const int bt_ = (t == 0) ? s + (a.lt - 1) * stt : s - stt;
             R ctf = (R)a.cf[3], ctb = (R)a.cb[3];
             if (a.apt) {
                 if (t + 1 == a.lt) ctf = -ctf;
                 if (t == 0) ctb = -ctb;
             }
-            hop<R, 3, +1>(in, U, Vp, f, s, ctf, acc);
-            hop<R, 3, -1>(in, U, Vp, b, b, ctb, acc);
+            hop<R, 3, +1>(in, U, Vp, ft, s, ctf, acc);
+            hop<R, 3, -1>(in, U, Vp, bt_, bt_, ctb, acc);
         }
     }
 #pragma unroll
-    for (int c = 0; c < 12; ++c) part[d][c][lane] = acc[c];
+    for (int c = 0; c < 12; ++c) part[w][c][lane] = acc[c];
     __syncthreads();
     if (s < a.Vp) {
         // padding sites carry zeros so that whole-vector reductions stay exact
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const int c = 3 * d + i;
+        for (int i = 0; i < 6; ++i) {
+            const int c = 6 * w + i;
             ST o;
             o.x = 0;
             o.y = 0;
             if (s < a.V) {
-                Cx<R> v = ld<R>(in + (int64_t)c * Vp + s) + part[0][c][lane] + part[1][c][lane] +
-                          part[2][c][lane] + part[3][c][lane];
+                Cx<R> v = ld<R>(in + (int64_t)c * Vp + s) + part[0][c][lane] + part[1][c][lane];
                 if (c >= 6) v = Cx<R>{-v.x, -v.y};    // gamma_5
                 o.x = v.x;
                 o.y = v.y;
@@ -282,8 +317,14 @@ void launch_wilson_h(const void* in, void* out, const void* U, bool links_fp32, 
     StencilArgs a;
     a.lx = g.lx; a.ly = g.ly; a.lz = g.lz; a.lt = g.lt; a.V = g.V; a.Vp = g.Vp; a.apt = g.apt;
     for (int i = 0; i < 4; ++i) { a.cf[i] = c.fwd[i]; a.cb[i] = c.bwd[i]; }
-    // the grid covers Vp sites (padding included; Vp is a multiple of 64) for each problem
-    dim3 blk(256), grid((unsigned)(ceil_div(g.Vp, 64) * bt.n));
+    // the work covers Vp sites (padding included; Vp is a multiple of 64) for each problem
+    const int64_t nsb = ceil_div(g.Vp, 64);
+    const int64_t total = nsb * bt.n;
+    a.total = (int)total;
+    a.per_xcd = (int)ceil_div(total, 8);
+    const int64_t P = (int64_t)g.lx * g.ly * g.lz;
+    a.bps = (P % 64 == 0 && g.lt % 2 == 0 && (int64_t)g.V == g.Vp) ? (int)(P / 64) : 0;
+    dim3 blk(128), grid((unsigned)(8 * a.per_xcd));
     if (!spinor_fp32 && !links_fp32)
         hipLaunchKernelGGL((k_wilson_h<double, cd, cd>), grid, blk, 0, st, (const cd*)in, (cd*)out,
                            (const cd*)U, a, bt);
