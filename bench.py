@@ -490,7 +490,8 @@ def uneven_batch(args):
         t.join()
     t_defl = time.perf_counter() - t0
     print("batch warm-up", file=sys.stderr, flush=True)
-    osa.batch_apply(ctxs, srcs, tol=w["tol"])          # warm-up: workspace growth
+    for _ in range(2):   # workspace growth, dot autotuning, then recording of segment graphs
+        osa.batch_apply(ctxs, srcs, tol=w["tol"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ys, infos, st = osa.batch_apply(ctxs, srcs, tol=w["tol"])
@@ -514,6 +515,8 @@ def uneven_batch(args):
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
         "statuses": sorted(set(int(i["status"]) for i in infos)),
+        "graphs": {"recorded": int(sum(c.graph_stats()[0] for c in ctxs)),
+                   "launches": int(sum(c.graph_stats()[1] for c in ctxs))},
         "k_used": {"min": int(min(i["k_used"] for i in infos)),
                    "max": int(max(i["k_used"] for i in infos))},
         "deflation": {"wall_ms": t_defl * 1e3, "host_threads": 8,

@@ -120,6 +120,13 @@ typedef struct {
                                    changes (the slower of the last two rates); the first
                                    estimate is the change itself;
                                    1: the change itself                                    */
+    int32_t no_graphs;          /* 1: launch every Arnoldi step directly.  Default 0: the steps
+                                   between two convergence checks (a segment) are recorded as a
+                                   HIP graph the second time the same segment (same steps,
+                                   active sources and deflation size) comes up, and replayed
+                                   with one graph launch from then on (bitwise the same
+                                   results); kernel timing (osa_profile_enable) and any
+                                   workspace reallocation switch replay off or reset it      */
 } osa_opts;
 
 /* Per-solve diagnostics (host struct). */
@@ -323,6 +330,23 @@ typedef struct {
 } osa_profile;
 OSA_API osa_status osa_profile_enable(osa_ctx* ctx, int32_t every);
 OSA_API osa_status osa_profile_read(osa_ctx* ctx, osa_profile* out);
+
+/* Autotuner of the dot kernels' row chunking (process-wide, on by default).
+ * The first launch for a vector length n and column bucket ceil(ncols / 32)
+ * times the candidate chunk counts (8 ... 64) on that launch's own operands and
+ * keeps the fastest for every later launch with the same (n, bucket), so the
+ * summation order of a problem depends on (n, ncols) alone within a process
+ * (batched and single-source results stay bitwise equal); across processes the
+ * chosen chunking, and with it the last bits of results, may differ.
+ * osa_set_autotune(0) uses the built-in choice for keys not yet tuned.
+ * osa_autotune_table copies up to cap entries (host arrays, may be NULL) and
+ * returns the number of tuned keys. */
+OSA_API osa_status osa_set_autotune(int32_t on);
+OSA_API int32_t osa_autotune_table(int64_t* n, int32_t* bucket, int32_t* chunks, int32_t cap);
+
+/* Graph replay counters of a context (host outputs, may be NULL): segments
+ * recorded as HIP graphs, and graph launches that replaced direct launches. */
+OSA_API osa_status osa_graph_stats(const osa_ctx* ctx, int64_t* captures, int64_t* launches);
 
 /* Human-readable detail of the last error on this context ("" if none);
  * valid until the next call on the context. */

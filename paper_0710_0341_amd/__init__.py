@@ -38,8 +38,8 @@ EXPORTS = ["overlap_sign_apply", "osa_create", "osa_deflate", "osa_set_deflation
            "osa_small_gemm", "osa_small_schur",
            "osa_set_links",
            "osa_profile_enable", "osa_profile_read", "osa_last_message", "osa_destroy",
-           "osa_status_string", "osa_set_allocator",
-           "osa_version"]
+           "osa_status_string", "osa_set_allocator", "osa_set_autotune", "osa_autotune_table",
+           "osa_graph_stats", "osa_version"]
 
 # device workspace allocator hook: alloc(bytes, stream, user), dealloc(ptr, stream, user)
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -57,7 +57,8 @@ class Opts(ctypes.Structure):
                 ("eig_max_restarts", ctypes.c_int32), ("eig_prec", ctypes.c_int32),
                 ("eig_tol", ctypes.c_double), ("max_batch", ctypes.c_int32),
                 ("orth", ctypes.c_int32), ("eig_filter", ctypes.c_int32),
-                ("deflation", ctypes.c_int32), ("stop_rule", ctypes.c_int32)]
+                ("deflation", ctypes.c_int32), ("stop_rule", ctypes.c_int32),
+                ("no_graphs", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -142,8 +143,15 @@ def lib() -> ctypes.CDLL:
     L.osa_status_string.restype = ctypes.c_char_p
     L.osa_version.restype = ctypes.c_char_p
     L.osa_set_allocator.argtypes = [ALLOC_FN, DEALLOC_FN, vp]
+    L.osa_set_autotune.argtypes = [i32]
+    L.osa_autotune_table.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32),
+                                     ctypes.POINTER(i32), i32]
+    L.osa_autotune_table.restype = i32
+    L.osa_graph_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
-        if name not in ("osa_destroy", "osa_status_string", "osa_version", "osa_last_message"):
+        if name not in ("osa_destroy", "osa_status_string", "osa_version", "osa_last_message",
+                        "osa_autotune_table"):
             getattr(L, name).restype = i32
     _lib = L
     return L
@@ -210,7 +218,7 @@ def _lattice(dims, antiperiodic_t=False):
 
 def make_opts(k_max=0, check_every=0, no_reproject=False, eig_ncv=0, eig_max_restarts=0,
               eig_prec=FP64, eig_tol=0.0, max_batch=0, orth=0, eig_filter=0, deflation=LR,
-              stop_rule=0):
+              stop_rule=0, no_graphs=False):
     o = Opts()
     o.k_max, o.check_every, o.no_reproject = int(k_max), int(check_every), int(bool(no_reproject))
     o.eig_ncv, o.eig_max_restarts, o.eig_prec = int(eig_ncv), int(eig_max_restarts), int(eig_prec)
@@ -220,6 +228,7 @@ def make_opts(k_max=0, check_every=0, no_reproject=False, eig_ncv=0, eig_max_res
     o.eig_filter = int(eig_filter)
     o.deflation = int(deflation)
     o.stop_rule = int(stop_rule)
+    o.no_graphs = int(bool(no_graphs))
     return o
 
 
@@ -382,6 +391,13 @@ class Context:
         _check(lib().osa_profile_read(self._h, ctypes.byref(out)), "osa_profile_read", False)
         return out.as_dict()
 
+    def graph_stats(self):
+        """(segments recorded as HIP graphs, graph launches) of this context."""
+        cap, lau = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().osa_graph_stats(self._h, ctypes.byref(cap), ctypes.byref(lau)),
+               "osa_graph_stats", False)
+        return cap.value, lau.value
+
     def apply_hw(self, X):
         """Y = H_w(mu) X (stencil only)."""
         torch = _torch()
@@ -392,6 +408,22 @@ class Context:
         _check(lib().osa_apply_hw(self._h, nrhs, xp, ctypes.c_void_p(Y.data_ptr())),
                "osa_apply_hw", False)
         return Y
+
+
+def set_autotune(on=True):
+    """Switch the dot-kernel autotuner on or off (process-wide)."""
+    _check(lib().osa_set_autotune(1 if on else 0), "osa_set_autotune", False)
+
+
+def autotune_table():
+    """[(n, column bucket, chunk count)] of the keys tuned so far."""
+    L = lib()
+    total = L.osa_autotune_table(None, None, None, 0)
+    n = (ctypes.c_int64 * max(total, 1))()
+    b = (ctypes.c_int32 * max(total, 1))()
+    w = (ctypes.c_int32 * max(total, 1))()
+    L.osa_autotune_table(n, b, w, total)
+    return [(int(n[i]), int(b[i]), int(w[i])) for i in range(total)]
 
 
 def batch_apply(contexts, sources, tol=1e-10, check=True):

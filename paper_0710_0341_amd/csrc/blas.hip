@@ -9,6 +9,12 @@
 // Every kernel takes a Batch: one grid axis runs over the problems of the
 // batch, and each array argument is offset by the problem's stride.  The
 // arithmetic of one problem does not depend on the batch it runs in.
+#include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "kernels.hpp"
 
 namespace osa {
@@ -61,6 +67,99 @@ static TsPlan dot_plan(int64_t n, int ncols, int C) {
     p.rows_per_chunk = (int)rpc;
     p.nchunks = (int)ceil_div(n, rpc);
     return p;
+}
+
+// ----------------------------------------------------------------- autotuner
+// The row chunking of the dot kernels (k_dot_partial, k_dot2_partial,
+// k_mdot_partial) is picked by measurement: at the first launch with a given
+// length n and column bucket ceil(ncols / 32) the launcher times each candidate
+// chunk count (8 ... 128 chunks, and the built-in choice) on the call's own
+// operands (the dot kernels only read them), keeps the fastest, and every later
+// launch with that (n, bucket), by any dot kernel, any batch and any thread of
+// the process, uses it.  A problem's summation order therefore depends on
+// (n, ncols) alone within a process, which keeps batched results bitwise those
+// of single-source solves.  Off (osa_set_autotune(0)), or while the stream is
+// being captured into a graph, the built-in choice is used for new keys.
+namespace {
+struct TuneKey {
+    int64_t n;
+    int bucket;
+    bool operator<(const TuneKey& o) const { return n < o.n || (n == o.n && bucket < o.bucket); }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;          // (n, bucket) -> chunk count target
+std::atomic<int> g_tune_on{1};
+}  // namespace
+
+void set_autotune(bool on) { g_tune_on.store(on ? 1 : 0); }
+bool autotune_enabled() { return g_tune_on.load() != 0; }
+
+int autotune_entries(int64_t* n, int* bucket, int* want, int cap) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    int i = 0;
+    for (const auto& kv : g_tune) {
+        if (i < cap) {
+            if (n) n[i] = kv.first.n;
+            if (bucket) bucket[i] = kv.first.bucket;
+            if (want) want[i] = kv.second;
+        }
+        ++i;
+    }
+    return i;
+}
+
+static TsPlan plan_for_want(int64_t n, int64_t want) {
+    TsPlan p;
+    p.n = n;
+    int64_t rpc = ceil_div(ceil_div(n, want), kBlock) * kBlock;
+    if (rpc < kBlock) rpc = kBlock;
+    p.rows_per_chunk = (int)rpc;
+    p.nchunks = (int)ceil_div(n, rpc);
+    return p;
+}
+
+// The plan of a dot launch; with the autotuner on and a new (n, bucket), first
+// times launch(candidate plan) for every candidate on stream st.
+template <typename F>
+static TsPlan tuned_plan(int64_t n, int ncols, int C, hipStream_t st, F&& launch) {
+    const TsPlan def = dot_plan(n, ncols, C);
+    const TuneKey key{n, (int)ceil_div(ncols > 0 ? ncols : 1, 32)};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return plan_for_want(n, it->second);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (!g_tune_on.load() || hipStreamIsCapturing(st, &cs) != hipSuccess ||
+        cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return def;
+    }
+    // at most kMaxChunks / 2 chunks, as the built-in choice: the two-vector dot
+    // writes 2 ncols partials per chunk into buffers sized ncols x kMaxChunks
+    std::vector<int> cands = {def.nchunks};
+    for (int w : {8, 16, 32, 48, 64})
+        if (std::find(cands.begin(), cands.end(), w) == cands.end()) cands.push_back(w);
+    hipEvent_t e0, e1;
+    OSA_HIP(hipEventCreate(&e0));
+    OSA_HIP(hipEventCreate(&e1));
+    int best = def.nchunks;
+    float best_ms = 1e30f;
+    for (int w : cands) {
+        const TsPlan p = plan_for_want(n, w);
+        if (p.nchunks > kMaxChunks / 2) continue;
+        launch(p);   // warm
+        OSA_HIP(hipEventRecord(e0, st));
+        launch(p);
+        launch(p);
+        OSA_HIP(hipEventRecord(e1, st));
+        OSA_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        OSA_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; best = w; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_tune[key] = best;
+    return plan_for_want(n, best);
 }
 
 TsPlan ts_plan(int64_t n) {
@@ -125,16 +224,19 @@ __global__ __launch_bounds__(kBlock) void k_dot_partial(const T* __restrict__ B,
 int launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bool fp32,
                        const TsPlan& pn, cd* partial, hipStream_t st, const Batch& bt) {
     constexpr int C = 8;
-    const TsPlan p = dot_plan(pn.n, ncols, C);
-    if (ncols <= 0 || bt.n <= 0) return p.nchunks;
-    dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)bt.n), blk(kBlock);
-    if (fp32)
-        hipLaunchKernelGGL((k_dot_partial<cf, C>), grid, blk, 0, st, (const cf*)B, ldb, ncols,
-                           (const cf*)w, p.n, p.rows_per_chunk, p.nchunks, partial, bt);
-    else
-        hipLaunchKernelGGL((k_dot_partial<cd, C>), grid, blk, 0, st, (const cd*)B, ldb, ncols,
-                           (const cd*)w, p.n, p.rows_per_chunk, p.nchunks, partial, bt);
-    OSA_LAUNCH_CHECK();
+    if (ncols <= 0 || bt.n <= 0) return dot_plan(pn.n, ncols, C).nchunks;
+    auto go = [&](const TsPlan& p) {
+        dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)bt.n), blk(kBlock);
+        if (fp32)
+            hipLaunchKernelGGL((k_dot_partial<cf, C>), grid, blk, 0, st, (const cf*)B, ldb, ncols,
+                               (const cf*)w, p.n, p.rows_per_chunk, p.nchunks, partial, bt);
+        else
+            hipLaunchKernelGGL((k_dot_partial<cd, C>), grid, blk, 0, st, (const cd*)B, ldb, ncols,
+                               (const cd*)w, p.n, p.rows_per_chunk, p.nchunks, partial, bt);
+        OSA_LAUNCH_CHECK();
+    };
+    const TsPlan p = tuned_plan(pn.n, ncols, C, st, go);
+    go(p);
     return p.nchunks;
 }
 
@@ -186,18 +288,21 @@ __global__ __launch_bounds__(kBlock) void k_dot2_partial(const T* __restrict__ B
 int launch_dot2_partial(const void* B, int64_t ldb, int ncols, const void* w1, const void* w2,
                         bool fp32, const TsPlan& pn, cd* partial, hipStream_t st, const Batch& bt) {
     constexpr int C = 8;
-    const TsPlan p = dot_plan(pn.n, ncols, C);
-    if (ncols <= 0 || bt.n <= 0) return p.nchunks;
-    dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)bt.n), blk(kBlock);
-    if (fp32)
-        hipLaunchKernelGGL((k_dot2_partial<cf, C>), grid, blk, 0, st, (const cf*)B, ldb, ncols,
-                           (const cf*)w1, (const cf*)w2, p.n, p.rows_per_chunk, p.nchunks, partial,
-                           bt);
-    else
-        hipLaunchKernelGGL((k_dot2_partial<cd, C>), grid, blk, 0, st, (const cd*)B, ldb, ncols,
-                           (const cd*)w1, (const cd*)w2, p.n, p.rows_per_chunk, p.nchunks, partial,
-                           bt);
-    OSA_LAUNCH_CHECK();
+    if (ncols <= 0 || bt.n <= 0) return dot_plan(pn.n, ncols, C).nchunks;
+    auto go = [&](const TsPlan& p) {
+        dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)bt.n), blk(kBlock);
+        if (fp32)
+            hipLaunchKernelGGL((k_dot2_partial<cf, C>), grid, blk, 0, st, (const cf*)B, ldb, ncols,
+                               (const cf*)w1, (const cf*)w2, p.n, p.rows_per_chunk, p.nchunks,
+                               partial, bt);
+        else
+            hipLaunchKernelGGL((k_dot2_partial<cd, C>), grid, blk, 0, st, (const cd*)B, ldb, ncols,
+                               (const cd*)w1, (const cd*)w2, p.n, p.rows_per_chunk, p.nchunks,
+                               partial, bt);
+        OSA_LAUNCH_CHECK();
+    };
+    const TsPlan p = tuned_plan(pn.n, ncols, C, st, go);
+    go(p);
     return p.nchunks;
 }
 
@@ -492,12 +597,16 @@ __global__ __launch_bounds__(kBlock) void k_mdot_partial(const cd* __restrict__ 
 int launch_mdot_partial(const cd* B, int64_t ldb, int ncols, const cd* w, const TsPlan& pn,
                         cd* partial, hipStream_t st, const Batch& bt) {
     constexpr int C = 8;
-    const TsPlan p = dot_plan(pn.n, ncols, C);   // the one-source plan: same chunks
-    if (ncols <= 0 || bt.n <= 0) return p.nchunks;
-    dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)ceil_div(bt.n, kMdotR));
-    hipLaunchKernelGGL(k_mdot_partial, grid, dim3(kBlock), 0, st, B, ldb, ncols, w, p.n,
-                       p.rows_per_chunk, p.nchunks, partial, bt);
-    OSA_LAUNCH_CHECK();
+    if (ncols <= 0 || bt.n <= 0) return dot_plan(pn.n, ncols, C).nchunks;
+    auto go = [&](const TsPlan& p) {
+        dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C),
+                  (unsigned)ceil_div(bt.n, kMdotR));
+        hipLaunchKernelGGL(k_mdot_partial, grid, dim3(kBlock), 0, st, B, ldb, ncols, w, p.n,
+                           p.rows_per_chunk, p.nchunks, partial, bt);
+        OSA_LAUNCH_CHECK();
+    };
+    const TsPlan p = tuned_plan(pn.n, ncols, C, st, go);   // the one-source plan: same chunks
+    go(p);
     return p.nchunks;
 }
 

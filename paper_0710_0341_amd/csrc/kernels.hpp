@@ -71,6 +71,12 @@ TsPlan ts_plan(int64_t n);
 // returns their number, which the following reduction takes.
 // Batch strides: basis (B), vec (w), part (partial).
 constexpr int kMaxChunks = 128;
+// Autotuner of the dot kernels' row chunking (process-wide, on by default):
+// see blas.hip.  autotune_entries copies up to cap (n, bucket, chunk count)
+// entries and returns how many there are.
+void set_autotune(bool on);
+bool autotune_enabled();
+int autotune_entries(int64_t* n, int* bucket, int* want, int cap);
 int launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, bool fp32,
                        const TsPlan& p, cd* partial, hipStream_t st, const Batch& bt = Batch());
 // out[c] = sum_q partial[c*nchunks+q] and accum[c] += out[c] (accum nullable).

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -48,6 +49,10 @@ AllocHook current_alloc_hook() {
     return g_alloc;
 }
 
+// Bumped by every device workspace (re)allocation and release: captured graphs
+// hold raw pointers, so a graph recorded before the last change is stale.
+std::atomic<uint64_t> g_alloc_epoch{1};
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
@@ -71,6 +76,7 @@ struct DevBuf {
             return;
         }
         if (p) {
+            g_alloc_epoch.fetch_add(1);
             if (hook.dealloc) {
                 // the hook's allocator may hand the block out again at once: let
                 // every queued kernel finish first (hipFree does the same)
@@ -88,6 +94,7 @@ struct DevBuf {
         if (b <= bytes && p) return;
         if (borrowed) throw std::length_error("borrowed workspace too small");
         release();
+        g_alloc_epoch.fetch_add(1);
         if (b == 0) b = 16;
         const AllocHook h = current_alloc_hook();
         if (h.alloc) {
@@ -246,7 +253,32 @@ struct osa_ctx {
     std::vector<hipEvent_t> prof_pool;
     osa_profile prof{};
     std::string msg;
+    // Arnoldi segments (the steps between two convergence checks) captured as
+    // HIP graphs and replayed; see run_segment
+    struct SegKey {
+        int j0, j1, m, flags;
+        uint64_t mask;
+        bool operator<(const SegKey& o) const {
+            if (j0 != o.j0) return j0 < o.j0;
+            if (j1 != o.j1) return j1 < o.j1;
+            if (m != o.m) return m < o.m;
+            if (flags != o.flags) return flags < o.flags;
+            return mask < o.mask;
+        }
+    };
+    struct SegGraph { hipGraphExec_t exec = nullptr; int seen = 0; bool failed = false; };
+    std::map<SegKey, SegGraph> seg_graphs;
+    uint64_t seg_epoch = 0;
+    hipStream_t cap_st = nullptr;   // private stream for graph capture
+    int64_t graph_launches = 0, graph_captures = 0;
+    void clear_graphs() {
+        for (auto& kv : seg_graphs)
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        seg_graphs.clear();
+    }
     ~osa_ctx() {
+        clear_graphs();
+        if (cap_st) (void)hipStreamDestroy(cap_st);
         for (auto& p : prof_pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
         for (auto e : prof_pool) (void)hipEventDestroy(e);
         if (own_stream && st) (void)hipStreamDestroy(st);
@@ -962,6 +994,72 @@ struct SolveResult {
     double bnorm = 0;
 };
 
+// Steps j0..j1 of a solve for the active problems act, as one HIP graph.  A
+// segment's launches depend only on (j0, j1, the active set, m and the solve
+// flags) and on the workspace pointers, so the graph recorded the second time a
+// segment is seen (the first run tunes the dot kernels, so the graph records
+// the tuned launches) is replayed every later time: one graph launch instead of
+// about ten kernel launches per step, with results bitwise those of direct
+// launches.  Recording runs on a private stream (capture cannot use the legacy
+// default stream) and the graph is launched on the context's stream.  Any
+// workspace (re)allocation invalidates every recorded graph.  Off while kernel
+// timing is on (events would be recorded into the graph) or with
+// opts.no_graphs; a segment whose capture fails runs directly from then on.
+template <typename F>
+void run_segment(osa_ctx* c, int j0, int j1, const std::vector<int>& act, int flags, F&& step) {
+    const bool use = !c->opts.no_graphs && !c->prof_on && act.size() <= 64;
+    if (!use) {
+        for (int j = j0; j <= j1; ++j) step(j);
+        return;
+    }
+    const uint64_t ep = g_alloc_epoch.load();
+    if (ep != c->seg_epoch) {
+        c->clear_graphs();
+        c->seg_epoch = ep;
+    }
+    if (c->seg_graphs.size() > 512) c->clear_graphs();
+    uint64_t mask = 0;
+    for (int b : act) mask |= 1ULL << b;
+    osa_ctx::SegGraph& g = c->seg_graphs[osa_ctx::SegKey{j0, j1, c->m_active, flags, mask}];
+    if (g.exec) {
+        OSA_HIP(hipGraphLaunch(g.exec, c->st));
+        ++c->graph_launches;
+        return;
+    }
+    if (g.failed || g.seen++ == 0) {
+        for (int j = j0; j <= j1; ++j) step(j);
+        return;
+    }
+    if (!c->cap_st) OSA_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+    hipStream_t own = c->st;
+    hipGraph_t graph = nullptr;
+    c->st = c->cap_st;
+    bool ok = hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        try {
+            for (int j = j0; j <= j1; ++j) step(j);
+        } catch (...) {
+            ok = false;
+        }
+        if (hipStreamEndCapture(c->cap_st, &graph) != hipSuccess) ok = false;
+    }
+    c->st = own;
+    if (ok && graph && hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        g.exec = nullptr;
+        ok = false;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (!ok || !g.exec) {
+        g.failed = true;   // run this segment directly from now on
+        for (int j = j0; j <= j1; ++j) step(j);
+        return;
+    }
+    ++c->graph_captures;
+    OSA_HIP(hipGraphLaunch(g.exec, c->st));
+    ++c->graph_launches;
+}
+
 // y_b = sign(H) x_b for nb internal-layout sources (contiguous, N apart) in
 // lockstep: every Arnoldi step applies the stencil, the re-projection, both
 // Gram-Schmidt passes and the normalisation to all unfinished sources in one
@@ -1101,8 +1199,8 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     std::vector<double> hd;
     // Step j: plain CGS2 extends the decomposition to size j + 1; the delayed
     // form (steps 1 .. kmax) completes size j and starts column j.
-    for (int j = dcgs ? 1 : 0; j < (dcgs ? kmax + 1 : kmax) && !act.empty(); ++j) {
-        const Batch bt = bat(act);
+    // One Arnoldi step j for the problems of bt (no host synchronisation inside).
+    auto do_step = [&](int j, const Batch& bt) {
         apply_h(c, V + (size_t)j * N, w, false, c->adj, bt);
         if (reproj && m > 0)   // Schur deflation: column j of X = S^dag H v_j
             project_out(c, w, schur ? ar + L.xs + (size_t)j * m : ar + L.coef2, ar + L.tmp, bt);
@@ -1133,8 +1231,22 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
                              H + (size_t)j * ldh + (j + 1), hfro2, 1e-14, flag, j,
                              H + (size_t)j * ldh, j + 1, c->st, bt);
         }
+    };
+    const int jbeg = dcgs ? 1 : 0, jend = dcgs ? kmax + 1 : kmax;
+    auto is_check = [&](int j) {
         const int kk = dcgs ? j : j + 1;
-        if (kk % every != 0 && kk != kmax) continue;
+        return kk % every == 0 || kk == kmax;
+    };
+    for (int j = jbeg; j < jend && !act.empty(); ++j) {
+        // the segment [j, je]: the steps up to and including the next check
+        int je = j;
+        while (je + 1 < jend && !is_check(je)) ++je;
+        run_segment(c, j, je, act, (schur ? 1 : 0) | (reproj ? 2 : 0) | (dcgs ? 4 : 0) |
+                                       (c->adj ? 8 : 0) | (fixed ? 16 : 0),
+                    [&](int jj) { do_step(jj, bat(act)); });
+        j = je;
+        const int kk = dcgs ? j : j + 1;
+        if (!is_check(j)) continue;
         // each source follows its own schedule, as it would alone
         std::vector<int> chk, wait;
         for (int b : act) {
@@ -2237,6 +2349,29 @@ osa_status osa_set_allocator(void* (*alloc)(size_t, void*, void*),
 
 const char* osa_last_message(const osa_ctx* c) { return c ? c->msg.c_str() : ""; }
 
+osa_status osa_set_autotune(int32_t on) {
+    set_autotune(on != 0);
+    return OSA_OK;
+}
+
+int32_t osa_autotune_table(int64_t* n, int32_t* bucket, int32_t* chunks, int32_t cap) {
+    if (cap < 0) cap = 0;
+    std::vector<int> b(cap), w(cap);
+    const int total = autotune_entries(n, b.data(), w.data(), cap);
+    for (int i = 0; i < std::min(total, (int)cap); ++i) {
+        if (bucket) bucket[i] = b[i];
+        if (chunks) chunks[i] = w[i];
+    }
+    return total;
+}
+
+osa_status osa_graph_stats(const osa_ctx* c, int64_t* captures, int64_t* launches) {
+    if (!c) return OSA_ERR_ARG;
+    if (captures) *captures = c->graph_captures;
+    if (launches) *launches = c->graph_launches;
+    return OSA_OK;
+}
+
 const char* osa_status_string(osa_status s) {
     switch (s) {
         case OSA_OK: return "ok";
@@ -2260,11 +2395,12 @@ osa_status osa_set_opts(osa_ctx* c, const osa_opts* opts) {
     if (o.k_max < 0 || o.k_max > 4000 || o.eig_ncv < 0 || o.eig_ncv > 96 || o.eig_tol < 0 ||
         o.eig_max_restarts < 0 || (o.eig_prec != OSA_FP64 && o.eig_prec != OSA_FP32) ||
         o.max_batch < 0 || o.max_batch > 64 || o.orth < 0 || o.orth > 1 || o.stop_rule < 0 ||
-        o.stop_rule > 1 || o.eig_filter < 0 ||
+        o.stop_rule > 1 || o.no_graphs < 0 || o.no_graphs > 1 || o.eig_filter < 0 ||
         o.eig_filter > 200)
         return OSA_ERR_ARG;
     fill_defaults(o);
     c->opts = o;
+    c->clear_graphs();
     return OSA_OK;
 }
 

@@ -247,3 +247,38 @@ def test_oom_from_allocator_hook(osa):
         osa.use_torch_allocator(False)
     c = osa.Context(links, dims, 0.3, -1.5)   # hipMalloc again
     c.close()
+
+
+# --------------------------------------------- graph replay and the autotuner
+def test_graph_replay_bitwise_and_autotune_table(osa, haar4):
+    """Arnoldi segments recorded as HIP graphs and replayed give bitwise the
+    results of direct launches (one source and a lockstep batch, repeated solves
+    with new sources); the dot-kernel autotuner has recorded its choices."""
+    dims, links, b, h = haar4
+    rng = np.random.default_rng(9)
+    srcs = rng.standard_normal((4, b.size)) + 1j * rng.standard_normal((4, b.size))
+    srcs /= np.linalg.norm(srcs, axis=1, keepdims=True)
+    say("graph replay vs direct launches")
+    outs = {}
+    for ng in (True, False):
+        ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=400, check_every=25, max_batch=3,
+                          no_graphs=ng)
+        ctx.deflate(10)
+        ys = []
+        for rep in range(3):                       # the third solve replays recorded graphs
+            y1, _, st1 = ctx.apply(dev(srcs[rep]), tol=1e-10)
+            y3, _, st3 = ctx.apply(dev(srcs[1:4]), tol=1e-10)
+            assert st1 == st3 == osa.OSA_OK
+            ys.append((host(y1), host(y3)))
+        cap, lau = ctx.graph_stats()
+        if ng:
+            assert cap == 0 and lau == 0
+        else:
+            assert cap > 0 and lau > cap
+        outs[ng] = ys
+        ctx.close()
+    for (a1, a3), (b1, b3) in zip(outs[True], outs[False]):
+        assert np.array_equal(a1, b1) and np.array_equal(a3, b3)
+    assert rel(outs[False][2][0], O.sign_eig_apply(h, srcs[2])) < 1e-9
+    table = osa.autotune_table()
+    assert table and all(1 <= w <= 64 for _, _, w in table)
