@@ -247,6 +247,8 @@ def parse():
                              "SAMPLE_JSON"),
                     help="reduce rocprofv3 --pmc outputs of --counters-sample and "
                          "--copy-calibration to profiles/<class>_dis16_hbm_traffic.json")
+    ap.add_argument("--with-block", action="store_true",
+                    help="dis16: also time the block Krylov variant on the 12 sources")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
                     help="per-kernel statistics of the timed steps from a rocprofv3 "
                          "--kernel-trace --marker-trace run of this benchmark")
@@ -629,6 +631,24 @@ def headline16(args):
     table_plain = class_table([ctx.profile_read()], 1)
     ctx.profile(False)
     bitwise = bool(torch.equal(Y, Yp))
+    block = None
+    if args.with_block:
+        # the block Krylov variant (one Krylov space for the 12 sources; not the paper's
+        # method), second of two runs, against the lockstep result
+        print("dis16: block Krylov variant", file=sys.stderr, flush=True)
+        ctx.set_opts(k_max=w["k_max"], check_every=CHECK_EVERY, max_batch=nsrc)
+        ctx.apply_block(B, tol=tol, check=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Yb, infb, stb = ctx.apply_block(B, tol=tol, check=False)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        block = {"solves_per_s": nsrc / tb, "ms": tb * 1e3, "status": int(stb),
+                 "dimension": infb[0]["k_used"],
+                 "max_resid_est": max(i["resid_est"] for i in infb),
+                 "max_rel_diff_vs_lockstep": max(
+                     float(torch.linalg.vector_norm(Yb[i] - Y[i]) / torch.linalg.vector_norm(Y[i]))
+                     for i in range(nsrc))}
     # accuracy: the same 12 against a tighter solve (tol 1e-12, change rule, k <= 800)
     print("dis16: reference solve at tol 1e-12", file=sys.stderr, flush=True)
     ctx.set_opts(k_max=800, check_every=50, max_batch=nsrc, stop_rule=1)
@@ -658,6 +678,7 @@ def headline16(args):
                                      "max_resid_est": max(i["resid_est"] for i in infr),
                                      "status": int(str_)}},
         "init_ms": init_ms,
+        "block_krylov_variant": block,
         "whole_path_solves_per_s": nsrc / (init_ms * 1e-3 + ms_per_step * 1e-3),
         "kernels": table,
         "profiling": f"HIP events on one launch in {PROF_EVERY} of each class, on the launching "

@@ -237,6 +237,21 @@ OSA_API osa_status osa_apply_adjoint(osa_ctx* ctx, int32_t nrhs, const void* B, 
 OSA_API osa_status osa_apply_overlap(osa_ctx* ctx, int32_t nrhs, const void* B, void* Y,
                                      double tol, osa_info* infos);
 
+/* Block Krylov variant for s sources (not the paper's method; its Eq. 11 and
+ * Eq. 22 applied to a block of sources): one Krylov space is built from all s
+ * sources together (block Arnoldi with classical Gram-Schmidt applied twice
+ * and a Gram-Schmidt QR of every new block), and sign(H) B is approximated by
+ * R sgn(Lambda) G^{-1} L^dag B + V_K sign(H_K) E_1 R_0 with the block Hessenberg
+ * matrix H_K (K s x K s).  B, Y: s*N complex128 (source j at offset j*N).  Uses
+ * the context's LR deflation data (OSA_ERR_STATE under Schur deflation).
+ * k_blocks: block steps at most (0: ceil(4 k_max / s)); K s <= 6000.  Checks
+ * every ceil(check_every / s) block steps (with check_every < 0 exactly
+ * k_blocks steps); resid_est per source: the geometric-tail estimate of the
+ * change of its column of sign(H_K) E_1 R_0 relative to |b|; k_used = K s.
+ * Returns OSA_OK, OSA_NOT_CONVERGED (result usable) or an error. */
+OSA_API osa_status osa_apply_block(osa_ctx* ctx, int32_t s, const void* B, void* Y, double tol,
+                                   int32_t k_blocks, osa_info* infos);
+
 /* Uneven batch: n independent contexts (different lattices, mu, m_w and
  * deflation data), one source each, solved concurrently: up to 8 instances at
  * a time, each on a stream of its own that waits for the work already queued

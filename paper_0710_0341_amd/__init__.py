@@ -33,7 +33,7 @@ LR, SCHUR = 0, 1   # osa_opts.deflation
 
 EXPORTS = ["overlap_sign_apply", "osa_create", "osa_deflate", "osa_set_deflation",
            "osa_get_deflation", "osa_set_active_deflation", "osa_apply", "osa_apply_adjoint",
-           "osa_apply_overlap", "osa_batch_apply",
+           "osa_apply_overlap", "osa_apply_block", "osa_batch_apply",
            "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_small_sign_noalloc",
            "osa_small_gemm", "osa_small_schur",
            "osa_set_links",
@@ -124,6 +124,7 @@ def lib() -> ctypes.CDLL:
     L.osa_apply.argtypes = [vp, i32, vp, vp, dbl, ctypes.POINTER(Info)]
     L.osa_apply_adjoint.argtypes = [vp, i32, vp, vp, dbl, ctypes.POINTER(Info)]
     L.osa_apply_overlap.argtypes = [vp, i32, vp, vp, dbl, ctypes.POINTER(Info)]
+    L.osa_apply_block.argtypes = [vp, i32, vp, vp, dbl, i32, ctypes.POINTER(Info)]
     L.osa_batch_apply.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   dbl, ctypes.POINTER(Info)]
     L.osa_set_opts.argtypes = [vp, ctypes.POINTER(Opts)]
@@ -355,6 +356,21 @@ class Context:
     def apply_overlap(self, B, tol=1e-10, check=True):
         """Y = D_ov B = B + gamma_5 sign(H) B (the overlap operator)."""
         return self._apply("osa_apply_overlap", B, tol, check)
+
+    def apply_block(self, B, tol=1e-10, k_blocks=0, check=True):
+        """Y = sign(H) B for the s rows of B by the block Krylov variant (one Krylov
+        space for all s sources).  Returns (Y, infos, status)."""
+        torch = _torch()
+        bp = _dev_ptr(B, torch.complex128, "B")
+        s = 1 if B.dim() == 1 else int(B.shape[0])
+        Y = torch.zeros_like(B)
+        self._after_current()
+        infos = (Info * s)()
+        st = lib().osa_apply_block(self._h, s, bp, ctypes.c_void_p(Y.data_ptr()), float(tol),
+                                   int(k_blocks), infos)
+        if check:
+            _check(st, "osa_apply_block")
+        return Y, [i.as_dict() for i in infos], st
 
     def _apply(self, name, B, tol, check):
         torch = _torch()

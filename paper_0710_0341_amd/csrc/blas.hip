@@ -663,6 +663,63 @@ void launch_mupdate(cd* w, const cd* B, int64_t ldb, int ncols, const cd* coef, 
     OSA_LAUNCH_CHECK();
 }
 
+// out_b[i] = a w_b[i] + sg sum_{c < ncols} B[c][i] coef_b[c] for every problem b
+// of the batch, the shared columns B read once per group of kMupdR problems and
+// the coefficients staged through LDS in tiles of kMupdCols: the block
+// Gram-Schmidt update W -= Q h and the block assembly Y += V (F E_1 R_0) of the
+// block Krylov variant.  Batch strides: vec (w), small (coef).
+__global__ __launch_bounds__(kBlock) void k_mcombine(cd* w, const cd* __restrict__ B, int64_t ldb,
+                                                     int ncols, const cd* __restrict__ coef,
+                                                     int64_t n, double a, double sg, Batch bt) {
+    __shared__ cd scoef[kMupdR][kMupdCols];
+    const int g0 = blockIdx.y * kMupdR;
+    const int nr = (bt.n - g0 < kMupdR) ? bt.n - g0 : kMupdR;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < n;
+    cd acc[kMupdR];
+#pragma unroll
+    for (int r = 0; r < kMupdR; ++r) acc[r] = mk(0.0, 0.0);
+    for (int cb = 0; cb < ncols; cb += kMupdCols) {
+        const int nc = (ncols - cb < kMupdCols) ? ncols - cb : kMupdCols;
+        __syncthreads();
+        for (int e = threadIdx.x; e < nr * nc; e += kBlock) {
+            const int r = e / nc, cc = e - r * nc;
+            scoef[r][cc] = coef[(int64_t)bt.idx[g0 + r] * bt.small + cb + cc];
+        }
+        __syncthreads();
+        if (valid) {
+            for (int c = 0; c < nc; ++c) {
+                const cd b = B[(int64_t)(cb + c) * ldb + i];
+#pragma unroll
+                for (int r = 0; r < kMupdR; ++r)
+                    if (r < nr) cfma(acc[r], b, scoef[r][c]);
+            }
+        }
+    }
+    if (!valid) return;
+#pragma unroll
+    for (int r = 0; r < kMupdR; ++r) {
+        if (r < nr) {
+            cd* wp = w + (int64_t)bt.idx[g0 + r] * bt.vec + i;
+            cd v = mk(sg * acc[r].x, sg * acc[r].y);
+            if (a != 0.0) {
+                const cd base = *wp;
+                v = mk(fma(a, base.x, v.x), fma(a, base.y, v.y));
+            }
+            *wp = v;
+        }
+    }
+}
+
+void launch_mcombine(cd* w, const cd* B, int64_t ldb, int ncols, const cd* coef, int64_t n,
+                     double a, double sg, hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0 || ncols <= 0) return;
+    dim3 grid((unsigned)ceil_div(n, kBlock), (unsigned)ceil_div(bt.n, kMupdR));
+    hipLaunchKernelGGL(k_mcombine, grid, dim3(kBlock), 0, st, w, B, ldb, ncols, coef, n, a, sg,
+                       bt);
+    OSA_LAUNCH_CHECK();
+}
+
 // ------------------------------------------------ delayed reorthogonalisation
 // Step j (>= 1) of the Arnoldi recurrence with delayed reorthogonalisation.
 // Column j of the basis holds u_j, orthogonalised once and not normalised; z =

@@ -107,6 +107,10 @@ int launch_mdot_partial(const cd* B, int64_t ldb, int ncols, const cd* w, const 
 bool mupdate_matches_single(int64_t n, int ncols);
 void launch_mupdate(cd* w, const cd* B, int64_t ldb, int ncols, const cd* coef, int64_t n,
                     hipStream_t st, const Batch& bt);
+// w_b = a w_b + sg B coef_b for every problem b (fp64, any ncols), B read once per
+// 16 problems.  Batch strides: vec (w), small (coef).
+void launch_mcombine(cd* w, const cd* B, int64_t ldb, int ncols, const cd* coef, int64_t n,
+                     double a, double sg, hipStream_t st, const Batch& bt);
 // Delayed reorthogonalisation (step j >= 1 of the Arnoldi recurrence).
 // Dots of the ncols columns of B with two vectors in one read of B:
 // partial[c*nchunks + q] for w1, partial[(ncols + c)*nchunks + q] for w2.

@@ -241,6 +241,9 @@ struct osa_ctx {
     DevBuf V, arena, w, x, y, coef, coef2, partial, normp, upd_scratch, dscal, flag, nflag, red;
     DevBuf sX, sM, sY, logpiv, gjws;
     DevBuf xio, yio;   // internal-layout sources and results of osa_apply
+    // block Krylov variant (osa_apply_block): basis, block Hessenberg matrix,
+    // work block, coefficient buffers and the small solution F E_1 R_0
+    DevBuf Vblk, Hblk, Wblk, cblk2, cdefb, ctmpb, r0b, ysmb, ccoefb;
     ArenaLayout lay;
     int64_t part_stride = 0, normp_stride = 0, red_stride = 0, gj_stride = 0;
     PinnedBuf host;
@@ -2199,6 +2202,237 @@ __global__ void k_overlap_finish(const cd* __restrict__ B, cd* Y, int64_t n) {
     Y[e] = spin < 2 ? cadd(b, y) : csub(b, y);
 }
 
+// ================================================================ block Krylov
+// A multi-source variant that is not the paper's method: one Krylov space is
+// built from all s sources together, the block full orthogonalisation
+// approximation of sign(H) B (Eq. 11 per block of sources; with s = 1 it is
+// Eq. 22), with the same LR deflation (Eq. 21-22):
+//   B_ominus = V_1 R_0 (the projected sources, QR by Gram-Schmidt),
+//   H V_j re-projected and orthogonalised against all blocks by classical
+//   Gram-Schmidt applied twice (the shared basis is read once per pass for all
+//   s vectors), then its QR gives V_{j+1} and the subdiagonal block,
+//   sign(H) B ~ R sgn(Lambda) G^{-1} L^dag B + V_K sign(H_K) E_1 R_0,
+// with H_K the K s x K s block upper Hessenberg matrix.  The convergence
+// estimate is the largest change of a column of sign(H_K) E_1 R_0 between
+// checks relative to its source's norm, with the geometric-tail rule of the
+// single-source solve.
+struct BlockResult {
+    osa_status st = OSA_OK;
+    int dim = 0;          // K s
+    int blocks = 0;
+    double est = NAN;
+    int newton_iters = 0;
+    int breakdown = 0;
+};
+
+void solve_block(osa_ctx* c, int s, const cd* xin, cd* yout, double tol, int kb_max,
+                 BlockResult& out, std::vector<double>& est_src) {
+    const int64_t N = c->N();
+    const int m = c->m_active;
+    check_deflation_state(c);
+    if (c->opts.deflation == 1 && m > 0)
+        throw OsaError{OSA_ERR_STATE, "the block variant uses LR deflation (deflation = 0)"};
+    const int D = (kb_max + 1) * s;     // basis columns
+    const int64_t ldh = D;
+    const int kdim = kb_max * s;        // largest small problem
+    ensure_exec(c, D + s, s);
+    c->Vblk.ensure(sizeof(cd) * (size_t)N * D);
+    c->Hblk.ensure(sizeof(cd) * (size_t)ldh * kdim);
+    c->Wblk.ensure(sizeof(cd) * (size_t)N * s);
+    c->cblk2.ensure(sizeof(cd) * (size_t)ldh * s);
+    const int mm = std::max(m, 1);
+    c->cdefb.ensure(sizeof(cd) * (size_t)mm * s);
+    c->ctmpb.ensure(sizeof(cd) * (size_t)mm * s);
+    c->ccoefb.ensure(sizeof(cd) * (size_t)mm * s);
+    c->r0b.ensure(sizeof(cd) * (size_t)s * s);
+    c->ysmb.ensure(sizeof(cd) * (size_t)kdim * s);
+    // small-sign workspace for one problem of size up to kdim
+    if (c->scap < kdim || c->kbatch < 1) {
+        c->scap = std::max(c->scap, kdim);
+        const int scap = c->scap;
+        const int nb = std::max(c->kbatch, 1);
+        c->kbatch = nb;
+        c->red_stride = newton_red_len(scap) + 16;
+        c->red.ensure(sizeof(double) * (size_t)c->red_stride * nb);
+        c->sX.ensure(sizeof(cd) * (size_t)scap * scap * nb);
+        c->sM.ensure(sizeof(cd) * (size_t)scap * scap * nb);
+        c->sY.ensure(sizeof(cd) * (size_t)scap * scap * nb);
+        c->logpiv.ensure(sizeof(double) * (size_t)scap * nb);
+        c->gj_stride = (int64_t)ceil_div((int64_t)gj_ws_bytes(scap), 256) * 256;
+        c->gjws.ensure((size_t)c->gj_stride * nb);
+        c->nflag.ensure(sizeof(int) * 4 * nb);
+        c->dscal.ensure(sizeof(cd) * 16);
+    }
+    const TsPlan p = ts_plan(N);
+    cd* Vb = c->Vblk.as<cd>();
+    cd* Hb = c->Hblk.as<cd>();
+    cd* W = c->Wblk.as<cd>();
+    cd* r0 = c->r0b.as<cd>();
+    int* flag = c->flag.as<int>();
+    double* hfro2 = (double*)(c->dscal.as<cd>() + 14);
+    const bool fixed = c->opts.check_every < 0;
+    const int cb = fixed ? kb_max : std::max(1, (int)ceil_div(std::max(1, c->opts.check_every), s));
+    Batch bs;   // the s sources: consecutive vectors
+    bs.n = s;
+    bs.basis = N;
+    bs.vec = N;
+    Batch bp = bs;   // projection coefficients: m per source
+    bp.small = mm;
+    Batch bd = bs;   // block Gram-Schmidt: coefficients are columns of H (stride ldh)
+    bd.part = c->part_stride;
+    bd.small = ldh;
+    Batch bu = bs;
+    bu.small = ldh;
+    OSA_HIP(hipMemsetAsync(Hb, 0, sizeof(cd) * (size_t)ldh * kdim, c->st));
+    OSA_HIP(hipMemsetAsync(r0, 0, sizeof(cd) * (size_t)s * s, c->st));
+    OSA_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, c->st));
+    OSA_HIP(hipMemsetAsync(hfro2, 0, sizeof(double), c->st));
+    OSA_HIP(hipMemcpyAsync(W, xin, sizeof(cd) * (size_t)N * s, hipMemcpyDeviceToDevice, c->st));
+    // |b| of every source (host) for the relative estimate
+    std::vector<double> bnorm(s);
+    for (int i = 0; i < s; ++i) {
+        vec_norm(c, W + (size_t)i * N, false, c->dscal.as<cd>() + 12);
+        cd hn;
+        d2h(c, c->dscal.as<cd>() + 12, 1, &hn);
+        bnorm[i] = hn.x;
+        if (!std::isfinite(bnorm[i])) throw OsaError{OSA_ERR_NONFINITE, "source"};
+    }
+    // B_ominus = B - R G^{-1} L^dag B (Eq. 21); cdefb keeps G^{-1} L^dag B
+    if (m > 0) project_out(c, W, c->cdefb.as<cd>(), c->ctmpb.as<cd>(), bp);
+    // thin QR B_ominus = V_1 R_0 by Gram-Schmidt (applied twice) column by column
+    auto block_qr = [&](cd* src, cd* dst, cd* rcol0, int64_t ldr, int step, bool track) {
+        for (int i = 0; i < s; ++i) {
+            cd* wcol = src + (size_t)i * N;
+            cd* rc = rcol0 + (size_t)i * ldr;   // column i of the R factor (rows 0..i)
+            if (i > 0)
+                cgs2(c, wcol, dst, N, i, false, rc, c->coef2.as<cd>());
+            else
+                launch_norm_partial(wcol, false, p, c->normp.as<double>(), c->st);
+            launch_normalize(wcol, dst + (size_t)i * N, false, p, c->normp.as<double>(), rc + i,
+                             track ? hfro2 : nullptr, track ? 1e-14 : 0.0, track ? flag : nullptr,
+                             step, track ? rc : nullptr, track ? i : 0, c->st);
+        }
+    };
+    block_qr(W, Vb, r0, s, 0, false);
+    std::vector<cd> ysm_prev, ysm_cur;
+    std::vector<double> changes, rates, kprev_list;
+    int kprev = 0, skipped = 0;
+    double tail = INFINITY;
+    for (int j = 0; j < kb_max; ++j) {
+        const int ncol = (j + 1) * s;
+        // W = H V_j, re-projected (Eq. 21)
+        apply_h(c, Vb + (size_t)j * s * N, W, false, false, bs);
+        if (m > 0) project_out(c, W, c->ctmpb.as<cd>(), c->ccoefb.as<cd>(), bp);
+        cd* hcol = Hb + (size_t)j * s * ldh;   // columns js .. js+s-1 of H
+        // block classical Gram-Schmidt, twice; the shared basis is read once per pass
+        int nch = 0;
+        timed(c, 0, (ncol + s) * (double)N * 16.0, [&] {
+            nch = launch_mdot_partial(Vb, N, ncol, W, p, c->partial.as<cd>(), c->st, bd);
+        });
+        launch_reduce_partial(c->partial.as<cd>(), nch, ncol, hcol, nullptr, nullptr, nullptr,
+                              c->st, bd);
+        timed(c, 1, (ncol + 2.0 * s) * (double)N * 16.0, [&] {
+            launch_mcombine(W, Vb, N, ncol, hcol, N, 1.0, -1.0, c->st, bu);
+        });
+        timed(c, 0, (ncol + s) * (double)N * 16.0, [&] {
+            nch = launch_mdot_partial(Vb, N, ncol, W, p, c->partial.as<cd>(), c->st, bd);
+        });
+        launch_reduce_partial(c->partial.as<cd>(), nch, ncol, c->cblk2.as<cd>(), hcol, nullptr,
+                              nullptr, c->st, bd);
+        timed(c, 1, (ncol + 2.0 * s) * (double)N * 16.0, [&] {
+            launch_mcombine(W, Vb, N, ncol, c->cblk2.as<cd>(), N, 1.0, -1.0, c->st, bu);
+        });
+        // QR of the new block: V_{j+1} and the subdiagonal block H[ncol:ncol+s, js:js+s]
+        block_qr(W, Vb + (size_t)ncol * N, hcol + ncol, ldh, j, true);
+        const int kb = j + 1;
+        const bool last = kb == kb_max;
+        if (!last && (fixed || kb % cb != 0)) continue;
+        int hf[2] = {0, 0};
+        d2h(c, flag, 2, hf);
+        if (hf[0] == 2) throw OsaError{OSA_ERR_NONFINITE, "block Arnoldi"};
+        const bool brk = hf[0] == 1;   // rank-deficient new block: the space is invariant
+        if (!last && !brk && !fixed && !changes.empty() && std::isfinite(tail)) {
+            // skip checks far before the predicted crossing (at most 3 in a row)
+            const double rho = rates.empty() ? 1.0 : rates.back();
+            const double pred = tail * std::pow(rho, (double)(kb * s - kprev));
+            if (rho < 1.0 && pred > 3.0 * tol && skipped < 3) { ++skipped; continue; }
+        }
+        skipped = 0;
+        const int dim = kb * s;
+        std::vector<int> iters(std::max(c->kbatch, 1), 0);
+        std::vector<char> okv(std::max(c->kbatch, 1), 0);
+        small_sign_batch(c, std::vector<int>{0}, dim, Hb, (int)ldh, 0, c->ysmb.as<cd>(), 0, iters,
+                         okv);
+        out.newton_iters = iters[0];
+        if (iters[0] < 0 || !okv[0]) throw OsaError{OSA_ERR_NEWTON_NOCONV, "block small sign"};
+        // F E_1 R_0: the first s columns of sign(H_K) times R_0
+        launch_zgemm(0, 0, dim, s, s, mk(1.0, 0.0), c->sX.as<cd>(), dim, r0, s, mk(0.0, 0.0),
+                     c->ysmb.as<cd>(), dim, c->st);
+        ysm_cur.resize((size_t)dim * s);
+        d2h(c, c->ysmb.p, (size_t)dim * s, ysm_cur.data());
+        out.blocks = kb;
+        out.dim = dim;
+        bool stop = brk || last;
+        if (brk) out.breakdown = 1;
+        if (kprev > 0 && !fixed) {
+            double change = 0;
+            for (int b = 0; b < s; ++b) {
+                double d2 = 0;
+                for (int i = 0; i < dim; ++i) {
+                    cd d = ysm_cur[(size_t)b * dim + i];
+                    if (i < kprev) d = csub(d, ysm_prev[(size_t)b * kprev + i]);
+                    d2 += cabs2(d);
+                }
+                const double e = std::sqrt(d2) / bnorm[b];
+                est_src[b] = e;
+                change = std::max(change, e);
+            }
+            tail = change;
+            if (!changes.empty()) {
+                const int d1 = kprev - (int)kprev_list.back();
+                const int d2 = dim - kprev;
+                const double rho = geometric_rate(changes.back(), d1, change, d2);
+                const double rho_use = rates.empty() ? rho : std::max(rho, rates.back());
+                rates.push_back(rho);
+                if (c->opts.stop_rule == 0) {
+                    const double q = std::pow(rho_use, (double)d2);
+                    tail = q < 1.0 ? 2.0 * change * q / (1.0 - q) : INFINITY;
+                    for (int b = 0; b < s; ++b)
+                        est_src[b] = q < 1.0 ? 2.0 * est_src[b] * q / (1.0 - q) : INFINITY;
+                }
+            }
+            changes.push_back(change);
+            kprev_list.push_back(kprev);
+            out.est = tail;
+            if (tail <= tol) stop = true;
+        }
+        if (brk) {
+            out.est = 0.0;
+            for (auto& e : est_src) e = 0.0;
+        }
+        ysm_prev.swap(ysm_cur);
+        kprev = dim;
+        if (stop) break;
+    }
+    // Y = R sgn(Re lambda) G^{-1} L^dag B + V_K (F E_1 R_0)  (Eq. 22 per block)
+    const int dim = out.dim;
+    Batch by = bs;
+    if (m > 0) {
+        Batch bo = bs;
+        bo.small = mm;
+        hipLaunchKernelGGL(k_sign_coef, dim3((unsigned)ceil_div(m, 64), s), dim3(64), 0, c->st, m,
+                           (const cd*)c->lam_dev.p, (const cd*)c->cdefb.p, c->ccoefb.as<cd>(), bo);
+        OSA_LAUNCH_CHECK();
+        by.small = mm;
+        launch_mcombine(yout, c->R.as<cd>(), N, m, c->ccoefb.as<cd>(), N, 0.0, 1.0, c->st, by);
+    }
+    by.small = dim;
+    launch_mcombine(yout, Vb, N, dim, c->ysmb.as<cd>(), N, m > 0 ? 1.0 : 0.0, 1.0, c->st, by);
+    if (!fixed && !(out.est <= tol)) out.st = OSA_NOT_CONVERGED;
+    if (fixed) out.est = NAN;
+    sync(c);
+}
+
 osa_status apply_impl(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double tol,
                       osa_info* infos, ApplyMode mode) {
     if (!c || nrhs < 1 || !B || !Y) return OSA_ERR_ARG;
@@ -2539,6 +2773,48 @@ osa_status osa_apply_adjoint(osa_ctx* c, int32_t nrhs, const void* B, void* Y, d
 osa_status osa_apply_overlap(osa_ctx* c, int32_t nrhs, const void* B, void* Y, double tol,
                              osa_info* infos) {
     return apply_impl(c, nrhs, B, Y, tol, infos, ApplyMode::kOverlap);
+}
+
+osa_status osa_apply_block(osa_ctx* c, int32_t s, const void* B, void* Y, double tol,
+                           int32_t k_blocks, osa_info* infos) {
+    if (!c || s < 1 || s > kMaxBatch || !B || !Y || k_blocks < 0) return OSA_ERR_ARG;
+    const bool fixed = c->opts.check_every < 0;
+    if (!fixed && !(tol > 0)) return OSA_ERR_ARG;
+    const int kb = k_blocks > 0 ? k_blocks : std::max(1, (int)ceil_div(4LL * c->opts.k_max, s));
+    if ((int64_t)kb * s > 6000 || (int64_t)(kb + 1) * s > 12LL * c->g.V) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        const int64_t N = c->N();
+        const int64_t nbnd = 12LL * c->g.V;
+        const double t0 = now_ms();
+        c->xio.ensure(sizeof(cd) * N * s);
+        c->yio.ensure(sizeof(cd) * N * s);
+        launch_vec_to_internal((const cd*)B, c->xio.p, false, c->g, s, c->st);
+        BlockResult r;
+        std::vector<double> est(s, NAN);
+        solve_block(c, s, c->xio.as<cd>(), c->yio.as<cd>(), tol, kb, r, est);
+        launch_vec_from_internal(c->yio.p, false, (cd*)Y, c->g, s, c->st);
+        sync(c);
+        const double t1 = now_ms();
+        if (infos) {
+            for (int b = 0; b < s; ++b) {
+                osa_info& in = infos[b];
+                std::memset(&in, 0, sizeof(in));
+                in.resid_est = fixed ? NAN : est[b];
+                in.k_used = r.dim;
+                in.n_defl = c->m_active;
+                in.status = r.st;
+                in.newton_iters = r.newton_iters;
+                in.breakdown = r.breakdown;
+                in.min_abs_re_lambda = c->m_active ? c->min_abs_re : NAN;
+                in.max_eig_resid = c->max_eig_resid;
+                in.t_init_ms = c->t_init_ms;
+                in.t_solve_ms = t1 - t0;
+                in.batch = s;
+            }
+        }
+        (void)nbnd;
+        return r.st;
+    }, &c->msg);
 }
 
 osa_status osa_batch_apply(int32_t n, osa_ctx* const* ctxs, const void* const* B, void* const* Y,
