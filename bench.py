@@ -465,6 +465,7 @@ def uneven_batch(args):
     torch.cuda.synchronize()
     eig_ms = [0.0] * len(ctxs)
     defl_err = [0] * len(ctxs)
+    defl_msg = [""] * len(ctxs)
     nxt = [0]
     lock = threading.Lock()
 
@@ -480,6 +481,7 @@ def uneven_batch(args):
                 ctxs[i].deflate(params[i]["n_defl"])
             except osa.OsaError as e:      # the instance is then solved without deflation
                 defl_err[i] = e.status
+                defl_msg[i] = str(e)
             eig_ms[i] = (time.perf_counter() - t0) * 1e3
             print(f"deflated instance {i} {params[i]['dims']} m={params[i]['n_defl']}: "
                   f"{eig_ms[i]:.0f} ms status {defl_err[i]}", file=sys.stderr, flush=True)
@@ -524,7 +526,8 @@ def uneven_batch(args):
         "deflation": {"wall_ms": t_defl * 1e3, "host_threads": 8,
                       "per_instance_ms_p50": float(np.percentile(eig_ms, 50)),
                       "per_instance_ms_p99": float(np.percentile(eig_ms, 99)),
-                      "failed": [{"inst": i, "status": e, "dims": params[i]["dims"],
+                      "failed": [{"inst": i, "status": e, "message": defl_msg[i],
+                                  "dims": params[i]["dims"],
                                   "n_defl": params[i]["n_defl"], "m_w": params[i]["m_w"],
                                   "mu": params[i]["mu"]} for i, e in enumerate(defl_err) if e]},
     }
