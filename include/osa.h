@@ -271,6 +271,26 @@ OSA_API osa_status osa_set_opts(osa_ctx* ctx, const osa_opts* opts);
  * for operator checks. */
 OSA_API osa_status osa_apply_hw(osa_ctx* ctx, int32_t nrhs, const void* X, void* Y);
 
+/* Y = H_w(mu) X (Eq. 1-2) with the FP32 stencil of the FP32 eigensearch:
+ * spinors and arithmetic in FP32, links as stored if FP32, else rounded once
+ * to FP32.  X, Y: nrhs vectors of V*12 complex64 each (device, boundary
+ * layout).  Checks the FP32 kernel instantiation against the operator. */
+OSA_API osa_status osa_apply_hw32(osa_ctx* ctx, int32_t nrhs, const void* X, void* Y);
+
+/* k Arnoldi steps (Eq. 7) on A = H(mu)^2 (adjoint = 0) or A = H(-mu)^2 =
+ * (H(mu)^dag)^2 (adjoint = 1), by the expansion of the Krylov-Schur search for
+ * the critical eigenpairs (Eq. 20): delayed second Gram-Schmidt pass, vectors
+ * and stencil in precision prec (OSA_FP64 or OSA_FP32; FP32 links as for
+ * osa_apply_hw32), reductions in FP64.  Gives A V_k = V_{k+1} S with
+ * v_1 = x / |x|, orthonormal V and upper Hessenberg S (real positive
+ * subdiagonal).  x: V*12 complex128 (device, boundary layout, not zero).
+ * V: k+1 such vectors (device, output; FP32 values promoted exactly).
+ * S: (k+1) x k complex128, column-major (device, output).  1 <= k <= 64 and
+ * k + 1 <= 12 V, else OSA_ERR_ARG.  A check entry of the eigensearch's
+ * kernels. */
+OSA_API osa_status osa_krylov_h2(osa_ctx* ctx, int32_t prec, int32_t adjoint, int32_t k,
+                                 const void* x, void* V, void* S);
+
 /* s = sign(A) e_1 for a k x k complex128 matrix A stored column-major (device,
  * leading dimension k), by the scaled Newton iteration used for f(H_k) e_1.
  * s: k complex128 (device).  iters (host, may be NULL).  Standalone entry of

@@ -34,7 +34,7 @@ LR, SCHUR = 0, 1   # osa_opts.deflation
 EXPORTS = ["overlap_sign_apply", "osa_create", "osa_deflate", "osa_set_deflation",
            "osa_get_deflation", "osa_set_active_deflation", "osa_apply", "osa_apply_adjoint",
            "osa_apply_overlap", "osa_apply_block", "osa_batch_apply",
-           "osa_set_opts", "osa_apply_hw", "osa_small_sign", "osa_small_sign_noalloc",
+           "osa_set_opts", "osa_apply_hw", "osa_apply_hw32", "osa_krylov_h2", "osa_small_sign", "osa_small_sign_noalloc",
            "osa_small_gemm", "osa_small_schur",
            "osa_set_links",
            "osa_profile_enable", "osa_profile_read", "osa_last_message", "osa_destroy",
@@ -129,6 +129,8 @@ def lib() -> ctypes.CDLL:
                                   dbl, ctypes.POINTER(Info)]
     L.osa_set_opts.argtypes = [vp, ctypes.POINTER(Opts)]
     L.osa_apply_hw.argtypes = [vp, i32, vp, vp]
+    L.osa_apply_hw32.argtypes = [vp, i32, vp, vp]
+    L.osa_krylov_h2.argtypes = [vp, i32, i32, i32, vp, vp, vp]
     L.osa_small_sign.argtypes = [i32, vp, vp, ctypes.POINTER(i32), vp]
     L.osa_small_schur.argtypes = [i32, vp, vp, vp, vp, i32, vp]
     L.osa_small_gemm.argtypes = [i32, i32, vp, vp, vp, vp]
@@ -424,6 +426,35 @@ class Context:
         _check(lib().osa_apply_hw(self._h, nrhs, xp, ctypes.c_void_p(Y.data_ptr())),
                "osa_apply_hw", False)
         return Y
+
+    def apply_hw32(self, X):
+        """Y = H_w(mu) X with the FP32 stencil (X, Y complex64)."""
+        torch = _torch()
+        xp = _dev_ptr(X, torch.complex64, "X")
+        nrhs = 1 if X.dim() == 1 else int(X.shape[0])
+        if X.numel() != nrhs * self.N:
+            raise ValueError(f"X must hold nrhs x {self.N} entries")
+        Y = torch.empty_like(X)
+        self._after_current()
+        _check(lib().osa_apply_hw32(self._h, nrhs, xp, ctypes.c_void_p(Y.data_ptr())),
+               "osa_apply_hw32", False)
+        return Y
+
+    def krylov_h2(self, x, k, prec=FP64, adjoint=False):
+        """k Arnoldi steps on H(mu)^2 (or H(-mu)^2) from x, as in the eigensearch.
+        Returns (V, S): V (k+1, N) complex128, S (k+1, k) complex128 with
+        A V[:k].T = V.T S."""
+        torch = _torch()
+        xp = _dev_ptr(x, torch.complex128, "x")
+        if x.numel() != self.N:
+            raise ValueError(f"x must hold {self.N} entries")
+        V = torch.empty((k + 1, self.N), dtype=torch.complex128, device=x.device)
+        S = torch.empty((k, k + 1), dtype=torch.complex128, device=x.device)
+        self._after_current()
+        _check(lib().osa_krylov_h2(self._h, prec, 1 if adjoint else 0, k, xp,
+                                   ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(S.data_ptr())),
+               "osa_krylov_h2", False)
+        return V, S.T
 
 
 def set_autotune(on=True):

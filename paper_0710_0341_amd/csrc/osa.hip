@@ -370,6 +370,15 @@ void apply_h(osa_ctx* c, const void* in, void* out, bool fp32, bool adjoint,
     });
 }
 
+// Links for the FP32 kernels: FP32-stored links as they are, FP64-stored ones
+// rounded once into U32 (kept in step by osa_set_links).
+void ensure_links32(osa_ctx* c) {
+    if (!c->links_fp32 && !c->U32.p) {
+        c->U32.ensure(sizeof(cf) * (size_t)c->g.Vp * 36);
+        launch_convert(c->U.p, false, c->U32.p, true, (int64_t)c->g.Vp * 36, c->st);
+    }
+}
+
 // nrhs contiguous vectors
 void apply_h_contig(osa_ctx* c, const void* in, void* out, bool fp32, bool adjoint, int nrhs) {
     const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
@@ -1943,10 +1952,7 @@ void deflate(osa_ctx* c, int m, osa_info* info, int ncv_req = 0, int maxr_req = 
     const int maxr = maxr_req > 0 ? maxr_req
                                   : (c->opts.eig_max_restarts > 0 ? c->opts.eig_max_restarts : 2000);
     const bool fp32 = (c->opts.eig_prec == OSA_FP32);
-    if (fp32 && !c->links_fp32 && !c->U32.p) {
-        c->U32.ensure(sizeof(cf) * (size_t)c->g.Vp * 36);
-        launch_convert(c->U.p, false, c->U32.p, true, (int64_t)c->g.Vp * 36, c->st);
-    }
+    if (fp32) ensure_links32(c);
     // Schur deflation needs the right eigenvectors only
     const bool right_only = c->opts.deflation == 1;
     DevBuf X, Rn, Ln, Xs;
@@ -2926,6 +2932,70 @@ osa_status osa_apply_hw(osa_ctx* c, int32_t nrhs, const void* X, void* Y) {
         apply_h_contig(c, a.p, b.p, false, false, nrhs);
         launch_vec_from_internal(b.p, false, (cd*)Y, c->g, nrhs, c->st);
         sync(c);
+        return OSA_OK;
+    });
+}
+
+osa_status osa_apply_hw32(osa_ctx* c, int32_t nrhs, const void* X, void* Y) {
+    if (!c || nrhs < 1 || !X || !Y) return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        if (!c->links()) throw OsaError{OSA_ERR_STATE, "no links set"};
+        const int64_t N = c->N();
+        const int64_t nb = 12LL * c->g.V * nrhs;   // boundary-layout entries
+        ensure_links32(c);
+        DevBuf t, a, b;
+        t.ensure(sizeof(cd) * (size_t)nb);
+        a.ensure(sizeof(cf) * (size_t)N * nrhs);
+        b.ensure(sizeof(cf) * (size_t)N * nrhs);
+        // complex64 -> complex128 (exact) -> internal complex64 (exact)
+        launch_convert(X, true, t.p, false, nb, c->st);
+        launch_vec_to_internal(t.as<cd>(), a.p, true, c->g, nrhs, c->st);
+        apply_h_contig(c, a.p, b.p, true, false, nrhs);
+        launch_vec_from_internal(b.p, true, t.as<cd>(), c->g, nrhs, c->st);
+        launch_convert(t.p, false, Y, true, nb, c->st);
+        sync(c);
+        return OSA_OK;
+    });
+}
+
+osa_status osa_krylov_h2(osa_ctx* c, int32_t prec, int32_t adjoint, int32_t k, const void* x,
+                         void* Vout, void* Sout) {
+    if (!c || (prec != OSA_FP64 && prec != OSA_FP32) || k < 1 || k > 64 || !x || !Vout ||
+        !Sout)
+        return OSA_ERR_ARG;
+    return guard([&]() -> osa_status {
+        if (!c->links()) throw OsaError{OSA_ERR_STATE, "no links set"};
+        if ((int64_t)k + 1 > 12LL * c->g.V) throw OsaError{OSA_ERR_ARG, "k + 1 exceeds N"};
+        const bool fp32 = prec == OSA_FP32;
+        const int64_t N = c->N();
+        const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
+        if (fp32) ensure_links32(c);
+        ensure_exec(c, k + 2);
+        const int ldS = k + 1;
+        DevBuf Vb, wv, tv, S, d;
+        Vb.ensure(es * (size_t)N * (k + 1));
+        wv.ensure(es * (size_t)N);
+        tv.ensure(es * (size_t)N);
+        S.ensure(sizeof(cd) * (size_t)ldS * (k + 1));
+        d.ensure(sizeof(cd) * 2 * (size_t)(k + 2));
+        launch_fill_zero(S.p, sizeof(cd) * (size_t)ldS * (k + 1), c->st);
+        double* hfro2 = (double*)(c->dscal.as<cd>() + 8);
+        launch_fill_zero(hfro2, sizeof(double), c->st);
+        launch_fill_zero(c->flag.p, sizeof(int) * 4, c->st);
+        const TsPlan pl = ts_plan(N);
+        launch_vec_to_internal((const cd*)x, Vb.p, fp32, c->g, 1, c->st);
+        launch_norm_partial(Vb.p, fp32, pl, c->normp.as<double>(), c->st);
+        launch_normalize(Vb.p, Vb.p, fp32, pl, c->normp.as<double>(), c->dscal.as<cd>() + 9,
+                         nullptr, 0.0, nullptr, 0, nullptr, 0, c->st);
+        KsStats st;
+        expand_delayed(c, adjoint != 0, fp32, (char*)Vb.p, N, S.as<cd>(), ldS, 0, k, wv.p, tv.p,
+                       d.as<cd>(), hfro2, c->flag.as<int>(), st);
+        launch_vec_from_internal(Vb.p, fp32, (cd*)Vout, c->g, k + 1, c->st);
+        OSA_HIP(hipMemcpyAsync(Sout, S.p, sizeof(cd) * (size_t)ldS * k, hipMemcpyDeviceToDevice,
+                               c->st));
+        int hf = 0;
+        d2h(c, c->flag.p, 1, &hf);
+        if (hf == 2) throw OsaError{OSA_ERR_NONFINITE, "non-finite Arnoldi vector"};
         return OSA_OK;
     });
 }
