@@ -227,6 +227,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eig-prec", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--orth", type=int, choices=[0, 1, 2], default=0,
+                    help="Arnoldi orthogonalisation of the solves (osa_opts.orth): 0 delayed "
+                         "one-step CGS2, 1 plain CGS2, 2 two-step blocks")
     ap.add_argument("--eig-ncv", type=int, default=0,
                     help="eigensolver active block (0: the library default)")
     ap.add_argument("--workload", choices=["dis16", "dis8", "haar4", "uneven64", "fig1", "haar12"],
@@ -599,7 +602,7 @@ def headline16(args):
     B = torch.from_numpy(B_np).to("cuda:0")
     nsrc = B.shape[0]
     ctx = osa.Context(links, dims, w["mu"], w["m_w"], k_max=w["k_max"], check_every=CHECK_EVERY,
-                      max_batch=nsrc)
+                      max_batch=nsrc, orth=args.orth)
     torch.cuda.synchronize()
     print("dis16: deflation (40 pairs)", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -625,7 +628,7 @@ def headline16(args):
     value = nsrc * args.steps / (t1 - t0)
     # the plain single-source path on the same context and sources
     print("dis16: the 12 sources one at a time", file=sys.stderr, flush=True)
-    ctx.set_opts(k_max=w["k_max"], check_every=CHECK_EVERY, max_batch=1)
+    ctx.set_opts(k_max=w["k_max"], check_every=CHECK_EVERY, max_batch=1, orth=args.orth)
     ctx.profile(True, every=PROF_EVERY)
     t0 = time.perf_counter()
     Yp, infp, stp = ctx.apply(B, tol=tol)
@@ -639,7 +642,7 @@ def headline16(args):
         # the block Krylov variant (one Krylov space for the 12 sources; not the paper's
         # method), second of two runs, against the lockstep result
         print("dis16: block Krylov variant", file=sys.stderr, flush=True)
-        ctx.set_opts(k_max=w["k_max"], check_every=CHECK_EVERY, max_batch=nsrc)
+        ctx.set_opts(k_max=w["k_max"], check_every=CHECK_EVERY, max_batch=nsrc, orth=args.orth)
         ctx.apply_block(B, tol=tol, check=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -669,6 +672,7 @@ def headline16(args):
                    "sources": "12 spin-colour point sources at site 0, one lockstep batch",
                    "n_defl": w["n_defl"], "deflation": "LR (Eq. 20-22), computed once",
                    "k_max": w["k_max"], "tol": tol, "check_every": CHECK_EVERY,
+                   "orth": ["delayed one-step CGS2", "plain CGS2", "two-step blocks"][args.orth],
                    "stop_rule": "geometric tail of the checkpoint changes (x2)",
                    "parallelism": "single GPU"},
         "roofline": roofline(table, "dis16"),

@@ -973,6 +973,390 @@ void launch_dcgs_coef(int j, cd* H, int ldh, const cd* d, cd* sc, double* hfro2,
     OSA_LAUNCH_CHECK();
 }
 
+// ------------------------------------------- two-step block Arnoldi
+// The two-step form of the Arnoldi recurrence (Eq. 7) extends the basis by two
+// vectors per outer step with one dot pass and one update pass over the basis:
+// columns n, n+1 hold the block U = [u_a, u_b] (orthogonalised once against
+// v_0..v_{n-1}, not yet against each other), columns n+2, n+3 the new block
+// W = [H u_b, H^2 u_b].  One dot pass gives [V_n, U]^H [U, W]; the coefficient
+// kernel finishes U into v_n, v_{n+1} (second Gram-Schmidt pass and a 2x2
+// Cholesky factor R), orthogonalises W once against v_0..v_{n+1}, recovers the
+// Hessenberg columns n-1 and n and the pending part of column n+1, and the
+// update pass forms all four columns from one read of the basis.  Same
+// decomposition as the one-vector recurrence in exact arithmetic.
+
+// Columns per block of the four-vector dot: 8 (twice the registers, fewer
+// loads in flight per wave) measured slower than 4.
+static constexpr int kDot4Cols = 4;
+
+// Dots of ncols columns of B with the four vectors W + v*ldw (v < 4), all in the
+// problem's basis: partial[(v*ncols + c)*nchunks + q].
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_dot4_partial(const cd* __restrict__ B, int64_t ldb,
+                                                         int ncols, const cd* __restrict__ W,
+                                                         int64_t ldw, int64_t n, int rpc,
+                                                         int nchunks, cd* __restrict__ partial,
+                                                         Batch bt) {
+    __shared__ double sm[kWaves * 8 * C];
+    __shared__ double so[8 * C];
+    const int pb = bt.idx[blockIdx.z];
+    B += pb * bt.basis;
+    W += pb * bt.basis;
+    partial += pb * bt.part;
+    const int q = blockIdx.x;
+    const int c0 = blockIdx.y * C;
+    const int64_t r0 = (int64_t)q * rpc;
+    const int64_t r1 = (r0 + rpc < n) ? r0 + rpc : n;
+    double acc[8 * C];
+#pragma unroll
+    for (int i = 0; i < 8 * C; ++i) acc[i] = 0.0;
+    const int nc = (ncols - c0 < C) ? ncols - c0 : C;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+        cd w[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w[v] = W[v * ldw + i];
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+            if (cc < nc) {
+                const cd b = B[(int64_t)(c0 + cc) * ldb + i];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {   // conj(b) w_v
+                    acc[8 * cc + 2 * v] = fma(b.x, w[v].x, fma(b.y, w[v].y, acc[8 * cc + 2 * v]));
+                    acc[8 * cc + 2 * v + 1] =
+                        fma(b.x, w[v].y, fma(-b.y, w[v].x, acc[8 * cc + 2 * v + 1]));
+                }
+            }
+        }
+    }
+    block_sum<8 * C>(acc, sm, so);
+    if (threadIdx.x < nc) {
+        const int c = c0 + threadIdx.x;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            partial[(int64_t)(v * ncols + c) * nchunks + q] =
+                mk(so[8 * threadIdx.x + 2 * v], so[8 * threadIdx.x + 2 * v + 1]);
+    }
+}
+
+int launch_dot4_partial(const cd* B, int64_t ldb, int ncols, const cd* W, int64_t ldw,
+                        const TsPlan& pn, cd* partial, hipStream_t st, const Batch& bt) {
+    constexpr int C = kDot4Cols;
+    if (ncols <= 0 || bt.n <= 0) return dot_plan(pn.n, ncols, C).nchunks;
+    auto go = [&](const TsPlan& p) {
+        dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)bt.n), blk(kBlock);
+        hipLaunchKernelGGL((k_dot4_partial<C>), grid, blk, 0, st, B, ldb, ncols, W, ldw, p.n,
+                           p.rows_per_chunk, p.nchunks, partial, bt);
+        OSA_LAUNCH_CHECK();
+    };
+    const TsPlan p = tuned_plan(pn.n, ncols, C, st, go);
+    go(p);
+    return p.nchunks;
+}
+
+// Columns o0 .. o0+NO-1 of the problem's basis become X M, X = columns 0 .. nin-1
+// (which include the output columns: each row is read whole before it is
+// written), M[o*ldm + c] the problem's coefficients.
+template <int NO>
+__global__ __launch_bounds__(kBlock) void k_blk_update(cd* V, int64_t ldb, int nin,
+                                                       const cd* __restrict__ M, int ldm, int o0,
+                                                       int64_t n, Batch bt) {
+    __shared__ cd sc[kCoefTile * NO];
+    const int pb = bt.idx[blockIdx.y];
+    V += pb * bt.basis;
+    M += pb * bt.small;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t ii = (i < n) ? i : n - 1;   // keep every thread in the barriers
+    cd acc[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) acc[o] = mk(0.0, 0.0);
+    for (int cb = 0; cb < nin; cb += kCoefTile) {
+        const int ce = (cb + kCoefTile < nin) ? cb + kCoefTile : nin;
+        __syncthreads();
+        for (int e = threadIdx.x; e < (ce - cb) * NO; e += kBlock)
+            sc[e] = M[(int64_t)(e % NO) * ldm + cb + e / NO];
+        __syncthreads();
+        int c = cb;
+        for (; c + 4 <= ce; c += 4) {
+            cd x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = V[(int64_t)(c + u) * ldb + ii];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int o = 0; o < NO; ++o) cfma(acc[o], x[u], sc[(c + u - cb) * NO + o]);
+        }
+        for (; c < ce; ++c) {
+            const cd x = V[(int64_t)c * ldb + ii];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) cfma(acc[o], x, sc[(c - cb) * NO + o]);
+        }
+    }
+    if (i < n) {
+#pragma unroll
+        for (int o = 0; o < NO; ++o) V[(int64_t)(o0 + o) * ldb + i] = acc[o];
+    }
+}
+
+void launch_blk_update(cd* V, int64_t ldb, int nin, const cd* M, int ldm, int o0, int nout,
+                       int64_t n, hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0) return;
+    const dim3 grid((unsigned)ceil_div(n, kBlock), (unsigned)bt.n);
+    if (nout == 4)
+        hipLaunchKernelGGL((k_blk_update<4>), grid, dim3(kBlock), 0, st, V, ldb, nin, M, ldm, o0,
+                           n, bt);
+    else if (nout == 2)
+        hipLaunchKernelGGL((k_blk_update<2>), grid, dim3(kBlock), 0, st, V, ldb, nin, M, ldm, o0,
+                           n, bt);
+    else
+        throw std::invalid_argument("launch_blk_update: nout must be 2 or 4");
+    OSA_LAUNCH_CHECK();
+}
+
+// Per-problem workspace of the two-step form (entries from b2, vl = slot length):
+//   D  [0, 4 vl)     dots, D[v*(n+2) + c] = column c ^H vector v
+//   M  [4 vl, 8 vl)  update coefficients, M[o*vl + c]
+//   a  [8 vl, 9 vl)  pending column: H v_{n-1} = V_n a + t0 u_a
+//   Cp [9 vl, 11 vl) first-pass coefficients of the block, Cp[o*vl + c]
+//   Y  [11 vl, 13 vl) Hessenberg products
+//   sc [13 vl, ...)  sc[0].x = t0
+// The first outer step: v_0 is column 0, W = [H v_0, H^2 v_0] columns 1, 2 and
+// d = v_0^H W (two entries).  U = W - v_0 d, H v_0 = d_0 v_0 + u_a.
+__global__ void k_blk2_init(cd* b2, int vl, const cd* __restrict__ d, Batch bt) {
+    const int pb = bt.idx[blockIdx.x];
+    b2 += pb * bt.small;
+    d += pb * bt.small;
+    if (threadIdx.x != 0) return;
+    cd* M = b2 + 4 * (int64_t)vl;
+    cd* a = b2 + 8 * (int64_t)vl;
+    cd* Cp = b2 + 9 * (int64_t)vl;
+    cd* sc = b2 + 13 * (int64_t)vl;
+    const cd zero = mk(0.0, 0.0), one = mk(1.0, 0.0);
+    const cd d0 = d[0], d1 = d[1];
+    a[0] = d0;
+    Cp[0] = d0;
+    Cp[vl] = d1;
+    sc[0] = one;
+    M[0] = mk(-d0.x, -d0.y);
+    M[1] = one;
+    M[2] = zero;
+    M[vl + 0] = mk(-d1.x, -d1.y);
+    M[vl + 1] = zero;
+    M[vl + 2] = one;
+}
+
+// Outer step n >= 1 (one block per problem).  With S = V_n^H U, G = U^H U,
+// CV = V_n^H W, E = U^H W from the dot pass:
+//   R^H R = G - S^H S (2x2 Cholesky),  [v_n, v_{n+1}] = (U - V_n S) R^{-1},
+//   CQ = R^{-H} (E - S^H CV),  U' = W - V_n CV - [v_n, v_{n+1}] CQ,
+//   column n-1:  H[0:n, n-1] = a + t0 S[:, 0],  H[n, n-1] = t0 R00,
+//   column n:    H[0:n+2, n] = ([Cp_b + S_b; R01; R11] - [H_n (Cp_a + S_a); 0]) / R00,
+//   pending n+1: a' = ([CV_a; CQ_a] - [H_n S_b; 0] - H[0:n+2, n] R01) / R11,
+//                t0' = 1 / R11,
+// where H_n = H[0:n+1, 0:n] (column n-1 included) and Cp the previous block's
+// first-pass coefficients (H u_a = V Cp_b + u_b - H V Cp_a).  A subdiagonal
+// entry (t0 R00, then R11 / R00) at most rel * |H|_F is a breakdown (flag[0] = 1,
+// flag[1] = the column); the reciprocals are then 0, so nothing non-finite
+// follows.  Non-finite input sets flag[0] = 2.
+__global__ __launch_bounds__(256) void k_blk2_coef(int n, cd* H, int ldh, cd* b2, int vl,
+                                                   double* hfro2, int* flag, double rel,
+                                                   Batch bt) {
+    __shared__ double sred[4][16];
+    __shared__ double sv[40];
+    const int pb = bt.idx[blockIdx.x];
+    H += pb * bt.small;
+    b2 += pb * bt.small;
+    hfro2 += 2 * pb * bt.scal;
+    flag += pb * bt.flag;
+    const int np2 = n + 2;
+    const cd* D = b2;
+    cd* M = b2 + 4 * (int64_t)vl;
+    cd* a = b2 + 8 * (int64_t)vl;
+    cd* Cp = b2 + 9 * (int64_t)vl;
+    cd* Y = b2 + 11 * (int64_t)vl;
+    cd* sc = b2 + 13 * (int64_t)vl;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double t0 = sc[0].x;
+    // ---- phase 1: S^H S, S^H CV, column n-1
+    double acc[13];
+#pragma unroll
+    for (int q = 0; q < 13; ++q) acc[q] = 0.0;
+    for (int c = threadIdx.x; c < n; c += 256) {
+        const cd s0 = D[c], s1 = D[np2 + c], v0 = D[2 * np2 + c], v1 = D[3 * np2 + c];
+        acc[0] += cabs2(s0);
+        acc[1] += cabs2(s1);
+        const cd s01 = cmulc(s0, s1);   // conj(s0) s1
+        acc[2] += s01.x;
+        acc[3] += s01.y;
+        const cd p00 = cmulc(s0, v0), p01 = cmulc(s0, v1), p10 = cmulc(s1, v0),
+                 p11 = cmulc(s1, v1);
+        acc[4] += p00.x; acc[5] += p00.y;
+        acc[6] += p01.x; acc[7] += p01.y;
+        acc[8] += p10.x; acc[9] += p10.y;
+        acc[10] += p11.x; acc[11] += p11.y;
+        const cd h = cadd(a[c], cscale(s0, t0));
+        H[c + (int64_t)(n - 1) * ldh] = h;
+        acc[12] += cabs2(h);
+    }
+#pragma unroll
+    for (int q = 0; q < 13; ++q) {
+        const double x = wave_sum(acc[q]);
+        if (lane == 0) sred[wave][q] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot[13];
+        for (int q = 0; q < 13; ++q) tot[q] = sred[0][q] + sred[1][q] + sred[2][q] + sred[3][q];
+        const double g00 = D[n].x, g11 = D[np2 + n + 1].x;
+        const cd g01 = D[np2 + n];   // u_a^H u_b
+        const double m00 = g00 - tot[0], m11 = g11 - tot[1];
+        const cd m01 = mk(g01.x - tot[2], g01.y - tot[3]);
+        const double r00 = sqrt(fmax(m00, 0.0));
+        // column n-1 done: its subdiagonal is t0 r00
+        const double sub = t0 * r00;
+        *hfro2 += tot[12];
+        int bd = (sub <= rel * sqrt(*hfro2 + sub * sub)) ? 1 : 0;
+        if (!(g00 == g00) || !(g11 == g11) || !(tot[12] == tot[12]) || !(m00 == m00) ||
+            fabs(g00) > 1e300)
+            bd = 2;
+        if (bd) {
+            if (flag[0] == 0) flag[1] = n - 1;
+            if (bd > flag[0]) flag[0] = bd;
+        }
+        H[n + (int64_t)(n - 1) * ldh] = mk(sub, 0.0);
+        const double ir00 = flag[0] ? 0.0 : 1.0 / r00;
+        const cd r01 = cscale(m01, ir00);
+        const double r11 = sqrt(fmax(m11 - cabs2(r01), 0.0));
+        sv[0] = r00; sv[1] = ir00; sv[2] = r01.x; sv[3] = r01.y; sv[4] = r11;
+        // E - S^H CV (row a: u_a / u_b, column o: w1 / w2)
+        const cd e00 = D[2 * np2 + n], e01 = D[3 * np2 + n], e10 = D[2 * np2 + n + 1],
+                 e11 = D[3 * np2 + n + 1];
+        sv[5] = e00.x - tot[4];  sv[6] = e00.y - tot[5];
+        sv[7] = e01.x - tot[6];  sv[8] = e01.y - tot[7];
+        sv[9] = e10.x - tot[8];  sv[10] = e10.y - tot[9];
+        sv[11] = e11.x - tot[10]; sv[12] = e11.y - tot[11];
+    }
+    __syncthreads();
+    // ---- phase 2: Y0 = H_n (Cp_a + S_a), Y1 = H_n S_b, rows 0..n
+    for (int r = threadIdx.x; r <= n; r += 256) {
+        cd y0 = mk(0.0, 0.0), y1 = mk(0.0, 0.0);
+        for (int c = (r > 0 ? r - 1 : 0); c < n; ++c) {
+            const cd h = H[r + (int64_t)c * ldh];
+            cfma(y0, h, cadd(Cp[c], D[c]));
+            cfma(y1, h, D[np2 + c]);
+        }
+        Y[r] = y0;
+        Y[vl + r] = y1;
+    }
+    __syncthreads();
+    // ---- phase 3: column n
+    const double ir00 = sv[1];
+    const cd r01 = mk(sv[2], sv[3]);
+    const double r11 = sv[4];
+    double col2 = 0.0;
+    for (int r = threadIdx.x; r <= n + 1; r += 256) {
+        cd base;
+        if (r < n) base = csub(cadd(Cp[vl + r], D[np2 + r]), Y[r]);
+        else if (r == n) base = csub(r01, Y[n]);
+        else base = mk(r11, 0.0);
+        const cd h = cscale(base, ir00);
+        H[r + (int64_t)n * ldh] = h;
+        if (r <= n) col2 += cabs2(h);
+    }
+    col2 = wave_sum(col2);
+    if (lane == 0) sred[wave][0] = col2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double tot = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
+        const double sub = r11 * ir00;
+        *hfro2 += tot;
+        int bd = (sub <= rel * sqrt(*hfro2 + sub * sub)) ? 1 : 0;
+        if (!(tot == tot) || !(r11 == r11)) bd = 2;
+        if (bd) {
+            if (flag[0] == 0) flag[1] = n;
+            if (bd > flag[0]) flag[0] = bd;
+        }
+        const double ir11 = flag[0] ? 0.0 : 1.0 / r11;
+        // CQ = R^{-H} F: CQ[0][o] = F[0][o] / r00, CQ[1][o] = (F[1][o] - conj(r01) CQ[0][o]) / r11
+        const cd f00 = mk(sv[5], sv[6]), f01 = mk(sv[7], sv[8]), f10 = mk(sv[9], sv[10]),
+                 f11 = mk(sv[11], sv[12]);
+        const cd q00 = cscale(f00, ir00), q01 = cscale(f01, ir00);
+        const cd q10 = cscale(csub(f10, cmulc(r01, q00)), ir11);
+        const cd q11 = cscale(csub(f11, cmulc(r01, q01)), ir11);
+        // R^{-1} = [[ir00, -r01 ir00 ir11], [0, ir11]];  RiCQ = R^{-1} CQ
+        const cd rinv01 = cscale(r01, -ir00 * ir11);
+        const cd k00 = cadd(cscale(q00, ir00), cmul(rinv01, q10));
+        const cd k01 = cadd(cscale(q01, ir00), cmul(rinv01, q11));
+        const cd k10 = cscale(q10, ir11), k11 = cscale(q11, ir11);
+        sv[13] = ir11;
+        sv[14] = rinv01.x; sv[15] = rinv01.y;
+        sv[16] = q00.x; sv[17] = q00.y; sv[18] = q01.x; sv[19] = q01.y;
+        sv[20] = q10.x; sv[21] = q10.y; sv[22] = q11.x; sv[23] = q11.y;
+        sv[24] = k00.x; sv[25] = k00.y; sv[26] = k01.x; sv[27] = k01.y;
+        sv[28] = k10.x; sv[29] = k10.y; sv[30] = k11.x; sv[31] = k11.y;
+    }
+    __syncthreads();
+    // ---- phase 4: update coefficients, pending column n+1, next first-pass block
+    const double ir11 = sv[13];
+    const cd rinv01 = mk(sv[14], sv[15]);
+    const cd q00 = mk(sv[16], sv[17]), q01 = mk(sv[18], sv[19]);
+    const cd q10 = mk(sv[20], sv[21]), q11 = mk(sv[22], sv[23]);
+    const cd k00 = mk(sv[24], sv[25]), k01 = mk(sv[26], sv[27]);
+    const cd k10 = mk(sv[28], sv[29]), k11 = mk(sv[30], sv[31]);
+    const cd zero = mk(0.0, 0.0);
+    for (int c = threadIdx.x; c < n + 4; c += 256) {
+        cd m0, m1, m2, m3;
+        if (c < n) {
+            const cd s0 = D[c], s1 = D[np2 + c], v0 = D[2 * np2 + c], v1 = D[3 * np2 + c];
+            const cd sr0 = cscale(s0, ir00);
+            const cd sr1 = cscale(csub(s1, cmul(sr0, r01)), ir11);
+            m0 = mk(-sr0.x, -sr0.y);
+            m1 = mk(-sr1.x, -sr1.y);
+            const cd t2 = csub(v0, cadd(cmul(sr0, q00), cmul(sr1, q10)));
+            const cd t3 = csub(v1, cadd(cmul(sr0, q01), cmul(sr1, q11)));
+            m2 = mk(-t2.x, -t2.y);
+            m3 = mk(-t3.x, -t3.y);
+        } else if (c == n) {
+            m0 = mk(ir00, 0.0); m1 = rinv01; m2 = mk(-k00.x, -k00.y); m3 = mk(-k01.x, -k01.y);
+        } else if (c == n + 1) {
+            m0 = zero; m1 = mk(ir11, 0.0); m2 = mk(-k10.x, -k10.y); m3 = mk(-k11.x, -k11.y);
+        } else if (c == n + 2) {
+            m0 = zero; m1 = zero; m2 = mk(1.0, 0.0); m3 = zero;
+        } else {
+            m0 = zero; m1 = zero; m2 = zero; m3 = mk(1.0, 0.0);
+        }
+        M[c] = m0;
+        M[vl + c] = m1;
+        M[2 * (int64_t)vl + c] = m2;
+        M[3 * (int64_t)vl + c] = m3;
+    }
+    for (int r = threadIdx.x; r < n + 2; r += 256) {
+        cd cva, cvb;
+        if (r < n) { cva = D[2 * np2 + r]; cvb = D[3 * np2 + r]; }
+        else if (r == n) { cva = q00; cvb = q01; }
+        else { cva = q10; cvb = q11; }
+        const cd y1 = (r <= n) ? Y[vl + r] : zero;
+        const cd hn = H[r + (int64_t)n * ldh];
+        a[r] = cscale(csub(csub(cva, y1), cmul(hn, r01)), ir11);
+        Cp[r] = cva;
+        Cp[vl + r] = cvb;
+    }
+    if (threadIdx.x == 0) sc[0] = mk(ir11, 0.0);
+}
+
+void launch_blk2_init(cd* b2, int vl, const cd* d, hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0) return;
+    hipLaunchKernelGGL(k_blk2_init, dim3((unsigned)bt.n), dim3(64), 0, st, b2, vl, d, bt);
+    OSA_LAUNCH_CHECK();
+}
+
+void launch_blk2_coef(int n, cd* H, int ldh, cd* b2, int vl, double* hfro2, int* flag,
+                      double rel, hipStream_t st, const Batch& bt) {
+    if (bt.n <= 0) return;
+    hipLaunchKernelGGL(k_blk2_coef, dim3((unsigned)bt.n), dim3(256), 0, st, n, H, ldh, b2, vl,
+                       hfro2, flag, rel, bt);
+    OSA_LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------- norms
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_norm_partial(const T* __restrict__ w, int64_t n,

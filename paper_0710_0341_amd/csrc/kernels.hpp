@@ -125,6 +125,17 @@ int launch_dot2_partial(const void* B, int64_t ldb, int ncols, const void* w1, c
 // of H[0:j+1, 0:j] enters the first-pass correction).  first_pass = false:
 // d = [s, u^H u] only; column j-1 and sc[0] = 1/r are set.
 // Batch strides: small (H, d), scal (sc, and hfro2 in cd slots), flag.
+// Two-step block Arnoldi (see blas.hip): dots of ncols basis columns with the
+// four basis columns W .. W + 3 ldw; X M into nout (2 or 4) columns from o0;
+// the first-step and per-step coefficient kernels on the per-problem
+// workspace b2 (slot length vl).
+int launch_dot4_partial(const cd* B, int64_t ldb, int ncols, const cd* W, int64_t ldw,
+                        const TsPlan& pn, cd* partial, hipStream_t st, const Batch& bt);
+void launch_blk_update(cd* V, int64_t ldb, int nin, const cd* M, int ldm, int o0, int nout,
+                       int64_t n, hipStream_t st, const Batch& bt);
+void launch_blk2_init(cd* b2, int vl, const cd* d, hipStream_t st, const Batch& bt);
+void launch_blk2_coef(int n, cd* H, int ldh, cd* b2, int vl, double* hfro2, int* flag,
+                      double rel, hipStream_t st, const Batch& bt);
 void launch_dcgs_coef(int j, cd* H, int ldh, const cd* d, cd* sc, double* hfro2, int* flag,
                       double rel, hipStream_t st, const Batch& bt = Batch(), bool hess = true,
                       bool first_pass = true);

@@ -170,6 +170,7 @@ struct ArenaLayout {
     int64_t vec_len = 0;   // entries of each vector slot
     int64_t H = 0, coef = 0, coef2 = 0, cdef = 0, craw = 0, tmp = 0, s_cur = 0, s_prev = 0, dc = 0,
             ds = 0;
+    int64_t b2 = 0;   // two-step block Arnoldi workspace (13 slots + scalars)
     int64_t xs = 0;   // Schur deflation: X = S^dag H V_k (m x (kcap + 1), ld m)
     int m = 0;
     int64_t stride = 0;
@@ -189,6 +190,7 @@ struct ArenaLayout {
         a.s_prev = o; o += a.vec_len;
         a.dc = o;     o += 2 * a.vec_len;
         a.ds = o;     o += 8;
+        a.b2 = o;     o += 13 * a.vec_len + 16;
         a.xs = o;     o += (int64_t)m * (kcap + 1);
         a.stride = ceil_div(o, 16) * 16;
         return a;
@@ -1085,7 +1087,9 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     check_deflation_state(c);
     const bool schur = c->opts.deflation == 1 && c->m_active > 0;   // Eq. 13-19
     // the Schur basis set-up uses m columns of the basis storage as scratch
-    ensure_krylov(c, schur ? std::max(kmax, c->m_active) : kmax, nb);
+    // the two-step form keeps two columns beyond the Krylov size
+    ensure_krylov(c, schur ? std::max(kmax, c->m_active) : (c->opts.orth == 2 ? kmax + 1 : kmax),
+                  nb);
     if (c->lay.vec_len < kmax + c->m_alloc + 2 || c->lay.m < c->m_alloc) {
         c->lay = ArenaLayout::make(c->kcap, std::max(c->m_alloc, 1));
         c->arena.ensure(sizeof(cd) * (size_t)c->lay.stride * c->kbatch);
@@ -1099,7 +1103,12 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     const bool reproj = !c->opts.no_reproject || schur;
     const TsPlan p = ts_plan(N);
     const int64_t VS = (int64_t)(c->kcap + 2) * N;   // basis stride
-    const bool dcgs = c->opts.orth == 0;           // delayed reorthogonalisation
+    // orth 2: two-step blocks (one dot and one update pass per two Arnoldi
+    // steps), with LR deflation or none; the Krylov size stays even (the check
+    // interval is rounded up to even, a last size kmax rounded down).  Schur
+    // deflation, or a fixed odd kmax, takes the delayed one-step form instead.
+    const bool blk2 = c->opts.orth == 2 && !schur && !(fixed && (kmax & 1));
+    const bool dcgs = c->opts.orth == 0 || (c->opts.orth == 2 && !blk2);   // delayed reorth.
     const int ldh = L.ldh;
     cd* V = c->V.as<cd>();
     cd* ar = c->arena.as<cd>();
@@ -1187,6 +1196,29 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
             });
             OSA_HIP(hipMemcpy2DAsync(V + N, sizeof(cd) * VS, w, sizeof(cd) * N, sizeof(cd) * N, nb,
                                      hipMemcpyDeviceToDevice, c->st));
+        } else if (blk2) {
+            // first two-step block: W = [H v_1, H^2 v_1] in columns 1, 2, one pass
+            // against v_1 (U = W - v_1 v_1^H W)
+            Batch bv = b0;
+            bv.vec = VS;   // the stencil writes into the basis
+            apply_h(c, V, V + N, false, c->adj, bv);
+            if (reproj && m > 0) project_out(c, V + N, ar + L.coef2, ar + L.tmp, bv);
+            apply_h(c, V + N, V + 2 * N, false, c->adj, bv);
+            if (reproj && m > 0) project_out(c, V + 2 * N, ar + L.coef2, ar + L.tmp, bv);
+            Batch bd = bv;
+            bd.part = c->part_stride;
+            int nch = 0;
+            timed(c, 0, 3.0 * N * 16.0 * b0.n, [&] {
+                nch = launch_dot2_partial(V, N, 1, V + N, V + 2 * N, false, p, c->partial.as<cd>(),
+                                          c->st, bd);
+            });
+            launch_reduce_partial(c->partial.as<cd>(), nch, 2, ar + L.dc, nullptr, nullptr, nullptr,
+                                  c->st, bd);
+            launch_blk2_init(ar + L.b2, (int)L.vec_len, ar + L.dc, c->st, b0);
+            timed(c, 1, 5.0 * N * 16.0 * b0.n, [&] {
+                launch_blk_update(V, N, 3, ar + L.b2 + 4 * L.vec_len, (int)L.vec_len, 1, 2, N,
+                                  c->st, b0);
+            });
         }
     }
     std::vector<int> kprev(nb, 0);
@@ -1244,30 +1276,64 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
                              H + (size_t)j * ldh, j + 1, c->st, bt);
         }
     };
-    const int jbeg = dcgs ? 1 : 0, jend = dcgs ? kmax + 1 : kmax;
+    // Two-step block, outer step n (odd): the stencil twice on u_b (column n+1)
+    // into columns n+2, n+3, one dot pass of columns 0..n+1 with columns n..n+3,
+    // the coefficients, one update pass forming columns n..n+3; completes size
+    // n + 1 (column n+1 of H stays pending).
+    auto do_step2 = [&](int n, const Batch& bt) {
+        Batch bv = bt;
+        bv.vec = VS;
+        cd* Vn = V + (size_t)n * N;
+        apply_h(c, Vn + N, Vn + 2 * N, false, c->adj, bv);
+        if (reproj && m > 0) project_out(c, Vn + 2 * N, ar + L.coef2, ar + L.tmp, bv);
+        apply_h(c, Vn + 2 * N, Vn + 3 * N, false, c->adj, bv);
+        if (reproj && m > 0) project_out(c, Vn + 3 * N, ar + L.coef2, ar + L.tmp, bv);
+        Batch bd = bt;
+        bd.part = c->part_stride;
+        int nch = 0;
+        timed(c, 0, (n + 4.0) * N * 16.0 * bt.n, [&] {
+            nch = launch_dot4_partial(V, N, n + 2, Vn, N, p, c->partial.as<cd>(), c->st, bd);
+        });
+        launch_reduce_partial(c->partial.as<cd>(), nch, 4 * (n + 2), ar + L.b2, nullptr, nullptr,
+                              nullptr, c->st, bd);
+        launch_blk2_coef(n, H, ldh, ar + L.b2, (int)L.vec_len, hfro2, flag, 1e-14, c->st, bt);
+        timed(c, 1, (n + 8.0) * N * 16.0 * bt.n, [&] {
+            launch_blk_update(V, N, n + 4, ar + L.b2 + 4 * L.vec_len, (int)L.vec_len, n, 4, N,
+                              c->st, bt);
+        });
+    };
+    // step index j: its Krylov size, the last size and the check interval
+    const int kmax_u = blk2 ? (kmax & ~1) : kmax;
+    const int every_u = (blk2 && (every & 1)) ? every + 1 : every;
+    auto size_of = [&](int j) { return blk2 ? 2 * j + 2 : (dcgs ? j : j + 1); };
+    const int jbeg = dcgs ? 1 : 0;
+    const int jend = blk2 ? kmax_u / 2 : (dcgs ? kmax + 1 : kmax);
     auto is_check = [&](int j) {
-        const int kk = dcgs ? j : j + 1;
-        return kk % every == 0 || kk == kmax;
+        const int kk = size_of(j);
+        return kk % every_u == 0 || kk == kmax_u;
     };
     for (int j = jbeg; j < jend && !act.empty(); ++j) {
         // the segment [j, je]: the steps up to and including the next check
         int je = j;
         while (je + 1 < jend && !is_check(je)) ++je;
         run_segment(c, j, je, act, (schur ? 1 : 0) | (reproj ? 2 : 0) | (dcgs ? 4 : 0) |
-                                       (c->adj ? 8 : 0) | (fixed ? 16 : 0),
-                    [&](int jj) { do_step(jj, bat(act)); });
+                                       (c->adj ? 8 : 0) | (fixed ? 16 : 0) | (blk2 ? 32 : 0),
+                    [&](int jj) {
+                        if (blk2) do_step2(2 * jj + 1, bat(act));
+                        else do_step(jj, bat(act));
+                    });
         j = je;
-        const int kk = dcgs ? j : j + 1;
+        const int kk = size_of(j);
         if (!is_check(j)) continue;
         // each source follows its own schedule, as it would alone
         std::vector<int> chk, wait;
         for (int b : act) {
             bool want = true;
-            if (!fixed && kk != kmax && !crate[b].empty()) {
+            if (!fixed && kk != kmax_u && !crate[b].empty()) {
                 const double rho = crate[b].back();
                 const double pred = ctail[b] * std::pow(rho, (double)(kk - cj[b].back()));
                 const bool near = !(rho < 1.0) || !(pred > 3.0 * tol);
-                if (!near && kk - cj[b].back() < 4 * every) want = false;
+                if (!near && kk - cj[b].back() < 4 * every_u) want = false;
             }
             (want ? chk : wait).push_back(b);
         }
@@ -1539,7 +1605,7 @@ void ks_run(osa_ctx* c, bool adjoint, int nev, int pa, bool fp32, double tol, in
     const int P = nev + pa;              // basis capacity (plus the next vector)
     const int ldS = P + 1;
     DevBuf Vb, Vt, wv, tv, S, T, Z, wr, bz, info, Spb, sws, dcb;
-    const bool dcgs = c->opts.orth == 0;   // delayed reorthogonalisation, as in the solve
+    const bool dcgs = c->opts.orth != 1;   // delayed reorthogonalisation, as in the solve
     dcb.ensure(sizeof(cd) * 2 * (size_t)(P + 2));
     Spb.ensure(sizeof(cd) * (size_t)pa * pa);
     if (pa > 64) sws.ensure(schur_ws_bytes(pa));
@@ -2640,7 +2706,7 @@ osa_status osa_set_opts(osa_ctx* c, const osa_opts* opts) {
     if (opts) o = *opts;
     if (o.k_max < 0 || o.k_max > 4000 || o.eig_ncv < 0 || o.eig_ncv > 96 || o.eig_tol < 0 ||
         o.eig_max_restarts < 0 || (o.eig_prec != OSA_FP64 && o.eig_prec != OSA_FP32) ||
-        o.max_batch < 0 || o.max_batch > 64 || o.orth < 0 || o.orth > 1 || o.stop_rule < 0 ||
+        o.max_batch < 0 || o.max_batch > 64 || o.orth < 0 || o.orth > 2 || o.stop_rule < 0 ||
         o.stop_rule > 1 || o.no_graphs < 0 || o.no_graphs > 1 || o.eig_filter < 0 ||
         o.eig_filter > 200)
         return OSA_ERR_ARG;

@@ -138,14 +138,29 @@ def _ks_like(p, rng, keep):
     return a
 
 
-@pytest.mark.parametrize("p,kind,mode", [(5, "dense", 0), (33, "dense", 1), (64, "ks", 0),
+def _split_hessenberg(p, rng):
+    """Upper Hessenberg with zero subdiagonal entries: QR sweeps on active blocks
+    that start and end inside the matrix."""
+    a = np.triu(rng.standard_normal((p, p)) + 1j * rng.standard_normal((p, p)), -1)
+    for i in range(3, p, 7):
+        a[i, i - 1] = 0
+    return a
+
+
+@pytest.mark.parametrize("p,kind,mode", [(2, "dense", 0), (3, "dense", 1), (4, "dense", 0),
+                                         (5, "dense", 0), (17, "ks", 1), (33, "dense", 1),
+                                         (48, "split", 0), (64, "ks", 0), (64, "split", 1),
                                          (65, "dense", 0), (80, "ks", 1), (96, "ks", 0),
                                          (96, "dense", 1)])
 def test_small_schur_properties(osa, p, kind, mode):
     say(f"small schur p={p} kind={kind} mode={mode}")
     rng = np.random.default_rng(p + 7 * mode)
-    a = (rng.standard_normal((p, p)) + 1j * rng.standard_normal((p, p))) if kind == "dense" \
-        else _ks_like(p, rng, p // 2)
+    if kind == "dense":
+        a = rng.standard_normal((p, p)) + 1j * rng.standard_normal((p, p))
+    elif kind == "split":
+        a = _split_hessenberg(p, rng)
+    else:
+        a = _ks_like(p, rng, p // 2)
     T, Z, w = osa.small_schur(dev(a), mode)
     T, Z, w = host(T), host(Z), host(w)
     nrm = np.linalg.norm(a)

@@ -1,0 +1,153 @@
+"""GPU parity of the two-step block form of the Arnoldi recurrence (opts.orth =
+2: the basis grows by H u and H^2 u per outer step, one dot pass and one
+update pass over the basis per two steps).  It builds the same Arnoldi
+decomposition (Eq. 7) as the oracle's CGS2 recurrence in exact arithmetic, so
+Eq. 22 at a fixed even k matches the oracle to the FP64 bar (1e-10) and the
+one-step delayed form to 1e-12; converged solves meet the dense sign; batches
+stay bitwise equal to single-source solves.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import lattice_inputs as LI
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def osa():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_0710_0341_amd as osa_mod
+    osa_mod.lib()
+    return osa_mod
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _solve_fixed(osa, links, dims, mu, b, k, orth, defl=None, reproject=True):
+    ctx = osa.Context(dev(links), dims, mu, -1.5, k_max=k, check_every=-1, orth=orth,
+                      no_reproject=not reproject)
+    if defl is not None:
+        ctx.set_deflation(dev(defl.r.T.copy()), dev(defl.l.T.copy()), defl.lam)
+    y, infos, st = ctx.apply(dev(b), tol=1e-30)
+    ctx.close()
+    return host(y), infos[0]
+
+
+@pytest.mark.parametrize("dims,kind,mu,m,k,reproject", [
+    ((2, 2, 2, 2), "haar", 0.3, 0, 40, True),
+    ((3, 4, 3, 4), "disordered", 0.5, 0, 90, True),
+    ((3, 4, 3, 4), "disordered", 0.5, 8, 90, True),
+    ((3, 4, 3, 4), "disordered", 0.5, 8, 60, False),
+    ((4, 4, 4, 4), "haar", 0.3, 10, 150, True),
+    ((3, 5, 4, 6), "haar", 0.4, 6, 2, True),       # a single outer step
+])
+def test_two_step_fixed_k_matches_oracle(osa, dims, kind, mu, m, k, reproject):
+    say(f"two-step fixed k dims={dims} m={m} k={k} reproject={reproject}")
+    links = LI.make_links(dims, kind, eps=0.6, cfg=9, inst=3)
+    b = LI.gaussian_source(dims, cfg=9, inst=3)
+    h = O.hermitian_wilson_sparse(links, dims, mu, -1.5)
+    defl = None
+    if m:
+        r, l, lam = O.critical_dense(h.toarray(), m)
+        defl = O.Deflation(r, l, lam)
+    y2, i2 = _solve_fixed(osa, links, dims, mu, b, k, 2, defl, reproject)
+    y0, i0 = _solve_fixed(osa, links, dims, mu, b, k, 0, defl, reproject)
+    yo, info = O.lr_arnoldi_sign(lambda x: h @ x, b, defl, k=k, reproject=reproject)
+    assert i2["k_used"] == i0["k_used"] == info["k_used"] == k
+    assert rel(y2, yo) < 1e-10
+    assert rel(y2, y0) < 1e-12
+
+
+def test_two_step_odd_fixed_k_uses_one_step_form(osa):
+    dims = (3, 4, 3, 4)
+    links = LI.make_links(dims, "disordered", eps=0.6, cfg=9, inst=4)
+    b = LI.gaussian_source(dims, cfg=9, inst=4)
+    h = O.hermitian_wilson_sparse(links, dims, 0.5, -1.5)
+    say("two-step requested, fixed odd k = 61")
+    y2, i2 = _solve_fixed(osa, links, dims, 0.5, b, 61, 2)
+    yo, _ = O.lr_arnoldi_sign(lambda x: h @ x, b, None, k=61)
+    assert i2["k_used"] == 61
+    assert rel(y2, yo) < 1e-10
+
+
+@pytest.fixture(scope="module")
+def haar4():
+    w = LI.WORKLOADS[0]
+    dims = w["dims"]
+    links = LI.make_links(dims, "haar", cfg=0, inst=0)
+    h = O.hermitian_wilson_dense(links, dims, w["mu"], w["m_w"])
+    return dims, links, h
+
+
+def test_two_step_converged_batch_and_adjoint(osa, haar4):
+    """Converged solves with GPU deflation: against the dense sign and its
+    adjoint; a lockstep batch of point and Gaussian sources is bitwise the
+    single-source results; the Krylov size stays even."""
+    dims, links, h = haar4
+    say("two-step converged haar4 (GPU deflation, m = 10)")
+    srcs = [LI.gaussian_source(dims, cfg=0, inst=0)] + [LI.point_source(dims, 0, s, 0)
+                                                        for s in range(3)]
+    B = np.stack(srcs)
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=501, check_every=25, orth=2)
+    ctx.deflate(10)
+    yb, infos, st = ctx.apply(dev(B), tol=1e-11)
+    assert st == osa.OSA_OK
+    yb = host(yb)
+    for i, src in enumerate(srcs):
+        assert infos[i]["k_used"] % 2 == 0
+        assert rel(yb[i], O.sign_eig_apply(h, src)) < 1e-10
+        y1, inf1, _ = ctx.apply(dev(src), tol=1e-11)
+        assert inf1[0]["k_used"] == infos[i]["k_used"]
+        assert np.array_equal(host(y1), yb[i])
+    ya, ia, sa = ctx.apply_adjoint(dev(srcs[0]), tol=1e-11)
+    assert sa == osa.OSA_OK
+    assert rel(host(ya), O.sign_eig_apply(h.conj().T, srcs[0])) < 1e-10
+    ctx.close()
+
+
+def test_two_step_breakdown_and_not_converged(osa):
+    say("two-step: breakdown on a free plane wave")
+    dims = (2, 2, 2, 4)
+    u = LI.make_links(dims, "unit")
+    t = np.arange(dims[3])
+    wave = np.exp(2j * np.pi * t / dims[3])[:, None, None, None, None, None] * np.ones((1, 2, 2, 2, 4, 3))
+    chi = np.zeros((4, 3), dtype=complex)
+    chi[0, 0] = 1.0
+    b = (wave * chi).reshape(-1)
+    b /= np.linalg.norm(b)
+    ctx = osa.Context(dev(u), dims, 0.3, -1.5, k_max=50, check_every=6, orth=2)
+    y, infos, st = ctx.apply(dev(b), tol=1e-12)
+    assert infos[0]["breakdown"] == 1 and infos[0]["k_used"] <= 4
+    assert rel(host(y), O.free_field_sign_apply(dims, 0.3, -1.5, b)) < 1e-12
+    ctx.close()
+    say("two-step: not converged at an odd k_max = 21 (last size 20)")
+    dims = (3, 3, 3, 3)
+    links = LI.make_links(dims, "haar", cfg=9, inst=7)
+    b = LI.gaussian_source(dims, cfg=9, inst=7)
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=21, check_every=10, orth=2)
+    y, infos, st = ctx.apply(dev(b), tol=1e-14)
+    assert st == osa.OSA_NOT_CONVERGED and infos[0]["k_used"] == 20
+    ctx.close()
