@@ -47,8 +47,8 @@ PROFILES = os.path.join(ROOT, "profiles")
 # kernel classes of osa_profile: the kernels behind each, the bound, and the
 # rocprofv3 counter summary (FETCH_SIZE / WRITE_SIZE) of the class, if any
 CLASS_INFO = {
-    "cgs_dot": ("k_dot_partial + k_dot2_partial", "hbm"),
-    "cgs_update": ("k_update_* + k_dcgs_*", "hbm"),
+    "cgs_dot": ("k_dot_partial + k_dot2_partial + k_dot4_partial", "hbm"),
+    "cgs_update": ("k_update_* + k_dcgs_* + k_blk_update", "hbm"),
     "stencil": ("k_wilson_h", "hbm"),
     "small_inverse": ("k_gj_*", "alu"),
     "small_gemm": ("k_zgemm_mfma", "mfma"),
@@ -227,7 +227,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eig-prec", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--orth", type=int, choices=[0, 1, 2], default=0,
+    ap.add_argument("--orth", type=int, choices=[0, 1, 2], default=2,
                     help="Arnoldi orthogonalisation of the solves (osa_opts.orth): 0 delayed "
                          "one-step CGS2, 1 plain CGS2, 2 two-step blocks")
     ap.add_argument("--eig-ncv", type=int, default=0,
@@ -279,22 +279,27 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 16, "copy_bytes_written": n * 16, "launches": 5}))
 
 
-COUNTER_K = 225   # the headline's Krylov size (k_used of every source)
+COUNTER_K = 225   # the headline's Krylov size with the one-step form (k_used of every source)
+COUNTER_K_TWO_STEP = 234   # with the two-step form (checks every 26: the first stopping size)
 
 # kernels behind each profiled class (rocprofv3 kernel names), and the source
 # regions whose hash dates a counter summary
 CLASS_KERNELS = {
-    "cgs_dot": r"k_dot_partial|k_dot2_partial",
+    "cgs_dot": r"k_dot_partial|k_dot2_partial|k_dot4_partial",
     "cgs_update": r"k_update_direct|k_update_split|k_update_finish|k_dcgs_update|k_dcgs_split|"
-                  r"k_dcgs_finish",
+                  r"k_dcgs_finish|k_blk_update",
     "stencil": r"k_wilson_h",
 }
 CLASS_REGIONS = {
     "cgs_dot": [("paper_0710_0341_amd/csrc/blas.hip", "static TsPlan dot_plan(",
-                 "// ---------------------------------------------------------------- reduce")],
+                 "// ---------------------------------------------------------------- reduce"),
+                ("paper_0710_0341_amd/csrc/blas.hip", "// Columns per block of the four-vector dot",
+                 "// Columns o0 .. o0+NO-1")],
     "cgs_update": [("paper_0710_0341_amd/csrc/blas.hip",
                     "// ---------------------------------------------------------------- update",
-                    "// ---------------------------------------------------------------- norms")],
+                    "// ------------------------------------------- two-step block Arnoldi"),
+                   ("paper_0710_0341_amd/csrc/blas.hip", "// Columns o0 .. o0+NO-1",
+                    "// Per-problem workspace of the two-step form")],
     "stencil": [("paper_0710_0341_amd/csrc/stencil.hip",
                  "// ------------------------------------------------------------------ stencil",
                  "void launch_wilson_h_contig(")],
@@ -314,8 +319,9 @@ def counters_sample(args):
     B = torch.from_numpy(point_sources(dims)).to("cuda:0")
     n = B.shape[1]
     r, l, lam = LI.placeholder_deflation(n, w["n_defl"], cfg=3, inst=0)
-    ctx = osa.Context(links, dims, w["mu"], w["m_w"], k_max=COUNTER_K, check_every=-1,
-                      max_batch=B.shape[0])
+    k = COUNTER_K_TWO_STEP if args.orth == 2 else COUNTER_K
+    ctx = osa.Context(links, dims, w["mu"], w["m_w"], k_max=k, check_every=-1,
+                      max_batch=B.shape[0], orth=args.orth)
     ctx.set_deflation(torch.from_numpy(np.ascontiguousarray(r.T)).to("cuda:0"),
                       torch.from_numpy(np.ascontiguousarray(l.T)).to("cuda:0"), lam)
     ctx.profile(True, every=1)
@@ -323,7 +329,7 @@ def counters_sample(args):
     torch.cuda.synchronize()
     table = class_table([ctx.profile_read()], 1)
     ctx.close()
-    print(json.dumps({"counters_sample": "dis16_12pt", "k": COUNTER_K, "classes": table}))
+    print(json.dumps({"counters_sample": "dis16_12pt", "k": k, "orth": args.orth, "classes": table}))
 
 
 def summarize_counters(args):
@@ -671,7 +677,8 @@ def headline16(args):
                    "links": "disordered eps=0.5, stored FP32", "m_w": w["m_w"], "mu": w["mu"],
                    "sources": "12 spin-colour point sources at site 0, one lockstep batch",
                    "n_defl": w["n_defl"], "deflation": "LR (Eq. 20-22), computed once",
-                   "k_max": w["k_max"], "tol": tol, "check_every": CHECK_EVERY,
+                   "k_max": w["k_max"], "tol": tol,
+                   "check_every": CHECK_EVERY + (1 if args.orth == 2 and CHECK_EVERY % 2 else 0),
                    "orth": ["delayed one-step CGS2", "plain CGS2", "two-step blocks"][args.orth],
                    "stop_rule": "geometric tail of the checkpoint changes (x2)",
                    "parallelism": "single GPU"},

@@ -602,3 +602,74 @@ def test_geometric_tail_estimate_reading(kind, eps):
                     stop_err = err
             prev_s = s
         assert stop_err is not None and stop_err <= 1e-8, d
+
+
+def _two_step_arnoldi(matvec, x, k, project=None):
+    """The GPU's two-step block form of the Arnoldi recurrence, written out in
+    numpy: per outer step W = [H u_b, H^2 u_b] from the last unfinished vector;
+    one set of inner products [V, U]^H [U, W]; U finished by its second
+    Gram-Schmidt pass and a 2x2 Cholesky factor R; W orthogonalised once; the
+    Hessenberg columns recovered from R and the first-pass coefficients."""
+    prj = project if project else (lambda v: v)
+    n_all = x.shape[0]
+    beta = np.linalg.norm(x)
+    vmat = np.zeros((n_all, k + 3), dtype=complex)
+    hmat = np.zeros((k + 3, k + 2), dtype=complex)
+    vmat[:, 0] = x / beta
+    w1 = prj(matvec(vmat[:, 0]))
+    w = np.stack([w1, prj(matvec(w1))], 1)
+    cv = vmat[:, :1].conj().T @ w
+    u = w - vmat[:, :1] @ cv
+    n, a, t0, cp = 1, cv[:, 0].copy(), 1.0, cv.copy()
+    while n + 1 <= k:
+        w1 = prj(matvec(u[:, 1]))
+        w = np.stack([w1, prj(matvec(w1))], 1)
+        vn = vmat[:, :n]
+        s, g = vn.conj().T @ u, u.conj().T @ u
+        cvn, e = vn.conj().T @ w, u.conj().T @ w
+        r = np.linalg.cholesky(g - s.conj().T @ s).conj().T
+        q = (u - vn @ s) @ np.linalg.inv(r)
+        vmat[:, n:n + 2] = q
+        cq = np.linalg.solve(r.conj().T, e - s.conj().T @ cvn)
+        u_next = w - vn @ cvn - q @ cq
+        hmat[:n, n - 1] = a + t0 * s[:, 0]
+        hmat[n, n - 1] = t0 * r[0, 0]
+        col = np.zeros(n + 2, dtype=complex)
+        col[:n] = cp[:, 1] + s[:, 1]
+        col[n], col[n + 1] = r[0, 1], r[1, 1]
+        col[:n + 1] -= hmat[:n + 1, :n] @ (cp[:, 0] + s[:, 0])
+        hmat[:n + 2, n] = col / r[0, 0]
+        a = np.concatenate([cvn[:, 0], cq[:, 0]])
+        a[:n + 1] -= hmat[:n + 1, :n] @ s[:, 1]
+        a -= hmat[:n + 2, n] * r[0, 1]
+        a /= r[1, 1]
+        t0, cp, u = 1.0 / r[1, 1].real, np.vstack([cvn, cq]), u_next
+        n += 2
+    kk = n - 1
+    return vmat[:, :kk + 1], hmat[:kk + 1, :kk], beta, kk
+
+
+@pytest.mark.parametrize("kind,mu,m", [("haar", 0.3, 0), ("disordered", 0.5, 8)])
+def test_two_step_arnoldi_reading(kind, mu, m):
+    """The two-step block form (the GPU's orth 2) builds the Arnoldi
+    decomposition of Eq. 7 that the oracle's CGS2 recurrence builds: the
+    decomposition with v_1 = x/|x| and a real positive subdiagonal is unique,
+    so the Hessenberg matrices, the bases and Eq. 22 agree to rounding, with
+    and without LR deflation and the per-vector re-projection."""
+    dims = (3, 4, 3, 4)
+    links = LI.make_links(dims, kind, eps=0.6, cfg=9, inst=41)
+    b = LI.gaussian_source(dims, cfg=9, inst=41)
+    h = O.hermitian_wilson_sparse(links, dims, mu, -1.5)
+    defl = O.Deflation(*O.critical_dense(h.toarray(), m)) if m else None
+    xo = defl.split(b)[1] if defl else b
+    proj = defl.project_out if defl else None
+    k = 120
+    v2, h2, b2, k2 = _two_step_arnoldi(lambda v: h @ v, xo, k, proj)
+    vo, ho, bo, ko = O.arnoldi_cgs2(lambda v: h @ v, xo, k, project=proj)
+    assert k2 == ko == k
+    assert np.abs(v2.conj().T @ v2 - np.eye(k + 1)).max() < 1e-13
+    assert np.abs(h2 - ho).max() < 1e-12 * np.abs(ho).max()
+    assert np.abs(v2 - vo).max() < 1e-11
+    y2 = b2 * v2[:, :k] @ O.small_sign_e1(h2[:k, :k])
+    yo = bo * vo[:, :k] @ O.small_sign_e1(ho[:k, :k])
+    assert rel(y2, yo) < 1e-12
