@@ -21,6 +21,8 @@ namespace osa {
 
 static constexpr int kBlock = 256;
 static constexpr int kWaves = kBlock / 64;
+// Workgroups of a launch are dealt to the 8 XCDs (each with its own L2) in turn.
+static constexpr int kXcds = 8;
 
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ double wave_sum(double v) {
@@ -241,22 +243,27 @@ int launch_dot_partial(const void* B, int64_t ldb, int ncols, const void* w, boo
 }
 
 // Two vectors against the same columns (one read of B): partial[c*nchunks + q]
-// for w1 and partial[(ncols + c)*nchunks + q] for w2.
+// for w1 and partial[(ncols + c)*nchunks + q] for w2.  The chunk's rows of w1,
+// w2 are read by every column group: XCD x takes a contiguous run of (chunk,
+// column group) items, column group fastest, so those re-reads stay in its L2.
 template <typename T, int C>
 __global__ __launch_bounds__(kBlock) void k_dot2_partial(const T* __restrict__ B, int64_t ldb,
                                                          int ncols, const T* __restrict__ w1,
                                                          const T* __restrict__ w2, int64_t n,
-                                                         int rpc, int nchunks,
-                                                         cd* __restrict__ partial, Batch bt) {
+                                                         int rpc, int nchunks, int ngroups,
+                                                         int per_xcd, cd* __restrict__ partial,
+                                                         Batch bt) {
     __shared__ double sm[kWaves * 4 * C];
     __shared__ double so[4 * C];
+    const int item = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+    if (item >= nchunks * ngroups) return;   // whole block: before any barrier
     const int pb = bt.idx[blockIdx.z];
     B += pb * bt.basis;
     w1 += pb * bt.basis;
     w2 += pb * bt.vec;
     partial += pb * bt.part;
-    const int q = blockIdx.x;
-    const int c0 = blockIdx.y * C;
+    const int q = item / ngroups;
+    const int c0 = (item % ngroups) * C;
     const int64_t r0 = (int64_t)q * rpc;
     const int64_t r1 = (r0 + rpc < n) ? r0 + rpc : n;
     double acc[4 * C];
@@ -290,15 +297,17 @@ int launch_dot2_partial(const void* B, int64_t ldb, int ncols, const void* w1, c
     constexpr int C = 8;
     if (ncols <= 0 || bt.n <= 0) return dot_plan(pn.n, ncols, C).nchunks;
     auto go = [&](const TsPlan& p) {
-        dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)bt.n), blk(kBlock);
+        const int ngroups = (int)ceil_div(ncols, C);
+        const int per_xcd = (int)ceil_div((int64_t)p.nchunks * ngroups, kXcds);
+        dim3 grid((unsigned)(kXcds * per_xcd), 1, (unsigned)bt.n), blk(kBlock);
         if (fp32)
             hipLaunchKernelGGL((k_dot2_partial<cf, C>), grid, blk, 0, st, (const cf*)B, ldb, ncols,
                                (const cf*)w1, (const cf*)w2, p.n, p.rows_per_chunk, p.nchunks,
-                               partial, bt);
+                               ngroups, per_xcd, partial, bt);
         else
             hipLaunchKernelGGL((k_dot2_partial<cd, C>), grid, blk, 0, st, (const cd*)B, ldb, ncols,
                                (const cd*)w1, (const cd*)w2, p.n, p.rows_per_chunk, p.nchunks,
-                               partial, bt);
+                               ngroups, per_xcd, partial, bt);
         OSA_LAUNCH_CHECK();
     };
     const TsPlan p = tuned_plan(pn.n, ncols, C, st, go);
@@ -542,19 +551,25 @@ void launch_combine(void* y, const void* B, int64_t ldb, int ncols, const cd* co
 // fma sequence per (column, source), the same block reduction), so batched
 // results stay bitwise those of single-source solves.
 
-// Dots of 8 shared columns with kMdotR vectors: block (chunk q, column group,
-// vector group); partial of problem b, column c at b*bt.part + c*nchunks + q.
-static constexpr int kMdotR = 4;
-
+// Dots of C shared columns with R sources' vectors per block (chunk q, column
+// group, source group); partial of problem b, column c at
+// b*bt.part + c*nchunks + q.  Up to 12 sources per group with 2 columns per block (all 12 sources of a
+// lockstep batch read the shared columns once), else 4 sources with 8 columns.
+// The sources' rows are re-read by every column group: XCD x takes a
+// contiguous run of (chunk, column group) items, column group fastest.
+template <int C, int R>
 __global__ __launch_bounds__(kBlock) void k_mdot_partial(const cd* __restrict__ B, int64_t ldb,
                                                          int ncols, const cd* __restrict__ w,
                                                          int64_t n, int rpc, int nchunks,
+                                                         int ngroups, int per_xcd,
                                                          cd* __restrict__ partial, Batch bt) {
-    constexpr int C = 8, R = kMdotR, NV = 2 * C * R;
+    constexpr int NV = 2 * C * R;
     __shared__ double sm[kWaves * NV];
     __shared__ double so[NV];
-    const int q = blockIdx.x;
-    const int c0 = blockIdx.y * C;
+    const int item = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+    if (item >= nchunks * ngroups) return;   // whole block: before any barrier
+    const int q = item / ngroups;
+    const int c0 = (item % ngroups) * C;
     const int g0 = blockIdx.z * R;
     const int nr = (bt.n - g0 < R) ? bt.n - g0 : R;
     const int nc = (ncols - c0 < C) ? ncols - c0 : C;
@@ -596,13 +611,20 @@ __global__ __launch_bounds__(kBlock) void k_mdot_partial(const cd* __restrict__ 
 
 int launch_mdot_partial(const cd* B, int64_t ldb, int ncols, const cd* w, const TsPlan& pn,
                         cd* partial, hipStream_t st, const Batch& bt) {
-    constexpr int C = 8;
+    constexpr int C = 8;   // the one-source kernel's column group: its chunk plan
     if (ncols <= 0 || bt.n <= 0) return dot_plan(pn.n, ncols, C).nchunks;
+    const bool wide = bt.n > 4;
     auto go = [&](const TsPlan& p) {
-        dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C),
-                  (unsigned)ceil_div(bt.n, kMdotR));
-        hipLaunchKernelGGL(k_mdot_partial, grid, dim3(kBlock), 0, st, B, ldb, ncols, w, p.n,
-                           p.rows_per_chunk, p.nchunks, partial, bt);
+        const int cg = wide ? 2 : 8, rg = wide ? 12 : 4;
+        const int ngroups = (int)ceil_div(ncols, cg);
+        const int per_xcd = (int)ceil_div((int64_t)p.nchunks * ngroups, kXcds);
+        dim3 grid((unsigned)(kXcds * per_xcd), 1, (unsigned)ceil_div(bt.n, rg));
+        if (wide)
+            hipLaunchKernelGGL((k_mdot_partial<2, 12>), grid, dim3(kBlock), 0, st, B, ldb, ncols, w,
+                               p.n, p.rows_per_chunk, p.nchunks, ngroups, per_xcd, partial, bt);
+        else
+            hipLaunchKernelGGL((k_mdot_partial<8, 4>), grid, dim3(kBlock), 0, st, B, ldb, ncols, w,
+                               p.n, p.rows_per_chunk, p.nchunks, ngroups, per_xcd, partial, bt);
         OSA_LAUNCH_CHECK();
     };
     const TsPlan p = tuned_plan(pn.n, ncols, C, st, go);   // the one-source plan: same chunks
@@ -985,26 +1007,32 @@ void launch_dcgs_coef(int j, cd* H, int ldh, const cd* d, cd* sc, double* hfro2,
 // update pass forms all four columns from one read of the basis.  Same
 // decomposition as the one-vector recurrence in exact arithmetic.
 
-// Columns per block of the four-vector dot: 8 (twice the registers, fewer
-// loads in flight per wave) measured slower than 4.
+// Dots of ncols columns of B with the four vectors W + v*ldw (v < 4), all in the
+// problem's basis: partial[(v*ncols + c)*nchunks + q].  A block takes C columns
+// over one chunk of rows; the chunk's rows of the four vectors are read by all
+// ncols / C column groups, so the blocks are ordered for the L2 caches:
+// workgroups are dealt to the 8 XCDs in turn, and XCD x takes a contiguous run
+// of (chunk, column group) items with the column group varying fastest, so the
+// re-reads of a chunk's vector rows follow each other in one L2.  (8 columns
+// per block, or the vectors split over two half-blocks, measured slower.)
 static constexpr int kDot4Cols = 4;
 
-// Dots of ncols columns of B with the four vectors W + v*ldw (v < 4), all in the
-// problem's basis: partial[(v*ncols + c)*nchunks + q].
 template <int C>
 __global__ __launch_bounds__(kBlock) void k_dot4_partial(const cd* __restrict__ B, int64_t ldb,
                                                          int ncols, const cd* __restrict__ W,
                                                          int64_t ldw, int64_t n, int rpc,
-                                                         int nchunks, cd* __restrict__ partial,
-                                                         Batch bt) {
+                                                         int nchunks, int ngroups, int per_xcd,
+                                                         cd* __restrict__ partial, Batch bt) {
     __shared__ double sm[kWaves * 8 * C];
     __shared__ double so[8 * C];
+    const int item = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+    if (item >= nchunks * ngroups) return;   // whole block: before any barrier
+    const int q = item / ngroups;
+    const int c0 = (item % ngroups) * C;
     const int pb = bt.idx[blockIdx.z];
     B += pb * bt.basis;
     W += pb * bt.basis;
     partial += pb * bt.part;
-    const int q = blockIdx.x;
-    const int c0 = blockIdx.y * C;
     const int64_t r0 = (int64_t)q * rpc;
     const int64_t r1 = (r0 + rpc < n) ? r0 + rpc : n;
     double acc[8 * C];
@@ -1043,9 +1071,11 @@ int launch_dot4_partial(const cd* B, int64_t ldb, int ncols, const cd* W, int64_
     constexpr int C = kDot4Cols;
     if (ncols <= 0 || bt.n <= 0) return dot_plan(pn.n, ncols, C).nchunks;
     auto go = [&](const TsPlan& p) {
-        dim3 grid((unsigned)p.nchunks, (unsigned)ceil_div(ncols, C), (unsigned)bt.n), blk(kBlock);
+        const int ngroups = (int)ceil_div(ncols, C);
+        const int per_xcd = (int)ceil_div((int64_t)p.nchunks * ngroups, kXcds);
+        dim3 grid((unsigned)(kXcds * per_xcd), 1, (unsigned)bt.n), blk(kBlock);
         hipLaunchKernelGGL((k_dot4_partial<C>), grid, blk, 0, st, B, ldb, ncols, W, ldw, p.n,
-                           p.rows_per_chunk, p.nchunks, partial, bt);
+                           p.rows_per_chunk, p.nchunks, ngroups, per_xcd, partial, bt);
         OSA_LAUNCH_CHECK();
     };
     const TsPlan p = tuned_plan(pn.n, ncols, C, st, go);
