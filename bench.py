@@ -279,8 +279,7 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 16, "copy_bytes_written": n * 16, "launches": 5}))
 
 
-COUNTER_K = 225   # the headline's Krylov size with the one-step form (k_used of every source)
-COUNTER_K_TWO_STEP = 234   # with the two-step form (checks every 26: the first stopping size)
+COUNTER_K = 225   # the headline's Krylov size (k_used of every source)
 
 # kernels behind each profiled class (rocprofv3 kernel names), and the source
 # regions whose hash dates a counter summary
@@ -319,7 +318,7 @@ def counters_sample(args):
     B = torch.from_numpy(point_sources(dims)).to("cuda:0")
     n = B.shape[1]
     r, l, lam = LI.placeholder_deflation(n, w["n_defl"], cfg=3, inst=0)
-    k = COUNTER_K_TWO_STEP if args.orth == 2 else COUNTER_K
+    k = COUNTER_K
     ctx = osa.Context(links, dims, w["mu"], w["m_w"], k_max=k, check_every=-1,
                       max_batch=B.shape[0], orth=args.orth)
     ctx.set_deflation(torch.from_numpy(np.ascontiguousarray(r.T)).to("cuda:0"),
@@ -678,7 +677,7 @@ def headline16(args):
                    "sources": "12 spin-colour point sources at site 0, one lockstep batch",
                    "n_defl": w["n_defl"], "deflation": "LR (Eq. 20-22), computed once",
                    "k_max": w["k_max"], "tol": tol,
-                   "check_every": CHECK_EVERY + (1 if args.orth == 2 and CHECK_EVERY % 2 else 0),
+                   "check_every": CHECK_EVERY,
                    "orth": ["delayed one-step CGS2", "plain CGS2", "two-step blocks"][args.orth],
                    "stop_rule": "geometric tail of the checkpoint changes (x2)",
                    "parallelism": "single GPU"},

@@ -97,10 +97,9 @@ typedef struct {
                                    the basis by two vectors (H u, H^2 u) per outer step
                                    with one dot pass and one update pass over the basis
                                    (half the basis traffic of 0), the second pass again
-                                   delayed; the Krylov size stays even (check_every
-                                   rounded up, an odd k_max down).  Under Schur
-                                   deflation, or with a fixed odd k_max, the solve uses 0;
-                                   the eigensolver uses 0                                  */
+                                   delayed; checks at the same sizes as with 0.  Under
+                                   Schur deflation the solve uses 0; the eigensolver
+                                   uses 0                                                  */
     int32_t eig_filter;         /* FP64 search for the critical pairs: 0 (default)
                                    Krylov-Schur; d in 1..200: Chebyshev-filtered subspace
                                    iteration on H^2 with a degree-d filter and a block of

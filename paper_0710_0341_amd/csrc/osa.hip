@@ -1087,8 +1087,8 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     check_deflation_state(c);
     const bool schur = c->opts.deflation == 1 && c->m_active > 0;   // Eq. 13-19
     // the Schur basis set-up uses m columns of the basis storage as scratch
-    // the two-step form keeps two columns beyond the Krylov size
-    ensure_krylov(c, schur ? std::max(kmax, c->m_active) : (c->opts.orth == 2 ? kmax + 1 : kmax),
+    // the two-step form keeps up to three columns beyond the Krylov size
+    ensure_krylov(c, schur ? std::max(kmax, c->m_active) : (c->opts.orth == 2 ? kmax + 2 : kmax),
                   nb);
     if (c->lay.vec_len < kmax + c->m_alloc + 2 || c->lay.m < c->m_alloc) {
         c->lay = ArenaLayout::make(c->kcap, std::max(c->m_alloc, 1));
@@ -1104,10 +1104,11 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     const TsPlan p = ts_plan(N);
     const int64_t VS = (int64_t)(c->kcap + 2) * N;   // basis stride
     // orth 2: two-step blocks (one dot and one update pass per two Arnoldi
-    // steps), with LR deflation or none; the Krylov size stays even (the check
-    // interval is rounded up to even, a last size kmax rounded down).  Schur
-    // deflation, or a fixed odd kmax, takes the delayed one-step form instead.
-    const bool blk2 = c->opts.orth == 2 && !schur && !(fixed && (kmax & 1));
+    // steps), with LR deflation or none.  Outer step n completes the
+    // decomposition of size n + 1, so the checks (at the multiples of
+    // check_every and at kmax) can take size n + 1 or n.  Schur deflation takes
+    // the delayed one-step form instead.
+    const bool blk2 = c->opts.orth == 2 && !schur;
     const bool dcgs = c->opts.orth == 0 || (c->opts.orth == 2 && !blk2);   // delayed reorth.
     const int ldh = L.ldh;
     cd* V = c->V.as<cd>();
@@ -1302,16 +1303,20 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
                               c->st, bt);
         });
     };
-    // step index j: its Krylov size, the last size and the check interval
-    const int kmax_u = blk2 ? (kmax & ~1) : kmax;
-    const int every_u = (blk2 && (every & 1)) ? every + 1 : every;
+    // step index j: the Krylov size it completes; check_size(j) is the size of a
+    // check after step j, 0 if none.  A two-step unit j (outer step n = 2j + 1,
+    // up to n = kmax) completes size 2j + 2 and can check at 2j + 2 or 2j + 1.
     auto size_of = [&](int j) { return blk2 ? 2 * j + 2 : (dcgs ? j : j + 1); };
     const int jbeg = dcgs ? 1 : 0;
-    const int jend = blk2 ? kmax_u / 2 : (dcgs ? kmax + 1 : kmax);
-    auto is_check = [&](int j) {
+    const int jend = blk2 ? (kmax + 1) / 2 : (dcgs ? kmax + 1 : kmax);
+    auto on_grid = [&](int kk) { return kk >= 1 && kk <= kmax && (kk % every == 0 || kk == kmax); };
+    auto check_size = [&](int j) {
         const int kk = size_of(j);
-        return kk % every_u == 0 || kk == kmax_u;
+        if (on_grid(kk)) return kk;
+        if (blk2 && on_grid(kk - 1)) return kk - 1;
+        return 0;
     };
+    auto is_check = [&](int j) { return check_size(j) > 0; };
     for (int j = jbeg; j < jend && !act.empty(); ++j) {
         // the segment [j, je]: the steps up to and including the next check
         int je = j;
@@ -1323,17 +1328,17 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
                         else do_step(jj, bat(act));
                     });
         j = je;
-        const int kk = size_of(j);
+        const int kk = check_size(j) > 0 ? check_size(j) : size_of(j);
         if (!is_check(j)) continue;
         // each source follows its own schedule, as it would alone
         std::vector<int> chk, wait;
         for (int b : act) {
             bool want = true;
-            if (!fixed && kk != kmax_u && !crate[b].empty()) {
+            if (!fixed && kk != kmax && !crate[b].empty()) {
                 const double rho = crate[b].back();
                 const double pred = ctail[b] * std::pow(rho, (double)(kk - cj[b].back()));
                 const bool near = !(rho < 1.0) || !(pred > 3.0 * tol);
-                if (!near && kk - cj[b].back() < 4 * every_u) want = false;
+                if (!near && kk - cj[b].back() < 4 * every) want = false;
             }
             (want ? chk : wait).push_back(b);
         }
