@@ -292,7 +292,7 @@ CLASS_KERNELS = {
 CLASS_REGIONS = {
     "cgs_dot": [("paper_0710_0341_amd/csrc/blas.hip", "static TsPlan dot_plan(",
                  "// ---------------------------------------------------------------- reduce"),
-                ("paper_0710_0341_amd/csrc/blas.hip", "// Columns per block of the four-vector dot",
+                ("paper_0710_0341_amd/csrc/blas.hip", "// Dots of ncols columns of B with the four vectors",
                  "// Columns o0 .. o0+NO-1")],
     "cgs_update": [("paper_0710_0341_amd/csrc/blas.hip",
                     "// ---------------------------------------------------------------- update",
