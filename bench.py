@@ -424,12 +424,12 @@ def batched_vs_plain(osa, ctx, dims, tol, m, reps=1):
     import torch
     B = torch.from_numpy(point_sources(dims)).to("cuda:0")
     k_max, eig_prec, ncv = ctx._opts.k_max, ctx._opts.eig_prec, ctx._opts.eig_ncv
-    defl = ctx._opts.deflation
+    defl, orth = ctx._opts.deflation, ctx._opts.orth
     out = {}
     ys = {}
     for name, mb in (("plain", 1), ("batched", 12)):
         ctx.set_opts(k_max=k_max, check_every=50, max_batch=mb, eig_prec=eig_prec, eig_ncv=ncv,
-                     deflation=defl)
+                     deflation=defl, orth=orth)
         ctx.set_active_deflation(m)
         ctx.apply(B, tol=tol)            # warm-up (workspace growth)
         torch.cuda.synchronize()
@@ -442,7 +442,8 @@ def batched_vs_plain(osa, ctx, dims, tol, m, reps=1):
         out[name] = {"solves_per_s": 12.0 / dt, "ms": dt * 1e3, "status": int(st),
                      "k_used": [i["k_used"] for i in infos],
                      "max_resid_est": max(i["resid_est"] for i in infos)}
-    ctx.set_opts(k_max=k_max, check_every=50, eig_prec=eig_prec, eig_ncv=ncv, deflation=defl)
+    ctx.set_opts(k_max=k_max, check_every=50, eig_prec=eig_prec, eig_ncv=ncv, deflation=defl,
+                 orth=orth)
     out["speedup"] = out["batched"]["solves_per_s"] / out["plain"]["solves_per_s"]
     out["bitwise_equal"] = bool(torch.equal(ys["plain"], ys["batched"]))
     out["sources"] = "12 spin-colour point sources at site 0"
@@ -468,7 +469,8 @@ def uneven_batch(args):
         links = LI.make_links(p["dims"], "disordered", eps=p["eps"], cfg=4, inst=p["inst"])
         b = LI.gaussian_source(p["dims"], cfg=4, inst=p["inst"])
         ctxs.append(osa.Context(torch.from_numpy(links).to("cuda:0"), p["dims"], p["mu"], p["m_w"],
-                                k_max=w["k_max"], check_every=50, stream=torch.cuda.Stream()))
+                                k_max=w["k_max"], check_every=50, orth=args.orth,
+                                stream=torch.cuda.Stream()))
         srcs.append(torch.from_numpy(b).to("cuda:0"))
     torch.cuda.synchronize()
     eig_ms = [0.0] * len(ctxs)
@@ -867,7 +869,7 @@ def main():
     eig_prec = osa.FP32 if args.eig_prec == "fp32" else osa.FP64
     scheme = osa.SCHUR if args.deflation == "schur" else osa.LR
     ctxs = [osa.Context(links, dims, mu, wl["m_w"], k_max=wl["k_max"], check_every=50,
-                        eig_prec=eig_prec, eig_ncv=args.eig_ncv, deflation=scheme)
+                        eig_prec=eig_prec, eig_ncv=args.eig_ncv, deflation=scheme, orth=args.orth)
             for mu in wl["mus"]]
     mmax = max(wl["ms"])
     records = []
@@ -896,7 +898,7 @@ def main():
         ctx.set_active_deflation(mmax)
         ctx.apply(b, tol=wl["tol"])
         rec = {"solve_only": True, "mu": ctx.mu, "m": mmax}
-        for orth in (0, 1):
+        for orth in (0, 1, 2):
             ctx.set_opts(k_max=wl["k_max"], check_every=50, orth=orth, deflation=scheme)
             ctx.set_active_deflation(mmax)
             torch.cuda.synchronize()
