@@ -296,6 +296,9 @@ CLASS_REGIONS = {
                  "// Columns o0 .. o0+NO-1")],
     "cgs_update": [("paper_0710_0341_amd/csrc/blas.hip",
                     "// ---------------------------------------------------------------- update",
+                    "// ------------------------------------------- shared basis, several vectors"),
+                   ("paper_0710_0341_amd/csrc/blas.hip",
+                    "// ------------------------------------------------ delayed reorthogonalisation",
                     "// ------------------------------------------- two-step block Arnoldi"),
                    ("paper_0710_0341_amd/csrc/blas.hip", "// Columns o0 .. o0+NO-1",
                     "// Per-problem workspace of the two-step form")],

@@ -632,41 +632,43 @@ int launch_mdot_partial(const cd* B, int64_t ldb, int ncols, const cd* w, const 
     return p.nchunks;
 }
 
-// w_b[i] -= sum_c B[c][i] coef_b[c] for up to kMupdR problems per launch
-// entry, B read once: the arithmetic of k_update_direct (alpha = 1, no norm
-// partials) for every problem.  Batch strides: vec (w), small (coef).
+// w_v[i] -= sum_c B[c][i] coef_v[c] for nv vectors per problem (vector t of
+// problem b at w + b*bt.vec + t*off2, its coefficients at coef + b*bt.small +
+// t*coff2), NR vectors per launch entry (at most kMupdV), B read once per entry:
+// the arithmetic of k_update_direct (alpha = 1, no norm partials) for every
+// vector.  The coefficients are uniform over the block and are read with
+// uniform addresses (scalar loads), not staged through LDS.
 static constexpr int kMupdR = 16;
+static constexpr int kMupdV = 24;
 static constexpr int kMupdCols = 64;
 
-__global__ __launch_bounds__(kBlock) void k_mupdate(cd* w, const cd* __restrict__ B, int64_t ldb,
+template <int NR>
+__global__ __launch_bounds__(kBlock) void k_mupdate(cd* w, int64_t off2, int nv,
+                                                    const cd* __restrict__ B, int64_t ldb,
                                                     int ncols, const cd* __restrict__ coef,
-                                                    int64_t n, Batch bt) {
-    __shared__ cd scoef[kMupdR][kMupdCols];
-    const int g0 = blockIdx.y * kMupdR;
-    const int nr = (bt.n - g0 < kMupdR) ? bt.n - g0 : kMupdR;
-    for (int e = threadIdx.x; e < nr * ncols; e += kBlock) {
-        const int r = e / ncols, c = e % ncols;
-        scoef[r][c] = coef[(int64_t)bt.idx[g0 + r] * bt.small + c];
+                                                    int64_t coff2, int64_t n, int v0, Batch bt) {
+    const cd* cp[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int v = v0 + r;
+        cp[r] = coef + (int64_t)bt.idx[v / nv] * bt.small + (int64_t)(v % nv) * coff2;
     }
-    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    cd acc[kMupdR];
+    cd acc[NR];
 #pragma unroll
-    for (int r = 0; r < kMupdR; ++r) acc[r] = mk(0.0, 0.0);
+    for (int r = 0; r < NR; ++r) acc[r] = mk(0.0, 0.0);
     for (int c = 0; c < ncols; ++c) {
         const cd b = B[(int64_t)c * ldb + i];
 #pragma unroll
-        for (int r = 0; r < kMupdR; ++r)
-            if (r < nr) cfma(acc[r], b, scoef[r][c]);
+        for (int r = 0; r < NR; ++r) cfma(acc[r], b, cp[r][c]);
     }
 #pragma unroll
-    for (int r = 0; r < kMupdR; ++r) {
-        if (r < nr) {
-            cd* wp = w + (int64_t)bt.idx[g0 + r] * bt.vec + i;
-            const cd base = *wp;
-            *wp = mk(base.x + -1.0 * acc[r].x, base.y + -1.0 * acc[r].y);
-        }
+    for (int r = 0; r < NR; ++r) {
+        const int v = v0 + r;
+        cd* wp = w + (int64_t)bt.idx[v / nv] * bt.vec + (int64_t)(v % nv) * off2 + i;
+        const cd base = *wp;
+        *wp = mk(base.x + -1.0 * acc[r].x, base.y + -1.0 * acc[r].y);
     }
 }
 
@@ -676,13 +678,242 @@ bool mupdate_matches_single(int64_t n, int ncols) {
     return ncols <= kMupdCols && (ncols <= 32 || ceil_div(n, kBlock) >= 1024);
 }
 
+template <int NR>
+static void mupdate_go(cd* w, int64_t off2, int nv, const cd* B, int64_t ldb, int ncols,
+                       const cd* coef, int64_t coff2, int64_t n, int v0, hipStream_t st,
+                       const Batch& bt) {
+    hipLaunchKernelGGL(k_mupdate<NR>, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, st, w,
+                       off2, nv, B, ldb, ncols, coef, coff2, n, v0, bt);
+}
+
 void launch_mupdate(cd* w, const cd* B, int64_t ldb, int ncols, const cd* coef, int64_t n,
-                    hipStream_t st, const Batch& bt) {
+                    hipStream_t st, const Batch& bt, int nv, int64_t off2, int64_t coff2) {
     if (bt.n <= 0 || ncols <= 0) return;
     if (ncols > kMupdCols) throw HipError{hipErrorInvalidValue, "launch_mupdate: ncols > 64"};
-    dim3 grid((unsigned)ceil_div(n, kBlock), (unsigned)ceil_div(bt.n, kMupdR));
-    hipLaunchKernelGGL(k_mupdate, grid, dim3(kBlock), 0, st, w, B, ldb, ncols, coef, n, bt);
-    OSA_LAUNCH_CHECK();
+    if (nv < 1 || nv > 2) throw HipError{hipErrorInvalidValue, "launch_mupdate: nv not 1 or 2"};
+    const int nvec = bt.n * nv;
+    for (int v0 = 0; v0 < nvec; v0 += kMupdV) {
+        const int nr = std::min(kMupdV, nvec - v0);
+#define OSA_MUPD(NR) \
+    case NR: mupdate_go<NR>(w, off2, nv, B, ldb, ncols, coef, coff2, n, v0, st, bt); break;
+        switch (nr) {
+            OSA_MUPD(1) OSA_MUPD(2) OSA_MUPD(3) OSA_MUPD(4) OSA_MUPD(5) OSA_MUPD(6)
+            OSA_MUPD(7) OSA_MUPD(8) OSA_MUPD(9) OSA_MUPD(10) OSA_MUPD(11) OSA_MUPD(12)
+            OSA_MUPD(13) OSA_MUPD(14) OSA_MUPD(15) OSA_MUPD(16) OSA_MUPD(17) OSA_MUPD(18)
+            OSA_MUPD(19) OSA_MUPD(20) OSA_MUPD(21) OSA_MUPD(22) OSA_MUPD(23)
+            default: mupdate_go<24>(w, off2, nv, B, ldb, ncols, coef, coff2, n, v0, st, bt); break;
+        }
+#undef OSA_MUPD
+        OSA_LAUNCH_CHECK();
+    }
+}
+
+// ------------------------------------------- projection dots, LDS tiles
+// Dots of the m shared columns L (m <= kPdMaxM) with the vectors of the batch,
+// nv per problem (vector t of problem b at w + b*bt.vec + t*off2): partial
+// [b*bt.part + (t*m + c)*nchunks + q] = sum over chunk q of conj(L[c][i]) w[i].
+// One block per row chunk and group of up to kPdMaxV vectors.  Tiles of kPdKT
+// rows of L and of the vectors are staged through LDS (double-buffered,
+// column-major with a one-row pad, the next tile's loads in flight during the
+// current tile's products), so L and the vectors are each read once from HBM.
+// Wave g of the block owns the rows r of its chunk with (r - r0) % 8 == g, in
+// increasing order; lane l owns the TC x TV (column, vector) pairs of column
+// group l % 8 and vector group l / 8.  A pair's dot is therefore the same fma
+// chain over the same rows whatever the batch or the lane split, and the eight
+// wave sums are added in the order 0..7: results depend on (n, m) only (the
+// chunk plan, pdot_plan), so a batched projection is bitwise that of one source.
+static constexpr int kPdSlices = 8;                 // waves per block
+static constexpr int kPdThreads = 64 * kPdSlices;
+static constexpr int kPdLanes = 8;                  // column groups (= vector groups)
+static constexpr int kPdKT = 16;                    // rows per tile
+static constexpr int kPdMaxV = 3 * kPdLanes;        // vectors per block
+
+template <int TC, int TV>
+__global__ __launch_bounds__(kPdThreads) void k_pdot_partial(
+    const cd* __restrict__ L, int64_t ldl, int m, const cd* __restrict__ w, int64_t off2, int nv,
+    int v0, int S, int64_t n, int rpc, int nchunks, cd* __restrict__ partial, Batch bt) {
+    extern __shared__ cd pd_sh[];
+    constexpr int KT = kPdKT, KTP = KT + 1;
+    constexpr int NLD = (kPdMaxM * KT + kPdThreads - 1) / kPdThreads;
+    constexpr int NWD = (kPdLanes * TV * KT + kPdThreads - 1) / kPdThreads;
+    const int bufsz = (m + S) * KTP;
+    cd* const sL0 = pd_sh;
+    cd* const sW0 = pd_sh + m * KTP;
+    const int q = blockIdx.x;
+    const int64_t r0 = (int64_t)q * rpc;
+    const int64_t r1 = (r0 + rpc < n) ? r0 + rpc : n;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int cb = (lane % kPdLanes) * TC, vb = (lane / kPdLanes) * TV;
+    // the tile loads: element e of the L tile is (column e / KT, row e % KT),
+    // clamped into range (the surplus loads repeat a valid address and are
+    // never stored), so every prefetch register is always written
+    const int ntile = (int)((r1 - r0 + KT - 1) / KT);
+    double2 rl[NLD], rw[NWD];
+    const int nle = m * KT, nwe = S * KT;
+    auto vec_ptr = [&](int v) {
+        const int gv = v0 + v;
+        return w + (int64_t)bt.idx[gv / nv] * bt.vec + (int64_t)(gv % nv) * off2;
+    };
+#define OSA_PD_LOAD(T)                                                                       \
+    {                                                                                        \
+        const int64_t t0n = r0 + (int64_t)(T) * KT;                                          \
+        _Pragma("unroll") for (int k = 0; k < NLD; ++k) {                                    \
+            int e = tid + k * kPdThreads;                                                    \
+            e = (e < nle) ? e : nle - 1;                                                     \
+            const int64_t rr = (t0n + e % KT < r1) ? t0n + e % KT : r1 - 1;                  \
+            rl[k] = *(const double2*)(L + (int64_t)(e / KT) * ldl + rr);                     \
+        }                                                                                    \
+        _Pragma("unroll") for (int k = 0; k < NWD; ++k) {                                    \
+            int e = tid + k * kPdThreads;                                                    \
+            e = (e < nwe) ? e : nwe - 1;                                                     \
+            const int64_t rr = (t0n + e % KT < r1) ? t0n + e % KT : r1 - 1;                  \
+            rw[k] = *(const double2*)(vec_ptr(e / KT) + rr);                                 \
+        }                                                                                    \
+    }
+#define OSA_PD_STORE(BUF)                                                                    \
+    {                                                                                        \
+        cd* sl_ = sL0 + (BUF) * bufsz;                                                       \
+        cd* sw_ = sW0 + (BUF) * bufsz;                                                       \
+        _Pragma("unroll") for (int k = 0; k < NLD; ++k) {                                    \
+            const int e = tid + k * kPdThreads;                                              \
+            if (e < nle) sl_[(e / KT) * KTP + e % KT] = mk(rl[k].x, rl[k].y);                \
+        }                                                                                    \
+        _Pragma("unroll") for (int k = 0; k < NWD; ++k) {                                    \
+            const int e = tid + k * kPdThreads;                                              \
+            if (e < nwe) sw_[(e / KT) * KTP + e % KT] = mk(rw[k].x, rw[k].y);                \
+        }                                                                                    \
+    }
+    double acc[TC][TV][2];
+#pragma unroll
+    for (int i = 0; i < TC; ++i)
+#pragma unroll
+        for (int k = 0; k < TV; ++k) acc[i][k][0] = acc[i][k][1] = 0.0;
+    int ci[TC], vi[TV];
+#pragma unroll
+    for (int i = 0; i < TC; ++i) ci[i] = (cb + i < m) ? cb + i : m - 1;
+#pragma unroll
+    for (int k = 0; k < TV; ++k) vi[k] = (vb + k < S) ? vb + k : S - 1;
+    if (ntile > 0) {
+        OSA_PD_LOAD(0)
+        OSA_PD_STORE(0)
+    }
+    __syncthreads();
+    for (int t = 0; t < ntile; ++t) {
+        if (t + 1 < ntile) OSA_PD_LOAD(t + 1)
+        const cd* sl = sL0 + (t & 1) * bufsz + g;
+        const cd* sw = sW0 + (t & 1) * bufsz + g;
+        const cd* pl[TC];
+        const cd* pw[TV];
+#pragma unroll
+        for (int i = 0; i < TC; ++i) pl[i] = sl + ci[i] * KTP;
+#pragma unroll
+        for (int k = 0; k < TV; ++k) pw[k] = sw + vi[k] * KTP;
+        const int64_t t0 = r0 + (int64_t)t * KT;
+        const int nrow = (r1 - t0 < KT) ? (int)(r1 - t0) : KT;
+#pragma unroll
+        for (int j = 0; j < KT / kPdSlices; ++j) {
+            if (g + kPdSlices * j < nrow) {
+                cd wv[TV];
+#pragma unroll
+                for (int k = 0; k < TV; ++k) wv[k] = pw[k][kPdSlices * j];
+#pragma unroll
+                for (int i = 0; i < TC; ++i) {
+                    const cd l = pl[i][kPdSlices * j];
+#pragma unroll
+                    for (int k = 0; k < TV; ++k) {   // conj(l) w
+                        acc[i][k][0] = fma(l.x, wv[k].x, fma(l.y, wv[k].y, acc[i][k][0]));
+                        acc[i][k][1] = fma(l.x, wv[k].y, fma(-l.y, wv[k].x, acc[i][k][1]));
+                    }
+                }
+            }
+        }
+        if (t + 1 < ntile) OSA_PD_STORE((t + 1) & 1)
+        __syncthreads();
+    }
+#undef OSA_PD_LOAD
+#undef OSA_PD_STORE
+    // the eight waves' sums, added in wave order
+    cd* red = pd_sh;
+    for (int s = 0; s < kPdSlices; ++s) {
+        if (g == s) {
+#pragma unroll
+            for (int i = 0; i < TC; ++i)
+#pragma unroll
+                for (int k = 0; k < TV; ++k)
+                    if (cb + i < m && vb + k < S) {
+                        cd* r = red + (cb + i) * S + vb + k;
+                        *r = (s == 0) ? mk(acc[i][k][0], acc[i][k][1])
+                                      : mk(r->x + acc[i][k][0], r->y + acc[i][k][1]);
+                    }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < m * S; e += kPdThreads) {
+        const int c = e % m, v = e / m, gv = v0 + v;
+        partial[(int64_t)bt.idx[gv / nv] * bt.part + (int64_t)((gv % nv) * m + c) * nchunks + q] =
+            red[c * S + v];
+    }
+}
+
+TsPlan pdot_plan(int64_t n, int m) {
+    // up to 512 chunks, at least 256 rows each, and 2 m chunks within the
+    // partial buffer's 160 kMaxChunks entries per problem (two vectors)
+    int64_t want = ceil_div(n, 256);
+    want = std::min<int64_t>(want, 512);
+    want = std::min<int64_t>(want, (int64_t)(160 * kMaxChunks) / (2 * std::max(m, 1)));
+    if (want < 1) want = 1;
+    TsPlan p;
+    p.n = n;
+    p.rows_per_chunk = (int)(ceil_div(ceil_div(n, want), kPdSlices) * kPdSlices);
+    p.nchunks = (int)ceil_div(n, p.rows_per_chunk);
+    return p;
+}
+
+template <int TC, int TV>
+static void pdot_go(const cd* L, int64_t ldl, int m, const cd* w, int64_t off2, int nv, int v0,
+                    int S, const TsPlan& p, cd* partial, hipStream_t st, const Batch& bt) {
+    const size_t lds = sizeof(cd) * std::max<size_t>((size_t)2 * (m + S) * (kPdKT + 1),
+                                                     (size_t)m * S);
+    hipLaunchKernelGGL((k_pdot_partial<TC, TV>), dim3((unsigned)p.nchunks), dim3(kPdThreads), lds,
+                       st, L, ldl, m, w, off2, nv, v0, S, p.n, p.rows_per_chunk, p.nchunks, partial,
+                       bt);
+}
+
+template <int TC>
+static void pdot_tv(int tv, const cd* L, int64_t ldl, int m, const cd* w, int64_t off2, int nv,
+                    int v0, int S, const TsPlan& p, cd* partial, hipStream_t st, const Batch& bt) {
+    if (tv == 1) pdot_go<TC, 1>(L, ldl, m, w, off2, nv, v0, S, p, partial, st, bt);
+    else if (tv == 2) pdot_go<TC, 2>(L, ldl, m, w, off2, nv, v0, S, p, partial, st, bt);
+    else pdot_go<TC, 3>(L, ldl, m, w, off2, nv, v0, S, p, partial, st, bt);
+}
+
+int launch_pdot_partial(const cd* L, int64_t ldl, int m, const cd* w, int64_t off2, int nv,
+                        int64_t n, cd* partial, hipStream_t st, const Batch& bt) {
+    const TsPlan p = pdot_plan(n, m);
+    if (m <= 0 || bt.n <= 0) return p.nchunks;
+    if (m > kPdMaxM) throw HipError{hipErrorInvalidValue, "launch_pdot_partial: m > 64"};
+    if (nv < 1 || nv > 2) throw HipError{hipErrorInvalidValue, "launch_pdot_partial: nv"};
+    if ((int64_t)2 * m * p.nchunks > (int64_t)160 * kMaxChunks)
+        throw HipError{hipErrorInvalidValue, "launch_pdot_partial: partial buffer"};
+    const int tc = (int)ceil_div(m, kPdLanes);
+    const int nvec = bt.n * nv;
+    for (int v0 = 0; v0 < nvec; v0 += kPdMaxV) {
+        const int S = std::min(kPdMaxV, nvec - v0);
+        const int tv = (int)ceil_div(S, kPdLanes);
+        switch (tc) {
+            case 1: pdot_tv<1>(tv, L, ldl, m, w, off2, nv, v0, S, p, partial, st, bt); break;
+            case 2: pdot_tv<2>(tv, L, ldl, m, w, off2, nv, v0, S, p, partial, st, bt); break;
+            case 3: pdot_tv<3>(tv, L, ldl, m, w, off2, nv, v0, S, p, partial, st, bt); break;
+            case 4: pdot_tv<4>(tv, L, ldl, m, w, off2, nv, v0, S, p, partial, st, bt); break;
+            case 5: pdot_tv<5>(tv, L, ldl, m, w, off2, nv, v0, S, p, partial, st, bt); break;
+            case 6: pdot_tv<6>(tv, L, ldl, m, w, off2, nv, v0, S, p, partial, st, bt); break;
+            case 7: pdot_tv<7>(tv, L, ldl, m, w, off2, nv, v0, S, p, partial, st, bt); break;
+            default: pdot_tv<8>(tv, L, ldl, m, w, off2, nv, v0, S, p, partial, st, bt); break;
+        }
+        OSA_LAUNCH_CHECK();
+    }
+    return p.nchunks;
 }
 
 // out_b[i] = a w_b[i] + sg sum_{c < ncols} B[c][i] coef_b[c] for every problem b

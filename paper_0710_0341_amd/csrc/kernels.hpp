@@ -101,12 +101,26 @@ void launch_combine(void* y, const void* B, int64_t ldb, int ncols, const cd* co
 // Batch strides: vec (w), part (partial).
 int launch_mdot_partial(const cd* B, int64_t ldb, int ncols, const cd* w, const TsPlan& p,
                         cd* partial, hipStream_t st, const Batch& bt);
-// w_b -= B coef_b for every problem b (fp64, ncols <= 64), B read once per 16
-// problems; bitwise what launch_update does for each problem alone whenever
-// mupdate_matches_single(n, ncols).  Batch strides: vec (w), small (coef).
+// w_v -= B coef_v for the nv vectors v of every problem b (fp64, ncols <= 64):
+// vector t of problem b at w + b*bt.vec + t*off2, its coefficients at
+// coef + b*bt.small + t*coff2; B read once per 24 vectors; bitwise what
+// launch_update does for each vector alone whenever mupdate_matches_single(n,
+// ncols).  nv is 1 or 2.
 bool mupdate_matches_single(int64_t n, int ncols);
 void launch_mupdate(cd* w, const cd* B, int64_t ldb, int ncols, const cd* coef, int64_t n,
-                    hipStream_t st, const Batch& bt);
+                    hipStream_t st, const Batch& bt, int nv = 1, int64_t off2 = 0,
+                    int64_t coff2 = 0);
+// LR projection dots: partial[b*bt.part + (t*m + c)*nchunks + q] = chunk q of
+// conj(L[c]) . w_(b,t) for the m <= kPdMaxM shared columns L and the nv (1 or 2)
+// vectors of every problem b (vector t at w + b*bt.vec + t*off2), L and the
+// vectors read once from HBM for up to 24 vectors.  The chunk plan pdot_plan
+// depends on (n, m) only and every (column, vector) dot has one fixed
+// summation order, so batched results are bitwise those of one vector alone.
+// Returns nchunks (for launch_reduce_partial).
+constexpr int kPdMaxM = 64;
+TsPlan pdot_plan(int64_t n, int m);
+int launch_pdot_partial(const cd* L, int64_t ldl, int m, const cd* w, int64_t off2, int nv,
+                        int64_t n, cd* partial, hipStream_t st, const Batch& bt);
 // w_b = a w_b + sg B coef_b for every problem b (fp64, any ncols), B read once per
 // 16 problems.  Batch strides: vec (w), small (coef).
 void launch_mcombine(cd* w, const cd* B, int64_t ldb, int ncols, const cd* coef, int64_t n,

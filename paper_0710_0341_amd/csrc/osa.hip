@@ -512,14 +512,16 @@ void cgs2(osa_ctx* c, void* wv, const void* B, int64_t ld, int ncols, bool fp32,
 }
 
 // Oblique projection w <- w - R G^{-1} L^dag w (Eq. 21) with the active pairs,
-// shared by every problem of the batch.  The coefficients G^{-1} L^dag w are
-// left in cout; tmp is m scratch entries.  Under Schur deflation the
-// projection is orthogonal, w <- w - S S^dag w, and cout = S^dag w.  Batch strides: vec (w), small (cout,
-// tmp).
-void project_out(osa_ctx* c, void* wv, cd* cout, cd* tmp, const Batch& bt) {
+// shared by every problem of the batch, for nv (1 or 2) vectors per problem:
+// vector t at wv + b*bt.vec + t*off2.  The coefficients G^{-1} L^dag w of vector
+// t are left in cout + t*m; tmp is nv*m scratch entries.  Under Schur deflation
+// the projection is orthogonal, w <- w - S S^dag w, and cout = S^dag w.  Batch
+// strides: vec (w), small (cout, tmp).
+void project_out(osa_ctx* c, void* wv, cd* cout, cd* tmp, const Batch& bt, int nv = 1,
+                 int64_t off2 = 0) {
     const int m = c->m_active;
     if (m == 0) return;
-    const TsPlan p = ts_plan(c->N());
+    const int64_t N = c->N();
     cd* part = c->partial.as<cd>();
     Batch bd = bt, bu = bt;
     bd.basis = bu.basis = 0;   // L and R are shared
@@ -530,18 +532,35 @@ void project_out(osa_ctx* c, void* wv, cd* cout, cd* tmp, const Batch& bt) {
     const void* Lp = sch ? c->Sch.p : (c->adj ? c->R.p : c->L.p);
     const void* Rp = sch ? c->Sch.p : (c->adj ? c->L.p : c->R.p);
     const cd* Gi = sch ? nullptr : (c->adj ? c->GinvH.as<cd>() : c->Ginv.as<cd>());
-    // several sources: the shared L and R are read once per group of sources
-    // (kernels with the one-source arithmetic, so results stay bitwise equal)
-    const bool multi = bt.n > 1;
-    const int nch = multi ? launch_mdot_partial((const cd*)Lp, c->N(), m, (const cd*)wv, p, part,
-                                                c->st, bd)
-                          : launch_dot_partial(Lp, c->N(), m, wv, false, p, part, c->st, bd);
-    launch_reduce_partial(part, nch, m, cout, nullptr, Gi, tmp, c->st, bd);
-    if (multi && mupdate_matches_single(c->N(), m))
-        launch_mupdate((cd*)wv, (const cd*)Rp, c->N(), m, cout, c->N(), c->st, bu);
-    else
-        launch_update(wv, Rp, c->N(), m, cout, false, p, nullptr, c->upd_scratch.as<cd>(),
-                      (int64_t)(c->upd_scratch.bytes / sizeof(cd)), c->st, bu);
+    cd* w = (cd*)wv;
+    if (m <= kPdMaxM) {
+        // the LDS-tiled dots read L once for up to 24 vectors; their summation
+        // order depends on (N, m) only, so one source and a batch agree bitwise
+        const int nch = launch_pdot_partial((const cd*)Lp, N, m, w, off2, nv, N, part, c->st, bd);
+        for (int t = 0; t < nv; ++t)
+            launch_reduce_partial(part + (size_t)t * m * nch, nch, m, cout + t * m, nullptr, Gi,
+                                  tmp + t * m, c->st, bd);
+        if (bt.n * nv > 1 && mupdate_matches_single(N, m)) {
+            launch_mupdate(w, (const cd*)Rp, N, m, cout, N, c->st, bu, nv, off2, m);
+            return;
+        }
+    } else {
+        const TsPlan p = ts_plan(N);
+        for (int t = 0; t < nv; ++t) {
+            // several sources: the shared L is read once per group of sources
+            // (kernels with the one-source arithmetic, so results stay bitwise equal)
+            const int nch = bt.n > 1 ? launch_mdot_partial((const cd*)Lp, N, m, w + t * off2, p,
+                                                           part, c->st, bd)
+                                     : launch_dot_partial(Lp, N, m, w + t * off2, false, p, part,
+                                                          c->st, bd);
+            launch_reduce_partial(part, nch, m, cout + t * m, nullptr, Gi, tmp + t * m, c->st,
+                                  bd);
+        }
+    }
+    for (int t = 0; t < nv; ++t)
+        launch_update(w + t * off2, Rp, N, m, cout + t * m, false, ts_plan(N), nullptr,
+                      c->upd_scratch.as<cd>(), (int64_t)(c->upd_scratch.bytes / sizeof(cd)),
+                      c->st, bu);
 }
 
 // Strided device-to-host copy of `width` bytes from each of the problems in
@@ -1203,9 +1222,8 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
             Batch bv = b0;
             bv.vec = VS;   // the stencil writes into the basis
             apply_h(c, V, V + N, false, c->adj, bv);
-            if (reproj && m > 0) project_out(c, V + N, ar + L.coef2, ar + L.tmp, bv);
             apply_h(c, V + N, V + 2 * N, false, c->adj, bv);
-            if (reproj && m > 0) project_out(c, V + 2 * N, ar + L.coef2, ar + L.tmp, bv);
+            if (reproj && m > 0) project_out(c, V + N, ar + L.coef2, ar + L.tmp, bv, 2, N);
             Batch bd = bv;
             bd.part = c->part_stride;
             int nch = 0;
@@ -1280,15 +1298,19 @@ void solve_batch(osa_ctx* c, int nb, const cd* xin, cd* yout, double tol,
     // Two-step block, outer step n (odd): the stencil twice on u_b (column n+1)
     // into columns n+2, n+3, one dot pass of columns 0..n+1 with columns n..n+3,
     // the coefficients, one update pass forming columns n..n+3; completes size
-    // n + 1 (column n+1 of H stays pending).
+    // n + 1 (column n+1 of H stays pending).  The re-projection takes both new
+    // columns in one pass over L and R, after the second stencil application:
+    // H^2 u_b is formed from the unprojected H u_b, and H commutes with the
+    // projector up to the deflated pairs' residual, so this differs from
+    // projecting after each application by that residual times the
+    // rounding-level component along the deflated directions.
     auto do_step2 = [&](int n, const Batch& bt) {
         Batch bv = bt;
         bv.vec = VS;
         cd* Vn = V + (size_t)n * N;
         apply_h(c, Vn + N, Vn + 2 * N, false, c->adj, bv);
-        if (reproj && m > 0) project_out(c, Vn + 2 * N, ar + L.coef2, ar + L.tmp, bv);
         apply_h(c, Vn + 2 * N, Vn + 3 * N, false, c->adj, bv);
-        if (reproj && m > 0) project_out(c, Vn + 3 * N, ar + L.coef2, ar + L.tmp, bv);
+        if (reproj && m > 0) project_out(c, Vn + 2 * N, ar + L.coef2, ar + L.tmp, bv, 2, N);
         Batch bd = bt;
         bd.part = c->part_stride;
         int nch = 0;

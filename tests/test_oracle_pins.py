@@ -604,26 +604,34 @@ def test_geometric_tail_estimate_reading(kind, eps):
         assert stop_err is not None and stop_err <= 1e-8, d
 
 
-def _two_step_arnoldi(matvec, x, k, project=None):
+def _two_step_arnoldi(matvec, x, k, project=None, merged=False):
     """The GPU's two-step block form of the Arnoldi recurrence, written out in
     numpy: per outer step W = [H u_b, H^2 u_b] from the last unfinished vector;
     one set of inner products [V, U]^H [U, W]; U finished by its second
     Gram-Schmidt pass and a 2x2 Cholesky factor R; W orthogonalised once; the
-    Hessenberg columns recovered from R and the first-pass coefficients."""
-    prj = project if project else (lambda v: v)
+    Hessenberg columns recovered from R and the first-pass coefficients.
+    merged: the re-projection of both columns of W after H^2 u_b = H (H u_b)
+    (the GPU's order), instead of projecting after each application."""
+    prj0 = project if project else (lambda v: v)
+
+    def block(v):
+        if merged:
+            w1 = matvec(v)
+            return np.stack([prj0(w1), prj0(matvec(w1))], 1)
+        w1 = prj0(matvec(v))
+        return np.stack([w1, prj0(matvec(w1))], 1)
+
     n_all = x.shape[0]
     beta = np.linalg.norm(x)
     vmat = np.zeros((n_all, k + 3), dtype=complex)
     hmat = np.zeros((k + 3, k + 2), dtype=complex)
     vmat[:, 0] = x / beta
-    w1 = prj(matvec(vmat[:, 0]))
-    w = np.stack([w1, prj(matvec(w1))], 1)
+    w = block(vmat[:, 0])
     cv = vmat[:, :1].conj().T @ w
     u = w - vmat[:, :1] @ cv
     n, a, t0, cp = 1, cv[:, 0].copy(), 1.0, cv.copy()
     while n + 1 <= k:
-        w1 = prj(matvec(u[:, 1]))
-        w = np.stack([w1, prj(matvec(w1))], 1)
+        w = block(u[:, 1])
         vn = vmat[:, :n]
         s, g = vn.conj().T @ u, u.conj().T @ u
         cvn, e = vn.conj().T @ w, u.conj().T @ w
@@ -649,13 +657,17 @@ def _two_step_arnoldi(matvec, x, k, project=None):
     return vmat[:, :kk + 1], hmat[:kk + 1, :kk], beta, kk
 
 
-@pytest.mark.parametrize("kind,mu,m", [("haar", 0.3, 0), ("disordered", 0.5, 8)])
-def test_two_step_arnoldi_reading(kind, mu, m):
+@pytest.mark.parametrize("kind,mu,m,merged", [("haar", 0.3, 0, False),
+                                              ("disordered", 0.5, 8, False),
+                                              ("disordered", 0.5, 8, True)])
+def test_two_step_arnoldi_reading(kind, mu, m, merged):
     """The two-step block form (the GPU's orth 2) builds the Arnoldi
     decomposition of Eq. 7 that the oracle's CGS2 recurrence builds: the
     decomposition with v_1 = x/|x| and a real positive subdiagonal is unique,
     so the Hessenberg matrices, the bases and Eq. 22 agree to rounding, with
-    and without LR deflation and the per-vector re-projection."""
+    and without LR deflation and the per-vector re-projection, also with both
+    new columns projected together after the second application of H (H
+    commutes with the LR projector, Eq. 21)."""
     dims = (3, 4, 3, 4)
     links = LI.make_links(dims, kind, eps=0.6, cfg=9, inst=41)
     b = LI.gaussian_source(dims, cfg=9, inst=41)
@@ -664,7 +676,7 @@ def test_two_step_arnoldi_reading(kind, mu, m):
     xo = defl.split(b)[1] if defl else b
     proj = defl.project_out if defl else None
     k = 120
-    v2, h2, b2, k2 = _two_step_arnoldi(lambda v: h @ v, xo, k, proj)
+    v2, h2, b2, k2 = _two_step_arnoldi(lambda v: h @ v, xo, k, proj, merged)
     vo, ho, bo, ko = O.arnoldi_cgs2(lambda v: h @ v, xo, k, project=proj)
     assert k2 == ko == k
     assert np.abs(v2.conj().T @ v2 - np.eye(k + 1)).max() < 1e-13
