@@ -345,21 +345,30 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const cd* __restrict__ part
 
 // One block per problem: val = sum over chunks, then out = M val (M: ncols x
 // ncols, used for G^{-1} L^dag w with the small m x m matrix G^{-1}).
-__global__ __launch_bounds__(1024) void k_reduce_apply(const cd* __restrict__ partial, int nchunks,
-                                                       int ncols, cd* out,
-                                                       const cd* __restrict__ M, cd* tmp,
-                                                       Batch bt) {
+__global__ __launch_bounds__(kBlock) void k_reduce_apply(const cd* __restrict__ partial,
+                                                         int nchunks, int ncols, cd* out,
+                                                         const cd* __restrict__ M, cd* tmp,
+                                                         Batch bt) {
     const int pb = bt.idx[blockIdx.x];
     partial += pb * bt.part;
     out += pb * bt.small;
     tmp += pb * bt.small;
-    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
-        cd s = mk(0.0, 0.0);
-        for (int q = 0; q < nchunks; ++q) s = cadd(s, partial[(int64_t)c * nchunks + q]);
-        tmp[c] = s;
+    // a wave per column: lane l sums chunks l, l + 64, ..., then a butterfly
+    // over the lanes (an order fixed by nchunks)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c = wave; c < ncols; c += kWaves) {
+        double sr = 0.0, si = 0.0;
+        for (int q = lane; q < nchunks; q += 64) {
+            const cd v = partial[(int64_t)c * nchunks + q];
+            sr += v.x;
+            si += v.y;
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) tmp[c] = mk(sr, si);
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+    for (int c = threadIdx.x; c < ncols; c += kBlock) {
         cd s = mk(0.0, 0.0);
         for (int d = 0; d < ncols; ++d) cfma(s, M[c + (int64_t)d * ncols], tmp[d]);
         out[c] = s;
@@ -370,8 +379,7 @@ void launch_reduce_partial(const cd* partial, int nchunks, int ncols, cd* out, c
                            const cd* M, cd* tmp, hipStream_t st, const Batch& bt) {
     if (ncols <= 0 || bt.n <= 0) return;
     if (M) {
-        int threads = ncols >= 1024 ? 1024 : (int)ceil_div(ncols, 64) * 64;
-        hipLaunchKernelGGL(k_reduce_apply, dim3((unsigned)bt.n), dim3(threads), 0, st, partial,
+        hipLaunchKernelGGL(k_reduce_apply, dim3((unsigned)bt.n), dim3(kBlock), 0, st, partial,
                            nchunks, ncols, out, M, tmp, bt);
     } else {
         hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)ceil_div(ncols, 4), (unsigned)bt.n),
