@@ -164,7 +164,7 @@ typedef struct osa_ctx osa_ctx;
  *              (FP32 links define the operator exactly as stored)
  *   source     N complex128;   result  N complex128 (may not alias source)
  *   tol        > 0, stop threshold on the convergence estimate
- *   n_defl     0 <= n_defl < N and n_defl <= 64
+ *   n_defl     0 <= n_defl < N and n_defl <= 48 (else OSA_ERR_ARG)
  *   resid_est  (host, may be NULL) final convergence estimate
  * Returns OSA_OK, OSA_NOT_CONVERGED (result usable) or an error.
  * ------------------------------------------------------------------------- */
@@ -191,14 +191,16 @@ OSA_API osa_status osa_create(osa_ctx** out, const osa_lattice* lat, const void*
  * With opts.deflation = 1 (Schur deflation) only the right eigenvectors are
  * computed: the paper's remark that Schur deflation halves the set-up cost.
  * info (host, may be NULL) receives eigensolver statistics.
- * Errors: OSA_ERR_EIG_NOCONV, OSA_ERR_IMAG_AXIS (|Re lambda| < 1e-12 |H|). */
+ * Errors: OSA_ERR_ARG (n_defl < 0, n_defl > 48 or n_defl >= N),
+ * OSA_ERR_EIG_NOCONV, OSA_ERR_IMAG_AXIS (|Re lambda| < 1e-12 |H|). */
 OSA_API osa_status osa_deflate(osa_ctx* ctx, int32_t n_defl, osa_info* info);
 
 /* Import deflation data: R, L are m vectors each (m*N complex128, vector j at
  * offset j*N, boundary layout); lambda (host) holds m complex128 values
  * (re, im interleaved).  Only the projector R (L^dag R)^{-1} L^dag and the
  * eigenvalues matter; scale and phase of the vectors are free.  Under Schur
- * deflation (opts.deflation = 1) L may be NULL: only span(R) is used. */
+ * deflation (opts.deflation = 1) L may be NULL: only span(R) is used.
+ * 0 <= m <= 64 and m < N, else OSA_ERR_ARG. */
 OSA_API osa_status osa_set_deflation(osa_ctx* ctx, int32_t m, const void* R, const void* L,
                              const double* lambda);
 

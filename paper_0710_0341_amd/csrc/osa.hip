@@ -533,29 +533,16 @@ void project_out(osa_ctx* c, void* wv, cd* cout, cd* tmp, const Batch& bt, int n
     const void* Rp = sch ? c->Sch.p : (c->adj ? c->L.p : c->R.p);
     const cd* Gi = sch ? nullptr : (c->adj ? c->GinvH.as<cd>() : c->Ginv.as<cd>());
     cd* w = (cd*)wv;
-    if (m <= kPdMaxM) {
-        // the LDS-tiled dots read L once for up to 24 vectors; their summation
-        // order depends on (N, m) only, so one source and a batch agree bitwise
-        const int nch = launch_pdot_partial((const cd*)Lp, N, m, w, off2, nv, N, part, c->st, bd);
-        for (int t = 0; t < nv; ++t)
-            launch_reduce_partial(part + (size_t)t * m * nch, nch, m, cout + t * m, nullptr, Gi,
-                                  tmp + t * m, c->st, bd);
-        if (bt.n * nv > 1 && mupdate_matches_single(N, m)) {
-            launch_mupdate(w, (const cd*)Rp, N, m, cout, N, c->st, bu, nv, off2, m);
-            return;
-        }
-    } else {
-        const TsPlan p = ts_plan(N);
-        for (int t = 0; t < nv; ++t) {
-            // several sources: the shared L is read once per group of sources
-            // (kernels with the one-source arithmetic, so results stay bitwise equal)
-            const int nch = bt.n > 1 ? launch_mdot_partial((const cd*)Lp, N, m, w + t * off2, p,
-                                                           part, c->st, bd)
-                                     : launch_dot_partial(Lp, N, m, w + t * off2, false, p, part,
-                                                          c->st, bd);
-            launch_reduce_partial(part, nch, m, cout + t * m, nullptr, Gi, tmp + t * m, c->st,
-                                  bd);
-        }
+    // the LDS-tiled dots read L once for up to 24 vectors (m <= 64, the
+    // deflation size limit); their summation order depends on (N, m) only, so
+    // one source and a batch agree bitwise
+    const int nch = launch_pdot_partial((const cd*)Lp, N, m, w, off2, nv, N, part, c->st, bd);
+    for (int t = 0; t < nv; ++t)
+        launch_reduce_partial(part + (size_t)t * m * nch, nch, m, cout + t * m, nullptr, Gi,
+                              tmp + t * m, c->st, bd);
+    if (bt.n * nv > 1 && mupdate_matches_single(N, m)) {
+        launch_mupdate(w, (const cd*)Rp, N, m, cout, N, c->st, bu, nv, off2, m);
+        return;
     }
     for (int t = 0; t < nv; ++t)
         launch_update(w + t * off2, Rp, N, m, cout + t * m, false, ts_plan(N), nullptr,

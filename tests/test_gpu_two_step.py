@@ -156,3 +156,56 @@ def test_two_step_breakdown_and_not_converged(osa):
     y, infos, st = ctx.apply(dev(b), tol=1e-14)
     assert st == osa.OSA_NOT_CONVERGED and infos[0]["k_used"] == 21
     ctx.close()
+
+
+def test_two_step_batch_beyond_one_projection_group(osa, haar4):
+    """14 sources in lockstep: the two new columns of every source make 28
+    projected vectors, more than one projection launch takes (24), so the
+    dots and the update run in two groups; each source stays bitwise its
+    single-source solve (fixed k, LR deflation with the re-projection)."""
+    dims, links, h = haar4
+    say("two-step lockstep batch of 14 sources (two projection groups)")
+    srcs = [LI.point_source(dims, 0, s, c) for s in range(4) for c in range(3)]
+    srcs += [LI.gaussian_source(dims, cfg=0, inst=i) for i in (2, 3)]
+    B = np.stack(srcs)
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=40, check_every=-1, orth=2,
+                      max_batch=16)
+    ctx.deflate(10)
+    yb, infos, st = ctx.apply(dev(B), tol=1e-30, check=False)
+    yb = host(yb)
+    assert all(i["k_used"] == 40 for i in infos)
+    for i in (0, 7, 12, 13):
+        y1, inf1, _ = ctx.apply(dev(srcs[i]), tol=1e-30, check=False)
+        assert inf1[0]["k_used"] == 40
+        assert np.array_equal(host(y1), yb[i])
+    ctx.close()
+
+
+def test_two_step_64_pairs(osa):
+    """The largest deflation (64 pairs, the widest projection kernel shape):
+    Eq. 22 at a fixed k against the oracle (1e-10) and the one-step form
+    (1e-12), a batch bitwise equal to single-source solves; 65 pairs are
+    rejected."""
+    dims = (3, 3, 3, 3)
+    links = LI.make_links(dims, "haar", cfg=9, inst=8)
+    h = O.hermitian_wilson_sparse(links, dims, 0.3, -1.5)
+    r, l, lam = O.critical_dense(h.toarray(), 65)
+    defl = O.Deflation(r[:, :64], l[:, :64], lam[:64])
+    srcs = [LI.gaussian_source(dims, cfg=9, inst=30 + i) for i in range(3)]
+    say("two-step with 64 deflation pairs, fixed k = 30")
+    y2, i2 = _solve_fixed(osa, links, dims, 0.3, srcs[0], 30, 2, defl)
+    y0, i0 = _solve_fixed(osa, links, dims, 0.3, srcs[0], 30, 0, defl)
+    yo, info = O.lr_arnoldi_sign(lambda x: h @ x, srcs[0], defl, k=30)
+    assert i2["k_used"] == i0["k_used"] == info["k_used"] == 30
+    assert rel(y2, yo) < 1e-10
+    assert rel(y2, y0) < 1e-12
+    ctx = osa.Context(dev(links), dims, 0.3, -1.5, k_max=30, check_every=-1, orth=2)
+    ctx.set_deflation(dev(defl.r.T.copy()), dev(defl.l.T.copy()), defl.lam)
+    yb, _, _ = ctx.apply(dev(np.stack(srcs)), tol=1e-30, check=False)
+    yb = host(yb)
+    for i, s in enumerate(srcs):
+        y1, _, _ = ctx.apply(dev(s), tol=1e-30, check=False)
+        assert np.array_equal(host(y1), yb[i])
+    with pytest.raises(osa.OsaError):
+        ctx.set_deflation(dev(r.T.copy()), dev(l.T.copy()), lam)
+    ctx.close()
