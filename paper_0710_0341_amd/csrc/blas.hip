@@ -1278,20 +1278,25 @@ __global__ __launch_bounds__(kBlock) void k_dot4_partial(const cd* __restrict__ 
 #pragma unroll
     for (int i = 0; i < 8 * C; ++i) acc[i] = 0.0;
     const int nc = (ncols - c0 < C) ? ncols - c0 : C;
+    // columns past ncols (the last group) read column c0 again and their sums
+    // are dropped, so every load of a row is issued before its products
+    const cd* bp[C];
+#pragma unroll
+    for (int cc = 0; cc < C; ++cc) bp[cc] = B + (int64_t)(c0 + (cc < nc ? cc : 0)) * ldb;
     for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
-        cd w[4];
+        cd w[4], bb[C];
 #pragma unroll
         for (int v = 0; v < 4; ++v) w[v] = W[v * ldw + i];
 #pragma unroll
-        for (int cc = 0; cc < C; ++cc) {
-            if (cc < nc) {
-                const cd b = B[(int64_t)(c0 + cc) * ldb + i];
+        for (int cc = 0; cc < C; ++cc) bb[cc] = bp[cc][i];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {   // conj(b) w_v
-                    acc[8 * cc + 2 * v] = fma(b.x, w[v].x, fma(b.y, w[v].y, acc[8 * cc + 2 * v]));
-                    acc[8 * cc + 2 * v + 1] =
-                        fma(b.x, w[v].y, fma(-b.y, w[v].x, acc[8 * cc + 2 * v + 1]));
-                }
+        for (int cc = 0; cc < C; ++cc) {
+            const cd b = bb[cc];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {   // conj(b) w_v
+                acc[8 * cc + 2 * v] = fma(b.x, w[v].x, fma(b.y, w[v].y, acc[8 * cc + 2 * v]));
+                acc[8 * cc + 2 * v + 1] =
+                    fma(b.x, w[v].y, fma(-b.y, w[v].x, acc[8 * cc + 2 * v + 1]));
             }
         }
     }
